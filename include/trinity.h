@@ -1,0 +1,235 @@
+/*
+ * trinity.h -- C-ABI of the MI355X (gfx950) time-dependent radiative-transfer
+ * step of TRINITY (Yajima et al., "TRINITY: a three-dimensional time-dependent
+ * radiative transfer code for in-vivo near-infrared imaging").
+ *
+ * The library advances the photon field N[d][v] (voxel v, HEALPix direction
+ * d) of a voxelised medium step by step:
+ *   inject   a collimated Gaussian pulse at a surface point (Sec. 3.1);
+ *   collide  N_c[:,v] = a_v N[:,v] + b_v (P N)[:,v] -- Eq. (10) with the
+ *            explicit source of Eq. (2)/(12), P the discrete Henyey-Greenstein
+ *            matrix of Eq. (11) on HEALPix directions (Sec. 2.1);
+ *   sweep    move every direction's photons one plane along long
+ *            characteristics that cross the box from face to face (Sec. 2.1,
+ *            Fig. 1), absorb what leaves the box (Sec. 3.1), reflect and
+ *            refract at refractive-index jumps (Eq. 13-14, Sec. 3.3);
+ *   tally    per-step light leaving through each detector patch (Fig. 9) and
+ *            a photon budget (injected, absorbed, escaped, in the box).
+ *
+ * Conventions that hold for every call:
+ *  - Every call returns a tr_status; nothing else crosses the ABI on error.
+ *    tr_last_error() gives a message for the calling thread's last failure.
+ *  - A medium whose device work failed (TR_EDEVICE, TR_ENUMERIC) is poisoned:
+ *    every later call on it except tr_destroy_medium returns TR_ESTATE.
+ *  - Inputs are copied during the call; the caller may free them on return.
+ *  - Outputs are caller-allocated.  The library owns all of its device memory
+ *    and frees it in tr_destroy_medium.
+ *  - Voxel arrays are float32, indexed v = (z*ny + y)*nx + x, x fastest.  z is
+ *    depth; the top face z = 0 carries source and detectors.  Lengths are mm,
+ *    coefficients 1/mm, times ps.
+ *  - Faces are numbered face = 2*axis + side: axis 0 = x, 1 = y, 2 = z; side 0
+ *    is the low-index face, side 1 the high-index face (face 4 = top).
+ *  - Device work is queued on the HIP stream given at creation and is
+ *    asynchronous unless a call says it synchronises.
+ *  - Calls on one medium must not overlap (one thread at a time per medium).
+ */
+#ifndef TRINITY_H
+#define TRINITY_H
+
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct tr_medium tr_medium;   /* opaque, library-owned */
+
+typedef enum {
+  TR_OK = 0,
+  TR_EINVAL = -1,     /* bad argument; nothing was changed */
+  TR_ENOMEM = -2,     /* device or host allocation failed; nothing was changed */
+  TR_EDEVICE = -3,    /* a HIP call failed; the medium is poisoned */
+  TR_ENUMERIC = -4,   /* NaN or Inf in the photon budget; the medium is poisoned */
+  TR_ESTATE = -5      /* call on a poisoned medium, or out of order */
+} tr_status;
+
+enum { TR_HG_SINKHORN = 0, TR_HG_ROW = 1 };
+enum { TR_COEF_PAPER = 0, TR_COEF_ABS_EXACT = 1 };
+enum { TR_ADVANCE_AUTO = 0, TR_ADVANCE_PHASE = 1, TR_ADVANCE_SPLIT = 2 };
+enum { TR_PREC_FP32 = 0, TR_PREC_BF16SPLIT = 1 };
+
+typedef struct {
+  int nx, ny, nz;     /* voxels per axis, each >= 1 and <= 4096 */
+  double dx_mm;       /* voxel edge */
+  int nside;          /* HEALPix resolution: N = 12 nside^2 directions, RING order, 1..16 */
+  double g;           /* Henyey-Greenstein anisotropy, Eq. (11); -1 < g < 1 */
+  double dt_ps;       /* time step; 0 => dx * min(n) / c0 (light at c0/min(n) crosses one voxel) */
+  int hg_norm;        /* TR_HG_SINKHORN: P = D K D, rows and columns sum to 1 (default);
+                         TR_HG_ROW: rows of K divided by their sums */
+  int coef;           /* TR_COEF_PAPER: b = (mu_s/mu_t)(1 - e^{-mu_t l}), Eq. (9)-(10) with
+                         S1 = S0; TR_COEF_ABS_EXACT: b = e^{-mu_a l}(1 - e^{-mu_s l}) */
+  int advance;        /* TR_ADVANCE_AUTO: phase if n is uniform, else split;
+                         TR_ADVANCE_PHASE: all photons of a direction move one plane on the
+                         steps the direction's phase selects (n must be uniform);
+                         TR_ADVANCE_SPLIT: the fraction nu_d * min(n)/n_v moves each step */
+  int precision;      /* TR_PREC_FP32 or TR_PREC_BF16SPLIT (P and N split into bf16 hi+lo,
+                         three bf16 MFMA products, fp32 accumulation) */
+} tr_grid_desc;
+
+typedef struct {
+  int ndir;           /* N = 12 nside^2 */
+  int nvox;           /* nx*ny*nz */
+  int mode;           /* TR_ADVANCE_PHASE or TR_ADVANCE_SPLIT as resolved */
+  int ninterceptions; /* (direction, voxel) pairs whose move crosses an index jump */
+  double dt_ps;       /* time step as resolved */
+  long long steps_done;
+  size_t device_bytes;  /* device memory the medium holds */
+} tr_info;
+
+/* ---- medium life cycle ------------------------------------------------- */
+
+/* Build a medium from per-voxel mu_a, mu_s (1/mm) and refractive index n
+ * (Table 1 quantities; c = c0/n, Sec. 2.1).  The arrays hold nx*ny*nz floats
+ * each, on the host (arrays_on_device = 0) or on the current device
+ * (arrays_on_device = 1).  hip_stream is a hipStream_t (NULL = the null
+ * stream) on which all of this medium's work is queued.  The host set-up
+ * (directions, phase matrix, ray lattice, coefficients, interface lists) runs
+ * in FP64 before the call returns; the state starts at zero with step 0 next.
+ * TR_EINVAL: bad sizes, nside, g, negative coefficients, n < 1, a time step that
+ * moves light more than one plane per step, phase mode with non-uniform n.
+ * TR_ENOMEM: device memory exhausted.  On error *out is NULL. */
+tr_status tr_create_medium(const tr_grid_desc* desc, const float* mua, const float* mus,
+                           const float* n, int arrays_on_device, void* hip_stream,
+                           tr_medium** out);
+
+/* Device bytes tr_create_medium would allocate for this descriptor with
+ * ndet detectors and room for max_steps steps (for admission by HBM budget).
+ * Returns 0 for an invalid descriptor. */
+size_t tr_bytes_required(const tr_grid_desc* desc, int ndet, int max_steps);
+
+/* Release every resource of the medium; waits for its queued work. NULL is OK. */
+tr_status tr_destroy_medium(tr_medium* m);
+
+/* Message for the calling thread's last failed call ("" if none). */
+const char* tr_last_error(void);
+
+/* ---- problem statement (Sec. 3.1) ------------------------------------- */
+
+/* Collimated pulse (Sec. 3.1: pulse collimated within 15 degrees at a surface
+ * point).  Photons enter the top-face voxel (ix, iy) (w = 1) or the 2x2 block
+ * (ix..ix+1, iy..iy+1) (w = 2) in the directions whose centres lie within
+ * cone_deg of +z (or the 4 nearest when none does).  The pulse is a Gaussian
+ * of the given FWHM centred at t0; step m receives its integral over
+ * [m dt, (m+1) dt), scaled so the pulse after t = 0 holds total_photons.
+ * Replaces any earlier source; takes effect from the next step.
+ * TR_EINVAL: voxels outside the top face, w not 1 or 2, fwhm <= 0. */
+tr_status tr_set_source(tr_medium* m, int ix, int iy, int w, double cone_deg, double t0_ps,
+                        double fwhm_ps, double total_photons);
+
+/* Detector patches (Sec. 3.1: detectors with the source's opening angle).
+ * Detector k is the voxel on face face[k] at in-face indices (i[k], j[k]) --
+ * the voxel indices along the two other axes in increasing axis order.  It
+ * records, each step, the light leaving through that face from that voxel in
+ * directions within cone_deg of the face's outward normal (4 nearest when
+ * none; every direction when cone_deg <= 0).  tr_read_detectors bins the
+ * per-step records into nbins bins of bin_ps.  1 <= ndet <= 64.  Clears the
+ * detector records of steps already run.  TR_EINVAL: bad face or indices. */
+tr_status tr_set_detectors(tr_medium* m, int ndet, const int* face, const int* i, const int* j,
+                           double cone_deg, double bin_ps, int nbins);
+
+/* ---- stepping (Sec. 2.4, Steps 3-7) ------------------------------------ */
+
+/* Queue nsteps steps (inject, collide, sweep, tally) on the medium's stream
+ * and return without waiting.  Steps run from the medium's step counter
+ * onward.  TR_EINVAL: nsteps < 0. */
+tr_status tr_step(tr_medium* m, int nsteps);
+
+/* tr_step, then wait for the stream and check the photon budget of the new
+ * steps for NaN/Inf (TR_ENUMERIC). */
+tr_status tr_solve(tr_medium* m, int nsteps);
+
+/* Wait for the medium's queued work; report a device error if one occurred. */
+tr_status tr_synchronize(tr_medium* m);
+
+/* Zero the state, the detector records and the budget; the next step is 0. */
+tr_status tr_reset(tr_medium* m);
+
+/* ---- read-out (Fig. 9; synchronises) ------------------------------------ */
+
+/* Detector signals binned in time: out[k*nbins + j] = light recorded by
+ * detector k in [j bin_ps, (j+1) bin_ps), the light of step m spread evenly
+ * over [m dt, (m+1) dt).  n_out must be >= ndet*nbins.  FP64. */
+tr_status tr_read_detectors(tr_medium* m, double* out, size_t n_out);
+
+/* Per-step detector records: out[k*steps_done + s].  n_out >= ndet*steps_done. */
+tr_status tr_read_detector_steps(tr_medium* m, double* out, size_t n_out);
+
+/* Photon budget per step: out[s*9 + q], q = 0 injected, 1 absorbed, 2 in the
+ * box after the step, 3..8 escaped through faces 0..5.  n_out >= 9*steps_done. */
+tr_status tr_read_budget(tr_medium* m, double* out, size_t n_out);
+
+/* Energy density proxy E[v] = sum_d N[d][v] (Figs. 7-8), nvox floats, written
+ * to host memory (on_device = 0) or device memory (on_device = 1). */
+tr_status tr_read_energy(tr_medium* m, float* out, int on_device);
+
+/* Copy the photon field N[d][v] (ndir*nvox floats, direction-major) out of
+ * or into the medium, in host or device memory.  For tests and restarts. */
+tr_status tr_get_state(tr_medium* m, float* out, int on_device);
+tr_status tr_set_state(tr_medium* m, const float* in, int on_device);
+
+tr_status tr_get_info(tr_medium* m, tr_info* out);
+
+/* ---- kernel timing ------------------------------------------------------ */
+
+/* Kernel kinds reported by tr_profile_end. */
+enum { TR_K_INJECT = 0, TR_K_COLLIDE = 1, TR_K_SWEEP = 2, TR_K_GATHER = 3, TR_K_REDUCE = 4,
+       TR_K_COUNT = 5 };
+
+/* Start timing: the next steps (up to max_steps of them) are queued one kernel
+ * at a time with a pair of HIP events on the medium's stream around every
+ * kernel (no graph replay while timing).  TR_EINVAL: max_steps < 1. */
+tr_status tr_profile_begin(tr_medium* m, int max_steps);
+
+/* Stop timing, wait for the stream, and return per kernel kind the summed
+ * device time in ms (kernel_ms[TR_K_COUNT]) and the number of launches timed
+ * (launches[TR_K_COUNT]).  TR_ESTATE if timing was not started. */
+tr_status tr_profile_end(tr_medium* m, double* kernel_ms, int* launches);
+
+/* ---- host set-up tables (no device needed; for checking the set-up) ---- */
+
+/* HEALPix RING centres (Sec. 2.1), out[3*N]. */
+tr_status tr_host_directions(int nside, double* out);
+
+/* Discrete phase matrix P[i*N + j] (Eq. 11-12) for directions of nside. */
+tr_status tr_host_phase_matrix(int nside, double g, int hg_norm, double* out);
+
+/* Ray lattice of the grid: axis[d], sign[d] and offset[(d*2 + q)*(maxext+1) + k]
+ * = transverse offset of the ray at plane k for transverse axis q (0 = b, 1 = c),
+ * maxext = max(nx, ny, nz). */
+tr_status tr_host_lattice(int nside, int nx, int ny, int nz, int* axis, int* sign, int* offset);
+
+/* Per-voxel collision coefficients a, b and relative path r (split-mode move
+ * fraction factor), and the resolved time step. */
+tr_status tr_host_coefficients(const tr_grid_desc* desc, const float* mua, const float* mus,
+                               const float* n, double* a, double* b, double* r, double* dt_ps);
+
+/* Directions within cone_deg of the unit vector (ax, ay, az), 4 nearest when
+ * none: indices written to out (capacity cap), count to *count. */
+tr_status tr_host_cone_set(int nside, double ax, double ay, double az, double cone_deg,
+                           int* out, int cap, int* count);
+
+/* Pulse weights q_m for m = m0 .. m0+count-1 (see tr_set_source). */
+tr_status tr_host_pulse(double dt_ps, double t0_ps, double fwhm_ps, double total, int m0,
+                        int count, double* out);
+
+/* Interface interceptions (Eq. 13-14) of the grid: arrays of capacity cap,
+ * count written to *count (also when it exceeds cap, in which case nothing
+ * else is written). */
+tr_status tr_host_interceptions(const tr_grid_desc* desc, const float* n, int* d, int* v,
+                                int* w, double* R, int* d_refl, int* d_refr, int cap,
+                                int* count);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* TRINITY_H */

@@ -1,0 +1,978 @@
+// C-ABI of the TRINITY step library (include/trinity.h): medium life cycle,
+// host set-up upload, the step loop (with hipGraph replay of the per-step
+// kernel sequence), read-out and rebinning.
+#include "trinity.h"
+
+#include <hip/hip_runtime_api.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <map>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "device.hpp"
+#include "host_setup.hpp"
+
+using namespace trinity;
+
+namespace {
+thread_local std::string g_err;
+
+tr_status fail(tr_status s, const std::string& msg) {
+  g_err = msg;
+  return s;
+}
+
+constexpr int kGraphSteps = 16;   // steps per captured graph
+constexpr int kMaxDet = 64;
+
+long long round_up(long long x, long long m) { return (x + m - 1) / m * m; }
+
+bool valid_desc(const tr_grid_desc* d, std::string& err) {
+  if (!d) return err = "null descriptor", false;
+  if (d->nx < 1 || d->ny < 1 || d->nz < 1 || d->nx > 4096 || d->ny > 4096 || d->nz > 4096)
+    return err = "grid sizes must be in 1..4096", false;
+  if ((long long)d->nx * d->ny * d->nz > (1LL << 30)) return err = "grid too large", false;
+  if (!(d->dx_mm > 0) || !std::isfinite(d->dx_mm)) return err = "dx_mm must be > 0", false;
+  if (d->nside < 1 || d->nside > 16) return err = "nside must be in 1..16", false;
+  if (!(d->g > -1.0 && d->g < 1.0)) return err = "g must be in (-1, 1)", false;
+  if (!(d->dt_ps >= 0) || !std::isfinite(d->dt_ps)) return err = "dt_ps must be >= 0", false;
+  if (d->hg_norm != 0 && d->hg_norm != 1) return err = "bad hg_norm", false;
+  if (d->coef != 0 && d->coef != 1) return err = "bad coef", false;
+  if (d->advance < 0 || d->advance > 2) return err = "bad advance", false;
+  if (d->precision != 0 && d->precision != 1) return err = "bad precision", false;
+  return true;
+}
+
+Field field_of(const tr_grid_desc* d) {
+  Field f;
+  f.ndir = 12 * d->nside * d->nside;
+  f.NP = int(round_up(f.ndir, 32));
+  f.nx = d->nx;
+  f.ny = d->ny;
+  f.nz = d->nz;
+  f.V = d->nx * d->ny * d->nz;
+  f.Vp = round_up(f.V, 256);
+  return f;
+}
+
+unsigned short f32_to_bf16_bits(float x) {
+  unsigned int u;
+  std::memcpy(&u, &x, 4);
+  u += 0x7FFFu + ((u >> 16) & 1u);
+  return (unsigned short)(u >> 16);
+}
+float bf16_bits_to_f32(unsigned short h) {
+  unsigned int u = unsigned(h) << 16;
+  float x;
+  std::memcpy(&x, &u, 4);
+  return x;
+}
+
+}  // namespace
+
+struct tr_medium {
+  tr_grid_desc desc{};
+  hipStream_t stream = nullptr;
+  Field f{};
+  int mode = TR_ADVANCE_PHASE;
+  bool fresnel = false;
+  bool poisoned = false;
+  double dt = 0;
+  std::vector<Vec3> dirs;
+  Lattice lat;
+  Coefficients co;
+  std::vector<float> nhost;
+  std::vector<Interception> icpt;
+
+  std::map<void*, size_t> owned;   // every device allocation and its size
+  size_t bytes = 0;
+
+  float *X = nullptr, *Y = nullptr, *P = nullptr, *a = nullptr, *b = nullptr, *r = nullptr;
+  uint16_t *Phi = nullptr, *Plo = nullptr;
+  DevDir* ddirs = nullptr;
+  int8_t* delta = nullptr;
+  int dstride = 0;
+  uint8_t* iface = nullptr;
+  float* nvox = nullptr;
+  int* islot = nullptr;
+  float* icptF = nullptr;
+  int niface = 0;
+  int ntgt = 0;
+  int *tgt_d = nullptr, *tgt_v = nullptr, *gptr = nullptr, *gsrc = nullptr;
+  float* gw = nullptr;
+
+  int* step_ctr = nullptr;
+  int* flag = nullptr;
+  double *cpart = nullptr, *spart = nullptr;
+  int cnwg = 0, snwg = 0, sweep_bpd = 0;
+
+  // capacity-dependent (reallocated when more steps are needed)
+  int cap = 0;
+  double* budget = nullptr;
+  double* det_steps = nullptr;
+  double* qdev = nullptr;
+
+  // source
+  bool have_source = false;
+  int src_ix = 0, src_iy = 0, src_w = 1;
+  double src_cone = 15, src_t0 = 20, src_fwhm = 10, src_total = 1;
+  int npairs = 0;
+  int* src_pairs = nullptr;
+
+  // detectors
+  int ndet = 0;
+  std::vector<int> det_face, det_vox;
+  double bin_ps = 1.0;
+  int nbins = 0;
+  int* det_pairs = nullptr;
+  int* det_first = nullptr;
+  int* det_vox_dev = nullptr;
+
+  long long steps_done = 0;
+
+  hipGraphExec_t graph = nullptr;
+
+  // kernel timing (tr_profile_begin / tr_profile_end)
+  bool profiling = false;
+  int prof_cap = 0, prof_used = 0;
+  std::vector<hipEvent_t> prof_ev;   // [prof_cap][TR_K_COUNT][2]
+  std::vector<int> prof_kind;        // kind of each recorded pair
+
+  void free_events() {
+    for (hipEvent_t e : prof_ev) (void)hipEventDestroy(e);
+    prof_ev.clear();
+    prof_kind.clear();
+  }
+
+  ~tr_medium() {
+    free_events();
+    if (graph) (void)hipGraphExecDestroy(graph);
+    for (auto& kv : owned) (void)hipFree(kv.first);
+  }
+
+  template <class T>
+  T* alloc(size_t count) {
+    void* p = nullptr;
+    if (count == 0) count = 1;
+    if (hipMalloc(&p, count * sizeof(T)) != hipSuccess) return nullptr;
+    owned[p] = count * sizeof(T);
+    bytes += count * sizeof(T);
+    return static_cast<T*>(p);
+  }
+  void release(void* p) {
+    if (!p) return;
+    auto it = owned.find(p);
+    if (it == owned.end()) return;
+    bytes -= it->second;
+    owned.erase(it);
+    (void)hipFree(p);
+  }
+  void drop_graph() {
+    if (graph) (void)hipGraphExecDestroy(graph);
+    graph = nullptr;
+  }
+};
+
+namespace {
+
+tr_status device_fail(tr_medium* m, hipError_t e, const char* what) {
+  if (m) m->poisoned = true;
+  return fail(TR_EDEVICE, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+#define TR_CHECK_ALLOC(p) \
+  if (!(p)) return fail(TR_ENOMEM, "device allocation failed")
+
+// Bytes of the allocations that do not depend on the step capacity.
+size_t fixed_bytes(const Field& f, int precision, size_t niface_guess) {
+  size_t b = 0;
+  b += 2 * size_t(f.NP) * f.Vp * sizeof(float);         // X, Y
+  b += size_t(f.NP) * f.NP * sizeof(float);              // P
+  if (precision == 1) b += 2 * size_t(f.NP) * f.NP * 2;  // P_hi, P_lo
+  b += 3 * size_t(f.Vp) * sizeof(float);                 // a, b, r
+  b += size_t(f.ndir) * sizeof(DevDir);
+  b += size_t(f.ndir) * 2 * (std::max(f.nx, std::max(f.ny, f.nz)) + 2);
+  const int cn = collide_nwg(f), sn = sweep_blocks_per_dir(f) * f.ndir;
+  b += (2 * size_t(cn) + 7 * size_t(sn)) * sizeof(double);
+  b += niface_guess * f.ndir * sizeof(float);
+  return b;
+}
+
+tr_status ensure_capacity(tr_medium* m, long long need) {
+  if (need <= m->cap) return TR_OK;
+  long long cap = std::max<long long>(need, std::max<long long>(1024, 2LL * m->cap));
+  if (cap > (1LL << 30)) return fail(TR_EINVAL, "too many steps");
+  hipError_t e = hipStreamSynchronize(m->stream);
+  if (e != hipSuccess) return device_fail(m, e, "synchronize");
+  double* budget = m->alloc<double>(size_t(cap) * 9);
+  double* dets = m->alloc<double>(size_t(std::max(m->ndet, 1)) * cap);
+  double* q = m->alloc<double>(size_t(cap));
+  if (!budget || !dets || !q) {
+    m->release(budget);
+    m->release(dets);
+    m->release(q);
+    return fail(TR_ENOMEM, "device allocation failed (step capacity)");
+  }
+  e = hipMemsetAsync(budget, 0, size_t(cap) * 9 * 8, m->stream);
+  if (e == hipSuccess) e = hipMemsetAsync(dets, 0, size_t(std::max(m->ndet, 1)) * cap * 8, m->stream);
+  if (e == hipSuccess && m->cap > 0) {
+    e = hipMemcpyAsync(budget, m->budget, size_t(m->cap) * 9 * 8, hipMemcpyDeviceToDevice,
+                       m->stream);
+    for (int k = 0; k < m->ndet && e == hipSuccess; ++k)
+      e = hipMemcpyAsync(dets + size_t(k) * cap, m->det_steps + size_t(k) * m->cap,
+                         size_t(m->cap) * 8, hipMemcpyDeviceToDevice, m->stream);
+  }
+  std::vector<double> qh(cap, 0.0);
+  if (m->have_source)
+    for (long long s = 0; s < cap; ++s)
+      qh[s] = pulse_weight(s, m->dt, m->src_t0, m->src_fwhm, m->src_total);
+  if (e == hipSuccess) e = hipMemcpyAsync(q, qh.data(), size_t(cap) * 8, hipMemcpyHostToDevice, m->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(m->stream);
+  if (e != hipSuccess) return device_fail(m, e, "capacity growth");
+  m->release(m->budget);
+  m->release(m->det_steps);
+  m->release(m->qdev);
+  m->budget = budget;
+  m->det_steps = dets;
+  m->qdev = q;
+  m->cap = int(cap);
+  m->drop_graph();
+  return TR_OK;
+}
+
+// Event pair around one kernel while timing is active (no-op otherwise).
+struct KernelTimer {
+  tr_medium* m;
+  int slot = -1;
+  KernelTimer(tr_medium* mm, int kind) : m(mm) {
+    if (!m->profiling || m->prof_used >= int(m->prof_kind.size())) return;
+    slot = m->prof_used++;
+    m->prof_kind[slot] = kind;
+    (void)hipEventRecord(m->prof_ev[2 * slot], m->stream);
+  }
+  ~KernelTimer() {
+    if (slot >= 0) (void)hipEventRecord(m->prof_ev[2 * slot + 1], m->stream);
+  }
+};
+
+hipError_t queue_step(tr_medium* m) {
+  const Field& f = m->f;
+  hipError_t e;
+  if (m->npairs > 0) {
+    KernelTimer t(m, TR_K_INJECT);
+    InjectArgs ia{m->X, f.Vp, m->src_pairs, m->npairs, m->qdev, m->cap, m->step_ctr, m->budget};
+    if ((e = launch_inject(ia, m->stream)) != hipSuccess) return e;
+  }
+  {
+    KernelTimer t(m, TR_K_COLLIDE);
+    CollideArgs ca{m->X, m->Y, m->P, m->Phi, m->Plo, m->a, m->b, f.Vp, f.NP, m->cpart};
+    if ((e = launch_collide(ca, f, m->desc.precision, 0, m->stream)) != hipSuccess) return e;
+  }
+  const bool split = m->mode == TR_ADVANCE_SPLIT;
+  {
+    KernelTimer t(m, TR_K_SWEEP);
+    SweepArgs sa{m->Y, m->X, f.Vp, f.V, f.nx, f.ny, f.nz, m->ddirs, m->delta, m->dstride,
+                 m->r, m->iface, m->nvox, m->islot, m->icptF, f.ndir, m->step_ctr, m->spart};
+    if ((e = launch_sweep(sa, f, split, m->fresnel, m->sweep_bpd, m->stream)) != hipSuccess)
+      return e;
+  }
+  if (m->fresnel) {
+    KernelTimer t(m, TR_K_GATHER);
+    GatherArgs ga{m->X, f.Vp, m->tgt_d, m->tgt_v, m->gptr, m->gsrc, m->gw, m->icptF, m->ntgt};
+    if ((e = launch_gather(ga, m->stream)) != hipSuccess) return e;
+  }
+  KernelTimer t(m, TR_K_REDUCE);
+  ReduceArgs ra{m->cpart, m->cnwg, m->spart, m->snwg, m->Y, f.Vp, m->det_pairs, m->det_first,
+                m->det_vox_dev, m->ndet, m->ddirs, m->r, split ? 1 : 0, m->step_ctr, m->budget,
+                m->det_steps, m->cap, m->flag};
+  return launch_reduce(ra, m->stream);
+}
+
+// Detector (direction) pairs: accepted directions whose ray leaves the box
+// through the detector's face from the detector's voxel.
+tr_status upload_detector_pairs(tr_medium* m, const std::vector<std::vector<int>>& acc) {
+  std::vector<int> pairs, first(1, 0);
+  const int nx = m->f.nx, ny = m->f.ny;
+  for (int k = 0; k < m->ndet; ++k) {
+    const int v = m->det_vox[k];
+    const int x = v % nx, y = (v / nx) % ny, z = v / (nx * ny);
+    for (int d : acc[k]) {
+      int face;
+      if (m->lat.downwind(d, x, y, z, &face) < 0 && face == m->det_face[k]) {
+        pairs.push_back(k);
+        pairs.push_back(d);
+      }
+    }
+    first.push_back(int(pairs.size() / 2));
+  }
+  int* dp = m->alloc<int>(std::max<size_t>(pairs.size(), 2));
+  int* df = m->alloc<int>(first.size());
+  int* dv = m->alloc<int>(std::max(m->ndet, 1));
+  if (!dp || !df || !dv) return fail(TR_ENOMEM, "device allocation failed");
+  hipError_t e = hipMemcpy(dp, pairs.data(), pairs.size() * sizeof(int), hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemcpy(df, first.data(), first.size() * sizeof(int), hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemcpy(dv, m->det_vox.data(), m->ndet * sizeof(int), hipMemcpyHostToDevice);
+  if (e != hipSuccess) return device_fail(m, e, "detector upload");
+  m->det_pairs = dp;
+  m->det_first = df;
+  m->det_vox_dev = dv;
+  return TR_OK;
+}
+
+tr_status check_medium(tr_medium* m) {
+  if (!m) return fail(TR_EINVAL, "null medium");
+  if (m->poisoned) return fail(TR_ESTATE, "medium is poisoned by an earlier device error");
+  return TR_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* tr_last_error(void) { return g_err.c_str(); }
+
+size_t tr_bytes_required(const tr_grid_desc* desc, int ndet, int max_steps) {
+  std::string err;
+  if (!valid_desc(desc, err) || ndet < 0 || max_steps < 0) return 0;
+  Field f = field_of(desc);
+  size_t b = fixed_bytes(f, desc->precision, 0);
+  long long cap = std::max(1024, max_steps);
+  b += size_t(cap) * (9 + std::max(ndet, 1) + 1) * sizeof(double);
+  b += size_t(f.ndir) * 8 * sizeof(int) + 4096;
+  return b;
+}
+
+tr_status tr_create_medium(const tr_grid_desc* desc, const float* mua, const float* mus,
+                           const float* n, int arrays_on_device, void* hip_stream,
+                           tr_medium** out) {
+  if (!out) return fail(TR_EINVAL, "null output pointer");
+  *out = nullptr;
+  std::string err;
+  if (!valid_desc(desc, err)) return fail(TR_EINVAL, err);
+  if (!mua || !mus || !n) return fail(TR_EINVAL, "null coefficient array");
+  tr_medium* m = new (std::nothrow) tr_medium();
+  if (!m) return fail(TR_ENOMEM, "host allocation failed");
+  m->desc = *desc;
+  m->stream = static_cast<hipStream_t>(hip_stream);
+  m->f = field_of(desc);
+  const Field& f = m->f;
+
+  std::vector<float> hmua, hmus;
+  const float *pa = mua, *ps = mus, *pn = n;
+  if (arrays_on_device) {
+    hmua.resize(f.V);
+    hmus.resize(f.V);
+    m->nhost.resize(f.V);
+    hipError_t e = hipMemcpy(hmua.data(), mua, f.V * 4, hipMemcpyDeviceToHost);
+    if (e == hipSuccess) e = hipMemcpy(hmus.data(), mus, f.V * 4, hipMemcpyDeviceToHost);
+    if (e == hipSuccess) e = hipMemcpy(m->nhost.data(), n, f.V * 4, hipMemcpyDeviceToHost);
+    if (e != hipSuccess) {
+      delete m;
+      return fail(TR_EINVAL, std::string("reading device arrays: ") + hipGetErrorString(e));
+    }
+    pa = hmua.data();
+    ps = hmus.data();
+  } else {
+    m->nhost.assign(n, n + f.V);
+  }
+  pn = m->nhost.data();
+
+  if (!build_coefficients(f.V, pa, ps, pn, desc->dx_mm, desc->dt_ps, desc->coef, m->co, err)) {
+    delete m;
+    return fail(TR_EINVAL, err);
+  }
+  m->dt = m->co.dt;
+  m->dirs = healpix_ring(desc->nside);
+  m->lat = build_lattice(m->dirs, f.nx, f.ny, f.nz);
+  int mode = desc->advance;
+  if (mode == TR_ADVANCE_AUTO) mode = m->co.uniform_n ? TR_ADVANCE_PHASE : TR_ADVANCE_SPLIT;
+  if (mode == TR_ADVANCE_PHASE && !m->co.uniform_n) {
+    delete m;
+    return fail(TR_EINVAL, "phase advance needs a uniform refractive index");
+  }
+  m->mode = mode;
+  double maxspeed = 0, maxr = 0;
+  for (double s : m->lat.speed) maxspeed = std::max(maxspeed, s);
+  for (double r : m->co.r) maxr = std::max(maxr, r);
+  if (maxspeed * m->co.ell_ref / desc->dx_mm * maxr > 1.0 + 1e-12) {
+    delete m;
+    return fail(TR_EINVAL, "time step moves light more than one plane per step");
+  }
+  std::vector<double> P64;
+  if (!phase_matrix(m->dirs, desc->g, desc->hg_norm, P64)) {
+    delete m;
+    return fail(TR_EINVAL, "phase matrix scaling did not converge");
+  }
+  if (mode == TR_ADVANCE_SPLIT && !m->co.uniform_n) {
+    m->icpt = interceptions(m->lat, m->dirs, pn);
+    m->fresnel = !m->icpt.empty();
+  }
+
+  // ---- device buffers
+  const size_t NV = size_t(f.NP) * f.Vp;
+  m->X = m->alloc<float>(NV);
+  m->Y = m->alloc<float>(NV);
+  m->P = m->alloc<float>(size_t(f.NP) * f.NP);
+  m->a = m->alloc<float>(f.Vp);
+  m->b = m->alloc<float>(f.Vp);
+  m->r = m->alloc<float>(f.Vp);
+  m->ddirs = m->alloc<DevDir>(f.ndir);
+  m->dstride = m->lat.maxext + 2;
+  m->delta = m->alloc<int8_t>(size_t(f.ndir) * 2 * m->dstride);
+  m->step_ctr = m->alloc<int>(1);
+  m->flag = m->alloc<int>(1);
+  m->cnwg = collide_nwg(f);
+  m->sweep_bpd = sweep_blocks_per_dir(f);
+  m->snwg = m->sweep_bpd * f.ndir;
+  m->cpart = m->alloc<double>(2 * size_t(m->cnwg));
+  m->spart = m->alloc<double>(7 * size_t(m->snwg));
+  if (desc->precision == 1) {
+    m->Phi = m->alloc<uint16_t>(size_t(f.NP) * f.NP);
+    m->Plo = m->alloc<uint16_t>(size_t(f.NP) * f.NP);
+  }
+  if (!m->X || !m->Y || !m->P || !m->a || !m->b || !m->r || !m->ddirs || !m->delta ||
+      !m->step_ctr || !m->flag || !m->cpart || !m->spart ||
+      (desc->precision == 1 && (!m->Phi || !m->Plo))) {
+    delete m;
+    return fail(TR_ENOMEM, "device allocation failed");
+  }
+
+  // host images
+  std::vector<float> P32(size_t(f.NP) * f.NP, 0.0f);
+  for (int i = 0; i < f.ndir; ++i)
+    for (int j = 0; j < f.ndir; ++j)
+      P32[size_t(i) * f.NP + j] =
+          float(0.5 * (P64[size_t(i) * f.ndir + j] + P64[size_t(j) * f.ndir + i]));
+  std::vector<float> av(f.Vp, 0.0f), bv(f.Vp, 0.0f), rv(f.Vp, 0.0f);
+  for (int v = 0; v < f.V; ++v) {
+    av[v] = float(m->co.a[v]);
+    bv[v] = float(m->co.b[v]);
+    rv[v] = float(m->co.r[v]);
+  }
+  std::vector<DevDir> dd(f.ndir);
+  std::vector<int8_t> dl(size_t(f.ndir) * 2 * m->dstride, 0);
+  const double nu_scale = m->co.ell_ref / desc->dx_mm;
+  for (int d = 0; d < f.ndir; ++d) {
+    dd[d].axis = m->lat.axis[d];
+    dd[d].sign = m->lat.sign[d];
+    dd[d].bax = m->lat.bax[d];
+    dd[d].cax = m->lat.cax[d];
+    dd[d].nu64 = m->lat.speed[d] * nu_scale;
+    dd[d].nu = float(dd[d].nu64);
+    dd[d].pad = 0;
+    for (int q = 0; q < 2; ++q)
+      for (int k = 1; k <= m->lat.maxext; ++k)
+        dl[(size_t(d) * 2 + q) * m->dstride + k] =
+            int8_t(m->lat.off(d, q, k) - m->lat.off(d, q, k - 1));
+  }
+  hipError_t e = hipMemset(m->X, 0, NV * 4);
+  if (e == hipSuccess) e = hipMemset(m->Y, 0, NV * 4);
+  if (e == hipSuccess) e = hipMemcpy(m->P, P32.data(), P32.size() * 4, hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemcpy(m->a, av.data(), av.size() * 4, hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemcpy(m->b, bv.data(), bv.size() * 4, hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemcpy(m->r, rv.data(), rv.size() * 4, hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemcpy(m->ddirs, dd.data(), dd.size() * sizeof(DevDir), hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemcpy(m->delta, dl.data(), dl.size(), hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemset(m->step_ctr, 0, sizeof(int));
+  if (e == hipSuccess) e = hipMemset(m->flag, 0, sizeof(int));
+  if (e == hipSuccess && desc->precision == 1) {
+    std::vector<uint16_t> hi(P32.size()), lo(P32.size());
+    for (size_t i = 0; i < P32.size(); ++i) {
+      hi[i] = f32_to_bf16_bits(P32[i]);
+      lo[i] = f32_to_bf16_bits(P32[i] - bf16_bits_to_f32(hi[i]));
+    }
+    e = hipMemcpy(m->Phi, hi.data(), hi.size() * 2, hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(m->Plo, lo.data(), lo.size() * 2, hipMemcpyHostToDevice);
+  }
+  if (e != hipSuccess) {
+    delete m;
+    return fail(TR_EDEVICE, std::string("upload: ") + hipGetErrorString(e));
+  }
+
+  // ---- Fresnel interface tables
+  if (m->fresnel) {
+    std::vector<uint8_t> iface(f.V, 0);
+    std::vector<int> islot(f.V, -1);
+    for (const Interception& ic : m->icpt) iface[ic.v] = 1;
+    int ni = 0;
+    for (int v = 0; v < f.V; ++v)
+      if (iface[v]) islot[v] = ni++;
+    m->niface = ni;
+    // targets: (d_refl, v) gets R F, (d_refr, w) gets (1 - R) F
+    std::map<std::pair<int, long long>, std::vector<std::pair<int, float>>> tg;
+    for (const Interception& ic : m->icpt) {
+      const int slot = islot[ic.v] * f.ndir + ic.d;
+      tg[{ic.d_refl, ic.v}].push_back({slot, float(ic.R)});
+      if (ic.d_refr >= 0) tg[{ic.d_refr, ic.w}].push_back({slot, float(1.0 - ic.R)});
+    }
+    std::vector<int> td, tv, ptr(1, 0), src;
+    std::vector<float> w;
+    for (auto& kv : tg) {
+      td.push_back(kv.first.first);
+      tv.push_back(int(kv.first.second));
+      for (auto& sw : kv.second) {
+        src.push_back(sw.first);
+        w.push_back(sw.second);
+      }
+      ptr.push_back(int(src.size()));
+    }
+    m->ntgt = int(td.size());
+    m->iface = m->alloc<uint8_t>(f.Vp);
+    m->nvox = m->alloc<float>(f.Vp);
+    m->islot = m->alloc<int>(f.Vp);
+    m->icptF = m->alloc<float>(size_t(ni) * f.ndir);
+    m->tgt_d = m->alloc<int>(td.size());
+    m->tgt_v = m->alloc<int>(tv.size());
+    m->gptr = m->alloc<int>(ptr.size());
+    m->gsrc = m->alloc<int>(src.size());
+    m->gw = m->alloc<float>(w.size());
+    if (!m->iface || !m->nvox || !m->islot || !m->icptF || !m->tgt_d || !m->tgt_v || !m->gptr ||
+        !m->gsrc || !m->gw) {
+      delete m;
+      return fail(TR_ENOMEM, "device allocation failed (interfaces)");
+    }
+    iface.resize(f.Vp, 0);
+    islot.resize(f.Vp, -1);
+    std::vector<float> nv(f.Vp, 1.0f);
+    std::copy(pn, pn + f.V, nv.begin());
+    e = hipMemcpy(m->iface, iface.data(), f.Vp, hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(m->nvox, nv.data(), f.Vp * 4, hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(m->islot, islot.data(), f.Vp * 4, hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemset(m->icptF, 0, size_t(ni) * f.ndir * 4);
+    if (e == hipSuccess) e = hipMemcpy(m->tgt_d, td.data(), td.size() * 4, hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(m->tgt_v, tv.data(), tv.size() * 4, hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(m->gptr, ptr.data(), ptr.size() * 4, hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(m->gsrc, src.data(), src.size() * 4, hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(m->gw, w.data(), w.size() * 4, hipMemcpyHostToDevice);
+    if (e != hipSuccess) {
+      delete m;
+      return fail(TR_EDEVICE, std::string("upload: ") + hipGetErrorString(e));
+    }
+  }
+  tr_status st = ensure_capacity(m, 1024);
+  if (st != TR_OK) {
+    delete m;
+    return st;
+  }
+  *out = m;
+  return TR_OK;
+}
+
+tr_status tr_destroy_medium(tr_medium* m) {
+  if (!m) return TR_OK;
+  if (m->stream) (void)hipStreamSynchronize(m->stream);
+  else (void)hipDeviceSynchronize();
+  delete m;
+  return TR_OK;
+}
+
+tr_status tr_set_source(tr_medium* m, int ix, int iy, int w, double cone_deg, double t0_ps,
+                        double fwhm_ps, double total_photons) {
+  tr_status st = check_medium(m);
+  if (st != TR_OK) return st;
+  if (w != 1 && w != 2) return fail(TR_EINVAL, "w must be 1 or 2");
+  if (ix < 0 || iy < 0 || ix + w > m->f.nx || iy + w > m->f.ny)
+    return fail(TR_EINVAL, "source voxels outside the top face");
+  if (!(fwhm_ps > 0) || !std::isfinite(t0_ps) || !std::isfinite(total_photons) ||
+      !std::isfinite(cone_deg))
+    return fail(TR_EINVAL, "bad pulse parameters");
+  std::vector<int> dirs = cone_set(m->dirs, Vec3{0, 0, 1}, cone_deg);
+  std::vector<int> pairs;
+  for (int d : dirs)
+    for (int dy = 0; dy < w; ++dy)
+      for (int dx = 0; dx < w; ++dx) {
+        pairs.push_back(d);
+        pairs.push_back((iy + dy) * m->f.nx + ix + dx);
+      }
+  hipError_t e = hipStreamSynchronize(m->stream);
+  if (e != hipSuccess) return device_fail(m, e, "synchronize");
+  int* dp = m->alloc<int>(pairs.size());
+  if (!dp) return fail(TR_ENOMEM, "device allocation failed");
+  e = hipMemcpy(dp, pairs.data(), pairs.size() * 4, hipMemcpyHostToDevice);
+  if (e != hipSuccess) return device_fail(m, e, "source upload");
+  m->release(m->src_pairs);
+  m->src_pairs = dp;
+  m->npairs = int(pairs.size() / 2);
+  m->have_source = true;
+  m->src_ix = ix;
+  m->src_iy = iy;
+  m->src_w = w;
+  m->src_cone = cone_deg;
+  m->src_t0 = t0_ps;
+  m->src_fwhm = fwhm_ps;
+  m->src_total = total_photons;
+  std::vector<double> qh(m->cap);
+  for (int s = 0; s < m->cap; ++s) qh[s] = pulse_weight(s, m->dt, t0_ps, fwhm_ps, total_photons);
+  e = hipMemcpy(m->qdev, qh.data(), qh.size() * 8, hipMemcpyHostToDevice);
+  if (e != hipSuccess) return device_fail(m, e, "pulse upload");
+  m->drop_graph();
+  return TR_OK;
+}
+
+tr_status tr_set_detectors(tr_medium* m, int ndet, const int* face, const int* i, const int* j,
+                           double cone_deg, double bin_ps, int nbins) {
+  tr_status st = check_medium(m);
+  if (st != TR_OK) return st;
+  if (ndet < 1 || ndet > kMaxDet) return fail(TR_EINVAL, "ndet must be in 1..64");
+  if (!face || !i || !j) return fail(TR_EINVAL, "null detector arrays");
+  if (!(bin_ps > 0) || nbins < 1) return fail(TR_EINVAL, "bad bins");
+  const int ext[3] = {m->f.nx, m->f.ny, m->f.nz};
+  std::vector<int> fv, vv;
+  std::vector<std::vector<int>> acc;
+  static const Vec3 normals[6] = {{-1, 0, 0}, {1, 0, 0}, {0, -1, 0}, {0, 1, 0}, {0, 0, -1}, {0, 0, 1}};
+  for (int k = 0; k < ndet; ++k) {
+    if (face[k] < 0 || face[k] > 5) return fail(TR_EINVAL, "bad detector face");
+    const int ax = face[k] / 2, side = face[k] % 2;
+    const int o1 = ax == 0 ? 1 : 0, o2 = ax == 2 ? 1 : 2;
+    if (i[k] < 0 || i[k] >= ext[o1] || j[k] < 0 || j[k] >= ext[o2])
+      return fail(TR_EINVAL, "detector indices outside the face");
+    int p[3];
+    p[ax] = side ? ext[ax] - 1 : 0;
+    p[o1] = i[k];
+    p[o2] = j[k];
+    fv.push_back(face[k]);
+    vv.push_back((p[2] * ext[1] + p[1]) * ext[0] + p[0]);
+    if (cone_deg <= 0) {
+      std::vector<int> all(m->f.ndir);
+      for (int d = 0; d < m->f.ndir; ++d) all[d] = d;
+      acc.push_back(all);
+    } else {
+      acc.push_back(cone_set(m->dirs, normals[face[k]], cone_deg));
+    }
+  }
+  hipError_t e = hipStreamSynchronize(m->stream);
+  if (e != hipSuccess) return device_fail(m, e, "synchronize");
+  // detector storage depends on ndet: rebuild the capacity-dependent buffers
+  int* old_pairs = m->det_pairs;
+  int* old_first = m->det_first;
+  int* old_vox = m->det_vox_dev;
+  m->ndet = ndet;
+  m->det_face = fv;
+  m->det_vox = vv;
+  m->bin_ps = bin_ps;
+  m->nbins = nbins;
+  st = upload_detector_pairs(m, acc);
+  if (st != TR_OK) return st;
+  m->release(old_pairs);
+  m->release(old_first);
+  m->release(old_vox);
+  m->release(m->det_steps);
+  m->det_steps = m->alloc<double>(size_t(ndet) * m->cap);
+  if (!m->det_steps) return fail(TR_ENOMEM, "device allocation failed");
+  e = hipMemset(m->det_steps, 0, size_t(ndet) * m->cap * 8);
+  if (e != hipSuccess) return device_fail(m, e, "detector reset");
+  m->drop_graph();
+  return TR_OK;
+}
+
+tr_status tr_reset(tr_medium* m) {
+  tr_status st = check_medium(m);
+  if (st != TR_OK) return st;
+  const Field& f = m->f;
+  hipError_t e = hipMemsetAsync(m->X, 0, size_t(f.NP) * f.Vp * 4, m->stream);
+  if (e == hipSuccess) e = hipMemsetAsync(m->Y, 0, size_t(f.NP) * f.Vp * 4, m->stream);
+  if (e == hipSuccess) e = hipMemsetAsync(m->budget, 0, size_t(m->cap) * 9 * 8, m->stream);
+  if (e == hipSuccess && m->ndet > 0)
+    e = hipMemsetAsync(m->det_steps, 0, size_t(m->ndet) * m->cap * 8, m->stream);
+  if (e == hipSuccess) e = hipMemsetAsync(m->step_ctr, 0, 4, m->stream);
+  if (e == hipSuccess) e = hipMemsetAsync(m->flag, 0, 4, m->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(m->stream);
+  if (e != hipSuccess) return device_fail(m, e, "reset");
+  m->steps_done = 0;
+  return TR_OK;
+}
+
+tr_status tr_step(tr_medium* m, int nsteps) {
+  tr_status st = check_medium(m);
+  if (st != TR_OK) return st;
+  if (nsteps < 0) return fail(TR_EINVAL, "nsteps < 0");
+  if (m->ndet == 0) return fail(TR_ESTATE, "detectors not set");
+  st = ensure_capacity(m, m->steps_done + nsteps);
+  if (st != TR_OK) return st;
+  int left = nsteps;
+  hipError_t e = hipSuccess;
+  // Replay a captured graph of kGraphSteps steps where possible (the kernels
+  // take the step index from the device counter, so replays need no new
+  // arguments); the null stream cannot be captured.
+  if (m->stream && left >= kGraphSteps && !m->profiling) {
+    if (!m->graph) {
+      hipGraph_t g;
+      e = hipStreamBeginCapture(m->stream, hipStreamCaptureModeThreadLocal);
+      for (int s = 0; s < kGraphSteps && e == hipSuccess; ++s) e = queue_step(m);
+      hipError_t e2 = hipStreamEndCapture(m->stream, &g);
+      if (e == hipSuccess) e = e2;
+      if (e == hipSuccess) {
+        e = hipGraphInstantiate(&m->graph, g, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(g);
+      }
+      if (e != hipSuccess) return device_fail(m, e, "graph capture");
+    }
+    while (left >= kGraphSteps) {
+      e = hipGraphLaunch(m->graph, m->stream);
+      if (e != hipSuccess) return device_fail(m, e, "graph launch");
+      left -= kGraphSteps;
+    }
+  }
+  for (; left > 0; --left) {
+    e = queue_step(m);
+    if (e != hipSuccess) return device_fail(m, e, "kernel launch");
+  }
+  m->steps_done += nsteps;
+  return TR_OK;
+}
+
+tr_status tr_synchronize(tr_medium* m) {
+  tr_status st = check_medium(m);
+  if (st != TR_OK) return st;
+  hipError_t e = hipStreamSynchronize(m->stream);
+  if (e != hipSuccess) return device_fail(m, e, "synchronize");
+  int flag = 0;
+  e = hipMemcpy(&flag, m->flag, 4, hipMemcpyDeviceToHost);
+  if (e != hipSuccess) return device_fail(m, e, "flag read");
+  if (flag & 2) {
+    m->poisoned = true;
+    return fail(TR_EDEVICE, "step beyond tally capacity");
+  }
+  if (flag & 1) {
+    m->poisoned = true;
+    return fail(TR_ENUMERIC, "non-finite photon budget");
+  }
+  return TR_OK;
+}
+
+tr_status tr_solve(tr_medium* m, int nsteps) {
+  tr_status st = tr_step(m, nsteps);
+  if (st != TR_OK) return st;
+  return tr_synchronize(m);
+}
+
+tr_status tr_read_detector_steps(tr_medium* m, double* out, size_t n_out) {
+  tr_status st = tr_synchronize(m);
+  if (st != TR_OK) return st;
+  const size_t need = size_t(m->ndet) * m->steps_done;
+  if (!out || n_out < need) return fail(TR_EINVAL, "output too small");
+  for (int k = 0; k < m->ndet; ++k) {
+    hipError_t e = hipMemcpy(out + size_t(k) * m->steps_done, m->det_steps + size_t(k) * m->cap,
+                             m->steps_done * 8, hipMemcpyDeviceToHost);
+    if (e != hipSuccess) return device_fail(m, e, "detector read");
+  }
+  return TR_OK;
+}
+
+tr_status tr_read_detectors(tr_medium* m, double* out, size_t n_out) {
+  tr_status st = check_medium(m);
+  if (st != TR_OK) return st;
+  const size_t need = size_t(m->ndet) * m->nbins;
+  if (!out || n_out < need) return fail(TR_EINVAL, "output too small");
+  std::vector<double> raw(size_t(m->ndet) * m->steps_done);
+  st = tr_read_detector_steps(m, raw.data(), raw.size());
+  if (st != TR_OK) return st;
+  std::fill(out, out + need, 0.0);
+  const double dt = m->dt, bw = m->bin_ps;
+  for (long long s = 0; s < m->steps_done; ++s) {
+    const double t0 = s * dt, t1 = (s + 1) * dt;
+    const long long j0 = std::max(0LL, (long long)std::floor(t0 / bw));
+    const long long j1 = std::min<long long>(m->nbins, (long long)std::ceil(t1 / bw));
+    for (long long j = j0; j < j1; ++j) {
+      const double lo = std::max(t0, j * bw), hi = std::min(t1, (j + 1) * bw);
+      if (hi <= lo) continue;
+      const double wgt = (hi - lo) / dt;
+      for (int k = 0; k < m->ndet; ++k)
+        out[size_t(k) * m->nbins + j] += raw[size_t(k) * m->steps_done + s] * wgt;
+    }
+  }
+  return TR_OK;
+}
+
+tr_status tr_read_budget(tr_medium* m, double* out, size_t n_out) {
+  tr_status st = tr_synchronize(m);
+  if (st != TR_OK) return st;
+  const size_t need = size_t(9) * m->steps_done;
+  if (!out || n_out < need) return fail(TR_EINVAL, "output too small");
+  hipError_t e = hipMemcpy(out, m->budget, need * 8, hipMemcpyDeviceToHost);
+  if (e != hipSuccess) return device_fail(m, e, "budget read");
+  return TR_OK;
+}
+
+tr_status tr_read_energy(tr_medium* m, float* out, int on_device) {
+  tr_status st = check_medium(m);
+  if (st != TR_OK) return st;
+  if (!out) return fail(TR_EINVAL, "null output");
+  float* E = on_device ? out : m->alloc<float>(m->f.V);
+  if (!E) return fail(TR_ENOMEM, "device allocation failed");
+  hipError_t e = launch_energy(m->X, m->f.Vp, m->f.ndir, m->f.V, E, m->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(m->stream);
+  if (e == hipSuccess && !on_device) e = hipMemcpy(out, E, m->f.V * 4, hipMemcpyDeviceToHost);
+  if (!on_device) m->release(E);
+  if (e != hipSuccess) return device_fail(m, e, "energy");
+  return TR_OK;
+}
+
+tr_status tr_get_state(tr_medium* m, float* out, int on_device) {
+  tr_status st = tr_synchronize(m);
+  if (st != TR_OK) return st;
+  if (!out) return fail(TR_EINVAL, "null output");
+  hipError_t e = hipMemcpy2D(out, m->f.V * 4, m->X, m->f.Vp * 4, m->f.V * 4, m->f.ndir,
+                             on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost);
+  if (e != hipSuccess) return device_fail(m, e, "state read");
+  return TR_OK;
+}
+
+tr_status tr_set_state(tr_medium* m, const float* in, int on_device) {
+  tr_status st = tr_synchronize(m);
+  if (st != TR_OK) return st;
+  if (!in) return fail(TR_EINVAL, "null input");
+  hipError_t e = hipMemcpy2D(m->X, m->f.Vp * 4, in, m->f.V * 4, m->f.V * 4, m->f.ndir,
+                             on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice);
+  if (e != hipSuccess) return device_fail(m, e, "state write");
+  return TR_OK;
+}
+
+tr_status tr_profile_begin(tr_medium* m, int max_steps) {
+  tr_status st = check_medium(m);
+  if (st != TR_OK) return st;
+  if (max_steps < 1) return fail(TR_EINVAL, "max_steps must be >= 1");
+  m->free_events();
+  const size_t pairs = size_t(max_steps) * TR_K_COUNT;
+  m->prof_ev.resize(2 * pairs, nullptr);
+  for (size_t i = 0; i < m->prof_ev.size(); ++i) {
+    hipError_t e = hipEventCreate(&m->prof_ev[i]);
+    if (e != hipSuccess) {
+      m->prof_ev.resize(i);
+      m->free_events();
+      return fail(TR_ENOMEM, "event creation failed");
+    }
+  }
+  m->prof_kind.assign(pairs, -1);
+  m->prof_used = 0;
+  m->profiling = true;
+  return TR_OK;
+}
+
+tr_status tr_profile_end(tr_medium* m, double* kernel_ms, int* launches) {
+  tr_status st = check_medium(m);
+  if (st != TR_OK) return st;
+  if (!m->profiling) return fail(TR_ESTATE, "timing was not started");
+  if (!kernel_ms || !launches) return fail(TR_EINVAL, "null output");
+  m->profiling = false;
+  hipError_t e = hipStreamSynchronize(m->stream);
+  if (e != hipSuccess) return device_fail(m, e, "synchronize");
+  for (int k = 0; k < TR_K_COUNT; ++k) {
+    kernel_ms[k] = 0;
+    launches[k] = 0;
+  }
+  for (int i = 0; i < m->prof_used; ++i) {
+    float ms = 0;
+    e = hipEventElapsedTime(&ms, m->prof_ev[2 * i], m->prof_ev[2 * i + 1]);
+    if (e != hipSuccess) return device_fail(m, e, "event timing");
+    kernel_ms[m->prof_kind[i]] += ms;
+    launches[m->prof_kind[i]] += 1;
+  }
+  m->free_events();
+  return TR_OK;
+}
+
+tr_status tr_get_info(tr_medium* m, tr_info* out) {
+  if (!m || !out) return fail(TR_EINVAL, "null argument");
+  out->ndir = m->f.ndir;
+  out->nvox = m->f.V;
+  out->mode = m->mode;
+  out->ninterceptions = int(m->icpt.size());
+  out->dt_ps = m->dt;
+  out->steps_done = m->steps_done;
+  out->device_bytes = m->bytes;
+  return TR_OK;
+}
+
+// ---- host set-up tables ----------------------------------------------------
+
+tr_status tr_host_directions(int nside, double* out) {
+  if (nside < 1 || nside > 64 || !out) return fail(TR_EINVAL, "bad nside or output");
+  std::vector<Vec3> d = healpix_ring(nside);
+  for (size_t i = 0; i < d.size(); ++i) {
+    out[3 * i] = d[i].x;
+    out[3 * i + 1] = d[i].y;
+    out[3 * i + 2] = d[i].z;
+  }
+  return TR_OK;
+}
+
+tr_status tr_host_phase_matrix(int nside, double g, int hg_norm, double* out) {
+  if (nside < 1 || nside > 16 || !out || !(g > -1 && g < 1)) return fail(TR_EINVAL, "bad arguments");
+  std::vector<double> P;
+  if (!phase_matrix(healpix_ring(nside), g, hg_norm, P)) return fail(TR_EINVAL, "no convergence");
+  std::copy(P.begin(), P.end(), out);
+  return TR_OK;
+}
+
+tr_status tr_host_lattice(int nside, int nx, int ny, int nz, int* axis, int* sign, int* offset) {
+  if (nside < 1 || nside > 16 || nx < 1 || ny < 1 || nz < 1 || !axis || !sign || !offset)
+    return fail(TR_EINVAL, "bad arguments");
+  Lattice L = build_lattice(healpix_ring(nside), nx, ny, nz);
+  std::copy(L.axis.begin(), L.axis.end(), axis);
+  std::copy(L.sign.begin(), L.sign.end(), sign);
+  std::copy(L.offset.begin(), L.offset.end(), offset);
+  return TR_OK;
+}
+
+tr_status tr_host_coefficients(const tr_grid_desc* desc, const float* mua, const float* mus,
+                               const float* n, double* a, double* b, double* r, double* dt_ps) {
+  std::string err;
+  if (!valid_desc(desc, err)) return fail(TR_EINVAL, err);
+  if (!mua || !mus || !n || !a || !b || !r || !dt_ps) return fail(TR_EINVAL, "null argument");
+  Coefficients c;
+  const int V = desc->nx * desc->ny * desc->nz;
+  if (!build_coefficients(V, mua, mus, n, desc->dx_mm, desc->dt_ps, desc->coef, c, err))
+    return fail(TR_EINVAL, err);
+  std::copy(c.a.begin(), c.a.end(), a);
+  std::copy(c.b.begin(), c.b.end(), b);
+  std::copy(c.r.begin(), c.r.end(), r);
+  *dt_ps = c.dt;
+  return TR_OK;
+}
+
+tr_status tr_host_cone_set(int nside, double ax, double ay, double az, double cone_deg, int* out,
+                           int cap, int* count) {
+  if (nside < 1 || nside > 16 || !out || !count) return fail(TR_EINVAL, "bad arguments");
+  std::vector<int> s = cone_set(healpix_ring(nside), Vec3{ax, ay, az}, cone_deg);
+  *count = int(s.size());
+  if (int(s.size()) > cap) return fail(TR_EINVAL, "output too small");
+  std::copy(s.begin(), s.end(), out);
+  return TR_OK;
+}
+
+tr_status tr_host_pulse(double dt_ps, double t0_ps, double fwhm_ps, double total, int m0, int count,
+                        double* out) {
+  if (!(dt_ps > 0) || !(fwhm_ps > 0) || count < 0 || m0 < 0 || !out)
+    return fail(TR_EINVAL, "bad arguments");
+  for (int i = 0; i < count; ++i) out[i] = pulse_weight(m0 + i, dt_ps, t0_ps, fwhm_ps, total);
+  return TR_OK;
+}
+
+tr_status tr_host_interceptions(const tr_grid_desc* desc, const float* n, int* d, int* v, int* w,
+                                double* R, int* d_refl, int* d_refr, int cap, int* count) {
+  std::string err;
+  if (!valid_desc(desc, err)) return fail(TR_EINVAL, err);
+  if (!n || !count) return fail(TR_EINVAL, "null argument");
+  std::vector<Vec3> dirs = healpix_ring(desc->nside);
+  Lattice L = build_lattice(dirs, desc->nx, desc->ny, desc->nz);
+  std::vector<Interception> ic = interceptions(L, dirs, n);
+  *count = int(ic.size());
+  if (int(ic.size()) > cap) return TR_OK;
+  if (!d || !v || !w || !R || !d_refl || !d_refr) return fail(TR_EINVAL, "null argument");
+  for (size_t i = 0; i < ic.size(); ++i) {
+    d[i] = ic[i].d;
+    v[i] = int(ic[i].v);
+    w[i] = int(ic[i].w);
+    R[i] = ic[i].R;
+    d_refl[i] = ic[i].d_refl;
+    d_refr[i] = ic[i].d_refr;
+  }
+  return TR_OK;
+}
+
+}  // extern "C"

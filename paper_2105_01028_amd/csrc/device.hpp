@@ -1,0 +1,115 @@
+// Device-side argument blocks and launchers of the TRINITY step kernels.
+// Shared by kernels.hip (definitions) and capi.cpp (callers).
+#pragma once
+
+#include <hip/hip_runtime_api.h>
+
+#include <cstdint>
+
+namespace trinity {
+
+// Per-direction lattice data on the device.
+struct DevDir {
+  int axis, sign, bax, cax;   // dominant axis a, sign of Omega_a, transverse axes b < c
+  float nu;                   // planes advanced per step at the reference path (split mode)
+  float pad;
+  double nu64;                // same, FP64, for the phase-mode move rule
+};
+
+// The photon field lives in N[d][v] buffers of NP rows (directions, padded to a
+// multiple of 32 with zero rows) by Vp columns (voxels, padded to a multiple of
+// 256 with zero columns).
+struct Field {
+  int ndir, NP;
+  int V, nx, ny, nz;
+  long long Vp;
+};
+
+struct InjectArgs {
+  float* X;
+  long long Vp;
+  const int* pairs;        // [npairs][2] (direction, voxel)
+  int npairs;
+  const double* q;         // pulse weight per step
+  int cap;                 // length of q and of the budget
+  const int* step_ctr;
+  double* budget;          // [cap][9]
+};
+
+struct CollideArgs {
+  const float* X;          // input field [NP][Vp]
+  float* Y;                // output field [NP][Vp]
+  const float* P;          // [NP][NP] fp32 phase matrix (symmetric, zero padded)
+  const uint16_t* Phi;     // [NP][NP] bf16 high part (bf16-split mode)
+  const uint16_t* Plo;     // [NP][NP] bf16 low part
+  const float* a;          // [Vp]
+  const float* b;          // [Vp]
+  long long Vp;
+  int NP;
+  double* part;            // [2][nwg]: absorbed, total
+};
+
+struct SweepArgs {
+  const float* Y;          // post-collision field
+  float* X;                // post-transport field
+  long long Vp;
+  int V, nx, ny, nz;
+  const DevDir* dirs;
+  const int8_t* delta;     // [d][2][dstride]: plane-to-plane transverse shift at plane k
+  int dstride;
+  const float* r;          // split mode: per-voxel path ratio
+  const uint8_t* iface;    // Fresnel: 1 for voxels next to a different index
+  const float* nvox;       // Fresnel: refractive index per voxel
+  const int* islot;        // Fresnel: compact interface-voxel index
+  float* icptF;            // Fresnel: intercepted flux [niface][ndir]
+  int ndir;
+  const int* step_ctr;
+  double* part;            // [7][nwg]: escape per face 0..5, in the box
+};
+
+struct GatherArgs {
+  float* X;
+  long long Vp;
+  const int* tgt_d;
+  const int* tgt_v;
+  const int* ptr;          // CSR over targets
+  const int* src;          // slot into icptF
+  const float* w;          // R or 1 - R
+  const float* icptF;
+  int ntgt;
+};
+
+struct ReduceArgs {
+  const double* cpart;
+  int cnwg;
+  const double* spart;
+  int snwg;
+  const float* Y;
+  long long Vp;
+  const int* det_pairs;    // [npairs][2] (detector, direction), grouped by detector
+  const int* det_first;    // [ndet+1] start of each detector's pairs
+  const int* det_vox;      // [ndet]
+  int ndet;
+  const DevDir* dirs;
+  const float* r;
+  int split;
+  int* step_ctr;
+  double* budget;          // [cap][9]
+  double* det_steps;       // [ndet][cap]
+  int cap;
+  int* flag;               // bit 0: non-finite budget, bit 1: step beyond capacity
+};
+
+// Launchers: queue the kernel on `s`.  Return the launch status.
+hipError_t launch_inject(const InjectArgs& a, hipStream_t s);
+hipError_t launch_collide(const CollideArgs& a, const Field& f, int bf16split, int nwg_cols,
+                          hipStream_t s);
+int collide_nwg(const Field& f);
+hipError_t launch_sweep(const SweepArgs& a, const Field& f, int split, int fresnel, int bpd,
+                        hipStream_t s);
+int sweep_blocks_per_dir(const Field& f);
+hipError_t launch_gather(const GatherArgs& a, hipStream_t s);
+hipError_t launch_reduce(const ReduceArgs& a, hipStream_t s);
+hipError_t launch_energy(const float* X, long long Vp, int ndir, int V, float* E, hipStream_t s);
+
+}  // namespace trinity

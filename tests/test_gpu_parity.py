@@ -1,0 +1,182 @@
+"""GPU parity: the HIP path, called through the C-ABI, against the FP64 oracle
+on the same seeded inputs.  Detector curves must agree to a relative L2 of
+1e-4 on bins above 1e-6 of the peak; single steps element by element."""
+import numpy as np
+import pytest
+
+from oracle import solve
+from paper_2105_01028_amd import trinity as T
+from paper_2105_01028_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+def _stream():
+    import torch
+    assert torch.cuda.is_available(), "these tests need the GPU"
+    s = torch.cuda.Stream()
+    return s
+
+
+def rel_l2_above(got, ref, floor=1e-6):
+    """Relative L2 over the bins whose reference exceeds floor * peak."""
+    mask = ref > floor * ref.max()
+    return float(np.linalg.norm(got[mask] - ref[mask]) / np.linalg.norm(ref[mask]))
+
+
+def run_gpu(prob, steps=None, stream=None, state0=None):
+    import torch
+    steps = prob.steps if steps is None else steps
+    s = stream or _stream()
+    with torch.cuda.stream(s):
+        m = T.Medium.from_problem(prob)
+        if state0 is not None:
+            m.set_state(state0)
+        m.solve(steps)
+        out = dict(binned=m.read_detectors(), steps=m.read_detector_steps(),
+                   budget=m.read_budget(), state=m.get_state(), info=m.info())
+        m.close()
+    return out
+
+
+def budget_closure(b):
+    inj = b[:, 0].sum()
+    return abs(inj - b[:, 1].sum() - b[:, 3:].sum() - b[-1, 2]) / inj
+
+
+@pytest.mark.parametrize("advance,seed", [("phase", 1), ("split", 2)])
+def test_single_step_matches_oracle(advance, seed):
+    """One step from a random state: every (direction, voxel) of the field."""
+    p = W.small_problem(nside=2, nx=13, ny=10, nz=9, mua=0.05, mus=3.0, g=0.8, steps=1,
+                        seed=seed, advance=advance, total_photons=0.0)
+    rng = np.random.default_rng(seed)
+    N0 = rng.uniform(0, 1, (48, p.nvox)).astype(np.float32)
+    ref = solve.forward(p, steps=1, state0=N0.astype(np.float64))
+    got = run_gpu(p, steps=1, state0=N0)
+    assert np.abs(got["state"] - ref.state).max() <= 2e-6 * np.abs(ref.state).max()
+    assert np.allclose(got["budget"][0, 3:], ref.escaped[0], rtol=2e-6, atol=1e-9)
+
+
+def test_free_streaming_is_exact():
+    """mu_a = mu_s = 0 in phase mode: transport only moves values, so the GPU
+    field equals the oracle's bit for bit after many steps."""
+    p = W.small_problem(nside=2, nx=11, ny=9, nz=10, mua=0.0, mus=0.0, g=0.5, steps=30,
+                        total_photons=0.0)
+    rng = np.random.default_rng(3)
+    N0 = (rng.uniform(0, 1, (48, p.nvox)) * (rng.uniform(size=p.nvox) < 0.2)).astype(np.float32)
+    ref = solve.forward(p, steps=30, state0=N0.astype(np.float64))
+    got = run_gpu(p, steps=30, state0=N0)
+    assert np.array_equal(got["state"].astype(np.float64), ref.state)
+
+
+def test_uniform_16cube_detectors():
+    """The 16^3 / 48-direction / 200-step uniform problem in full."""
+    p = W.config1()
+    ref = solve.forward(p)
+    got = run_gpu(p)
+    rb = ref.binned(p.bin_ps, p.nbins)
+    for k in range(p.ndet):
+        assert rel_l2_above(got["binned"][k], rb[k]) < 1e-4, k
+    assert rel_l2_above(got["steps"].ravel(), ref.det.ravel()) < 1e-4
+    assert budget_closure(got["budget"]) < 1e-6
+
+
+@pytest.mark.parametrize("advance,coef,nside", [("phase", "paper", 2), ("split", "paper", 2),
+                                                ("phase", "abs_exact", 4)])
+def test_ragged_noisy_medium(advance, coef, nside):
+    """Non-cubic grid whose sizes are not tile multiples, voxel noise."""
+    p = W.small_problem(nside=nside, nx=21, ny=14, nz=11, mua=0.02, mus=3.0, g=0.85,
+                        steps=60, seed=7, advance=advance, coef=coef, det_cone_deg=0.0)
+    ref = solve.forward(p)
+    got = run_gpu(p)
+    assert rel_l2_above(got["steps"].ravel(), ref.det.ravel()) < 1e-4
+    assert np.allclose(got["budget"][:, 1], ref.absorbed, rtol=1e-4, atol=1e-9)
+    assert budget_closure(got["budget"]) < 1e-6
+
+
+def test_refraction_air_cylinder():
+    """Split mode with an air cylinder: Fresnel interception and gather."""
+    p = W.config3(nx=24).copy(nside=2, steps=80, nbins=400)
+    ref = solve.forward(p)
+    got = run_gpu(p)
+    assert got["info"].ninterceptions == len(ref.setup.icpt) > 0
+    assert rel_l2_above(got["steps"].ravel(), ref.det.ravel()) < 1e-4
+    assert budget_closure(got["budget"]) < 1e-6
+    assert np.abs(got["state"] - ref.state).max() <= 1e-5 * np.abs(ref.state).max()
+
+
+def test_bf16split_matches_oracle():
+    p = W.small_problem(nside=4, nx=16, ny=12, nz=10, mua=0.01, mus=5.0, g=0.85, steps=60,
+                        seed=9, det_cone_deg=0.0, precision="bf16split")
+    ref = solve.forward(p)
+    got = run_gpu(p)
+    assert rel_l2_above(got["steps"].ravel(), ref.det.ravel()) < 1e-4
+    assert budget_closure(got["budget"]) < 1e-5
+
+
+def test_graph_replay_equals_single_steps():
+    """Steps replayed from the captured graph give the same bits as steps
+    launched one at a time (all tallies use fixed summation orders)."""
+    import torch
+    p = W.small_problem(nside=2, nx=12, ny=12, nz=12, steps=40, seed=5)
+    s = _stream()
+    with torch.cuda.stream(s):
+        a = T.Medium.from_problem(p)
+        a.solve(40)
+        b = T.Medium.from_problem(p)
+        for _ in range(40):
+            b.step(1)
+        b.synchronize()
+        assert np.array_equal(a.read_detector_steps(), b.read_detector_steps())
+        assert np.array_equal(a.get_state(), b.get_state())
+        a.reset()
+        a.solve(40)
+        assert np.array_equal(a.read_detector_steps(), b.read_detector_steps())
+        a.close()
+        b.close()
+
+
+def test_edge_cases():
+    """nside 1 (12 directions), a one-voxel-thick slab, zero steps."""
+    p = W.small_problem(nside=1, nx=5, ny=3, nz=1, mua=0.01, mus=1.0, g=0.3, steps=15,
+                        det_cone_deg=0.0, dets=([4, 5, 0], [2, 1, 1], [1, 1, 0]))
+    p.src_ix, p.src_iy = 1, 0
+    ref = solve.forward(p)
+    got = run_gpu(p)
+    assert rel_l2_above(got["steps"].ravel(), ref.det.ravel()) < 1e-4
+    z = run_gpu(p, steps=0)
+    assert z["steps"].size == 0 and z["budget"].size == 0
+
+
+def test_energy_and_state_roundtrip():
+    import torch
+    p = W.small_problem(nside=2, steps=10, seed=2)
+    with torch.cuda.stream(_stream()):
+        m = T.Medium.from_problem(p)
+        m.solve(10)
+        st = m.get_state()
+        e = m.read_energy()
+        assert np.allclose(e, st.sum(axis=0), rtol=1e-5, atol=1e-12)
+        dev = torch.zeros(st.shape, dtype=torch.float32, device="cuda")
+        m.get_state(dev)
+        torch.cuda.synchronize()
+        assert np.array_equal(dev.cpu().numpy(), st)
+        m.set_state(np.zeros_like(st))
+        assert m.get_state().max() == 0.0
+        m.close()
+
+
+def test_errors_are_reported_not_raised_across_the_abi():
+    p = W.small_problem(nside=2, steps=1)
+    import torch
+    with torch.cuda.stream(_stream()):
+        m = T.Medium.from_problem(p)
+        with pytest.raises(T.TrinityError) as e:
+            m.set_source(p.nx, 0, 1)
+        assert e.value.status == T.TR_EINVAL
+        with pytest.raises(T.TrinityError):
+            m.set_detectors([7], [0], [0])
+        with pytest.raises(T.TrinityError):
+            m.step(-1)
+        m.solve(2)
+        m.close()

@@ -1,0 +1,116 @@
+"""The C++ host set-up, called through the C-ABI without a GPU, reproduces the
+oracle's independently computed tables: exactly for integers, to FP64
+rounding for reals.  Also checks that the library exports every symbol the
+header declares."""
+import os
+import re
+
+import numpy as np
+import pytest
+
+from oracle import angles, lattice, medium, optics, setup
+from paper_2105_01028_amd import trinity as T
+from paper_2105_01028_amd import workloads as W
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def test_library_exports_every_declared_symbol():
+    hdr = open(os.path.join(ROOT, "include", "trinity.h")).read()
+    declared = set(re.findall(r"\b(tr_[a-z_]+)\s*\(", hdr))
+    assert len(declared) >= 20
+    L = T.lib()
+    for name in sorted(declared):
+        assert hasattr(L, name), name
+    assert declared == set(T.EXPORTED)
+
+
+@pytest.mark.parametrize("nside", [1, 2, 4, 8])
+def test_directions(nside):
+    assert np.abs(T.host_directions(nside) - angles.healpix_ring(nside)).max() < 2e-16
+
+
+@pytest.mark.parametrize("nside,g,norm", [(2, 0.9, "sinkhorn"), (4, 0.85, "sinkhorn"),
+                                          (2, 0.0, "sinkhorn"), (2, 0.9, "row"),
+                                          (8, 0.9, "sinkhorn")])
+def test_phase_matrix(nside, g, norm):
+    ref = angles.phase_matrix(angles.healpix_ring(nside), g, norm)
+    got = T.host_phase_matrix(nside, g, norm)
+    # both stop the scaling once row sums are within 1e-14 of one
+    assert np.abs(got - ref).max() < 1e-14 * np.abs(ref).max()
+
+
+@pytest.mark.parametrize("nside,shape", [(2, (16, 16, 16)), (4, (9, 13, 7)), (8, (5, 6, 40))])
+def test_lattice(nside, shape):
+    nz, ny, nx = shape
+    lat = lattice.RayLattice(angles.healpix_ring(nside), shape)
+    axis, sign, off = T.host_lattice(nside, nx, ny, nz)
+    assert np.array_equal(axis, lat.axis)
+    assert np.array_equal(sign, lat.sign)
+    for d in range(len(lat.dirs)):
+        na = lat.ext[lat.axis[d]]
+        assert np.array_equal(off[d, :, : na + 1], lat.offset[d])
+
+
+@pytest.mark.parametrize("coef", ["paper", "abs_exact"])
+def test_coefficients(coef):
+    p = W.small_problem(nx=7, ny=5, nz=6, mua=0.03, mus=4.0, n=1.4, seed=4, coef=coef)
+    n = p.n.copy()
+    n[2:4] = 1.0
+    mua = p.mua.copy()
+    mua[2:4] = 0.0
+    mus = p.mus.copy()
+    mus[2:4] = 0.0
+    p = p.copy(n=n, mua=mua, mus=mus)
+    a, b, r, dt = T.host_coefficients(p)
+    dt_ref = medium.time_step(p.dx_mm, np.asarray(p.n, np.float64))
+    ar, br, _, _ = medium.collision_coefficients(p.mua, p.mus, np.asarray(p.n, np.float64),
+                                                 dt_ref, coef)
+    assert abs(dt - dt_ref) < 1e-15 * dt_ref
+    assert np.abs(a - ar.ravel()).max() < 1e-15
+    assert np.abs(b - br.ravel()).max() < 1e-15
+    nref = medium.reference_index(p.n)
+    assert np.array_equal(r, (nref / np.asarray(p.n, np.float64)).ravel())
+
+
+@pytest.mark.parametrize("nside", [2, 4, 8])
+def test_cone_sets(nside):
+    d = angles.healpix_ring(nside)
+    for face, normal in setup.FACE_NORMALS.items():
+        for cone in (15.0, 30.0):
+            assert T.host_cone_set(nside, normal, cone) == setup.cone_set(d, normal, cone)
+
+
+def test_pulse():
+    got = T.host_pulse(4.6699, 20.0, 10.0, 1.0, 0, 200)
+    ref = setup.pulse_weights(200, 4.6699, 20.0, 10.0, 1.0)
+    assert np.abs(got - ref).max() < 1e-16
+
+
+def test_interceptions_match_oracle():
+    p = W.config3(nx=24)
+    p = p.copy(nside=2)
+    got = T.host_interceptions(p)
+    lat = lattice.RayLattice(angles.healpix_ring(2), p.shape)
+    ref = optics.interceptions(lat, np.asarray(p.n, np.float64))
+    assert len(got) == len(ref) > 100
+    for g, r in zip(got, ref):
+        assert g[0] == r[0] and g[1] == r[1] and g[2] == r[2]
+        assert abs(g[3] - r[3]) < 1e-14
+        assert g[4] == r[4] and g[5] == r[5]
+
+
+def test_invalid_descriptor_is_rejected():
+    p = W.small_problem()
+    bad = T.grid_desc(p)
+    bad.nside = 0
+    assert T.bytes_required(bad) == 0
+    with pytest.raises(T.TrinityError) as e:
+        T.lib()  # loaded
+        import ctypes
+        h = ctypes.c_void_p()
+        mua = np.zeros(p.nvox, np.float32)
+        T._check(T.lib().tr_create_medium(ctypes.byref(bad), mua.ctypes.data, mua.ctypes.data,
+                                          mua.ctypes.data, 0, 0, ctypes.byref(h)))
+    assert e.value.status == T.TR_EINVAL
+    assert "nside" in str(e.value)
