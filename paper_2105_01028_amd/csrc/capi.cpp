@@ -72,6 +72,59 @@ float bf16_bits_to_f32(unsigned short h) {
   return x;
 }
 
+// Rounding P to fp32 leaves each column sum (the light scattered out of one
+// incoming direction) off one by up to a few ulp of its largest entries, with a
+// bias that creates or destroys light at every scattering.  Nudge the smallest
+// entries of each column that can absorb the residual without changing sign:
+// each pass shrinks the residual to half an ulp of a small entry.
+void conserve_columns_f32(std::vector<float>& P, int n, int ld) {
+  std::vector<int> order(n);
+  for (int j = 0; j < n; ++j) {
+    for (int i = 0; i < n; ++i) order[i] = i;
+    std::sort(order.begin(), order.end(), [&](int p, int q) {
+      return P[size_t(p) * ld + j] < P[size_t(q) * ld + j];
+    });
+    for (int pass = 0; pass < 4; ++pass) {
+      double s = 0;
+      for (int i = 0; i < n; ++i) s += double(P[size_t(i) * ld + j]);
+      const double r = 1.0 - s;
+      if (r == 0.0) break;
+      for (int i : order) {
+        float& p = P[size_t(i) * ld + j];
+        if (double(p) > 64.0 * std::fabs(r)) {
+          p = float(double(p) + r);
+          break;
+        }
+      }
+    }
+  }
+}
+
+// The same for the bf16 pair P = P_hi + P_lo: nudge the low parts.
+void conserve_columns_bf16(std::vector<uint16_t>& hi, std::vector<uint16_t>& lo, int n, int ld) {
+  std::vector<int> order(n);
+  auto val = [&](size_t k) { return double(bf16_bits_to_f32(hi[k])) + double(bf16_bits_to_f32(lo[k])); };
+  for (int j = 0; j < n; ++j) {
+    for (int i = 0; i < n; ++i) order[i] = i;
+    std::sort(order.begin(), order.end(), [&](int p, int q) {
+      return val(size_t(p) * ld + j) < val(size_t(q) * ld + j);
+    });
+    for (int pass = 0; pass < 8; ++pass) {
+      double s = 0;
+      for (int i = 0; i < n; ++i) s += val(size_t(i) * ld + j);
+      const double r = 1.0 - s;
+      if (r == 0.0) break;
+      for (int i : order) {
+        const size_t k = size_t(i) * ld + j;
+        if (val(k) > 64.0 * std::fabs(r)) {
+          lo[k] = f32_to_bf16_bits(float(double(bf16_bits_to_f32(lo[k])) + r));
+          break;
+        }
+      }
+    }
+  }
+}
+
 }  // namespace
 
 struct tr_medium {
@@ -441,12 +494,16 @@ tr_status tr_create_medium(const tr_grid_desc* desc, const float* mua, const flo
     return fail(TR_ENOMEM, "device allocation failed");
   }
 
-  // host images
+  // host images of P: fp32 with every column summing to one (see
+  // conserve_columns), stored transposed for the fp32 kernel and split into
+  // bf16 high and low parts for the bf16-split kernel.
   std::vector<float> P32(size_t(f.NP) * f.NP, 0.0f);
   for (int i = 0; i < f.ndir; ++i)
-    for (int j = 0; j < f.ndir; ++j)
-      P32[size_t(i) * f.NP + j] =
-          float(0.5 * (P64[size_t(i) * f.ndir + j] + P64[size_t(j) * f.ndir + i]));
+    for (int j = 0; j < f.ndir; ++j) P32[size_t(i) * f.NP + j] = float(P64[size_t(i) * f.ndir + j]);
+  if (desc->hg_norm == TR_HG_SINKHORN) conserve_columns_f32(P32, f.ndir, f.NP);
+  std::vector<float> PT(P32.size(), 0.0f);
+  for (int i = 0; i < f.ndir; ++i)
+    for (int j = 0; j < f.ndir; ++j) PT[size_t(j) * f.NP + i] = P32[size_t(i) * f.NP + j];
   std::vector<float> av(f.Vp, 0.0f), bv(f.Vp, 0.0f), rv(f.Vp, 0.0f);
   for (int v = 0; v < f.V; ++v) {
     av[v] = float(m->co.a[v]);
@@ -471,7 +528,7 @@ tr_status tr_create_medium(const tr_grid_desc* desc, const float* mua, const flo
   }
   hipError_t e = hipMemset(m->X, 0, NV * 4);
   if (e == hipSuccess) e = hipMemset(m->Y, 0, NV * 4);
-  if (e == hipSuccess) e = hipMemcpy(m->P, P32.data(), P32.size() * 4, hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemcpy(m->P, PT.data(), PT.size() * 4, hipMemcpyHostToDevice);
   if (e == hipSuccess) e = hipMemcpy(m->a, av.data(), av.size() * 4, hipMemcpyHostToDevice);
   if (e == hipSuccess) e = hipMemcpy(m->b, bv.data(), bv.size() * 4, hipMemcpyHostToDevice);
   if (e == hipSuccess) e = hipMemcpy(m->r, rv.data(), rv.size() * 4, hipMemcpyHostToDevice);
@@ -485,6 +542,7 @@ tr_status tr_create_medium(const tr_grid_desc* desc, const float* mua, const flo
       hi[i] = f32_to_bf16_bits(P32[i]);
       lo[i] = f32_to_bf16_bits(P32[i] - bf16_bits_to_f32(hi[i]));
     }
+    if (desc->hg_norm == TR_HG_SINKHORN) conserve_columns_bf16(hi, lo, f.ndir, f.NP);
     e = hipMemcpy(m->Phi, hi.data(), hi.size() * 2, hipMemcpyHostToDevice);
     if (e == hipSuccess) e = hipMemcpy(m->Plo, lo.data(), lo.size() * 2, hipMemcpyHostToDevice);
   }
@@ -506,8 +564,9 @@ tr_status tr_create_medium(const tr_grid_desc* desc, const float* mua, const flo
     std::map<std::pair<int, long long>, std::vector<std::pair<int, float>>> tg;
     for (const Interception& ic : m->icpt) {
       const int slot = islot[ic.v] * f.ndir + ic.d;
+      // reflected share R F; refracted share F - R F, encoded as weight -R
       tg[{ic.d_refl, ic.v}].push_back({slot, float(ic.R)});
-      if (ic.d_refr >= 0) tg[{ic.d_refr, ic.w}].push_back({slot, float(1.0 - ic.R)});
+      if (ic.d_refr >= 0) tg[{ic.d_refr, ic.w}].push_back({slot, -float(ic.R)});
     }
     std::vector<int> td, tv, ptr(1, 0), src;
     std::vector<float> w;
@@ -754,6 +813,7 @@ tr_status tr_read_detector_steps(tr_medium* m, double* out, size_t n_out) {
   tr_status st = tr_synchronize(m);
   if (st != TR_OK) return st;
   const size_t need = size_t(m->ndet) * m->steps_done;
+  if (need == 0) return TR_OK;
   if (!out || n_out < need) return fail(TR_EINVAL, "output too small");
   for (int k = 0; k < m->ndet; ++k) {
     hipError_t e = hipMemcpy(out + size_t(k) * m->steps_done, m->det_steps + size_t(k) * m->cap,
@@ -792,6 +852,7 @@ tr_status tr_read_budget(tr_medium* m, double* out, size_t n_out) {
   tr_status st = tr_synchronize(m);
   if (st != TR_OK) return st;
   const size_t need = size_t(9) * m->steps_done;
+  if (need == 0) return TR_OK;
   if (!out || n_out < need) return fail(TR_EINVAL, "output too small");
   hipError_t e = hipMemcpy(out, m->budget, need * 8, hipMemcpyDeviceToHost);
   if (e != hipSuccess) return device_fail(m, e, "budget read");

@@ -39,7 +39,7 @@ struct InjectArgs {
 struct CollideArgs {
   const float* X;          // input field [NP][Vp]
   float* Y;                // output field [NP][Vp]
-  const float* P;          // [NP][NP] fp32 phase matrix (symmetric, zero padded)
+  const float* P;          // [NP][NP] fp32 phase matrix, transposed (zero padded)
   const uint16_t* Phi;     // [NP][NP] bf16 high part (bf16-split mode)
   const uint16_t* Plo;     // [NP][NP] bf16 low part
   const float* a;          // [Vp]
@@ -74,7 +74,7 @@ struct GatherArgs {
   const int* tgt_v;
   const int* ptr;          // CSR over targets
   const int* src;          // slot into icptF
-  const float* w;          // R or 1 - R
+  const float* w;          // R (reflected share) or -R (refracted share F - R F)
   const float* icptF;
   int ntgt;
 };

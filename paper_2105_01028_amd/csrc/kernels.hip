@@ -85,8 +85,9 @@ __global__ void inject_kernel(InjectArgs A) {
 // A GEMM with M = K = NP (directions) and N = voxels, on v_mfma_f32_32x32x2f32.
 // Workgroup tile: MT rows (directions) x 128 columns (voxels), four wavefronts
 // of 32 columns each, every wavefront holding all MT rows in accumulators.
-// P (symmetric, so P[k][row] = P[row][k]) is staged through LDS in chunks of
-// KC directions as [k][row]; X goes straight from HBM into the B operand.
+// P is staged through LDS in chunks of KC directions as [k][row], read from
+// its transpose PT (A.P holds P^T, row k = column k of P, contiguous in row);
+// X goes straight from HBM into the B operand.
 // The epilogue applies a, b per voxel and sums the FP64 budget partials:
 // absorbed = sum_v (1 - a_v - b_v) sum_d X[d][v], total = sum X.
 template <int MT>
@@ -311,7 +312,11 @@ __global__ void gather_kernel(GatherArgs A) {
   const int t = blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= A.ntgt) return;
   float s = 0.0f;
-  for (int j = A.ptr[t]; j < A.ptr[t + 1]; ++j) s = fmaf(A.w[j], A.icptF[A.src[j]], s);
+  for (int j = A.ptr[t]; j < A.ptr[t + 1]; ++j) {
+    const float F = A.icptF[A.src[j]], w = A.w[j];
+    // w >= 0: reflected share w F; w < 0: refracted share F - |w| F (one rounding)
+    s += w >= 0.0f ? w * F : fmaf(w, F, F);
+  }
   A.X[size_t(A.tgt_d[t]) * A.Vp + A.tgt_v[t]] += s;
 }
 

