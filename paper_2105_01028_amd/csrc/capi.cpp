@@ -144,7 +144,8 @@ struct tr_medium {
   std::map<void*, size_t> owned;   // every device allocation and its size
   size_t bytes = 0;
 
-  float *X = nullptr, *Y = nullptr, *P = nullptr, *a = nullptr, *b = nullptr, *r = nullptr;
+  float *X = nullptr, *Y = nullptr, *P = nullptr, *Prow = nullptr, *a = nullptr, *b = nullptr,
+        *r = nullptr;
   uint16_t *Phi = nullptr, *Plo = nullptr;
   DevDir* ddirs = nullptr;
   int8_t* delta = nullptr;
@@ -160,6 +161,8 @@ struct tr_medium {
 
   int* step_ctr = nullptr;
   int* flag = nullptr;
+  double* rscratch = nullptr;
+  int* rdone = nullptr;
   double *cpart = nullptr, *spart = nullptr;
   int cnwg = 0, snwg = 0, sweep_bpd = 0;
 
@@ -244,12 +247,12 @@ tr_status device_fail(tr_medium* m, hipError_t e, const char* what) {
 size_t fixed_bytes(const Field& f, int precision, size_t niface_guess) {
   size_t b = 0;
   b += 2 * size_t(f.NP) * f.Vp * sizeof(float);         // X, Y
-  b += size_t(f.NP) * f.NP * sizeof(float);              // P
+  b += 2 * size_t(f.NP) * f.NP * sizeof(float);          // P and its transpose
   if (precision == 1) b += 2 * size_t(f.NP) * f.NP * 2;  // P_hi, P_lo
   b += 3 * size_t(f.Vp) * sizeof(float);                 // a, b, r
   b += size_t(f.ndir) * sizeof(DevDir);
   b += size_t(f.ndir) * 2 * (std::max(f.nx, std::max(f.ny, f.nz)) + 2);
-  const int cn = collide_nwg(f), sn = sweep_blocks_per_dir(f) * f.ndir;
+  const int cn = collide_nwg(f, precision), sn = sweep_blocks_per_dir(f) * f.ndir;
   b += (2 * size_t(cn) + 7 * size_t(sn)) * sizeof(double);
   b += niface_guess * f.ndir * sizeof(float);
   return b;
@@ -322,7 +325,7 @@ hipError_t queue_step(tr_medium* m) {
   }
   {
     KernelTimer t(m, TR_K_COLLIDE);
-    CollideArgs ca{m->X, m->Y, m->P, m->Phi, m->Plo, m->a, m->b, f.Vp, f.NP, m->cpart};
+    CollideArgs ca{m->X, m->Y, m->P, m->Prow, m->Phi, m->Plo, m->a, m->b, f.Vp, f.NP, m->cpart};
     if ((e = launch_collide(ca, f, m->desc.precision, 0, m->stream)) != hipSuccess) return e;
   }
   const bool split = m->mode == TR_ADVANCE_SPLIT;
@@ -341,7 +344,7 @@ hipError_t queue_step(tr_medium* m) {
   KernelTimer t(m, TR_K_REDUCE);
   ReduceArgs ra{m->cpart, m->cnwg, m->spart, m->snwg, m->Y, f.Vp, m->det_pairs, m->det_first,
                 m->det_vox_dev, m->ndet, m->ddirs, m->r, split ? 1 : 0, m->step_ctr, m->budget,
-                m->det_steps, m->cap, m->flag};
+                m->det_steps, m->cap, m->flag, m->rscratch, m->rdone};
   return launch_reduce(ra, m->stream);
 }
 
@@ -470,6 +473,7 @@ tr_status tr_create_medium(const tr_grid_desc* desc, const float* mua, const flo
   m->X = m->alloc<float>(NV);
   m->Y = m->alloc<float>(NV);
   m->P = m->alloc<float>(size_t(f.NP) * f.NP);
+  m->Prow = m->alloc<float>(size_t(f.NP) * f.NP);
   m->a = m->alloc<float>(f.Vp);
   m->b = m->alloc<float>(f.Vp);
   m->r = m->alloc<float>(f.Vp);
@@ -478,7 +482,9 @@ tr_status tr_create_medium(const tr_grid_desc* desc, const float* mua, const flo
   m->delta = m->alloc<int8_t>(size_t(f.ndir) * 2 * m->dstride);
   m->step_ctr = m->alloc<int>(1);
   m->flag = m->alloc<int>(1);
-  m->cnwg = collide_nwg(f);
+  m->rscratch = m->alloc<double>(8);
+  m->rdone = m->alloc<int>(1);
+  m->cnwg = collide_nwg(f, desc->precision);
   m->sweep_bpd = sweep_blocks_per_dir(f);
   m->snwg = m->sweep_bpd * f.ndir;
   m->cpart = m->alloc<double>(2 * size_t(m->cnwg));
@@ -487,8 +493,8 @@ tr_status tr_create_medium(const tr_grid_desc* desc, const float* mua, const flo
     m->Phi = m->alloc<uint16_t>(size_t(f.NP) * f.NP);
     m->Plo = m->alloc<uint16_t>(size_t(f.NP) * f.NP);
   }
-  if (!m->X || !m->Y || !m->P || !m->a || !m->b || !m->r || !m->ddirs || !m->delta ||
-      !m->step_ctr || !m->flag || !m->cpart || !m->spart ||
+  if (!m->X || !m->Y || !m->P || !m->Prow || !m->a || !m->b || !m->r || !m->ddirs || !m->delta ||
+      !m->step_ctr || !m->flag || !m->cpart || !m->spart || !m->rscratch || !m->rdone ||
       (desc->precision == 1 && (!m->Phi || !m->Plo))) {
     delete m;
     return fail(TR_ENOMEM, "device allocation failed");
@@ -526,9 +532,11 @@ tr_status tr_create_medium(const tr_grid_desc* desc, const float* mua, const flo
         dl[(size_t(d) * 2 + q) * m->dstride + k] =
             int8_t(m->lat.off(d, q, k) - m->lat.off(d, q, k - 1));
   }
-  hipError_t e = hipMemset(m->X, 0, NV * 4);
+  hipError_t e = prepare_collide(f, desc->precision);
+  if (e == hipSuccess) e = hipMemset(m->X, 0, NV * 4);
   if (e == hipSuccess) e = hipMemset(m->Y, 0, NV * 4);
   if (e == hipSuccess) e = hipMemcpy(m->P, PT.data(), PT.size() * 4, hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemcpy(m->Prow, P32.data(), P32.size() * 4, hipMemcpyHostToDevice);
   if (e == hipSuccess) e = hipMemcpy(m->a, av.data(), av.size() * 4, hipMemcpyHostToDevice);
   if (e == hipSuccess) e = hipMemcpy(m->b, bv.data(), bv.size() * 4, hipMemcpyHostToDevice);
   if (e == hipSuccess) e = hipMemcpy(m->r, rv.data(), rv.size() * 4, hipMemcpyHostToDevice);
@@ -536,6 +544,7 @@ tr_status tr_create_medium(const tr_grid_desc* desc, const float* mua, const flo
   if (e == hipSuccess) e = hipMemcpy(m->delta, dl.data(), dl.size(), hipMemcpyHostToDevice);
   if (e == hipSuccess) e = hipMemset(m->step_ctr, 0, sizeof(int));
   if (e == hipSuccess) e = hipMemset(m->flag, 0, sizeof(int));
+  if (e == hipSuccess) e = hipMemset(m->rdone, 0, sizeof(int));
   if (e == hipSuccess && desc->precision == 1) {
     std::vector<uint16_t> hi(P32.size()), lo(P32.size());
     for (size_t i = 0; i < P32.size(); ++i) {
@@ -739,6 +748,7 @@ tr_status tr_reset(tr_medium* m) {
     e = hipMemsetAsync(m->det_steps, 0, size_t(m->ndet) * m->cap * 8, m->stream);
   if (e == hipSuccess) e = hipMemsetAsync(m->step_ctr, 0, 4, m->stream);
   if (e == hipSuccess) e = hipMemsetAsync(m->flag, 0, 4, m->stream);
+  if (e == hipSuccess) e = hipMemsetAsync(m->rdone, 0, 4, m->stream);
   if (e == hipSuccess) e = hipStreamSynchronize(m->stream);
   if (e != hipSuccess) return device_fail(m, e, "reset");
   m->steps_done = 0;

@@ -40,6 +40,7 @@ struct CollideArgs {
   const float* X;          // input field [NP][Vp]
   float* Y;                // output field [NP][Vp]
   const float* P;          // [NP][NP] fp32 phase matrix, transposed (zero padded)
+  const float* Prow;       // [NP][NP] fp32 phase matrix, row-major (zero padded)
   const uint16_t* Phi;     // [NP][NP] bf16 high part (bf16-split mode)
   const uint16_t* Plo;     // [NP][NP] bf16 low part
   const float* a;          // [Vp]
@@ -98,13 +99,16 @@ struct ReduceArgs {
   double* det_steps;       // [ndet][cap]
   int cap;
   int* flag;               // bit 0: non-finite budget, bit 1: step beyond capacity
+  double* scratch;         // [8] per-quantity sums of the current step
+  int* done;               // workgroups finished (reset by the last one)
 };
 
 // Launchers: queue the kernel on `s`.  Return the launch status.
 hipError_t launch_inject(const InjectArgs& a, hipStream_t s);
 hipError_t launch_collide(const CollideArgs& a, const Field& f, int bf16split, int nwg_cols,
                           hipStream_t s);
-int collide_nwg(const Field& f);
+int collide_nwg(const Field& f, int bf16split);
+hipError_t prepare_collide(const Field& f, int bf16split);   // once per process and shape
 hipError_t launch_sweep(const SweepArgs& a, const Field& f, int split, int fresnel, int bpd,
                         hipStream_t s);
 int sweep_blocks_per_dir(const Field& f);

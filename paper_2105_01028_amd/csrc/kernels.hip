@@ -141,6 +141,112 @@ __global__ __launch_bounds__(kThreads, 2) void collide_f32_kernel(CollideArgs A)
   block_sums<2>(vals, A.part + (long long)blockIdx.y * gridDim.x + blockIdx.x, nwg);
 }
 
+// Collision with P resident in LDS (NP <= 192, 147 KB): a persistent kernel,
+// one 512-thread workgroup per CU, each wavefront owning 32 voxel columns of a
+// 256-column tile and all NP direction rows.  In chunk c of the K loop (rows
+// 32c .. 32c+31) lane half h loads the X rows 32c + 8(s/4) + 4h + s%4,
+// s = 0..15, which are exactly the rows of accumulator block c that the lane
+// holds, so the a_v X term is added to the accumulator as those rows arrive:
+//   acc = sum_k P[i][k] (b_v X[k][v]) + a_v X[i][v] = Y[i][v]
+// and the epilogue only stores.  The next chunk's X is loaded into registers
+// while the current one feeds the MFMAs; P comes from LDS as [row][k] with a
+// padded pitch, four k per 16-byte read.
+template <int NP>
+__global__ __launch_bounds__(512, 1) void collide_f32_res_kernel(CollideArgs A, int ntiles) {
+  constexpr int NQ = NP / 32;
+  constexpr int LDK = NP + 4;
+  extern __shared__ float Ps[];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int hl = lane >> 5, cl = lane & 31;
+  for (int e = tid * 4; e < NP * NP; e += 512 * 4) {
+    const int r = e / NP, k = e - r * NP;
+    *reinterpret_cast<float4*>(Ps + r * LDK + k) =
+        *reinterpret_cast<const float4*>(A.Prow + size_t(r) * NP + k);
+  }
+  __syncthreads();
+  const size_t rowbytes = size_t(A.Vp) * sizeof(float);
+  // per-lane byte offset inside a group of rows: column plus the lane half's 4-row shift
+  double absorbed = 0.0, total = 0.0;
+  const float* __restrict__ Pl = Ps + cl * LDK + 4 * hl;
+#pragma unroll 1
+  for (int tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+    const long long col = (long long)tile * 256 + wave * 32 + cl;
+    const unsigned voff = unsigned(size_t(col) * sizeof(float) + size_t(4 * hl) * rowbytes);
+    const char* __restrict__ xb0 = reinterpret_cast<const char*>(A.X);
+    const float av = A.a[col], bv = A.b[col];
+    floatx16 acc[NQ];
+#pragma unroll
+    for (int q = 0; q < NQ; ++q)
+#pragma unroll
+      for (int r = 0; r < 16; ++r) acc[q][r] = 0.0f;
+    // row of step s in chunk c for lane half h: 32c + 8(s/4) + 4h + s%4; the 4h part is in voff
+    auto ld = [&](int c, int s) {
+      const char* rb = xb0 + size_t(32 * c + 8 * (s >> 2) + (s & 3)) * rowbytes;
+      return *reinterpret_cast<const float*>(rb + voff);
+    };
+    float bcur[16], bnext[16];
+#pragma unroll
+    for (int s = 0; s < 16; ++s) bcur[s] = ld(0, s);
+    double colsum64 = 0.0;
+#pragma unroll 1
+    for (int c = 0; c < NQ; ++c) {
+      const int cn = c + 1 < NQ ? c + 1 : c;   // last chunk reloads itself (in bounds, unused)
+#pragma unroll
+      for (int s = 0; s < 16; ++s) bnext[s] = ld(cn, s);
+      float colsum = 0.0f;
+#pragma unroll
+      for (int s = 0; s < 16; ++s) colsum += bcur[s];
+      colsum64 += double(colsum);
+      // a_v X for the rows of accumulator block c (uniform branch)
+#pragma unroll
+      for (int q = 0; q < NQ; ++q)
+        if (q == c) {
+#pragma unroll
+          for (int s = 0; s < 16; ++s) acc[q][s] = fmaf(av, bcur[s], acc[q][s]);
+        }
+#pragma unroll
+      for (int s = 0; s < 16; ++s) bcur[s] *= bv;
+#pragma unroll
+      for (int s4 = 0; s4 < 16; s4 += 4) {
+        // k of step s (s = s4..s4+3): 32c + 8(s/4) + 4h + s%4 -> four consecutive k per half
+        const int kk = 32 * c + 8 * (s4 >> 2);
+#pragma unroll
+        for (int q = 0; q < NQ; ++q) {
+          const float4 a4 = *reinterpret_cast<const float4*>(Pl + q * 32 * LDK + kk);
+          acc[q] = __builtin_amdgcn_mfma_f32_32x32x2f32(a4.x, bcur[s4 + 0], acc[q], 0, 0, 0);
+          acc[q] = __builtin_amdgcn_mfma_f32_32x32x2f32(a4.y, bcur[s4 + 1], acc[q], 0, 0, 0);
+          acc[q] = __builtin_amdgcn_mfma_f32_32x32x2f32(a4.z, bcur[s4 + 2], acc[q], 0, 0, 0);
+          acc[q] = __builtin_amdgcn_mfma_f32_32x32x2f32(a4.w, bcur[s4 + 3], acc[q], 0, 0, 0);
+        }
+      }
+#pragma unroll
+      for (int s = 0; s < 16; ++s) bcur[s] = bnext[s];
+    }
+    char* __restrict__ yb0 = reinterpret_cast<char*>(A.Y);
+#pragma unroll
+    for (int q = 0; q < NQ; ++q)
+#pragma unroll
+      for (int r = 0; r < 16; ++r)
+        *reinterpret_cast<float*>(yb0 + size_t(q * 32 + 8 * (r >> 2) + (r & 3)) * rowbytes + voff) =
+            acc[q][r];
+    absorbed += (1.0 - double(av) - double(bv)) * colsum64;
+    total += colsum64;
+  }
+  __syncthreads();
+  __shared__ double red2[2][8];
+  double sa = wave_sum(absorbed), st = wave_sum(total);
+  if (lane == 0) {
+    red2[0][wave] = sa;
+    red2[1][wave] = st;
+  }
+  __syncthreads();
+  if (tid < 2) {
+    double t = 0;
+    for (int w = 0; w < 8; ++w) t += red2[tid][w];
+    A.part[(long long)tid * gridDim.x + blockIdx.x] = t;
+  }
+}
+
 // Same contraction with P and X each split into bf16 high and low parts,
 // X = X_hi + X_lo, P = P_hi + P_lo, and (P X) ~ P_hi X_hi + P_hi X_lo + P_lo X_hi
 // on v_mfma_f32_32x32x16_bf16 with fp32 accumulation (the dropped P_lo X_lo term
@@ -223,85 +329,201 @@ __global__ __launch_bounds__(kThreads, 2) void collide_bf16split_kernel(CollideA
 // crosses (dominant axis first, then b, then c).
 //   X[d][v] = (1 - f_v) Y[d][v] + f_u Y[d][u]
 // Phase mode: f is 0 or 1 for the whole direction at step m.  Split mode:
-// f_v = nu_d r_v.  Grid: (blocks per direction, directions); x runs along lanes
-// so each wavefront reads and writes contiguous voxels.
-template <bool SPLIT, bool FRESNEL>
-__global__ __launch_bounds__(kThreads) void sweep_kernel(SweepArgs A) {
-  const int d = blockIdx.y;
-  const DevDir D = A.dirs[d];
-  const int m = *A.step_ctr;
-  const float fph = SPLIT ? 0.0f : phase_move(D.nu64, m);
-  const int nx = A.nx, ny = A.ny, nz = A.nz;
-  const int ea = pick(D.axis, nx, ny, nz), eb = pick(D.bax, nx, ny, nz),
-            ec = pick(D.cax, nx, ny, nz);
-  const long long sxy = (long long)nx * ny;
-  const long long sa = D.axis == 0 ? 1 : (D.axis == 1 ? nx : sxy);
-  const long long sb = D.bax == 0 ? 1 : (D.bax == 1 ? nx : sxy);
-  const long long sc = D.cax == 0 ? 1 : (D.cax == 1 ? nx : sxy);
-  const int8_t* db = A.delta + (size_t(d) * 2 + 0) * A.dstride;
-  const int8_t* dc = A.delta + (size_t(d) * 2 + 1) * A.dstride;
-  const float* Yd = A.Y + size_t(d) * A.Vp;
-  float* Xd = A.X + size_t(d) * A.Vp;
-  double esc_a = 0, esc_b0 = 0, esc_b1 = 0, esc_c0 = 0, esc_c1 = 0, dom = 0;
-  const bool moving = SPLIT || fph != 0.0f;
+// f_v = nu_d r_v.  Grid: (row slabs, directions).  Lanes run along x, so every
+// wavefront reads and writes contiguous voxels; the upwind row of a y- or
+// z-dominant direction is one shifted row, that of an x-dominant direction
+// differs lane by lane by at most one row in y and one in z.
 
-  for (int v = blockIdx.x * kThreads + threadIdx.x; v < A.V; v += gridDim.x * kThreads) {
-    const int x = v % nx, t = v / nx, y = t % ny, z = t / ny;
-    const int pa = pick(D.axis, x, y, z), pb = pick(D.bax, x, y, z), pc = pick(D.cax, x, y, z);
-    const int k = D.sign > 0 ? pa : ea - 1 - pa;
-    const float yv = Yd[v];
-    const float fv = SPLIT ? D.nu * A.r[v] : fph;
-    float out = (1.0f - fv) * yv;
-    if (moving && k > 0) {
-      const int dbk = db[k], dck = dc[k];
-      const int ub = pb - dbk, uc = pc - dck;
-      if ((unsigned)ub < (unsigned)eb && (unsigned)uc < (unsigned)ec) {
-        const long long u = v - D.sign * sa - dbk * sb - dck * sc;
-        bool blocked = false;
-        if (FRESNEL) blocked = A.iface[u] && A.nvox[u] != A.nvox[v];
-        if (!blocked) {
-          const float fu = SPLIT ? D.nu * A.r[u] : fph;
-          out = fmaf(fu, Yd[u], out);
-        }
-      }
-    }
-    Xd[v] = out;
-    dom += double(out);
-    if (moving) {
-      const float mv = fv * yv;
-      if (k + 1 >= ea) {
-        esc_a += double(mv);
-      } else {
-        const int dbn = db[k + 1], dcn = dc[k + 1];
-        const int wb = pb + dbn, wc = pc + dcn;
-        if ((unsigned)wb >= (unsigned)eb) {
-          if (dbn > 0) esc_b1 += double(mv); else esc_b0 += double(mv);
-        } else if ((unsigned)wc >= (unsigned)ec) {
-          if (dcn > 0) esc_c1 += double(mv); else esc_c0 += double(mv);
-        } else if (FRESNEL && A.iface[v]) {
-          const long long w = v + D.sign * sa + dbn * sb + dcn * sc;
-          if (A.nvox[w] != A.nvox[v]) {
-            A.icptF[size_t(A.islot[v]) * A.ndir + d] = mv;
-            dom += double(mv);
-          }
-        }
+namespace {
+
+struct SweepAcc {
+  double esc_a = 0, esc_b0 = 0, esc_b1 = 0, esc_c0 = 0, esc_c1 = 0, dom = 0;
+};
+
+constexpr int kMaxExt = 4096;   // largest grid extent (the C-ABI rejects larger)
+constexpr int kRows = 4;        // rows a thread works on at once
+
+// Rows [rb, re) of direction d with dominant axis AX.  Thread layout: tpr
+// threads per row (tpr = min(nx, 256)), rpi = 256 / tpr rows per pass; each
+// thread takes kRows rows per iteration and issues all their loads first.
+// Phase mode (SPLIT false) is only called for directions that move this step
+// (f = 1): a voxel then takes its upwind voxel's value and only light that
+// leaves the box needs the voxel's own value.
+template <int AX, bool SPLIT, bool FRESNEL>
+__device__ __forceinline__ void sweep_rows(const SweepArgs& A, const DevDir& D, int d, int rb,
+                                           int re, const int8_t* __restrict__ db,
+                                           const int8_t* __restrict__ dc, SweepAcc& acc) {
+  const int nx = A.nx, ny = A.ny, nz = A.nz;
+  const long long sxy = (long long)nx * ny;
+  constexpr int BX = AX == 0 ? 1 : 0;   // transverse axes b < c
+  constexpr int CX = AX == 2 ? 1 : 2;
+  const int ext[3] = {nx, ny, nz};
+  const long long str[3] = {1, nx, sxy};
+  const int ea = ext[AX], eb = ext[BX], ec = ext[CX];
+  const long long sa = str[AX], sb = str[BX], sc = str[CX];
+  const float* __restrict__ Yd = A.Y + size_t(d) * A.Vp;
+  float* __restrict__ Xd = A.X + size_t(d) * A.Vp;
+  const int tpr = nx < kThreads ? nx : kThreads;
+  const int rpi = kThreads / tpr;
+  const int xs = threadIdx.x % tpr, rsub = threadIdx.x / tpr;
+  if (rsub >= rpi) return;
+  const int sign = D.sign;
+  const float nu = D.nu;
+  // (y, z) of this thread's next kRows rows, advanced without division
+  int yy[kRows], zz[kRows];
+  {
+    const int row = rb + rsub;
+    zz[0] = row / ny;
+    yy[0] = row - zz[0] * ny;
+#pragma unroll
+    for (int i = 1; i < kRows; ++i) {
+      yy[i] = yy[i - 1] + rpi;
+      zz[i] = zz[i - 1];
+      while (yy[i] >= ny) {
+        yy[i] -= ny;
+        ++zz[i];
       }
     }
   }
-  double face[6] = {0, 0, 0, 0, 0, 0};
-  // map the five per-direction accumulators onto faces (uniform per block)
+  for (int row0 = rb + rsub; row0 < re; row0 += kRows * rpi) {
+    for (int x = xs; x < nx; x += tpr) {
+      long long v[kRows], u[kRows];
+      int k[kRows], pb[kRows], pc[kRows], dbn[kRows], dcn[kRows];
+      bool live[kRows], inflow[kRows];
+      float yv[kRows], yu[kRows];
+#pragma unroll
+      for (int i = 0; i < kRows; ++i) {
+        const int row = row0 + i * rpi;
+        live[i] = row < re;
+        const int z = zz[i], y = yy[i];
+        const int pa = AX == 0 ? x : (AX == 1 ? y : z);
+        k[i] = sign > 0 ? pa : ea - 1 - pa;
+        pb[i] = BX == 0 ? x : y;
+        pc[i] = CX == 1 ? y : z;
+        v[i] = (long long)row * nx + x;
+        const int dbk = db[k[i]], dck = dc[k[i]];
+        dbn[i] = db[k[i] + 1];
+        dcn[i] = dc[k[i] + 1];
+        const int ub = pb[i] - dbk, uc = pc[i] - dck;
+        inflow[i] = live[i] && k[i] > 0 && (unsigned)ub < (unsigned)eb && (unsigned)uc < (unsigned)ec;
+        u[i] = v[i] - sign * sa - dbk * sb - dck * sc;
+        if (FRESNEL && inflow[i]) inflow[i] = !(A.iface[u[i]] && A.nvox[u[i]] != A.nvox[v[i]]);
+      }
+      // exits: the downwind voxel is outside the box
+      int exitf[kRows];   // 0 none, 1 a, 2 b0, 3 b1, 4 c0, 5 c1
+#pragma unroll
+      for (int i = 0; i < kRows; ++i) {
+        int e = 0;
+        if (k[i] + 1 >= ea) e = 1;
+        else if ((unsigned)(pb[i] + dbn[i]) >= (unsigned)eb) e = dbn[i] > 0 ? 3 : 2;
+        else if ((unsigned)(pc[i] + dcn[i]) >= (unsigned)ec) e = dcn[i] > 0 ? 5 : 4;
+        exitf[i] = live[i] ? e : 0;
+      }
+#pragma unroll
+      for (int i = 0; i < kRows; ++i) {
+        yu[i] = inflow[i] ? Yd[u[i]] : 0.0f;
+        const bool need_v = SPLIT || FRESNEL || exitf[i] != 0;
+        yv[i] = (live[i] && need_v) ? Yd[v[i]] : 0.0f;
+      }
+#pragma unroll
+      for (int i = 0; i < kRows; ++i) {
+        if (!live[i]) continue;
+        float fv = 1.0f, fu = 1.0f;
+        if (SPLIT) {
+          fv = nu * A.r[v[i]];
+          fu = inflow[i] ? nu * A.r[u[i]] : 0.0f;
+        }
+        const float out = SPLIT ? fmaf(fu, yu[i], (1.0f - fv) * yv[i]) : yu[i];
+        Xd[v[i]] = out;
+        acc.dom += double(out);
+        const float mv = fv * yv[i];
+        switch (exitf[i]) {
+          case 1: acc.esc_a += double(mv); break;
+          case 2: acc.esc_b0 += double(mv); break;
+          case 3: acc.esc_b1 += double(mv); break;
+          case 4: acc.esc_c0 += double(mv); break;
+          case 5: acc.esc_c1 += double(mv); break;
+          default:
+            if (FRESNEL && A.iface[v[i]]) {
+              const long long w = v[i] + sign * sa + dbn[i] * sb + dcn[i] * sc;
+              if (A.nvox[w] != A.nvox[v[i]]) {
+                A.icptF[size_t(A.islot[v[i]]) * A.ndir + d] = mv;
+                acc.dom += double(mv);
+              }
+            }
+        }
+      }
+    }
+#pragma unroll
+    for (int i = 0; i < kRows; ++i) {
+      yy[i] += kRows * rpi;
+      while (yy[i] >= ny) {
+        yy[i] -= ny;
+        ++zz[i];
+      }
+    }
+  }
+}
+
+}  // namespace
+
+template <bool SPLIT, bool FRESNEL>
+__global__ __launch_bounds__(kThreads) void sweep_kernel(SweepArgs A) {
+  __shared__ int8_t sdelta[2][kMaxExt + 2];
+  const int d = blockIdx.y;
+  const DevDir D = A.dirs[d];
+  const int m = *A.step_ctr;
+  const float fph = SPLIT ? 1.0f : phase_move(D.nu64, m);
+  const int R = A.ny * A.nz;
+  const int rb = int((long long)R * blockIdx.x / gridDim.x);
+  const int re = int((long long)R * (blockIdx.x + 1) / gridDim.x);
+  SweepAcc acc;
+  if (fph == 0.0f) {
+    // phase mode, this direction does not move at step m: the field passes through
+    const float4* __restrict__ Yd = reinterpret_cast<const float4*>(A.Y + size_t(d) * A.Vp);
+    float4* __restrict__ Xd = reinterpret_cast<float4*>(A.X + size_t(d) * A.Vp);
+    const long long v0 = (long long)rb * A.nx, v1 = (long long)re * A.nx;
+    // whole float4s inside [v0, v1) are copied as vectors, the ragged ends one by one
+    const long long q0 = (v0 + 3) / 4, q1 = v1 / 4;
+    for (long long q = q0 + threadIdx.x; q < q1; q += kThreads) {
+      const float4 y = Yd[q];
+      Xd[q] = y;
+      acc.dom += (double(y.x) + double(y.y)) + (double(y.z) + double(y.w));
+    }
+    const float* Ys = A.Y + size_t(d) * A.Vp;
+    float* Xs = A.X + size_t(d) * A.Vp;
+    for (long long v = v0 + threadIdx.x; v < v1; v += kThreads) {
+      if (v >= 4 * q0 && v < 4 * q1) continue;
+      Xs[v] = Ys[v];
+      acc.dom += double(Ys[v]);
+    }
+  } else {
+    const int ea = D.axis == 0 ? A.nx : (D.axis == 1 ? A.ny : A.nz);
+    for (int i = threadIdx.x; i <= ea; i += kThreads) {
+      sdelta[0][i] = A.delta[(size_t(d) * 2 + 0) * A.dstride + i];
+      sdelta[1][i] = A.delta[(size_t(d) * 2 + 1) * A.dstride + i];
+    }
+    __syncthreads();
+    if (D.axis == 2)
+      sweep_rows<2, SPLIT, FRESNEL>(A, D, d, rb, re, sdelta[0], sdelta[1], acc);
+    else if (D.axis == 1)
+      sweep_rows<1, SPLIT, FRESNEL>(A, D, d, rb, re, sdelta[0], sdelta[1], acc);
+    else
+      sweep_rows<0, SPLIT, FRESNEL>(A, D, d, rb, re, sdelta[0], sdelta[1], acc);
+  }
+  double face[6];
   const int fa = 2 * D.axis + (D.sign > 0 ? 1 : 0);
 #pragma unroll
   for (int f = 0; f < 6; ++f) {
     double s = 0;
-    if (f == fa) s += esc_a;
-    if (f == 2 * D.bax) s += esc_b0;
-    if (f == 2 * D.bax + 1) s += esc_b1;
-    if (f == 2 * D.cax) s += esc_c0;
-    if (f == 2 * D.cax + 1) s += esc_c1;
+    if (f == fa) s += acc.esc_a;
+    if (f == 2 * D.bax) s += acc.esc_b0;
+    if (f == 2 * D.bax + 1) s += acc.esc_b1;
+    if (f == 2 * D.cax) s += acc.esc_c0;
+    if (f == 2 * D.cax + 1) s += acc.esc_c1;
     face[f] = s;
   }
-  const double vals[7] = {face[0], face[1], face[2], face[3], face[4], face[5], dom};
+  const double vals[7] = {face[0], face[1], face[2], face[3], face[4], face[5], acc.dom};
   const long long nwg = (long long)gridDim.x * gridDim.y;
   block_sums<7>(vals, A.part + (long long)blockIdx.y * gridDim.x + blockIdx.x, nwg);
 }
@@ -320,61 +542,71 @@ __global__ void gather_kernel(GatherArgs A) {
   A.X[size_t(A.tgt_d[t]) * A.Vp + A.tgt_v[t]] += s;
 }
 
-// Per-step tallies (one workgroup, fixed summation order): budget of step m and
-// the light leaving through each detector patch, then advance the step counter.
+// Per-step tallies.  Workgroup q sums quantity q over the kernels' per-workgroup
+// partials in a fixed order (q = 0 absorbed, 1 in the box, 2..7 escape through
+// faces 0..5); workgroup 0 also sums the light leaving through each detector
+// patch.  The last workgroup to finish writes the budget of step m, checks it
+// and advances the step counter.  Deterministic: same inputs, same bits.
 __global__ __launch_bounds__(kThreads) void reduce_kernel(ReduceArgs A) {
   __shared__ double red[kThreads];
-  __shared__ double res[8];
-  const int tid = threadIdx.x;
+  __shared__ bool last;
+  const int tid = threadIdx.x, q = blockIdx.x;
   const int m = *A.step_ctr;
-  for (int q = 0; q < 8; ++q) {
-    const double* src;
-    long long n;
-    if (q == 0) {
-      src = A.cpart;               // absorbed
-      n = A.cnwg;
-    } else {
-      src = A.spart + (long long)(q == 1 ? 6 : q - 2) * A.snwg;   // in the box, faces 0..5
-      n = A.snwg;
-    }
-    double s = 0;
-    for (long long i = tid; i < n; i += kThreads) s += src[i];
-    red[tid] = s;
-    __syncthreads();
-    for (int w = kThreads / 2; w > 0; w >>= 1) {
-      if (tid < w) red[tid] += red[tid + w];
-      __syncthreads();
-    }
-    if (tid == 0) res[q] = red[0];
-    __syncthreads();
-  }
   const bool ok = m < A.cap;
-  for (int k = tid; k < A.ndet; k += kThreads) {
-    double s = 0;
-    const int v = A.det_vox[k];
-    for (int p = A.det_first[k]; p < A.det_first[k + 1]; ++p) {
-      const int d = A.det_pairs[2 * p + 1];
-      const DevDir D = A.dirs[d];
-      const float f = A.split ? D.nu * A.r[v] : phase_move(D.nu64, m);
-      s += double(f * A.Y[size_t(d) * A.Vp + v]);
-    }
-    if (ok) A.det_steps[size_t(k) * A.cap + m] = s;
+  const double* src;
+  long long n;
+  if (q == 0) {
+    src = A.cpart;
+    n = A.cnwg;
+  } else {
+    src = A.spart + (long long)(q == 1 ? 6 : q - 2) * A.snwg;
+    n = A.snwg;
   }
-  if (tid == 0) {
-    if (ok) {
-      double* b = A.budget + size_t(m) * 9;
-      b[1] = res[0];
-      b[2] = res[1];
-      for (int f = 0; f < 6; ++f) b[3 + f] = res[2 + f];
-      bool finite = true;
-      for (int q = 0; q < 9; ++q) finite = finite && isfinite(b[q]);
-      if (!finite) atomicOr(A.flag, 1);
-    } else {
-      atomicOr(A.flag, 2);
-    }
-    __threadfence();
-    *A.step_ctr = m + 1;
+  double s = 0;
+  for (long long i = tid; i < n; i += kThreads) s += src[i];
+  red[tid] = s;
+  __syncthreads();
+  for (int w = kThreads / 2; w > 0; w >>= 1) {
+    if (tid < w) red[tid] += red[tid + w];
+    __syncthreads();
   }
+  if (tid == 0) A.scratch[q] = red[0];
+  if (q == 0) {
+    for (int k = tid; k < A.ndet; k += kThreads) {
+      double sd = 0;
+      const int v = A.det_vox[k];
+      for (int p = A.det_first[k]; p < A.det_first[k + 1]; ++p) {
+        const int d = A.det_pairs[2 * p + 1];
+        const DevDir D = A.dirs[d];
+        const float f = A.split ? D.nu * A.r[v] : phase_move(D.nu64, m);
+        sd += double(f * A.Y[size_t(d) * A.Vp + v]);
+      }
+      if (ok) A.det_steps[size_t(k) * A.cap + m] = sd;
+    }
+  }
+  __threadfence();
+  __syncthreads();
+  if (tid == 0) last = atomicAdd(A.done, 1) == int(gridDim.x) - 1;
+  __syncthreads();
+  if (!last || tid != 0) return;
+  __threadfence();
+  double res[8];
+  for (int i = 0; i < 8; ++i)
+    res[i] = __hip_atomic_load(A.scratch + i, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  if (ok) {
+    double* b = A.budget + size_t(m) * 9;
+    b[1] = res[0];
+    b[2] = res[1];
+    for (int f = 0; f < 6; ++f) b[3 + f] = res[2 + f];
+    bool finite = true;
+    for (int i = 0; i < 9; ++i) finite = finite && isfinite(b[i]);
+    if (!finite) atomicOr(A.flag, 1);
+  } else {
+    atomicOr(A.flag, 2);
+  }
+  *A.done = 0;
+  __threadfence();
+  *A.step_ctr = m + 1;
 }
 
 __global__ void energy_kernel(const float* X, long long Vp, int ndir, int V, float* E) {
@@ -412,11 +644,74 @@ hipError_t launch_collide_mt(const CollideArgs& a, const Field& f, int bf16split
     hipLaunchKernelGGL(collide_f32_kernel<MT>, grid, dim3(kThreads), 0, s, a);
   return hipGetLastError();
 }
+
+int resident_blocks() {
+  static int n = 0;
+  if (n == 0) {
+    int dev = 0, cus = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+        cus < 1)
+      cus = 256;
+    n = cus;
+  }
+  return n;
+}
+
+template <int NP>
+hipError_t prepare_res() {
+  const size_t lds = size_t(NP) * (NP + 4) * sizeof(float);
+  return hipFuncSetAttribute(reinterpret_cast<const void*>(&collide_f32_res_kernel<NP>),
+                             hipFuncAttributeMaxDynamicSharedMemorySize, int(lds));
+}
+
+template <int NP>
+hipError_t launch_res(const CollideArgs& a, const Field& f, hipStream_t s) {
+  const size_t lds = size_t(NP) * (NP + 4) * sizeof(float);
+  const int ntiles = int(f.Vp / 256);
+  const int nb = ntiles < resident_blocks() ? ntiles : resident_blocks();
+  hipLaunchKernelGGL(collide_f32_res_kernel<NP>, dim3(unsigned(nb)), dim3(512), lds, s, a, ntiles);
+  return hipGetLastError();
+}
+
+// The resident kernel keeps 32-bit per-lane byte offsets of up to 5 rows.
+bool use_resident(const Field& f, int bf16split) {
+  return !bf16split && f.NP <= 192 && f.Vp * 4 * 5 < (1LL << 31);
+}
+
 }  // namespace
 
-int collide_nwg(const Field& f) { return int(f.Vp / 128) * (f.NP / collide_mt(f.NP)); }
+hipError_t prepare_collide(const Field& f, int bf16split) {
+  if (!use_resident(f, bf16split)) return hipSuccess;
+  switch (f.NP) {
+    case 32: return prepare_res<32>();
+    case 64: return prepare_res<64>();
+    case 96: return prepare_res<96>();
+    case 128: return prepare_res<128>();
+    case 160: return prepare_res<160>();
+    default: return prepare_res<192>();
+  }
+}
+
+int collide_nwg(const Field& f, int bf16split) {
+  if (use_resident(f, bf16split)) {
+    const int ntiles = int(f.Vp / 256);
+    return ntiles < resident_blocks() ? ntiles : resident_blocks();
+  }
+  return int(f.Vp / 128) * (f.NP / collide_mt(f.NP));
+}
 
 hipError_t launch_collide(const CollideArgs& a, const Field& f, int bf16split, int, hipStream_t s) {
+  if (use_resident(f, bf16split)) {
+    switch (f.NP) {
+      case 32: return launch_res<32>(a, f, s);
+      case 64: return launch_res<64>(a, f, s);
+      case 96: return launch_res<96>(a, f, s);
+      case 128: return launch_res<128>(a, f, s);
+      case 160: return launch_res<160>(a, f, s);
+      default: return launch_res<192>(a, f, s);
+    }
+  }
   switch (collide_mt(f.NP)) {
     case 256: return launch_collide_mt<256>(a, f, bf16split, s);
     case 224: return launch_collide_mt<224>(a, f, bf16split, s);
@@ -430,8 +725,14 @@ hipError_t launch_collide(const CollideArgs& a, const Field& f, int bf16split, i
 }
 
 int sweep_blocks_per_dir(const Field& f) {
-  int b = (f.V + kThreads * 16 - 1) / (kThreads * 16);
-  return b < 1 ? 1 : (b > 64 ? 64 : b);
+  // about 64 voxels per thread, at most the number of rows, and no more than
+  // about 4096 workgroups in all (each leaves 7 partial sums)
+  long long b = (f.V + kThreads * 64 - 1) / (kThreads * 64);
+  const long long rows = (long long)f.ny * f.nz;
+  const long long cap = 4096 / f.ndir > 1 ? 4096 / f.ndir : 1;
+  if (b > cap) b = cap;
+  if (b > rows) b = rows;
+  return int(b < 1 ? 1 : b);
 }
 
 hipError_t launch_sweep(const SweepArgs& a, const Field& f, int split, int fresnel, int bpd,
@@ -453,7 +754,7 @@ hipError_t launch_gather(const GatherArgs& a, hipStream_t s) {
 }
 
 hipError_t launch_reduce(const ReduceArgs& a, hipStream_t s) {
-  hipLaunchKernelGGL(reduce_kernel, dim3(1), dim3(kThreads), 0, s, a);
+  hipLaunchKernelGGL(reduce_kernel, dim3(8), dim3(kThreads), 0, s, a);
   return hipGetLastError();
 }
 
