@@ -195,6 +195,93 @@ tr_status tr_profile_begin(tr_medium* m, int max_steps);
  * (launches[TR_K_COUNT]).  TR_ESTATE if timing was not started. */
 tr_status tr_profile_end(tr_medium* m, double* kernel_ms, int* launches);
 
+/* ---- continuous-batching server ----------------------------------------- */
+/*
+ * Serves many forward solves, as a diffuse-optical-tomography reconstruction
+ * issues them (Sec. 1, Sec. 4), on one device at once.  All requests share the
+ * angular set-up (nside, g, normalisation, coefficient form) and run in phase
+ * mode (uniform refractive index per request), FP32; grids, media, sources,
+ * detectors and step counts differ per request.  Requests are admitted in
+ * submission order whenever a slot is free and their device memory fits in
+ * the remaining budget; every server step advances all admitted requests by
+ * one step in batched kernels, so requests that arrive while others run join
+ * the batch as soon as memory frees up.  A request's result is the same bits
+ * whether it runs alone or in a batch.
+ */
+typedef struct tr_server tr_server;   /* opaque, library-owned */
+
+typedef struct {
+  int nside;            /* 1..4 (up to 192 directions) */
+  double g;             /* Henyey-Greenstein anisotropy */
+  int hg_norm;          /* as tr_grid_desc */
+  int coef;             /* as tr_grid_desc */
+  size_t budget_bytes;  /* device memory the server may hold for requests */
+  int max_slots;        /* requests on the device at once, 1..256 */
+} tr_server_desc;
+
+typedef struct {
+  int nx, ny, nz;       /* voxels per axis */
+  double dx_mm;
+  double dt_ps;         /* 0 => dx * n / c0 */
+  const float* mua;     /* host arrays of nx*ny*nz values, copied at submit */
+  const float* mus;
+  const float* n;       /* must be uniform */
+  int src_ix, src_iy, src_w;   /* as tr_set_source */
+  double src_cone_deg, t0_ps, fwhm_ps, total_photons;
+  int ndet;             /* as tr_set_detectors */
+  const int* det_face;
+  const int* det_i;
+  const int* det_j;
+  double det_cone_deg, bin_ps;
+  int nbins;
+  int nsteps;           /* steps the solve runs, >= 1 */
+} tr_request;
+
+enum { TR_REQ_QUEUED = 0, TR_REQ_RUNNING = 1, TR_REQ_DONE = 2, TR_REQ_FAILED = 3,
+       TR_REQ_CANCELLED = 4 };
+
+typedef struct {
+  int status;           /* TR_REQ_* */
+  long long steps_done;
+  double queued_ms;     /* submit to admission (or to now / cancellation) */
+  double run_ms;        /* admission to completion (or to now) */
+  size_t bytes;         /* device memory the request holds while admitted */
+} tr_request_info;
+
+/* Create a server whose work is queued on hip_stream.  TR_EINVAL: bad
+ * descriptor; TR_ENOMEM: device set-up failed. */
+tr_status tr_server_create(const tr_server_desc* desc, void* hip_stream, tr_server** out);
+
+/* Release the server and every request it holds; waits for its queued work. */
+tr_status tr_server_destroy(tr_server* s);
+
+/* Device bytes a request would hold while admitted (validates it). */
+tr_status tr_server_request_bytes(const tr_server* s, const tr_request* req, size_t* bytes);
+
+/* Validate and queue a request (inputs are copied); *id identifies it.
+ * TR_EINVAL: invalid request (bad sizes, non-finite or negative coefficients,
+ * non-uniform n, ...); TR_ENOMEM: the request alone exceeds the budget. */
+tr_status tr_server_submit(tr_server* s, const tr_request* req, long long* id);
+
+/* Retire finished and cancelled requests, admit queued ones while slots and
+ * budget allow, then run up to max_steps server steps (fewer when an admitted
+ * request finishes earlier) and retire what finished.  Synchronises when a
+ * request finishes.  *running / *queued (may be NULL) receive the counts. */
+tr_status tr_server_advance(tr_server* s, int max_steps, int* running, int* queued);
+
+/* State and timing of a request.  TR_EINVAL: unknown id. */
+tr_status tr_server_info(tr_server* s, long long id, tr_request_info* out);
+
+/* Results of a finished request: binned detector signals (ndet*nbins, as
+ * tr_read_detectors) and per-step budget (nsteps*9, as tr_read_budget); either
+ * pointer may be NULL.  TR_ESTATE: not done; TR_ENUMERIC: the request failed
+ * (its budget went non-finite) -- other requests are unaffected. */
+tr_status tr_server_result(tr_server* s, long long id, double* det, size_t n_det, double* budget,
+                           size_t n_budget);
+
+/* Cancel a queued or running request; a running one leaves at the next advance. */
+tr_status tr_server_cancel(tr_server* s, long long id);
+
 /* ---- host set-up tables (no device needed; for checking the set-up) ---- */
 
 /* HEALPix RING centres (Sec. 2.1), out[3*N]. */

@@ -13,119 +13,13 @@
 #include <string>
 #include <vector>
 
+#include "common.hpp"
 #include "device.hpp"
 #include "host_setup.hpp"
 
 using namespace trinity;
 
-namespace {
-thread_local std::string g_err;
-
-tr_status fail(tr_status s, const std::string& msg) {
-  g_err = msg;
-  return s;
-}
-
 constexpr int kGraphSteps = 16;   // steps per captured graph
-constexpr int kMaxDet = 64;
-
-long long round_up(long long x, long long m) { return (x + m - 1) / m * m; }
-
-bool valid_desc(const tr_grid_desc* d, std::string& err) {
-  if (!d) return err = "null descriptor", false;
-  if (d->nx < 1 || d->ny < 1 || d->nz < 1 || d->nx > 4096 || d->ny > 4096 || d->nz > 4096)
-    return err = "grid sizes must be in 1..4096", false;
-  if ((long long)d->nx * d->ny * d->nz > (1LL << 30)) return err = "grid too large", false;
-  if (!(d->dx_mm > 0) || !std::isfinite(d->dx_mm)) return err = "dx_mm must be > 0", false;
-  if (d->nside < 1 || d->nside > 16) return err = "nside must be in 1..16", false;
-  if (!(d->g > -1.0 && d->g < 1.0)) return err = "g must be in (-1, 1)", false;
-  if (!(d->dt_ps >= 0) || !std::isfinite(d->dt_ps)) return err = "dt_ps must be >= 0", false;
-  if (d->hg_norm != 0 && d->hg_norm != 1) return err = "bad hg_norm", false;
-  if (d->coef != 0 && d->coef != 1) return err = "bad coef", false;
-  if (d->advance < 0 || d->advance > 2) return err = "bad advance", false;
-  if (d->precision != 0 && d->precision != 1) return err = "bad precision", false;
-  return true;
-}
-
-Field field_of(const tr_grid_desc* d) {
-  Field f;
-  f.ndir = 12 * d->nside * d->nside;
-  f.NP = int(round_up(f.ndir, 32));
-  f.nx = d->nx;
-  f.ny = d->ny;
-  f.nz = d->nz;
-  f.V = d->nx * d->ny * d->nz;
-  f.Vp = round_up(f.V, 256);
-  return f;
-}
-
-unsigned short f32_to_bf16_bits(float x) {
-  unsigned int u;
-  std::memcpy(&u, &x, 4);
-  u += 0x7FFFu + ((u >> 16) & 1u);
-  return (unsigned short)(u >> 16);
-}
-float bf16_bits_to_f32(unsigned short h) {
-  unsigned int u = unsigned(h) << 16;
-  float x;
-  std::memcpy(&x, &u, 4);
-  return x;
-}
-
-// Rounding P to fp32 leaves each column sum (the light scattered out of one
-// incoming direction) off one by up to a few ulp of its largest entries, with a
-// bias that creates or destroys light at every scattering.  Nudge the smallest
-// entries of each column that can absorb the residual without changing sign:
-// each pass shrinks the residual to half an ulp of a small entry.
-void conserve_columns_f32(std::vector<float>& P, int n, int ld) {
-  std::vector<int> order(n);
-  for (int j = 0; j < n; ++j) {
-    for (int i = 0; i < n; ++i) order[i] = i;
-    std::sort(order.begin(), order.end(), [&](int p, int q) {
-      return P[size_t(p) * ld + j] < P[size_t(q) * ld + j];
-    });
-    for (int pass = 0; pass < 4; ++pass) {
-      double s = 0;
-      for (int i = 0; i < n; ++i) s += double(P[size_t(i) * ld + j]);
-      const double r = 1.0 - s;
-      if (r == 0.0) break;
-      for (int i : order) {
-        float& p = P[size_t(i) * ld + j];
-        if (double(p) > 64.0 * std::fabs(r)) {
-          p = float(double(p) + r);
-          break;
-        }
-      }
-    }
-  }
-}
-
-// The same for the bf16 pair P = P_hi + P_lo: nudge the low parts.
-void conserve_columns_bf16(std::vector<uint16_t>& hi, std::vector<uint16_t>& lo, int n, int ld) {
-  std::vector<int> order(n);
-  auto val = [&](size_t k) { return double(bf16_bits_to_f32(hi[k])) + double(bf16_bits_to_f32(lo[k])); };
-  for (int j = 0; j < n; ++j) {
-    for (int i = 0; i < n; ++i) order[i] = i;
-    std::sort(order.begin(), order.end(), [&](int p, int q) {
-      return val(size_t(p) * ld + j) < val(size_t(q) * ld + j);
-    });
-    for (int pass = 0; pass < 8; ++pass) {
-      double s = 0;
-      for (int i = 0; i < n; ++i) s += val(size_t(i) * ld + j);
-      const double r = 1.0 - s;
-      if (r == 0.0) break;
-      for (int i : order) {
-        const size_t k = size_t(i) * ld + j;
-        if (val(k) > 64.0 * std::fabs(r)) {
-          lo[k] = f32_to_bf16_bits(float(double(bf16_bits_to_f32(lo[k])) + r));
-          break;
-        }
-      }
-    }
-  }
-}
-
-}  // namespace
 
 struct tr_medium {
   tr_grid_desc desc{};
@@ -389,7 +283,7 @@ tr_status check_medium(tr_medium* m) {
 
 extern "C" {
 
-const char* tr_last_error(void) { return g_err.c_str(); }
+const char* tr_last_error(void) { return last_error().c_str(); }
 
 size_t tr_bytes_required(const tr_grid_desc* desc, int ndet, int max_steps) {
   std::string err;
@@ -458,8 +352,8 @@ tr_status tr_create_medium(const tr_grid_desc* desc, const float* mua, const flo
     delete m;
     return fail(TR_EINVAL, "time step moves light more than one plane per step");
   }
-  std::vector<double> P64;
-  if (!phase_matrix(m->dirs, desc->g, desc->hg_norm, P64)) {
+  std::vector<float> P32, PT;
+  if (!build_p32(m->dirs, desc->g, desc->hg_norm, f.NP, P32, PT)) {
     delete m;
     return fail(TR_EINVAL, "phase matrix scaling did not converge");
   }
@@ -500,16 +394,6 @@ tr_status tr_create_medium(const tr_grid_desc* desc, const float* mua, const flo
     return fail(TR_ENOMEM, "device allocation failed");
   }
 
-  // host images of P: fp32 with every column summing to one (see
-  // conserve_columns), stored transposed for the fp32 kernel and split into
-  // bf16 high and low parts for the bf16-split kernel.
-  std::vector<float> P32(size_t(f.NP) * f.NP, 0.0f);
-  for (int i = 0; i < f.ndir; ++i)
-    for (int j = 0; j < f.ndir; ++j) P32[size_t(i) * f.NP + j] = float(P64[size_t(i) * f.ndir + j]);
-  if (desc->hg_norm == TR_HG_SINKHORN) conserve_columns_f32(P32, f.ndir, f.NP);
-  std::vector<float> PT(P32.size(), 0.0f);
-  for (int i = 0; i < f.ndir; ++i)
-    for (int j = 0; j < f.ndir; ++j) PT[size_t(j) * f.NP + i] = P32[size_t(i) * f.NP + j];
   std::vector<float> av(f.Vp, 0.0f), bv(f.Vp, 0.0f), rv(f.Vp, 0.0f);
   for (int v = 0; v < f.V; ++v) {
     av[v] = float(m->co.a[v]);
@@ -841,20 +725,7 @@ tr_status tr_read_detectors(tr_medium* m, double* out, size_t n_out) {
   std::vector<double> raw(size_t(m->ndet) * m->steps_done);
   st = tr_read_detector_steps(m, raw.data(), raw.size());
   if (st != TR_OK) return st;
-  std::fill(out, out + need, 0.0);
-  const double dt = m->dt, bw = m->bin_ps;
-  for (long long s = 0; s < m->steps_done; ++s) {
-    const double t0 = s * dt, t1 = (s + 1) * dt;
-    const long long j0 = std::max(0LL, (long long)std::floor(t0 / bw));
-    const long long j1 = std::min<long long>(m->nbins, (long long)std::ceil(t1 / bw));
-    for (long long j = j0; j < j1; ++j) {
-      const double lo = std::max(t0, j * bw), hi = std::min(t1, (j + 1) * bw);
-      if (hi <= lo) continue;
-      const double wgt = (hi - lo) / dt;
-      for (int k = 0; k < m->ndet; ++k)
-        out[size_t(k) * m->nbins + j] += raw[size_t(k) * m->steps_done + s] * wgt;
-    }
-  }
+  rebin(raw.data(), m->steps_done, m->steps_done, m->ndet, m->dt, m->bin_ps, m->nbins, out);
   return TR_OK;
 }
 

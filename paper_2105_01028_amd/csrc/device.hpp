@@ -103,6 +103,19 @@ struct ReduceArgs {
   int* done;               // workgroups finished (reset by the last one)
 };
 
+// One request of the batched server: its argument blocks as the single-medium
+// kernels take them, plus what the batched kernels need to walk it.
+struct ReqDev {
+  InjectArgs inj;
+  CollideArgs col;     // col.part: [2][ntiles] per-tile absorbed / total
+  SweepArgs swp;       // swp.part: [7][ndir * bpd]
+  ReduceArgs red;
+  int nsteps;          // steps the request runs
+  int ntiles;          // 256-voxel collide tiles
+  int bpd;             // sweep blocks per direction
+  int live;            // 1 while the slot holds a request
+};
+
 // Launchers: queue the kernel on `s`.  Return the launch status.
 hipError_t launch_inject(const InjectArgs& a, hipStream_t s);
 hipError_t launch_collide(const CollideArgs& a, const Field& f, int bf16split, int nwg_cols,
@@ -114,6 +127,13 @@ hipError_t launch_sweep(const SweepArgs& a, const Field& f, int split, int fresn
 int sweep_blocks_per_dir(const Field& f);
 hipError_t launch_gather(const GatherArgs& a, hipStream_t s);
 hipError_t launch_reduce(const ReduceArgs& a, hipStream_t s);
+// Batched server step over `nslots` request slots: work lists citems (slot,
+// tile) and sitems (slot, direction, block, 0), with counts[0] / counts[1]
+// items, all in device memory so a captured graph stays valid as they change.
+hipError_t launch_server_step(const ReqDev* reqs, int nslots, const int* citems,
+                              const int* sitems, const int* counts, const float* Prow, int NP,
+                              hipStream_t s);
+hipError_t prepare_server(int NP);
 hipError_t launch_energy(const float* X, long long Vp, int ndir, int V, float* E, hipStream_t s);
 
 }  // namespace trinity

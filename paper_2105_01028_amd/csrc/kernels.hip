@@ -68,7 +68,7 @@ __device__ inline float bf16_to_float(unsigned short h) { return __uint_as_float
 // ---------------------------------------------------------------------------
 // Injection: the pulse's photons of step m spread over (source direction,
 // source voxel) pairs (Sec. 3.1).  One wavefront.
-__global__ void inject_kernel(InjectArgs A) {
+__device__ __forceinline__ void inject_body(const InjectArgs& A) {
   const int m = *A.step_ctr;
   const double q = m < A.cap ? A.q[m] : 0.0;
   const float share = float(q / double(A.npairs));
@@ -78,6 +78,8 @@ __global__ void inject_kernel(InjectArgs A) {
   }
   if (threadIdx.x == 0 && m < A.cap) A.budget[size_t(m) * 9 + 0] = double(share) * A.npairs;
 }
+
+__global__ void inject_kernel(InjectArgs A) { inject_body(A); }
 
 // ---------------------------------------------------------------------------
 // Collision (Eq. 10 with the explicit source of Eq. 2/12):
@@ -152,99 +154,118 @@ __global__ __launch_bounds__(kThreads, 2) void collide_f32_kernel(CollideArgs A)
 // while the current one feeds the MFMAs; P comes from LDS as [row][k] with a
 // padded pitch, four k per 16-byte read.
 template <int NP>
-__global__ __launch_bounds__(512, 1) void collide_f32_res_kernel(CollideArgs A, int ntiles) {
-  constexpr int NQ = NP / 32;
+__device__ __forceinline__ void load_p_lds(const float* __restrict__ Prow, float* Ps) {
   constexpr int LDK = NP + 4;
-  extern __shared__ float Ps[];
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int hl = lane >> 5, cl = lane & 31;
-  for (int e = tid * 4; e < NP * NP; e += 512 * 4) {
+  for (int e = threadIdx.x * 4; e < NP * NP; e += 512 * 4) {
     const int r = e / NP, k = e - r * NP;
     *reinterpret_cast<float4*>(Ps + r * LDK + k) =
-        *reinterpret_cast<const float4*>(A.Prow + size_t(r) * NP + k);
+        *reinterpret_cast<const float4*>(Prow + size_t(r) * NP + k);
   }
-  __syncthreads();
+}
+
+// One 256-column tile (eight wavefronts of 32 columns); adds this thread's share
+// of the tile's budget sums to absorbed and total.
+template <int NP>
+__device__ __forceinline__ void collide_res_tile(const CollideArgs& A, const float* Ps, int tile,
+                                                 double& absorbed, double& total) {
+  constexpr int NQ = NP / 32;
+  constexpr int LDK = NP + 4;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int hl = lane >> 5, cl = lane & 31;
   const size_t rowbytes = size_t(A.Vp) * sizeof(float);
-  // per-lane byte offset inside a group of rows: column plus the lane half's 4-row shift
-  double absorbed = 0.0, total = 0.0;
   const float* __restrict__ Pl = Ps + cl * LDK + 4 * hl;
+  const long long col = (long long)tile * 256 + wave * 32 + cl;
+  // per-lane byte offset inside a group of rows: column plus the lane half's 4-row shift
+  const unsigned voff = unsigned(size_t(col) * sizeof(float) + size_t(4 * hl) * rowbytes);
+  const char* __restrict__ xb0 = reinterpret_cast<const char*>(A.X);
+  const float av = A.a[col], bv = A.b[col];
+  floatx16 acc[NQ];
+#pragma unroll
+  for (int q = 0; q < NQ; ++q)
+#pragma unroll
+    for (int r = 0; r < 16; ++r) acc[q][r] = 0.0f;
+  // row of step s in chunk c for lane half h: 32c + 8(s/4) + 4h + s%4; the 4h part is in voff
+  auto ld = [&](int c, int s) {
+    const char* rb = xb0 + size_t(32 * c + 8 * (s >> 2) + (s & 3)) * rowbytes;
+    return *reinterpret_cast<const float*>(rb + voff);
+  };
+  float bcur[16], bnext[16];
+#pragma unroll
+  for (int s = 0; s < 16; ++s) bcur[s] = ld(0, s);
+  double colsum64 = 0.0;
 #pragma unroll 1
-  for (int tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
-    const long long col = (long long)tile * 256 + wave * 32 + cl;
-    const unsigned voff = unsigned(size_t(col) * sizeof(float) + size_t(4 * hl) * rowbytes);
-    const char* __restrict__ xb0 = reinterpret_cast<const char*>(A.X);
-    const float av = A.a[col], bv = A.b[col];
-    floatx16 acc[NQ];
+  for (int c = 0; c < NQ; ++c) {
+    const int cn = c + 1 < NQ ? c + 1 : c;   // last chunk reloads itself (in bounds, unused)
+#pragma unroll
+    for (int s = 0; s < 16; ++s) bnext[s] = ld(cn, s);
+    float colsum = 0.0f;
+#pragma unroll
+    for (int s = 0; s < 16; ++s) colsum += bcur[s];
+    colsum64 += double(colsum);
+    // a_v X for the rows of accumulator block c (uniform branch)
 #pragma unroll
     for (int q = 0; q < NQ; ++q)
+      if (q == c) {
 #pragma unroll
-      for (int r = 0; r < 16; ++r) acc[q][r] = 0.0f;
-    // row of step s in chunk c for lane half h: 32c + 8(s/4) + 4h + s%4; the 4h part is in voff
-    auto ld = [&](int c, int s) {
-      const char* rb = xb0 + size_t(32 * c + 8 * (s >> 2) + (s & 3)) * rowbytes;
-      return *reinterpret_cast<const float*>(rb + voff);
-    };
-    float bcur[16], bnext[16];
-#pragma unroll
-    for (int s = 0; s < 16; ++s) bcur[s] = ld(0, s);
-    double colsum64 = 0.0;
-#pragma unroll 1
-    for (int c = 0; c < NQ; ++c) {
-      const int cn = c + 1 < NQ ? c + 1 : c;   // last chunk reloads itself (in bounds, unused)
-#pragma unroll
-      for (int s = 0; s < 16; ++s) bnext[s] = ld(cn, s);
-      float colsum = 0.0f;
-#pragma unroll
-      for (int s = 0; s < 16; ++s) colsum += bcur[s];
-      colsum64 += double(colsum);
-      // a_v X for the rows of accumulator block c (uniform branch)
-#pragma unroll
-      for (int q = 0; q < NQ; ++q)
-        if (q == c) {
-#pragma unroll
-          for (int s = 0; s < 16; ++s) acc[q][s] = fmaf(av, bcur[s], acc[q][s]);
-        }
-#pragma unroll
-      for (int s = 0; s < 16; ++s) bcur[s] *= bv;
-#pragma unroll
-      for (int s4 = 0; s4 < 16; s4 += 4) {
-        // k of step s (s = s4..s4+3): 32c + 8(s/4) + 4h + s%4 -> four consecutive k per half
-        const int kk = 32 * c + 8 * (s4 >> 2);
-#pragma unroll
-        for (int q = 0; q < NQ; ++q) {
-          const float4 a4 = *reinterpret_cast<const float4*>(Pl + q * 32 * LDK + kk);
-          acc[q] = __builtin_amdgcn_mfma_f32_32x32x2f32(a4.x, bcur[s4 + 0], acc[q], 0, 0, 0);
-          acc[q] = __builtin_amdgcn_mfma_f32_32x32x2f32(a4.y, bcur[s4 + 1], acc[q], 0, 0, 0);
-          acc[q] = __builtin_amdgcn_mfma_f32_32x32x2f32(a4.z, bcur[s4 + 2], acc[q], 0, 0, 0);
-          acc[q] = __builtin_amdgcn_mfma_f32_32x32x2f32(a4.w, bcur[s4 + 3], acc[q], 0, 0, 0);
-        }
+        for (int s = 0; s < 16; ++s) acc[q][s] = fmaf(av, bcur[s], acc[q][s]);
       }
 #pragma unroll
-      for (int s = 0; s < 16; ++s) bcur[s] = bnext[s];
+    for (int s = 0; s < 16; ++s) bcur[s] *= bv;
+#pragma unroll
+    for (int s4 = 0; s4 < 16; s4 += 4) {
+      // k of step s (s = s4..s4+3): 32c + 8(s/4) + 4h + s%4 -> four consecutive k per half
+      const int kk = 32 * c + 8 * (s4 >> 2);
+#pragma unroll
+      for (int q = 0; q < NQ; ++q) {
+        const float4 a4 = *reinterpret_cast<const float4*>(Pl + q * 32 * LDK + kk);
+        acc[q] = __builtin_amdgcn_mfma_f32_32x32x2f32(a4.x, bcur[s4 + 0], acc[q], 0, 0, 0);
+        acc[q] = __builtin_amdgcn_mfma_f32_32x32x2f32(a4.y, bcur[s4 + 1], acc[q], 0, 0, 0);
+        acc[q] = __builtin_amdgcn_mfma_f32_32x32x2f32(a4.z, bcur[s4 + 2], acc[q], 0, 0, 0);
+        acc[q] = __builtin_amdgcn_mfma_f32_32x32x2f32(a4.w, bcur[s4 + 3], acc[q], 0, 0, 0);
+      }
     }
-    char* __restrict__ yb0 = reinterpret_cast<char*>(A.Y);
 #pragma unroll
-    for (int q = 0; q < NQ; ++q)
-#pragma unroll
-      for (int r = 0; r < 16; ++r)
-        *reinterpret_cast<float*>(yb0 + size_t(q * 32 + 8 * (r >> 2) + (r & 3)) * rowbytes + voff) =
-            acc[q][r];
-    absorbed += (1.0 - double(av) - double(bv)) * colsum64;
-    total += colsum64;
+    for (int s = 0; s < 16; ++s) bcur[s] = bnext[s];
   }
-  __syncthreads();
+  char* __restrict__ yb0 = reinterpret_cast<char*>(A.Y);
+#pragma unroll
+  for (int q = 0; q < NQ; ++q)
+#pragma unroll
+    for (int r = 0; r < 16; ++r)
+      *reinterpret_cast<float*>(yb0 + size_t(q * 32 + 8 * (r >> 2) + (r & 3)) * rowbytes + voff) =
+          acc[q][r];
+  absorbed += (1.0 - double(av) - double(bv)) * colsum64;
+  total += colsum64;
+}
+
+// Sums of two doubles over a 512-thread workgroup, written by thread 0 and 1.
+__device__ __forceinline__ void block_sums512(double a, double t, double* out_a, double* out_t) {
   __shared__ double red2[2][8];
-  double sa = wave_sum(absorbed), st = wave_sum(total);
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const double sa = wave_sum(a), st = wave_sum(t);
+  __syncthreads();
   if (lane == 0) {
     red2[0][wave] = sa;
     red2[1][wave] = st;
   }
   __syncthreads();
-  if (tid < 2) {
-    double t = 0;
-    for (int w = 0; w < 8; ++w) t += red2[tid][w];
-    A.part[(long long)tid * gridDim.x + blockIdx.x] = t;
+  if (threadIdx.x < 2) {
+    double s = 0;
+    for (int w = 0; w < 8; ++w) s += red2[threadIdx.x][w];
+    *(threadIdx.x == 0 ? out_a : out_t) = s;
   }
+}
+
+template <int NP>
+__global__ __launch_bounds__(512, 1) void collide_f32_res_kernel(CollideArgs A, int ntiles) {
+  extern __shared__ float Ps[];
+  load_p_lds<NP>(A.Prow, Ps);
+  __syncthreads();
+  double absorbed = 0.0, total = 0.0;
+#pragma unroll 1
+  for (int tile = blockIdx.x; tile < ntiles; tile += gridDim.x)
+    collide_res_tile<NP>(A, Ps, tile, absorbed, total);
+  block_sums512(absorbed, total, A.part + blockIdx.x, A.part + gridDim.x + blockIdx.x);
 }
 
 // Same contraction with P and X each split into bf16 high and low parts,
@@ -467,16 +488,17 @@ __device__ __forceinline__ void sweep_rows(const SweepArgs& A, const DevDir& D, 
 
 }  // namespace
 
+// Block blk of nblk row slabs of direction d; writes the block's 7 partial sums
+// (escape per face, light in the box) to A.part[q * ndir * nblk + d * nblk + blk].
 template <bool SPLIT, bool FRESNEL>
-__global__ __launch_bounds__(kThreads) void sweep_kernel(SweepArgs A) {
-  __shared__ int8_t sdelta[2][kMaxExt + 2];
-  const int d = blockIdx.y;
+__device__ __forceinline__ void sweep_block(const SweepArgs& A, int d, int blk, int nblk,
+                                            int8_t (&sdelta)[2][kMaxExt + 2]) {
   const DevDir D = A.dirs[d];
   const int m = *A.step_ctr;
   const float fph = SPLIT ? 1.0f : phase_move(D.nu64, m);
   const int R = A.ny * A.nz;
-  const int rb = int((long long)R * blockIdx.x / gridDim.x);
-  const int re = int((long long)R * (blockIdx.x + 1) / gridDim.x);
+  const int rb = int((long long)R * blk / nblk);
+  const int re = int((long long)R * (blk + 1) / nblk);
   SweepAcc acc;
   if (fph == 0.0f) {
     // phase mode, this direction does not move at step m: the field passes through
@@ -524,8 +546,14 @@ __global__ __launch_bounds__(kThreads) void sweep_kernel(SweepArgs A) {
     face[f] = s;
   }
   const double vals[7] = {face[0], face[1], face[2], face[3], face[4], face[5], acc.dom};
-  const long long nwg = (long long)gridDim.x * gridDim.y;
-  block_sums<7>(vals, A.part + (long long)blockIdx.y * gridDim.x + blockIdx.x, nwg);
+  block_sums<7>(vals, A.part + (long long)d * nblk + blk, (long long)A.ndir * nblk);
+  __syncthreads();   // LDS (shift tables, partial sums) is reused by the next block of work
+}
+
+template <bool SPLIT, bool FRESNEL>
+__global__ __launch_bounds__(kThreads) void sweep_kernel(SweepArgs A) {
+  __shared__ int8_t sdelta[2][kMaxExt + 2];
+  sweep_block<SPLIT, FRESNEL>(A, blockIdx.y, blockIdx.x, gridDim.x, sdelta);
 }
 
 // Fresnel redistribution (Eq. 13-14): every target (direction, voxel) adds the
@@ -547,10 +575,10 @@ __global__ void gather_kernel(GatherArgs A) {
 // faces 0..5); workgroup 0 also sums the light leaving through each detector
 // patch.  The last workgroup to finish writes the budget of step m, checks it
 // and advances the step counter.  Deterministic: same inputs, same bits.
-__global__ __launch_bounds__(kThreads) void reduce_kernel(ReduceArgs A) {
+__device__ __forceinline__ void reduce_part(const ReduceArgs& A, int q, int nq) {
   __shared__ double red[kThreads];
   __shared__ bool last;
-  const int tid = threadIdx.x, q = blockIdx.x;
+  const int tid = threadIdx.x;
   const int m = *A.step_ctr;
   const bool ok = m < A.cap;
   const double* src;
@@ -586,7 +614,7 @@ __global__ __launch_bounds__(kThreads) void reduce_kernel(ReduceArgs A) {
   }
   __threadfence();
   __syncthreads();
-  if (tid == 0) last = atomicAdd(A.done, 1) == int(gridDim.x) - 1;
+  if (tid == 0) last = atomicAdd(A.done, 1) == nq - 1;
   __syncthreads();
   if (!last || tid != 0) return;
   __threadfence();
@@ -607,6 +635,69 @@ __global__ __launch_bounds__(kThreads) void reduce_kernel(ReduceArgs A) {
   *A.done = 0;
   __threadfence();
   *A.step_ctr = m + 1;
+}
+
+__global__ __launch_bounds__(kThreads) void reduce_kernel(ReduceArgs A) {
+  reduce_part(A, blockIdx.x, gridDim.x);
+}
+
+// ---------------------------------------------------------------------------
+// Batched server kernels.  Each walks a device-resident work list over all
+// live request slots and runs the same per-tile / per-block device code as the
+// single-medium kernels, so a request's result does not depend on what else
+// is in the batch.  Slots whose request has no steps left are skipped.
+
+__device__ __forceinline__ bool req_running(const ReqDev& r) {
+  return r.live && *r.swp.step_ctr < r.nsteps;
+}
+
+__global__ void srv_inject_kernel(const ReqDev* R) {
+  const ReqDev& r = R[blockIdx.x];
+  if (!req_running(r) || r.inj.npairs == 0) return;
+  const InjectArgs A = r.inj;
+  inject_body(A);
+}
+
+template <int NP>
+__global__ __launch_bounds__(512, 1) void srv_collide_kernel(const ReqDev* R, const int2* items,
+                                                             const int* counts,
+                                                             const float* Prow) {
+  extern __shared__ float Ps[];
+  load_p_lds<NP>(Prow, Ps);
+  __syncthreads();
+  const int n = counts[0];
+  for (int it = blockIdx.x; it < n; it += gridDim.x) {
+    const int slot = __builtin_amdgcn_readfirstlane(items[it].x);
+    const int tile = __builtin_amdgcn_readfirstlane(items[it].y);
+    const ReqDev& r = R[slot];
+    if (!req_running(r)) continue;
+    const CollideArgs A = r.col;
+    double ab = 0.0, tot = 0.0;
+    collide_res_tile<NP>(A, Ps, tile, ab, tot);
+    block_sums512(ab, tot, A.part + tile, A.part + r.ntiles + tile);
+  }
+}
+
+__global__ __launch_bounds__(kThreads) void srv_sweep_kernel(const ReqDev* R, const int4* items,
+                                                             const int* counts) {
+  __shared__ int8_t sdelta[2][kMaxExt + 2];
+  const int n = counts[1];
+  for (int it = blockIdx.x; it < n; it += gridDim.x) {
+    const int slot = __builtin_amdgcn_readfirstlane(items[it].x);
+    const int d = __builtin_amdgcn_readfirstlane(items[it].y);
+    const int blk = __builtin_amdgcn_readfirstlane(items[it].z);
+    const ReqDev& r = R[slot];
+    if (!req_running(r)) continue;
+    const SweepArgs A = r.swp;
+    sweep_block<false, false>(A, d, blk, r.bpd, sdelta);
+  }
+}
+
+__global__ __launch_bounds__(kThreads) void srv_reduce_kernel(const ReqDev* R) {
+  const ReqDev& r = R[blockIdx.y];
+  if (!req_running(r)) return;
+  const ReduceArgs A = r.red;
+  reduce_part(A, blockIdx.x, 8);
 }
 
 __global__ void energy_kernel(const float* X, long long Vp, int ndir, int V, float* E) {
@@ -755,6 +846,59 @@ hipError_t launch_gather(const GatherArgs& a, hipStream_t s) {
 
 hipError_t launch_reduce(const ReduceArgs& a, hipStream_t s) {
   hipLaunchKernelGGL(reduce_kernel, dim3(8), dim3(kThreads), 0, s, a);
+  return hipGetLastError();
+}
+
+namespace {
+template <int NP>
+hipError_t prepare_srv() {
+  const size_t lds = size_t(NP) * (NP + 4) * sizeof(float);
+  return hipFuncSetAttribute(reinterpret_cast<const void*>(&srv_collide_kernel<NP>),
+                             hipFuncAttributeMaxDynamicSharedMemorySize, int(lds));
+}
+
+template <int NP>
+hipError_t launch_srv_collide(const ReqDev* reqs, const int* citems, const int* counts,
+                              const float* Prow, hipStream_t s) {
+  const size_t lds = size_t(NP) * (NP + 4) * sizeof(float);
+  hipLaunchKernelGGL(srv_collide_kernel<NP>, dim3(unsigned(resident_blocks())), dim3(512), lds, s,
+                     reqs, reinterpret_cast<const int2*>(citems), counts, Prow);
+  return hipGetLastError();
+}
+}  // namespace
+
+hipError_t prepare_server(int NP) {
+  switch (NP) {
+    case 32: return prepare_srv<32>();
+    case 64: return prepare_srv<64>();
+    case 96: return prepare_srv<96>();
+    case 128: return prepare_srv<128>();
+    case 160: return prepare_srv<160>();
+    case 192: return prepare_srv<192>();
+    default: return hipErrorInvalidValue;
+  }
+}
+
+hipError_t launch_server_step(const ReqDev* reqs, int nslots, const int* citems,
+                              const int* sitems, const int* counts, const float* Prow, int NP,
+                              hipStream_t s) {
+  hipLaunchKernelGGL(srv_inject_kernel, dim3(unsigned(nslots)), dim3(64), 0, s, reqs);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  switch (NP) {
+    case 32: e = launch_srv_collide<32>(reqs, citems, counts, Prow, s); break;
+    case 64: e = launch_srv_collide<64>(reqs, citems, counts, Prow, s); break;
+    case 96: e = launch_srv_collide<96>(reqs, citems, counts, Prow, s); break;
+    case 128: e = launch_srv_collide<128>(reqs, citems, counts, Prow, s); break;
+    case 160: e = launch_srv_collide<160>(reqs, citems, counts, Prow, s); break;
+    case 192: e = launch_srv_collide<192>(reqs, citems, counts, Prow, s); break;
+    default: return hipErrorInvalidValue;
+  }
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(srv_sweep_kernel, dim3(unsigned(4 * resident_blocks())), dim3(kThreads), 0, s,
+                     reqs, reinterpret_cast<const int4*>(sitems), counts);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  hipLaunchKernelGGL(srv_reduce_kernel, dim3(8, unsigned(nslots)), dim3(kThreads), 0, s, reqs);
   return hipGetLastError();
 }
 

@@ -46,6 +46,33 @@ class Info(ctypes.Structure):
                 ("steps_done", ctypes.c_longlong), ("device_bytes", ctypes.c_size_t)]
 
 
+class ServerDesc(ctypes.Structure):
+    _fields_ = [("nside", ctypes.c_int), ("g", ctypes.c_double), ("hg_norm", ctypes.c_int),
+                ("coef", ctypes.c_int), ("budget_bytes", ctypes.c_size_t),
+                ("max_slots", ctypes.c_int)]
+
+
+class Request(ctypes.Structure):
+    _fields_ = [("nx", ctypes.c_int), ("ny", ctypes.c_int), ("nz", ctypes.c_int),
+                ("dx_mm", ctypes.c_double), ("dt_ps", ctypes.c_double),
+                ("mua", ctypes.c_void_p), ("mus", ctypes.c_void_p), ("n", ctypes.c_void_p),
+                ("src_ix", ctypes.c_int), ("src_iy", ctypes.c_int), ("src_w", ctypes.c_int),
+                ("src_cone_deg", ctypes.c_double), ("t0_ps", ctypes.c_double),
+                ("fwhm_ps", ctypes.c_double), ("total_photons", ctypes.c_double),
+                ("ndet", ctypes.c_int), ("det_face", ctypes.c_void_p),
+                ("det_i", ctypes.c_void_p), ("det_j", ctypes.c_void_p),
+                ("det_cone_deg", ctypes.c_double), ("bin_ps", ctypes.c_double),
+                ("nbins", ctypes.c_int), ("nsteps", ctypes.c_int)]
+
+
+class RequestInfo(ctypes.Structure):
+    _fields_ = [("status", ctypes.c_int), ("steps_done", ctypes.c_longlong),
+                ("queued_ms", ctypes.c_double), ("run_ms", ctypes.c_double),
+                ("bytes", ctypes.c_size_t)]
+
+
+REQ_QUEUED, REQ_RUNNING, REQ_DONE, REQ_FAILED, REQ_CANCELLED = 0, 1, 2, 3, 4
+
 _P = ctypes.c_void_p
 _I = ctypes.c_int
 _D = ctypes.c_double
@@ -71,6 +98,14 @@ _SIGS = {
     "tr_get_info": [_P, ctypes.POINTER(Info)],
     "tr_profile_begin": [_P, _I],
     "tr_profile_end": [_P, _PD, _PI],
+    "tr_server_create": [ctypes.POINTER(ServerDesc), _P, ctypes.POINTER(_P)],
+    "tr_server_destroy": [_P],
+    "tr_server_request_bytes": [_P, ctypes.POINTER(Request), ctypes.POINTER(ctypes.c_size_t)],
+    "tr_server_submit": [_P, ctypes.POINTER(Request), ctypes.POINTER(ctypes.c_longlong)],
+    "tr_server_advance": [_P, _I, _PI, _PI],
+    "tr_server_info": [_P, ctypes.c_longlong, ctypes.POINTER(RequestInfo)],
+    "tr_server_result": [_P, ctypes.c_longlong, _PD, ctypes.c_size_t, _PD, ctypes.c_size_t],
+    "tr_server_cancel": [_P, ctypes.c_longlong],
     "tr_host_directions": [_I, _PD],
     "tr_host_phase_matrix": [_I, _D, _I, _PD],
     "tr_host_lattice": [_I, _I, _I, _I, _PI, _PI, _PI],
@@ -291,6 +326,80 @@ class Medium:
         else:
             s = np.ascontiguousarray(state, dtype=np.float32)
             _check(lib().tr_set_state(self._h, s.ctypes.data, 0))
+
+
+class Server:
+    """Continuous-batching server of forward solves (tr_server_* of the C-ABI)."""
+
+    def __init__(self, nside=4, g=0.85, budget_bytes=8 << 30, max_slots=16, hg_norm="sinkhorn",
+                 coef="paper", stream: Optional[int] = None):
+        self._h = _P()
+        self.stream = current_stream() if stream is None else int(stream)
+        d = ServerDesc(int(nside), float(g), HG[hg_norm], COEF[coef], int(budget_bytes),
+                       int(max_slots))
+        _check(lib().tr_server_create(ctypes.byref(d), self.stream, ctypes.byref(self._h)))
+        self._shape = {}
+
+    @staticmethod
+    def _request(prob):
+        keep = [np.ascontiguousarray(a, dtype=np.float32).ravel() for a in (prob.mua, prob.mus,
+                                                                            prob.n)]
+        dets = [np.ascontiguousarray(a, dtype=np.int32) for a in (prob.det_face, prob.det_i,
+                                                                  prob.det_j)]
+        r = Request(prob.nx, prob.ny, prob.nz, float(prob.dx_mm), float(prob.dt_ps),
+                    keep[0].ctypes.data, keep[1].ctypes.data, keep[2].ctypes.data,
+                    int(prob.src_ix), int(prob.src_iy), int(prob.src_w), float(prob.src_cone_deg),
+                    float(prob.t0_ps), float(prob.fwhm_ps), float(prob.total_photons),
+                    len(dets[0]), dets[0].ctypes.data, dets[1].ctypes.data, dets[2].ctypes.data,
+                    float(prob.det_cone_deg), float(prob.bin_ps), int(prob.nbins),
+                    int(prob.steps))
+        return r, keep + dets
+
+    def request_bytes(self, prob) -> int:
+        r, keep = self._request(prob)
+        out = ctypes.c_size_t()
+        _check(lib().tr_server_request_bytes(self._h, ctypes.byref(r), ctypes.byref(out)))
+        return int(out.value)
+
+    def submit(self, prob) -> int:
+        r, keep = self._request(prob)
+        rid = ctypes.c_longlong()
+        _check(lib().tr_server_submit(self._h, ctypes.byref(r), ctypes.byref(rid)))
+        self._shape[rid.value] = (len(prob.det_face), int(prob.nbins), int(prob.steps))
+        return int(rid.value)
+
+    def advance(self, max_steps=64):
+        running, queued = ctypes.c_int(), ctypes.c_int()
+        _check(lib().tr_server_advance(self._h, int(max_steps), ctypes.byref(running),
+                                       ctypes.byref(queued)))
+        return running.value, queued.value
+
+    def info(self, rid) -> RequestInfo:
+        out = RequestInfo()
+        _check(lib().tr_server_info(self._h, int(rid), ctypes.byref(out)))
+        return out
+
+    def result(self, rid):
+        ndet, nbins, steps = self._shape[rid]
+        det = np.zeros(ndet * nbins)
+        bud = np.zeros(9 * steps)
+        _check(lib().tr_server_result(self._h, int(rid), _dptr(det), det.size, _dptr(bud),
+                                      bud.size))
+        return det.reshape(ndet, nbins), bud.reshape(steps, 9)
+
+    def cancel(self, rid):
+        _check(lib().tr_server_cancel(self._h, int(rid)))
+
+    def close(self):
+        if self._h:
+            _check(lib().tr_server_destroy(self._h))
+            self._h = _P()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 def create_medium(prob, stream=None) -> Medium:
