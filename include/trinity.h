@@ -179,6 +179,25 @@ tr_status tr_set_state(tr_medium* m, const float* in, int on_device);
 
 tr_status tr_get_info(tr_medium* m, tr_info* out);
 
+/* ---- gradients (adjoint) ------------------------------------------------- */
+
+/* Reset the medium, then solve nsteps steps from step 0 keeping a copy of the
+ * field every ckpt_every steps (memory: ceil(nsteps/ckpt_every) fields) for
+ * tr_backward.  Synchronises.  TR_EINVAL: nsteps or ckpt_every < 1. */
+tr_status tr_solve_checkpointed(tr_medium* m, int nsteps, int ckpt_every);
+
+/* Gradient of a loss of the binned detector signals with respect to the
+ * per-voxel mu_a and mu_s, by the exact adjoint of the steps run by
+ * tr_solve_checkpointed: the transposed sweep, detector read-out and collision
+ * run backwards through time, segment by segment, each segment's fields
+ * recomputed from its checkpoint.  dL_dbins[k*nbins + j] = dL/d(binned signal
+ * of detector k in bin j) (host, FP64).  dmua, dmus: nvox floats each (host).
+ * The medium's field, step counter and records are as before the call.
+ * Supported for phase advance, FP32, up to 192 directions.  TR_ESTATE: no
+ * checkpointed solve to differentiate; TR_EINVAL: unsupported configuration;
+ * TR_ENOMEM: no room for ckpt_every recomputed fields. */
+tr_status tr_backward(tr_medium* m, const double* dL_dbins, float* dmua, float* dmus);
+
 /* ---- kernel timing ------------------------------------------------------ */
 
 /* Kernel kinds reported by tr_profile_end. */

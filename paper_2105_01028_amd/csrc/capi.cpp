@@ -86,6 +86,12 @@ struct tr_medium {
 
   hipGraphExec_t graph = nullptr;
 
+  // checkpoints of tr_solve_checkpointed (one allocation of nckpt fields)
+  float* ckpt = nullptr;
+  int nckpt = 0, ckpt_every = 0;
+  long long ckpt_steps = 0;
+  std::vector<float> mua_host, mus_host;
+
   // kernel timing (tr_profile_begin / tr_profile_end)
   bool profiling = false;
   int prof_cap = 0, prof_used = 0;
@@ -331,6 +337,8 @@ tr_status tr_create_medium(const tr_grid_desc* desc, const float* mua, const flo
   }
   pn = m->nhost.data();
 
+  m->mua_host.assign(pa, pa + f.V);
+  m->mus_host.assign(ps, ps + f.V);
   if (!build_coefficients(f.V, pa, ps, pn, desc->dx_mm, desc->dt_ps, desc->coef, m->co, err)) {
     delete m;
     return fail(TR_EINVAL, err);
@@ -771,6 +779,157 @@ tr_status tr_set_state(tr_medium* m, const float* in, int on_device) {
   hipError_t e = hipMemcpy2D(m->X, m->f.Vp * 4, in, m->f.V * 4, m->f.V * 4, m->f.ndir,
                              on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice);
   if (e != hipSuccess) return device_fail(m, e, "state write");
+  return TR_OK;
+}
+
+tr_status tr_solve_checkpointed(tr_medium* m, int nsteps, int ckpt_every) {
+  tr_status st = check_medium(m);
+  if (st != TR_OK) return st;
+  if (nsteps < 1 || ckpt_every < 1) return fail(TR_EINVAL, "nsteps and ckpt_every must be >= 1");
+  if ((st = tr_reset(m)) != TR_OK) return st;
+  const Field& f = m->f;
+  const size_t NV = size_t(f.NP) * f.Vp;
+  const int nseg = (nsteps + ckpt_every - 1) / ckpt_every;
+  m->release(m->ckpt);
+  m->ckpt = m->alloc<float>(NV * nseg);
+  m->nckpt = 0;
+  m->ckpt_steps = 0;
+  if (!m->ckpt) return fail(TR_ENOMEM, "no device memory for the checkpoints");
+  for (int seg = 0; seg < nseg; ++seg) {
+    hipError_t e = hipMemcpyAsync(m->ckpt + NV * seg, m->X, NV * 4, hipMemcpyDeviceToDevice, m->stream);
+    if (e != hipSuccess) return device_fail(m, e, "checkpoint");
+    if ((st = tr_step(m, std::min(ckpt_every, nsteps - seg * ckpt_every))) != TR_OK) return st;
+  }
+  m->nckpt = nseg;
+  m->ckpt_every = ckpt_every;
+  m->ckpt_steps = nsteps;
+  return tr_synchronize(m);
+}
+
+tr_status tr_backward(tr_medium* m, const double* dL_dbins, float* dmua, float* dmus) {
+  tr_status st = check_medium(m);
+  if (st != TR_OK) return st;
+  if (!dL_dbins || !dmua || !dmus) return fail(TR_EINVAL, "null argument");
+  if (m->nckpt == 0 || m->ckpt_steps != m->steps_done)
+    return fail(TR_ESTATE, "no checkpointed solve of the current steps to differentiate");
+  if (m->mode != TR_ADVANCE_PHASE || m->desc.precision != TR_PREC_FP32 || m->f.NP > 192 ||
+      m->f.Vp * 4 * 5 >= (1LL << 31))
+    return fail(TR_EINVAL, "the adjoint supports phase advance, fp32 and up to 192 directions");
+  const Field& f = m->f;
+  const size_t NV = size_t(f.NP) * f.Vp;
+  const long long steps = m->steps_done;
+  const int K = m->ckpt_every;
+  // seeds dL/d det[k][s]: transpose of the rebinning
+  std::vector<double> seed(size_t(m->ndet) * steps, 0.0);
+  for (long long s = 0; s < steps; ++s) {
+    const double t0 = s * m->dt, t1 = (s + 1) * m->dt;
+    const long long j0 = std::max(0LL, (long long)std::floor(t0 / m->bin_ps));
+    const long long j1 = std::min<long long>(m->nbins, (long long)std::ceil(t1 / m->bin_ps));
+    for (long long j = j0; j < j1; ++j) {
+      const double lo = std::max(t0, j * m->bin_ps), hi = std::min(t1, (j + 1) * m->bin_ps);
+      if (hi <= lo) continue;
+      const double wgt = (hi - lo) / m->dt;
+      for (int k = 0; k < m->ndet; ++k)
+        seed[size_t(k) * steps + s] += dL_dbins[size_t(k) * m->nbins + j] * wgt;
+    }
+  }
+  hipError_t e = prepare_adjoint(f.NP);
+  if (e != hipSuccess) return device_fail(m, e, "adjoint set-up");
+  float* lam = m->alloc<float>(NV);
+  float* mu = m->alloc<float>(NV);
+  float* seg = m->alloc<float>(NV * size_t(K));
+  float* keep = m->alloc<float>(NV);
+  double* ga = m->alloc<double>(f.Vp);
+  double* gb = m->alloc<double>(f.Vp);
+  double* sd = m->alloc<double>(seed.size());
+  auto cleanup = [&]() {
+    for (void* p : {(void*)lam, (void*)mu, (void*)seg, (void*)keep, (void*)ga, (void*)gb, (void*)sd})
+      m->release(p);
+  };
+  if (!lam || !mu || !seg || !keep || !ga || !gb || !sd) {
+    cleanup();
+    return fail(TR_ENOMEM, "no device memory for the adjoint");
+  }
+  e = hipMemcpyAsync(keep, m->X, NV * 4, hipMemcpyDeviceToDevice, m->stream);
+  if (e == hipSuccess) e = hipMemsetAsync(lam, 0, NV * 4, m->stream);
+  if (e == hipSuccess) e = hipMemsetAsync(mu, 0, NV * 4, m->stream);
+  if (e == hipSuccess) e = hipMemsetAsync(seg, 0, NV * 4 * size_t(K), m->stream);
+  if (e == hipSuccess) e = hipMemsetAsync(ga, 0, f.Vp * 8, m->stream);
+  if (e == hipSuccess) e = hipMemsetAsync(gb, 0, f.Vp * 8, m->stream);
+  if (e == hipSuccess) e = hipMemcpy(sd, seed.data(), seed.size() * 8, hipMemcpyHostToDevice);
+  AdjArgs A{lam, mu, lam, nullptr, m->P, m->a, m->b, ga, gb, f.Vp, f.V, f.nx, f.ny, f.nz, f.ndir,
+            f.NP, m->ddirs, m->delta, m->dstride, nullptr, 0, m->det_vox_dev, sd, int(steps)};
+  // detector pairs of the medium (host copy rebuilt from the device lists)
+  std::vector<int> first(m->ndet + 1);
+  if (e == hipSuccess) e = hipMemcpy(first.data(), m->det_first, first.size() * 4, hipMemcpyDeviceToHost);
+  A.det_pairs = m->det_pairs;
+  A.ndet_pairs = first[m->ndet];
+  const bool split = false;
+  for (int sgi = m->nckpt - 1; sgi >= 0 && e == hipSuccess; --sgi) {
+    const int m0 = sgi * K;
+    const int cnt = int(std::min<long long>(K, steps - m0));
+    // recompute the segment's pre-collision fields from its checkpoint
+    e = hipMemcpyAsync(m->X, m->ckpt + NV * sgi, NV * 4, hipMemcpyDeviceToDevice, m->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(m->stream);
+    if (e == hipSuccess) e = hipMemcpy(m->step_ctr, &m0, 4, hipMemcpyHostToDevice);
+    for (int i = 0; i < cnt && e == hipSuccess; ++i) {
+      if (m->npairs > 0) {
+        InjectArgs ia{m->X, f.Vp, m->src_pairs, m->npairs, m->qdev, m->cap, m->step_ctr, m->budget};
+        e = launch_inject(ia, m->stream);
+      }
+      if (e == hipSuccess)
+        e = hipMemcpyAsync(seg + NV * i, m->X, NV * 4, hipMemcpyDeviceToDevice, m->stream);
+      CollideArgs ca{m->X, m->Y, m->P, m->Prow, m->Phi, m->Plo, m->a, m->b, f.Vp, f.NP, m->cpart};
+      if (e == hipSuccess) e = launch_collide(ca, f, 0, 0, m->stream);
+      SweepArgs sa{m->Y, m->X, f.Vp, f.V, f.nx, f.ny, f.nz, m->ddirs, m->delta, m->dstride,
+                   m->r, m->iface, m->nvox, m->islot, m->icptF, f.ndir, m->step_ctr, m->spart};
+      if (e == hipSuccess) e = launch_sweep(sa, f, split, 0, m->sweep_bpd, m->stream);
+      ReduceArgs ra{m->cpart, m->cnwg, m->spart, m->snwg, m->Y, f.Vp, m->det_pairs, m->det_first,
+                    m->det_vox_dev, m->ndet, m->ddirs, m->r, 0, m->step_ctr, m->budget,
+                    m->det_steps, m->cap, m->flag, m->rscratch, m->rdone};
+      if (e == hipSuccess) e = launch_reduce(ra, m->stream);
+    }
+    // adjoint steps backwards through the segment
+    for (int i = cnt - 1; i >= 0 && e == hipSuccess; --i) {
+      A.xs = seg + NV * i;
+      e = launch_adjoint_step(A, m0 + i, m->stream);
+    }
+  }
+  std::vector<double> hga(f.V), hgb(f.V);
+  if (e == hipSuccess) e = hipMemcpyAsync(m->X, keep, NV * 4, hipMemcpyDeviceToDevice, m->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(m->stream);
+  if (e == hipSuccess) {
+    const int sd_steps = int(steps);
+    e = hipMemcpy(m->step_ctr, &sd_steps, 4, hipMemcpyHostToDevice);
+  }
+  if (e == hipSuccess) e = hipMemcpy(hga.data(), ga, f.V * 8, hipMemcpyDeviceToHost);
+  if (e == hipSuccess) e = hipMemcpy(hgb.data(), gb, f.V * 8, hipMemcpyDeviceToHost);
+  cleanup();
+  if (e != hipSuccess) return device_fail(m, e, "adjoint");
+  // chain rule through a(mu_a, mu_s), b(mu_a, mu_s)
+  for (int v = 0; v < f.V; ++v) {
+    const double ma = m->mua_host[v], ms = m->mus_host[v], mt = ma + ms;
+    const double ell = kC0 * m->dt / double(m->nhost[v]);
+    const double a = std::exp(-mt * ell);
+    const double da = -ell * a;
+    double db_a, db_s;
+    if (m->desc.coef == TR_COEF_PAPER) {
+      if (mt > 0) {
+        const double om = ms / mt, oneminus = -std::expm1(-mt * ell);
+        db_a = -(ms / (mt * mt)) * oneminus + om * ell * a;
+        db_s = (ma / (mt * mt)) * oneminus + om * ell * a;
+      } else {
+        db_a = 0.0;
+        db_s = ell;
+      }
+    } else {
+      const double ea = std::exp(-ma * ell), es = std::exp(-ms * ell);
+      db_a = -ell * ea * (1.0 - es);
+      db_s = ell * ea * es;
+    }
+    dmua[v] = float(hga[v] * da + hgb[v] * db_a);
+    dmus[v] = float(hga[v] * da + hgb[v] * db_s);
+  }
   return TR_OK;
 }
 

@@ -116,6 +116,29 @@ struct ReqDev {
   int live;            // 1 while the slot holds a request
 };
 
+// Adjoint (transposed) step of phase mode, for one step m.
+struct AdjArgs {
+  const float* lam;        // adjoint of the field after the step, [NP][Vp]
+  float* mu;               // adjoint of the post-collision field, [NP][Vp]
+  float* lam_out;          // adjoint of the pre-collision field, [NP][Vp]
+  const float* xs;         // forward pre-collision field of step m, [NP][Vp]
+  const float* PT;         // P transposed, row-major [NP][NP] (what the forward calls Prow of P^T)
+  const float* a;
+  const float* b;
+  double* ga;              // dL/da per voxel, accumulated
+  double* gb;              // dL/db per voxel, accumulated
+  long long Vp;
+  int V, nx, ny, nz, ndir, NP;
+  const DevDir* dirs;
+  const int8_t* delta;
+  int dstride;
+  const int* det_pairs;    // [npairs][2] (detector, direction)
+  int ndet_pairs;
+  const int* det_vox;
+  const double* seed;      // dL/d det[k][m], [ndet][steps]
+  int steps;
+};
+
 // Launchers: queue the kernel on `s`.  Return the launch status.
 hipError_t launch_inject(const InjectArgs& a, hipStream_t s);
 hipError_t launch_collide(const CollideArgs& a, const Field& f, int bf16split, int nwg_cols,
@@ -134,6 +157,10 @@ hipError_t launch_server_step(const ReqDev* reqs, int nslots, const int* citems,
                               const int* sitems, const int* counts, const float* Prow, int NP,
                               hipStream_t s);
 hipError_t prepare_server(int NP);
+// mu = T_m^T lam + D_m^T seed;  lam_out = a mu + b (P^T mu); ga += sum_d mu xs,
+// gb += sum_d (P^T mu) xs.  Needs NP <= 192.
+hipError_t launch_adjoint_step(const AdjArgs& a, int m, hipStream_t s);
+hipError_t prepare_adjoint(int NP);
 hipError_t launch_energy(const float* X, long long Vp, int ndir, int V, float* E, hipStream_t s);
 
 }  // namespace trinity

@@ -700,6 +700,123 @@ __global__ __launch_bounds__(kThreads) void srv_reduce_kernel(const ReqDev* R) {
   reduce_part(A, blockIdx.x, 8);
 }
 
+// ---------------------------------------------------------------------------
+// Adjoint of the phase-mode step (transposes of the sweep, the detector
+// read-out and the collision), for gradients of a detector loss.
+
+// mu[d][v] = T_m^T lam: the photons of v went to its downwind voxel w (if the
+// direction moved at step m and w is inside the box), so v's adjoint is w's.
+__global__ __launch_bounds__(kThreads) void adj_sweep_kernel(AdjArgs A, int m) {
+  const int d = blockIdx.y;
+  const DevDir D = A.dirs[d];
+  const float f = phase_move(D.nu64, m);
+  const float* __restrict__ L = A.lam + size_t(d) * A.Vp;
+  float* __restrict__ M = A.mu + size_t(d) * A.Vp;
+  const int nx = A.nx, ny = A.ny, nz = A.nz;
+  const int ea = pick(D.axis, nx, ny, nz), eb = pick(D.bax, nx, ny, nz), ec = pick(D.cax, nx, ny, nz);
+  const long long sxy = (long long)nx * ny;
+  const long long sa = D.axis == 0 ? 1 : (D.axis == 1 ? nx : sxy);
+  const long long sb = D.bax == 0 ? 1 : (D.bax == 1 ? nx : sxy);
+  const long long sc = D.cax == 0 ? 1 : (D.cax == 1 ? nx : sxy);
+  const int8_t* db = A.delta + (size_t(d) * 2 + 0) * A.dstride;
+  const int8_t* dc = A.delta + (size_t(d) * 2 + 1) * A.dstride;
+  for (int v = blockIdx.x * kThreads + threadIdx.x; v < A.V; v += gridDim.x * kThreads) {
+    if (f == 0.0f) {
+      M[v] = L[v];
+      continue;
+    }
+    const int x = v % nx, t = v / nx, y = t % ny, z = t / ny;
+    const int pa = pick(D.axis, x, y, z), pb = pick(D.bax, x, y, z), pc = pick(D.cax, x, y, z);
+    const int k = D.sign > 0 ? pa : ea - 1 - pa;
+    float out = 0.0f;
+    if (k + 1 < ea) {
+      const int dbn = db[k + 1], dcn = dc[k + 1];
+      if ((unsigned)(pb + dbn) < (unsigned)eb && (unsigned)(pc + dcn) < (unsigned)ec)
+        out = L[v + D.sign * sa + dbn * sb + dcn * sc];
+    }
+    M[v] = out;
+  }
+}
+
+// mu[d][v_k] += f_d(m) seed[k][m] for every (detector k, direction d) pair.
+__global__ void adj_detector_kernel(AdjArgs A, int m) {
+  if (threadIdx.x != 0) return;
+  for (int p = 0; p < A.ndet_pairs; ++p) {
+    const int k = A.det_pairs[2 * p], d = A.det_pairs[2 * p + 1];
+    const float f = phase_move(A.dirs[d].nu64, m);
+    const int v = A.det_vox[k];
+    A.mu[size_t(d) * A.Vp + v] += f * float(A.seed[size_t(k) * A.steps + m]);
+  }
+}
+
+// Transposed collision on LDS-resident P^T (same tiling as the forward kernel):
+// z = P^T mu per voxel, lam_out = a mu + b z, and the voxel's gradient sums.
+template <int NP>
+__global__ __launch_bounds__(512, 1) void adj_collide_kernel(AdjArgs A, int ntiles) {
+  constexpr int NQ = NP / 32;
+  constexpr int LDK = NP + 4;
+  extern __shared__ float Ps[];
+  load_p_lds<NP>(A.PT, Ps);
+  __syncthreads();
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int hl = lane >> 5, cl = lane & 31;
+  const size_t rowbytes = size_t(A.Vp) * sizeof(float);
+  const float* __restrict__ Pl = Ps + cl * LDK + 4 * hl;
+#pragma unroll 1
+  for (int tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+    const long long col = (long long)tile * 256 + wave * 32 + cl;
+    const unsigned voff = unsigned(size_t(col) * sizeof(float) + size_t(4 * hl) * rowbytes);
+    const char* __restrict__ mb0 = reinterpret_cast<const char*>(A.mu);
+    floatx16 acc[NQ];
+#pragma unroll
+    for (int q = 0; q < NQ; ++q)
+#pragma unroll
+      for (int r = 0; r < 16; ++r) acc[q][r] = 0.0f;
+#pragma unroll 1
+    for (int c = 0; c < NQ; ++c) {
+      float bm[16];
+#pragma unroll
+      for (int s = 0; s < 16; ++s)
+        bm[s] = *reinterpret_cast<const float*>(
+            mb0 + size_t(32 * c + 8 * (s >> 2) + (s & 3)) * rowbytes + voff);
+#pragma unroll
+      for (int s4 = 0; s4 < 16; s4 += 4) {
+        const int kk = 32 * c + 8 * (s4 >> 2);
+#pragma unroll
+        for (int q = 0; q < NQ; ++q) {
+          const float4 a4 = *reinterpret_cast<const float4*>(Pl + q * 32 * LDK + kk);
+          acc[q] = __builtin_amdgcn_mfma_f32_32x32x2f32(a4.x, bm[s4 + 0], acc[q], 0, 0, 0);
+          acc[q] = __builtin_amdgcn_mfma_f32_32x32x2f32(a4.y, bm[s4 + 1], acc[q], 0, 0, 0);
+          acc[q] = __builtin_amdgcn_mfma_f32_32x32x2f32(a4.z, bm[s4 + 2], acc[q], 0, 0, 0);
+          acc[q] = __builtin_amdgcn_mfma_f32_32x32x2f32(a4.w, bm[s4 + 3], acc[q], 0, 0, 0);
+        }
+      }
+    }
+    const float av = A.a[col], bv = A.b[col];
+    const char* __restrict__ xb0 = reinterpret_cast<const char*>(A.xs);
+    char* __restrict__ lb0 = reinterpret_cast<char*>(A.lam_out);
+    double ga = 0.0, gb = 0.0;
+#pragma unroll
+    for (int q = 0; q < NQ; ++q)
+#pragma unroll
+      for (int r = 0; r < 16; ++r) {
+        const size_t off = size_t(q * 32 + 8 * (r >> 2) + (r & 3)) * rowbytes + voff;
+        const float mu = *reinterpret_cast<const float*>(mb0 + off);
+        const float x = *reinterpret_cast<const float*>(xb0 + off);
+        const float z = acc[q][r];
+        *reinterpret_cast<float*>(lb0 + off) = av * mu + bv * z;
+        ga += double(mu) * double(x);
+        gb += double(z) * double(x);
+      }
+    ga += __shfl_xor(ga, 32, 64);
+    gb += __shfl_xor(gb, 32, 64);
+    if (hl == 0 && col < A.V) {
+      A.ga[col] += ga;
+      A.gb[col] += gb;
+    }
+  }
+}
+
 __global__ void energy_kernel(const float* X, long long Vp, int ndir, int V, float* E) {
   const int v = blockIdx.x * blockDim.x + threadIdx.x;
   if (v >= V) return;
@@ -900,6 +1017,56 @@ hipError_t launch_server_step(const ReqDev* reqs, int nslots, const int* citems,
   if ((e = hipGetLastError()) != hipSuccess) return e;
   hipLaunchKernelGGL(srv_reduce_kernel, dim3(8, unsigned(nslots)), dim3(kThreads), 0, s, reqs);
   return hipGetLastError();
+}
+
+namespace {
+template <int NP>
+hipError_t prepare_adj() {
+  const size_t lds = size_t(NP) * (NP + 4) * sizeof(float);
+  return hipFuncSetAttribute(reinterpret_cast<const void*>(&adj_collide_kernel<NP>),
+                             hipFuncAttributeMaxDynamicSharedMemorySize, int(lds));
+}
+template <int NP>
+hipError_t launch_adj_collide(const AdjArgs& a, hipStream_t s) {
+  const size_t lds = size_t(NP) * (NP + 4) * sizeof(float);
+  const int ntiles = int(a.Vp / 256);
+  const int nb = ntiles < resident_blocks() ? ntiles : resident_blocks();
+  hipLaunchKernelGGL(adj_collide_kernel<NP>, dim3(unsigned(nb)), dim3(512), lds, s, a, ntiles);
+  return hipGetLastError();
+}
+}  // namespace
+
+hipError_t prepare_adjoint(int NP) {
+  switch (NP) {
+    case 32: return prepare_adj<32>();
+    case 64: return prepare_adj<64>();
+    case 96: return prepare_adj<96>();
+    case 128: return prepare_adj<128>();
+    case 160: return prepare_adj<160>();
+    case 192: return prepare_adj<192>();
+    default: return hipErrorInvalidValue;
+  }
+}
+
+hipError_t launch_adjoint_step(const AdjArgs& a, int m, hipStream_t s) {
+  const int bpd = (a.V + kThreads * 16 - 1) / (kThreads * 16);
+  hipLaunchKernelGGL(adj_sweep_kernel, dim3(unsigned(bpd < 64 ? bpd : 64), unsigned(a.ndir)),
+                     dim3(kThreads), 0, s, a, m);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  if (a.ndet_pairs > 0) {
+    hipLaunchKernelGGL(adj_detector_kernel, dim3(1), dim3(64), 0, s, a, m);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+  }
+  switch (a.NP) {
+    case 32: return launch_adj_collide<32>(a, s);
+    case 64: return launch_adj_collide<64>(a, s);
+    case 96: return launch_adj_collide<96>(a, s);
+    case 128: return launch_adj_collide<128>(a, s);
+    case 160: return launch_adj_collide<160>(a, s);
+    case 192: return launch_adj_collide<192>(a, s);
+    default: return hipErrorInvalidValue;
+  }
 }
 
 hipError_t launch_energy(const float* X, long long Vp, int ndir, int V, float* E, hipStream_t s) {

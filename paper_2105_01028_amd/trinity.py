@@ -97,6 +97,8 @@ _SIGS = {
     "tr_set_state": [_P, _P, _I],
     "tr_get_info": [_P, ctypes.POINTER(Info)],
     "tr_profile_begin": [_P, _I],
+    "tr_solve_checkpointed": [_P, _I, _I],
+    "tr_backward": [_P, _PD, _PF, _PF],
     "tr_profile_end": [_P, _PD, _PI],
     "tr_server_create": [ctypes.POINTER(ServerDesc), _P, ctypes.POINTER(_P)],
     "tr_server_destroy": [_P],
@@ -265,6 +267,22 @@ class Medium:
 
     def reset(self):
         _check(lib().tr_reset(self._h))
+
+    # ---- gradients
+    def solve_checkpointed(self, nsteps: int, ckpt_every: int = 50):
+        _check(lib().tr_solve_checkpointed(self._h, int(nsteps), int(ckpt_every)))
+
+    def backward(self, dL_dbins):
+        """dL/d(mu_a), dL/d(mu_s) per voxel for dL/d(binned detector signals)."""
+        g = np.ascontiguousarray(dL_dbins, dtype=np.float64).ravel()
+        if g.size != self.ndet * self.nbins:
+            raise ValueError("dL_dbins must hold ndet * nbins values")
+        nv = self.desc.nx * self.desc.ny * self.desc.nz
+        dmua = np.zeros(nv, np.float32)
+        dmus = np.zeros(nv, np.float32)
+        _check(lib().tr_backward(self._h, _dptr(g), _fptr(dmua), _fptr(dmus)))
+        shape = (self.desc.nz, self.desc.ny, self.desc.nx)
+        return dmua.reshape(shape), dmus.reshape(shape)
 
     # ---- kernel timing
     KERNELS = ("inject", "collide", "sweep", "gather", "reduce")
