@@ -362,7 +362,10 @@ struct SweepAcc {
 };
 
 constexpr int kMaxExt = 4096;   // largest grid extent (the C-ABI rejects larger)
-constexpr int kRows = 4;        // rows a thread works on at once
+#ifndef TRINITY_SWEEP_ROWS
+#define TRINITY_SWEEP_ROWS 4
+#endif
+constexpr int kRows = TRINITY_SWEEP_ROWS;   // rows a thread works on at once
 
 // Rows [rb, re) of direction d with dominant axis AX.  Thread layout: tpr
 // threads per row (tpr = min(nx, 256)), rpi = 256 / tpr rows per pass; each
@@ -486,6 +489,153 @@ __device__ __forceinline__ void sweep_rows(const SweepArgs& A, const DevDir& D, 
   }
 }
 
+// Phase mode, a direction that moves at this step (f = 1): every voxel takes
+// its upwind voxel's value, light in the exit plane (or crossing a side of the
+// box) leaves.  Per-row (or, for x-dominant directions, per-lane) quantities
+// are hoisted; indices are 32-bit (the C-ABI limits a grid to 2^30 voxels).
+template <int AX>
+__device__ __forceinline__ void sweep_phase_rows(const SweepArgs& A, const DevDir& D, int d,
+                                                 int rb, int re, const int8_t* __restrict__ db,
+                                                 const int8_t* __restrict__ dc, SweepAcc& acc) {
+  const int nx = A.nx, ny = A.ny, nz = A.nz;
+  const int nxy = nx * ny;
+  constexpr int CX = AX == 2 ? 1 : 2;
+  const int ea = AX == 0 ? nx : (AX == 1 ? ny : nz);
+  const int ec = CX == 1 ? ny : nz;
+  const int sa = AX == 0 ? 1 : (AX == 1 ? nx : nxy);
+  const int sc = CX == 1 ? nx : nxy;
+  const float* __restrict__ Yd = A.Y + size_t(d) * A.Vp;
+  float* __restrict__ Xd = A.X + size_t(d) * A.Vp;
+  const int tpr = nx < kThreads ? nx : kThreads;
+  const int rpi = kThreads / tpr;
+  const int xs = threadIdx.x % tpr, rsub = threadIdx.x / tpr;
+  if (rsub >= rpi) return;
+  const int sign = D.sign;
+  if (AX == 0) {
+    // lanes run across planes: the plane index and its shifts are per lane
+    for (int x = xs; x < nx; x += tpr) {
+      const int k = sign > 0 ? x : nx - 1 - x;
+      const int dbk = db[k], dck = dc[k], dbn = db[k + 1], dcn = dc[k + 1];
+      const bool exit_a = k + 1 >= nx;
+      const int uoff = -sign - dbk * nx - dck * nxy;
+      constexpr int RB = 4;
+      int yy[RB], zz[RB];
+      {
+        const int row = rb + rsub;
+        zz[0] = row / ny;
+        yy[0] = row - zz[0] * ny;
+#pragma unroll
+        for (int i = 1; i < RB; ++i) {
+          yy[i] = yy[i - 1] + rpi;
+          zz[i] = zz[i - 1];
+          while (yy[i] >= ny) {
+            yy[i] -= ny;
+            ++zz[i];
+          }
+        }
+      }
+      for (int row0 = rb + rsub; row0 < re; row0 += RB * rpi) {
+        float out[RB];
+        int v[RB];
+        bool live[RB];
+#pragma unroll
+        for (int i = 0; i < RB; ++i) {
+          const int row = row0 + i * rpi;
+          live[i] = row < re;
+          v[i] = row * nx + x;
+          const bool in = live[i] && k > 0 && (unsigned)(yy[i] - dbk) < (unsigned)ny &&
+                          (unsigned)(zz[i] - dck) < (unsigned)nz;
+          out[i] = in ? Yd[v[i] + uoff] : 0.0f;
+        }
+#pragma unroll
+        for (int i = 0; i < RB; ++i) {
+          if (!live[i]) continue;
+          Xd[v[i]] = out[i];
+          acc.dom += double(out[i]);
+          if (exit_a) {
+            acc.esc_a += double(Yd[v[i]]);
+          } else if ((unsigned)(yy[i] + dbn) >= (unsigned)ny) {
+            if (dbn > 0) acc.esc_b1 += double(Yd[v[i]]); else acc.esc_b0 += double(Yd[v[i]]);
+          } else if ((unsigned)(zz[i] + dcn) >= (unsigned)nz) {
+            if (dcn > 0) acc.esc_c1 += double(Yd[v[i]]); else acc.esc_c0 += double(Yd[v[i]]);
+          }
+        }
+#pragma unroll
+        for (int i = 0; i < RB; ++i) {
+          yy[i] += RB * rpi;
+          while (yy[i] >= ny) {
+            yy[i] -= ny;
+            ++zz[i];
+          }
+        }
+      }
+    }
+  } else {
+    // four rows per iteration, all loads issued before the stores
+    constexpr int RB = 4;
+    int yy[RB], zz[RB];
+    {
+      const int row = rb + rsub;
+      zz[0] = row / ny;
+      yy[0] = row - zz[0] * ny;
+#pragma unroll
+      for (int i = 1; i < RB; ++i) {
+        yy[i] = yy[i - 1] + rpi;
+        zz[i] = zz[i - 1];
+        while (yy[i] >= ny) {
+          yy[i] -= ny;
+          ++zz[i];
+        }
+      }
+    }
+    for (int row0 = rb + rsub; row0 < re; row0 += RB * rpi) {
+      for (int x = xs; x < nx; x += tpr) {
+        int v[RB], k[RB], dbn[RB], dcn[RB];
+        bool live[RB], last[RB], cexit[RB];
+        float out[RB];
+#pragma unroll
+        for (int i = 0; i < RB; ++i) {
+          const int row = row0 + i * rpi;
+          live[i] = row < re;
+          const int pa = AX == 1 ? yy[i] : zz[i];
+          const int pc = CX == 1 ? yy[i] : zz[i];
+          k[i] = sign > 0 ? pa : ea - 1 - pa;
+          const int dbk = db[k[i]], dck = dc[k[i]];
+          dbn[i] = db[k[i] + 1];
+          dcn[i] = dc[k[i] + 1];
+          const bool in = live[i] && k[i] > 0 && (unsigned)(pc - dck) < (unsigned)ec &&
+                          (unsigned)(x - dbk) < (unsigned)nx;
+          last[i] = k[i] + 1 >= ea;
+          cexit[i] = !last[i] && (unsigned)(pc + dcn[i]) >= (unsigned)ec;
+          v[i] = row * nx + x;
+          out[i] = in ? Yd[v[i] - sign * sa - dck * sc - dbk] : 0.0f;
+        }
+#pragma unroll
+        for (int i = 0; i < RB; ++i) {
+          if (!live[i]) continue;
+          Xd[v[i]] = out[i];
+          acc.dom += double(out[i]);
+          if (last[i]) {
+            acc.esc_a += double(Yd[v[i]]);
+          } else if ((unsigned)(x + dbn[i]) >= (unsigned)nx) {
+            if (dbn[i] > 0) acc.esc_b1 += double(Yd[v[i]]); else acc.esc_b0 += double(Yd[v[i]]);
+          } else if (cexit[i]) {
+            if (dcn[i] > 0) acc.esc_c1 += double(Yd[v[i]]); else acc.esc_c0 += double(Yd[v[i]]);
+          }
+        }
+      }
+#pragma unroll
+      for (int i = 0; i < RB; ++i) {
+        yy[i] += RB * rpi;
+        while (yy[i] >= ny) {
+          yy[i] -= ny;
+          ++zz[i];
+        }
+      }
+    }
+  }
+}
+
 }  // namespace
 
 // Block blk of nblk row slabs of direction d; writes the block's 7 partial sums
@@ -526,12 +676,20 @@ __device__ __forceinline__ void sweep_block(const SweepArgs& A, int d, int blk, 
       sdelta[1][i] = A.delta[(size_t(d) * 2 + 1) * A.dstride + i];
     }
     __syncthreads();
-    if (D.axis == 2)
+    if (!SPLIT) {
+      if (D.axis == 2)
+        sweep_phase_rows<2>(A, D, d, rb, re, sdelta[0], sdelta[1], acc);
+      else if (D.axis == 1)
+        sweep_phase_rows<1>(A, D, d, rb, re, sdelta[0], sdelta[1], acc);
+      else
+        sweep_phase_rows<0>(A, D, d, rb, re, sdelta[0], sdelta[1], acc);
+    } else if (D.axis == 2) {
       sweep_rows<2, SPLIT, FRESNEL>(A, D, d, rb, re, sdelta[0], sdelta[1], acc);
-    else if (D.axis == 1)
+    } else if (D.axis == 1) {
       sweep_rows<1, SPLIT, FRESNEL>(A, D, d, rb, re, sdelta[0], sdelta[1], acc);
-    else
+    } else {
       sweep_rows<0, SPLIT, FRESNEL>(A, D, d, rb, re, sdelta[0], sdelta[1], acc);
+    }
   }
   double face[6];
   const int fa = 2 * D.axis + (D.sign > 0 ? 1 : 0);
