@@ -418,11 +418,13 @@ tr_status tr_create_medium(const tr_grid_desc* desc, const float* mua, const flo
     dd[d].cax = m->lat.cax[d];
     dd[d].nu64 = m->lat.speed[d] * nu_scale;
     dd[d].nu = float(dd[d].nu64);
-    dd[d].pad = 0;
+    dd[d].unitb = 1;
     for (int q = 0; q < 2; ++q)
-      for (int k = 1; k <= m->lat.maxext; ++k)
-        dl[(size_t(d) * 2 + q) * m->dstride + k] =
-            int8_t(m->lat.off(d, q, k) - m->lat.off(d, q, k - 1));
+      for (int k = 1; k <= m->lat.maxext; ++k) {
+        const int s = m->lat.off(d, q, k) - m->lat.off(d, q, k - 1);
+        dl[(size_t(d) * 2 + q) * m->dstride + k] = int8_t(s);
+        if (q == 0 && (s < -1 || s > 1)) dd[d].unitb = 0;
+      }
   }
   hipError_t e = prepare_collide(f, desc->precision);
   if (e == hipSuccess) e = hipMemset(m->X, 0, NV * 4);

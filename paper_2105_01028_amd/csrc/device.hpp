@@ -12,7 +12,7 @@ namespace trinity {
 struct DevDir {
   int axis, sign, bax, cax;   // dominant axis a, sign of Omega_a, transverse axes b < c
   float nu;                   // planes advanced per step at the reference path (split mode)
-  float pad;
+  int unitb;                  // 1 if every plane-to-plane shift along b is -1, 0 or +1
   double nu64;                // same, FP64, for the phase-mode move rule
 };
 

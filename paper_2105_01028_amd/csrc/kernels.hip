@@ -636,6 +636,85 @@ __device__ __forceinline__ void sweep_phase_rows(const SweepArgs& A, const DevDi
   }
 }
 
+// Phase mode, a moving direction whose dominant axis is y or z, on a grid with
+// nx a multiple of 4: every lane moves four consecutive voxels of a row as one
+// 16-byte load and store.  The source row is the upwind row, displaced along x
+// by the plane-to-plane shift s in {-1, 0, 1}; the one value a lane needs from
+// the next four voxels over comes from its neighbour lane (or, at the edge of
+// the wave, from memory).  Same tallies, in the same order of precedence, as
+// the scalar path.
+template <int AX>
+__device__ __forceinline__ void sweep_phase_vec(const SweepArgs& A, const DevDir& D, int d,
+                                                int rb, int re, const int8_t* __restrict__ db,
+                                                const int8_t* __restrict__ dc, SweepAcc& acc) {
+  static_assert(AX == 1 || AX == 2, "rows run along x");
+  constexpr int CX = AX == 2 ? 1 : 2;
+  const int nx = A.nx, ny = A.ny, nz = A.nz;
+  const int ea = AX == 1 ? ny : nz;
+  const int ec = CX == 1 ? ny : nz;
+  const int tq = nx >> 2;                              // float4 per row
+  const int sa4 = AX == 1 ? tq : tq * ny;              // plane stride in float4
+  const int sc4 = CX == 1 ? tq : tq * ny;
+  const float4* __restrict__ Yd = reinterpret_cast<const float4*>(A.Y + size_t(d) * A.Vp);
+  float4* __restrict__ Xd = reinterpret_cast<float4*>(A.X + size_t(d) * A.Vp);
+  const float* __restrict__ Ys = A.Y + size_t(d) * A.Vp;
+  const int sign = D.sign;
+  const int lane = threadIdx.x & 63;
+  const int ge = re * tq;
+  // flat float4 index g = row * tq + q, advanced by kThreads per pass
+  int g = rb * tq + threadIdx.x;
+  int row = g / tq, q = g - row * tq;
+  int zz = row / ny, yy = row - zz * ny;
+  const int drow = kThreads / tq, dq = kThreads - drow * tq;
+  for (; g < ge; g += kThreads) {
+    const int pa = AX == 1 ? yy : zz;
+    const int pc = CX == 1 ? yy : zz;
+    const int k = sign > 0 ? pa : ea - 1 - pa;
+    const int dbk = db[k], dck = dc[k], dbn = db[k + 1], dcn = dc[k + 1];
+    const bool rowin = k > 0 && (unsigned)(pc - dck) < (unsigned)ec;
+    const int u = g - sign * sa4 - dck * sc4;
+    const float4 y = rowin ? Yd[u] : make_float4(0.f, 0.f, 0.f, 0.f);
+    // the neighbour lane holds the next four voxels of the same row (q > 0 / q < tq - 1)
+    const float prev_w = __shfl_up(y.w, 1);
+    const float next_x = __shfl_down(y.x, 1);
+    float4 o = y;
+    if (dbk > 0) {
+      float w = 0.f;
+      if (rowin && q > 0) w = lane > 0 ? prev_w : Ys[4 * u - 1];
+      o = make_float4(w, y.x, y.y, y.z);
+    } else if (dbk < 0) {
+      float x = 0.f;
+      if (rowin && q < tq - 1) x = lane < 63 ? next_x : Ys[4 * u + 4];
+      o = make_float4(y.y, y.z, y.w, x);
+    }
+    Xd[g] = o;
+    acc.dom += (double(o.x) + double(o.y)) + (double(o.z) + double(o.w));
+    // light that leaves: through the exit plane, then the x sides, then the c sides
+    const bool last = k + 1 >= ea;
+    const bool bx = !last && ((dbn > 0 && q == tq - 1) || (dbn < 0 && q == 0));
+    const bool cexit = !last && (unsigned)(pc + dcn) >= (unsigned)ec;
+    if (last || bx || cexit) {
+      const float4 s4 = Yd[g];
+      if (last) {
+        acc.esc_a += (double(s4.x) + double(s4.y)) + (double(s4.z) + double(s4.w));
+      } else {
+        float e0 = s4.x, e3 = s4.w;
+        if (bx && dbn > 0) { acc.esc_b1 += double(s4.w); e3 = 0.f; }
+        if (bx && dbn < 0) { acc.esc_b0 += double(s4.x); e0 = 0.f; }
+        if (cexit) {
+          const double t = (double(e0) + double(s4.y)) + (double(s4.z) + double(e3));
+          if (dcn > 0) acc.esc_c1 += t; else acc.esc_c0 += t;
+        }
+      }
+    }
+    q += dq;
+    int adv = drow;
+    if (q >= tq) { q -= tq; ++adv; }
+    yy += adv;
+    while (yy >= ny) { yy -= ny; ++zz; }
+  }
+}
+
 }  // namespace
 
 // Block blk of nblk row slabs of direction d; writes the block's 7 partial sums
@@ -676,7 +755,12 @@ __device__ __forceinline__ void sweep_block(const SweepArgs& A, int d, int blk, 
       sdelta[1][i] = A.delta[(size_t(d) * 2 + 1) * A.dstride + i];
     }
     __syncthreads();
-    if (!SPLIT) {
+    if (!SPLIT && D.axis != 0 && (A.nx & 3) == 0 && D.unitb) {
+      if (D.axis == 2)
+        sweep_phase_vec<2>(A, D, d, rb, re, sdelta[0], sdelta[1], acc);
+      else
+        sweep_phase_vec<1>(A, D, d, rb, re, sdelta[0], sdelta[1], acc);
+    } else if (!SPLIT) {
       if (D.axis == 2)
         sweep_phase_rows<2>(A, D, d, rb, re, sdelta[0], sdelta[1], acc);
       else if (D.axis == 1)

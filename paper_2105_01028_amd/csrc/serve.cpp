@@ -168,10 +168,13 @@ tr_status build_request(const tr_server* s, const tr_request* q, Request& r) {
     D.cax = lat.cax[d];
     D.nu64 = lat.speed[d] * nu_scale;
     D.nu = float(D.nu64);
-    D.pad = 0;
+    D.unitb = 1;
     for (int qq = 0; qq < 2; ++qq)
-      for (int k = 1; k <= lat.maxext; ++k)
-        r.delta[(size_t(d) * 2 + qq) * r.dstride + k] = int8_t(lat.off(d, qq, k) - lat.off(d, qq, k - 1));
+      for (int k = 1; k <= lat.maxext; ++k) {
+        const int s = lat.off(d, qq, k) - lat.off(d, qq, k - 1);
+        r.delta[(size_t(d) * 2 + qq) * r.dstride + k] = int8_t(s);
+        if (qq == 0 && (s < -1 || s > 1)) D.unitb = 0;
+      }
   }
   // source
   if (q->src_w != 1 && q->src_w != 2) return fail(TR_EINVAL, "src_w must be 1 or 2");

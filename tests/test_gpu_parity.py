@@ -52,10 +52,16 @@ def closure_bound(b, ulps=1.0):
     return ulps * 2.0 ** -23 * b[:, 2].sum() / b[:, 0].sum() + 1e-12
 
 
-@pytest.mark.parametrize("advance,seed", [("phase", 1), ("split", 2)])
-def test_single_step_matches_oracle(advance, seed):
+@pytest.mark.parametrize("advance,seed,shape", [
+    ("phase", 1, (13, 10, 9)), ("split", 2, (13, 10, 9)),
+    # nx a multiple of 4 (16-byte row moves): rows shorter than, across and
+    # longer than a wavefront, and a one-vector row
+    ("phase", 3, (20, 7, 9)), ("phase", 4, (264, 3, 4)), ("phase", 5, (4, 6, 5)),
+    ("phase", 6, (12, 11, 3))])
+def test_single_step_matches_oracle(advance, seed, shape):
     """One step from a random state: every (direction, voxel) of the field."""
-    p = W.small_problem(nside=2, nx=13, ny=10, nz=9, mua=0.05, mus=3.0, g=0.8, steps=1,
+    nx, ny, nz = shape
+    p = W.small_problem(nside=2, nx=nx, ny=ny, nz=nz, mua=0.05, mus=3.0, g=0.8, steps=1,
                         seed=seed, advance=advance, total_photons=0.0)
     rng = np.random.default_rng(seed)
     N0 = rng.uniform(0, 1, (48, p.nvox)).astype(np.float32)
@@ -65,10 +71,12 @@ def test_single_step_matches_oracle(advance, seed):
     assert np.allclose(got["budget"][0, 3:], ref.escaped[0], rtol=2e-6, atol=1e-9)
 
 
-def test_free_streaming_is_exact():
+@pytest.mark.parametrize("shape", [(11, 9, 10), (12, 9, 10), (20, 5, 7)])
+def test_free_streaming_is_exact(shape):
     """mu_a = mu_s = 0 in phase mode: transport only moves values, so the GPU
     field equals the oracle's bit for bit after many steps."""
-    p = W.small_problem(nside=2, nx=11, ny=9, nz=10, mua=0.0, mus=0.0, g=0.5, steps=30,
+    nx, ny, nz = shape
+    p = W.small_problem(nside=2, nx=nx, ny=ny, nz=nz, mua=0.0, mus=0.0, g=0.5, steps=30,
                         total_photons=0.0)
     rng = np.random.default_rng(3)
     N0 = (rng.uniform(0, 1, (48, p.nvox)) * (rng.uniform(size=p.nvox) < 0.2)).astype(np.float32)
