@@ -47,6 +47,8 @@ struct tr_medium {
   uint8_t* iface = nullptr;
   float* nvox = nullptr;
   int* islot = nullptr;
+  uint8_t* mat = nullptr;   // split mode: index class | interface bit << 7, or null
+  float* rtab = nullptr;    // split mode: path ratio of each index class
   float* icptF = nullptr;
   int niface = 0;
   int ntgt = 0;
@@ -232,7 +234,8 @@ hipError_t queue_step(tr_medium* m) {
   {
     KernelTimer t(m, TR_K_SWEEP);
     SweepArgs sa{m->Y, m->X, f.Vp, f.V, f.nx, f.ny, f.nz, m->ddirs, m->delta, m->dstride,
-                 m->r, m->iface, m->nvox, m->islot, m->icptF, f.ndir, m->step_ctr, m->spart};
+                 m->r, m->iface, m->nvox, m->islot, m->icptF, f.ndir, m->step_ctr, m->spart,
+                 m->mat, m->rtab};
     if ((e = launch_sweep(sa, f, split, m->fresnel, m->sweep_bpd, m->stream)) != hipSuccess)
       return e;
   }
@@ -513,6 +516,36 @@ tr_status tr_create_medium(const tr_grid_desc* desc, const float* mua, const flo
     if (e != hipSuccess) {
       delete m;
       return fail(TR_EDEVICE, std::string("upload: ") + hipGetErrorString(e));
+    }
+  }
+  // ---- split mode: one byte per voxel naming its index class (at most 127
+  // distinct values of n) and whether it starts an interception
+  if (m->mode == TR_ADVANCE_SPLIT) {
+    std::map<float, int> cls;
+    for (int v = 0; v < f.V && cls.size() <= 127; ++v) cls.emplace(pn[v], 0);
+    if (cls.size() <= 127) {
+      std::vector<float> rt(128, 0.0f);
+      std::vector<uint8_t> mb(f.Vp, 0);
+      int c = 0;
+      for (auto& kv : cls) kv.second = c++;
+      for (int v = 0; v < f.V; ++v) {
+        const int k = cls[pn[v]];
+        rt[k] = float(m->co.r[v]);
+        mb[v] = uint8_t(k);
+      }
+      for (const Interception& ic : m->icpt) mb[ic.v] |= 0x80;
+      m->mat = m->alloc<uint8_t>(f.Vp);
+      m->rtab = m->alloc<float>(128);
+      if (!m->mat || !m->rtab) {
+        delete m;
+        return fail(TR_ENOMEM, "device allocation failed (index classes)");
+      }
+      e = hipMemcpy(m->mat, mb.data(), f.Vp, hipMemcpyHostToDevice);
+      if (e == hipSuccess) e = hipMemcpy(m->rtab, rt.data(), 128 * 4, hipMemcpyHostToDevice);
+      if (e != hipSuccess) {
+        delete m;
+        return fail(TR_EDEVICE, std::string("upload: ") + hipGetErrorString(e));
+      }
     }
   }
   tr_status st = ensure_capacity(m, 1024);

@@ -66,6 +66,8 @@ struct SweepArgs {
   int ndir;
   const int* step_ctr;
   double* part;            // [7][nwg]: escape per face 0..5, in the box
+  const uint8_t* mat;      // split mode, optional: index class (bits 0-6), iface (bit 7)
+  const float* rtab;       // split mode, with mat: path ratio per index class [128]
 };
 
 struct GatherArgs {

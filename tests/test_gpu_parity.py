@@ -57,7 +57,8 @@ def closure_bound(b, ulps=1.0):
     # nx a multiple of 4 (16-byte row moves): rows shorter than, across and
     # longer than a wavefront, and a one-vector row
     ("phase", 3, (20, 7, 9)), ("phase", 4, (264, 3, 4)), ("phase", 5, (4, 6, 5)),
-    ("phase", 6, (12, 11, 3))])
+    ("phase", 6, (12, 11, 3)), ("split", 7, (20, 7, 9)), ("split", 8, (264, 3, 4)),
+    ("split", 9, (12, 11, 3))])
 def test_single_step_matches_oracle(advance, seed, shape):
     """One step from a random state: every (direction, voxel) of the field."""
     nx, ny, nz = shape
@@ -67,6 +68,29 @@ def test_single_step_matches_oracle(advance, seed, shape):
     N0 = rng.uniform(0, 1, (48, p.nvox)).astype(np.float32)
     ref = solve.forward(p, steps=1, state0=N0.astype(np.float64))
     got = run_gpu(p, steps=1, state0=N0)
+    assert np.abs(got["state"] - ref.state).max() <= 2e-6 * np.abs(ref.state).max()
+    assert np.allclose(got["budget"][0, 3:], ref.escaped[0], rtol=2e-6, atol=1e-9)
+
+
+@pytest.mark.parametrize("shape,seed", [((13, 10, 9), 1), ((20, 12, 9), 2), ((8, 70, 5), 3)])
+def test_single_step_with_interfaces(shape, seed):
+    """One split-mode step from a random state in a medium with an index blob
+    and a slab of a third index: interception, held light and redistribution,
+    element by element."""
+    nx, ny, nz = shape
+    p = W.small_problem(nside=2, nx=nx, ny=ny, nz=nz, mua=0.05, mus=3.0, g=0.8, steps=1,
+                        seed=seed, advance="split", total_photons=0.0)
+    z, y, x = np.meshgrid(np.arange(nz), np.arange(ny), np.arange(nx), indexing="ij")
+    n = np.full((nz, ny, nx), 1.4, np.float32)
+    n[(x - nx / 2) ** 2 + (y - ny / 2) ** 2 + (z - nz / 2) ** 2 < (min(shape) / 3) ** 2] = 1.0
+    n[:, :, : max(1, nx // 5)] = 1.33
+    p.n = n
+    rng = np.random.default_rng(seed)
+    N0 = rng.uniform(0, 1, (48, p.nvox)).astype(np.float32)
+    ref = solve.forward(p, steps=1, state0=N0.astype(np.float64))
+    assert len(ref.setup.icpt) > 0
+    got = run_gpu(p, steps=1, state0=N0)
+    assert got["info"].ninterceptions == len(ref.setup.icpt)
     assert np.abs(got["state"] - ref.state).max() <= 2e-6 * np.abs(ref.state).max()
     assert np.allclose(got["budget"][0, 3:], ref.escaped[0], rtol=2e-6, atol=1e-9)
 
