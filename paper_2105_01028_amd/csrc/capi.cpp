@@ -48,6 +48,7 @@ struct tr_medium {
   float* nvox = nullptr;
   int* islot = nullptr;
   uint8_t* mat = nullptr;   // split mode: index class | interface bit << 7, or null
+  int fast_split = 0;       // nx % 4 == 0 and unit b shifts in every direction
   float* rtab = nullptr;    // split mode: path ratio of each index class
   float* icptF = nullptr;
   int niface = 0;
@@ -236,7 +237,8 @@ hipError_t queue_step(tr_medium* m) {
     SweepArgs sa{m->Y, m->X, f.Vp, f.V, f.nx, f.ny, f.nz, m->ddirs, m->delta, m->dstride,
                  m->r, m->iface, m->nvox, m->islot, m->icptF, f.ndir, m->step_ctr, m->spart,
                  m->mat, m->rtab};
-    if ((e = launch_sweep(sa, f, split, m->fresnel, m->sweep_bpd, m->stream)) != hipSuccess)
+    if ((e = launch_sweep(sa, f, split, m->fresnel, m->sweep_bpd, m->stream, m->fast_split)) !=
+        hipSuccess)
       return e;
   }
   if (m->fresnel) {
@@ -429,6 +431,8 @@ tr_status tr_create_medium(const tr_grid_desc* desc, const float* mua, const flo
         if (q == 0 && (s < -1 || s > 1)) dd[d].unitb = 0;
       }
   }
+  m->fast_split = f.nx % 4 == 0;
+  for (const DevDir& D : dd) m->fast_split = m->fast_split && D.unitb;
   hipError_t e = prepare_collide(f, desc->precision);
   if (e == hipSuccess) e = hipMemset(m->X, 0, NV * 4);
   if (e == hipSuccess) e = hipMemset(m->Y, 0, NV * 4);

@@ -147,8 +147,10 @@ hipError_t launch_collide(const CollideArgs& a, const Field& f, int bf16split, i
                           hipStream_t s);
 int collide_nwg(const Field& f, int bf16split);
 hipError_t prepare_collide(const Field& f, int bf16split);   // once per process and shape
+// fast_split_ok: nx is a multiple of 4 and every direction's b shifts are unit
+// (then split mode with class bytes runs the fast kernel).
 hipError_t launch_sweep(const SweepArgs& a, const Field& f, int split, int fresnel, int bpd,
-                        hipStream_t s);
+                        hipStream_t s, int fast_split_ok = 0);
 int sweep_blocks_per_dir(const Field& f);
 hipError_t launch_gather(const GatherArgs& a, hipStream_t s);
 hipError_t launch_reduce(const ReduceArgs& a, hipStream_t s);

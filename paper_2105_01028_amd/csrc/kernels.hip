@@ -945,7 +945,10 @@ __device__ __forceinline__ void sweep_split_rows0(const SweepArgs& A, const DevD
 
 // Block blk of nblk row slabs of direction d; writes the block's 7 partial sums
 // (escape per face, light in the box) to A.part[q * ndir * nblk + d * nblk + blk].
-template <bool SPLIT, bool FRESNEL>
+// FAST: every direction takes one of the class-byte split paths (x-dominant
+// lanes or 16-byte rows); the generic row path is then left out of the kernel,
+// which keeps its register count, and so its occupancy, that of the fast paths.
+template <bool SPLIT, bool FRESNEL, bool FAST = false>
 __device__ __forceinline__ void sweep_block(const SweepArgs& A, int d, int blk, int nblk,
                                             int8_t (&sdelta)[2][kMaxExt + 2],
                                             float* srt = nullptr) {
@@ -982,11 +985,18 @@ __device__ __forceinline__ void sweep_block(const SweepArgs& A, int d, int blk, 
       sdelta[1][i] = A.delta[(size_t(d) * 2 + 1) * A.dstride + i];
     }
     const bool vec = D.axis != 0 && (A.nx & 3) == 0 && D.unitb;
-    const bool smat = SPLIT && A.mat != nullptr && srt != nullptr;
+    const bool smat = FAST || (SPLIT && A.mat != nullptr && srt != nullptr);
     const bool svec = smat && vec;
     if (smat && threadIdx.x < 128) srt[threadIdx.x] = A.rtab[threadIdx.x];
     __syncthreads();
-    if (smat && D.axis == 0) {
+    if (FAST) {
+      if (D.axis == 0)
+        sweep_split_rows0<FRESNEL>(A, D, d, rb, re, sdelta[0], sdelta[1], srt, acc);
+      else if (D.axis == 2)
+        sweep_split_vec<2, FRESNEL>(A, D, d, rb, re, sdelta[0], sdelta[1], srt, acc);
+      else
+        sweep_split_vec<1, FRESNEL>(A, D, d, rb, re, sdelta[0], sdelta[1], srt, acc);
+    } else if (smat && D.axis == 0) {
       sweep_split_rows0<FRESNEL>(A, D, d, rb, re, sdelta[0], sdelta[1], srt, acc);
     } else if (svec) {
       if (D.axis == 2)
@@ -1030,11 +1040,11 @@ __device__ __forceinline__ void sweep_block(const SweepArgs& A, int d, int blk, 
   __syncthreads();   // LDS (shift tables, partial sums) is reused by the next block of work
 }
 
-template <bool SPLIT, bool FRESNEL>
+template <bool SPLIT, bool FRESNEL, bool FAST>
 __global__ __launch_bounds__(kThreads) void sweep_kernel(SweepArgs A) {
   __shared__ int8_t sdelta[2][kMaxExt + 2];
   __shared__ float srt[128];
-  sweep_block<SPLIT, FRESNEL>(A, blockIdx.y, blockIdx.x, gridDim.x, sdelta, srt);
+  sweep_block<SPLIT, FRESNEL, FAST>(A, blockIdx.y, blockIdx.x, gridDim.x, sdelta, srt);
 }
 
 // Fresnel redistribution (Eq. 13-14): every target (direction, voxel) adds the
@@ -1425,14 +1435,20 @@ int sweep_blocks_per_dir(const Field& f) {
 }
 
 hipError_t launch_sweep(const SweepArgs& a, const Field& f, int split, int fresnel, int bpd,
-                        hipStream_t s) {
+                        hipStream_t s, int fast_split_ok) {
   dim3 grid(unsigned(bpd), unsigned(f.ndir));
-  if (split && fresnel)
-    hipLaunchKernelGGL((sweep_kernel<true, true>), grid, dim3(kThreads), 0, s, a);
+  // split mode: fast kernel when every direction has a class-byte path
+  const bool fast = split && a.mat != nullptr && fast_split_ok;
+  if (split && fresnel && fast)
+    hipLaunchKernelGGL((sweep_kernel<true, true, true>), grid, dim3(kThreads), 0, s, a);
+  else if (split && fresnel)
+    hipLaunchKernelGGL((sweep_kernel<true, true, false>), grid, dim3(kThreads), 0, s, a);
+  else if (split && fast)
+    hipLaunchKernelGGL((sweep_kernel<true, false, true>), grid, dim3(kThreads), 0, s, a);
   else if (split)
-    hipLaunchKernelGGL((sweep_kernel<true, false>), grid, dim3(kThreads), 0, s, a);
+    hipLaunchKernelGGL((sweep_kernel<true, false, false>), grid, dim3(kThreads), 0, s, a);
   else
-    hipLaunchKernelGGL((sweep_kernel<false, false>), grid, dim3(kThreads), 0, s, a);
+    hipLaunchKernelGGL((sweep_kernel<false, false, false>), grid, dim3(kThreads), 0, s, a);
   return hipGetLastError();
 }
 
