@@ -1424,11 +1424,13 @@ hipError_t launch_collide(const CollideArgs& a, const Field& f, int bf16split, i
 }
 
 int sweep_blocks_per_dir(const Field& f) {
-  // about 64 voxels per thread, at most the number of rows, and no more than
-  // about 4096 workgroups in all (each leaves 7 partial sums)
-  long long b = (f.V + kThreads * 64 - 1) / (kThreads * 64);
+  // about 6144 voxels (24 per thread) or more per workgroup, at least one row,
+  // and no more than about 32768 workgroups in all (each leaves 7 partial
+  // sums): enough rounds of resident workgroups that the last, partly filled
+  // round costs little
+  long long b = f.V / 6144;
   const long long rows = (long long)f.ny * f.nz;
-  const long long cap = 4096 / f.ndir > 1 ? 4096 / f.ndir : 1;
+  const long long cap = 32768 / f.ndir > 1 ? 32768 / f.ndir : 1;
   if (b > cap) b = cap;
   if (b > rows) b = rows;
   return int(b < 1 ? 1 : b);
