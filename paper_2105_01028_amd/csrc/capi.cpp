@@ -48,6 +48,8 @@ struct tr_medium {
   float* nvox = nullptr;
   int* islot = nullptr;
   uint8_t* mat = nullptr;   // split mode: index class | interface bit << 7, or null
+  uint32_t* rowbits = nullptr;  // split mode: rows of background class only
+  unsigned bgcls = 0;
   int fast_split = 0;       // nx % 4 == 0 and unit b shifts in every direction
   float* rtab = nullptr;    // split mode: path ratio of each index class
   float* icptF = nullptr;
@@ -236,7 +238,7 @@ hipError_t queue_step(tr_medium* m) {
     KernelTimer t(m, TR_K_SWEEP);
     SweepArgs sa{m->Y, m->X, f.Vp, f.V, f.nx, f.ny, f.nz, m->ddirs, m->delta, m->dstride,
                  m->r, m->iface, m->nvox, m->islot, m->icptF, f.ndir, m->step_ctr, m->spart,
-                 m->mat, m->rtab};
+                 m->mat, m->rtab, m->rowbits, m->bgcls};
     if ((e = launch_sweep(sa, f, split, m->fresnel, m->sweep_bpd, m->stream, m->fast_split)) !=
         hipSuccess)
       return e;
@@ -538,14 +540,29 @@ tr_status tr_create_medium(const tr_grid_desc* desc, const float* mua, const flo
         mb[v] = uint8_t(k);
       }
       for (const Interception& ic : m->icpt) mb[ic.v] |= 0x80;
+      // background class and the bitmap of rows made of it alone
+      std::vector<long long> count(128, 0);
+      for (int v = 0; v < f.V; ++v) ++count[mb[v] & 0x7f];
+      m->bgcls = unsigned(std::max_element(count.begin(), count.end()) - count.begin());
+      const int nrow = std::min(f.ny * f.nz, kMaxRowBits);
+      std::vector<uint32_t> rb((nrow + 31) / 32, 0u);
+      for (int row = 0; row < nrow; ++row) {
+        const uint8_t* p = mb.data() + size_t(row) * f.nx;
+        bool bg = true;
+        for (int x = 0; x < f.nx && bg; ++x) bg = p[x] == m->bgcls;
+        if (bg) rb[row >> 5] |= 1u << (row & 31);
+      }
       m->mat = m->alloc<uint8_t>(f.Vp);
       m->rtab = m->alloc<float>(128);
-      if (!m->mat || !m->rtab) {
+      m->rowbits = m->alloc<uint32_t>(rb.size());
+      if (!m->mat || !m->rtab || !m->rowbits) {
         delete m;
         return fail(TR_ENOMEM, "device allocation failed (index classes)");
       }
       e = hipMemcpy(m->mat, mb.data(), f.Vp, hipMemcpyHostToDevice);
       if (e == hipSuccess) e = hipMemcpy(m->rtab, rt.data(), 128 * 4, hipMemcpyHostToDevice);
+      if (e == hipSuccess)
+        e = hipMemcpy(m->rowbits, rb.data(), rb.size() * 4, hipMemcpyHostToDevice);
       if (e != hipSuccess) {
         delete m;
         return fail(TR_EDEVICE, std::string("upload: ") + hipGetErrorString(e));

@@ -68,7 +68,13 @@ struct SweepArgs {
   double* part;            // [7][nwg]: escape per face 0..5, in the box
   const uint8_t* mat;      // split mode, optional: index class (bits 0-6), iface (bit 7)
   const float* rtab;       // split mode, with mat: path ratio per index class [128]
+  const uint32_t* rowbits;  // split mode, with mat: bit of row (y, z) < kMaxRowBits set
+                            // when all its voxels have class bgcls and none starts an
+                            // interception
+  unsigned bgcls;           // the class of most voxels
 };
+
+constexpr int kMaxRowBits = 65536;   // rows covered by the uniform-row bitmap (8 KB)
 
 struct GatherArgs {
   float* X;

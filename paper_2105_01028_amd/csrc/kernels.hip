@@ -13,6 +13,7 @@ typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 namespace {
 
 constexpr int kThreads = 256;
+using f32x4 = float __attribute__((ext_vector_type(4)));
 
 // Sum of a double over the 64 lanes of a wavefront (all lanes get the total).
 __device__ inline double wave_sum(double v) {
@@ -715,24 +716,46 @@ __device__ __forceinline__ void sweep_phase_vec(const SweepArgs& A, const DevDir
   }
 }
 
-// Split mode, a direction whose dominant axis is y or z, nx a multiple of 4 and
-// one index-class byte per voxel: four voxels of a row per lane as in
-// sweep_phase_vec.  A voxel keeps (1 - f_v) of its light and takes f_u of its
-// upwind voxel's; the path ratio r comes from the class byte through a table in
-// LDS.  Light never crosses between classes on the lattice: where the upwind
-// voxel's class differs, nothing flows in, and a voxel whose downwind voxel has
-// another class hands its moving share to the interception buffer (Eq. 13-14)
-// instead.  Tallies as in the scalar split path.
+// Split mode with index-class bytes.  A voxel keeps (1 - f_v) of its light and
+// takes f_u of its upwind voxel's; the path ratio r comes from the class byte
+// through a table in LDS.  Light never crosses between classes on the lattice:
+// where the upwind voxel's class differs nothing flows in, and a voxel whose
+// downwind voxel has another class hands its moving share to the interception
+// buffer (Eq. 13-14) instead.
+//
+// Every value of Y is read twice, as a voxel's own value and as its downwind
+// neighbour's upwind value.  The rows of a direction are therefore taken in
+// band order: bands of TB rows across one transverse axis, walked plane by
+// plane along the other, and a workgroup takes a contiguous range of (band,
+// plane) items.  A row's upwind row was then read at most one item earlier
+// (or is read one item later) and is still in the L2 cache, so HBM delivers
+// each value once.
+
+// Row (y, z) holds only background-class voxels, none starting an interception.
+__device__ __forceinline__ bool bg_row(const uint32_t* __restrict__ rbits, int row) {
+  return row < kMaxRowBits && ((rbits[row >> 5] >> (row & 31)) & 1u);
+}
+
+// Dominant axis y or z, nx a multiple of 4: four voxels of a row per lane, as
+// one 16-byte load and store; the upwind row is displaced along x by the shift
+// s in {-1, 0, 1}, and the one value a lane needs from the next four voxels
+// over comes from its neighbour lane (or, at the edge of the wave, from memory).
+// Bands run across the non-dominant transverse axis c and are walked along the
+// dominant axis in the direction of propagation.
 template <int AX, bool FRESNEL>
 __device__ __forceinline__ void sweep_split_vec(const SweepArgs& A, const DevDir& D, int d,
-                                                int rb, int re, const int8_t* __restrict__ db,
+                                                int blk, int nblk,
+                                                const int8_t* __restrict__ db,
                                                 const int8_t* __restrict__ dc,
-                                                const float* __restrict__ srt, SweepAcc& acc) {
+                                                const float* __restrict__ srt,
+                                                const uint32_t* __restrict__ rbits,
+                                                SweepAcc& acc) {
   static_assert(AX == 1 || AX == 2, "rows run along x");
   constexpr int CX = AX == 2 ? 1 : 2;
-  const int nx = A.nx, ny = A.ny, nz = A.nz;
-  const int ea = AX == 1 ? ny : nz;
-  const int ec = CX == 1 ? ny : nz;
+  const int nx = A.nx, ny = A.ny;
+  const unsigned bg4 = A.bgcls * 0x01010101u;
+  const int ns = AX == 1 ? ny : A.nz;   // planes along the dominant axis
+  const int nf = CX == 1 ? ny : A.nz;   // rows across c
   const int tq = nx >> 2;
   const int sa4 = AX == 1 ? tq : tq * ny;
   const int sc4 = CX == 1 ? tq : tq * ny;
@@ -743,76 +766,105 @@ __device__ __forceinline__ void sweep_split_vec(const SweepArgs& A, const DevDir
   const int sign = D.sign;
   const float nu = D.nu;
   const int lane = threadIdx.x & 63;
-  const int ge = re * tq;
-  int g = rb * tq + threadIdx.x;
-  int row = g / tq, q = g - row * tq;
-  int zz = row / ny, yy = row - zz * ny;
-  const int drow = kThreads / tq, dq = kThreads - drow * tq;
-  for (; g < ge; g += kThreads) {
-    const int pa = AX == 1 ? yy : zz;
-    const int pc = CX == 1 ? yy : zz;
-    const int k = sign > 0 ? pa : ea - 1 - pa;
-    const int dbk = db[k], dck = dc[k], dbn = db[k + 1], dcn = dc[k + 1];
-    const bool rowin = k > 0 && (unsigned)(pc - dck) < (unsigned)ec;
-    const int u = g - sign * sa4 - dck * sc4;
-    const float4 yv = Yd[g];
-    const unsigned mv = M4[g];
-    float4 yu = make_float4(0.f, 0.f, 0.f, 0.f);
-    unsigned mu = 0;
-    if (rowin) {
-      yu = Yd[u];
-      mu = M4[u];
-    }
-    const float prev_w = __shfl_up(yu.w, 1);
-    const float next_x = __shfl_down(yu.x, 1);
-    const unsigned prev_m = __shfl_up(mu, 1) >> 24;
-    const unsigned next_m = __shfl_down(mu, 1) & 0xffu;
-    // upwind value and class of each of the four voxels, and whether it exists
-    float su[4] = {yu.x, yu.y, yu.z, yu.w};
-    unsigned cu[4] = {mu & 0xffu, (mu >> 8) & 0xffu, (mu >> 16) & 0xffu, mu >> 24};
-    bool in[4] = {rowin, rowin, rowin, rowin};
-    if (dbk > 0) {
-      float w = 0.f;
-      unsigned cw = 0;
-      const bool have = rowin && q > 0;
-      if (have) {
-        w = lane > 0 ? prev_w : Ys[4 * u - 1];
-        cw = lane > 0 ? prev_m : A.mat[4 * u - 1];
-      }
-      su[3] = su[2]; su[2] = su[1]; su[1] = su[0]; su[0] = w;
-      cu[3] = cu[2]; cu[2] = cu[1]; cu[1] = cu[0]; cu[0] = cw;
-      in[0] = have;
-    } else if (dbk < 0) {
-      float w = 0.f;
-      unsigned cw = 0;
-      const bool have = rowin && q < tq - 1;
-      if (have) {
-        w = lane < 63 ? next_x : Ys[4 * u + 4];
-        cw = lane < 63 ? next_m : A.mat[4 * u + 4];
-      }
-      su[0] = su[1]; su[1] = su[2]; su[2] = su[3]; su[3] = w;
-      cu[0] = cu[1]; cu[1] = cu[2]; cu[2] = cu[3]; cu[3] = cw;
-      in[3] = have;
-    }
-    const float sv[4] = {yv.x, yv.y, yv.z, yv.w};
-    float o[4], mvv[4];
+  // band of TB rows: about two float4 per thread per item (at most four when
+  // one row alone exceeds that, nx <= 4096)
+  int TB = 2 * kThreads / tq;
+  if (TB < 1) TB = 1;
+  if (TB > nf) TB = nf;
+  const int per = TB * tq;
+  constexpr int EMAX = 4;
+  int fo[EMAX], qq[EMAX];
 #pragma unroll
-    for (int j = 0; j < 4; ++j) {
-      const unsigned cv = (mv >> (8 * j)) & 0xffu;
-      const float fv = nu * srt[cv & 0x7fu];
-      bool inj = in[j];
-      if (FRESNEL) inj = inj && ((cu[j] ^ cv) & 0x7fu) == 0;
-      const float fu = inj ? nu * srt[cu[j] & 0x7fu] : 0.0f;
-      o[j] = fmaf(fu, su[j], (1.0f - fv) * sv[j]);
-      mvv[j] = fv * sv[j];
-    }
-    Xd[g] = make_float4(o[0], o[1], o[2], o[3]);
-    acc.dom += (double(o[0]) + double(o[1])) + (double(o[2]) + double(o[3]));
-    const bool last = k + 1 >= ea;
-    if (last) {
-      acc.esc_a += (double(mvv[0]) + double(mvv[1])) + (double(mvv[2]) + double(mvv[3]));
-    } else {
-      const bool cexit = (unsigned)(pc + dcn) >= (unsigned)ec;
+  for (int j = 0; j < EMAX; ++j) {
+    const int e = threadIdx.x + j * kThreads;
+    fo[j] = e / tq;
+    qq[j] = e - fo[j] * tq;
+  }
+  const int nb = (nf + TB - 1) / TB;
+  const long long T = (long long)nb * ns;   // at most 4096^2 items
+  const int i0 = int(T * blk / nblk), i1 = int(T * (blk + 1) / nblk);
+  for (int i = i0; i < i1; ++i) {
+    const int band = i / ns, k = i - band * ns;
+    const int pa = sign > 0 ? k : ns - 1 - k;
+    const int dbk = db[k], dck = dc[k], dbn = db[k + 1], dcn = dc[k + 1];
+    const bool last = k + 1 >= ns;
+#pragma unroll
+    for (int j = 0; j < EMAX; ++j) {
+      if (j * kThreads >= per) break;
+      const int pc = band * TB + fo[j];
+      const int q = qq[j];
+      const bool act = threadIdx.x + j * kThreads < per && pc < nf;
+      const int y = AX == 2 ? pc : pa, z = AX == 2 ? pa : pc;
+      const int g = (z * ny + y) * tq + q;
+      const bool rowin = act && k > 0 && (unsigned)(pc - dck) < (unsigned)nf;
+      const int u = g - sign * sa4 - dck * sc4;
+      float4 yv = make_float4(0.f, 0.f, 0.f, 0.f), yu = yv;
+      unsigned mv = 0, mu = 0;
+      // class bytes: the background class for rows the bitmap marks, else per voxel
+      const int row = z * ny + y;
+      const int urow = row - sign * (AX == 1 ? 1 : ny) - dck * (CX == 1 ? 1 : ny);
+      if (act) {
+        yv = Yd[g];
+        mv = bg_row(rbits, row) ? bg4 : M4[g];
+      }
+      if (rowin) {
+        yu = Yd[u];
+        mu = bg_row(rbits, urow) ? bg4 : M4[u];
+      }
+      // the neighbour lane holds the next four voxels of the same row
+      const float prev_w = __shfl_up(yu.w, 1);
+      const float next_x = __shfl_down(yu.x, 1);
+      const unsigned prev_m = __shfl_up(mu, 1) >> 24;
+      const unsigned next_m = __shfl_down(mu, 1) & 0xffu;
+      if (!act) continue;
+      float su[4] = {yu.x, yu.y, yu.z, yu.w};
+      unsigned cu[4] = {mu & 0xffu, (mu >> 8) & 0xffu, (mu >> 16) & 0xffu, mu >> 24};
+      bool in[4] = {rowin, rowin, rowin, rowin};
+      if (dbk > 0) {
+        float w = 0.f;
+        unsigned cw = 0;
+        const bool have = rowin && q > 0;
+        if (have) {
+          w = lane > 0 ? prev_w : Ys[4 * u - 1];
+          cw = lane > 0 ? prev_m : A.mat[4 * u - 1];
+        }
+        su[3] = su[2]; su[2] = su[1]; su[1] = su[0]; su[0] = w;
+        cu[3] = cu[2]; cu[2] = cu[1]; cu[1] = cu[0]; cu[0] = cw;
+        in[0] = have;
+      } else if (dbk < 0) {
+        float w = 0.f;
+        unsigned cw = 0;
+        const bool have = rowin && q < tq - 1;
+        if (have) {
+          w = lane < 63 ? next_x : Ys[4 * u + 4];
+          cw = lane < 63 ? next_m : A.mat[4 * u + 4];
+        }
+        su[0] = su[1]; su[1] = su[2]; su[2] = su[3]; su[3] = w;
+        cu[0] = cu[1]; cu[1] = cu[2]; cu[2] = cu[3]; cu[3] = cw;
+        in[3] = have;
+      }
+      const float sv[4] = {yv.x, yv.y, yv.z, yv.w};
+      float o[4], mvv[4];
+#pragma unroll
+      for (int t = 0; t < 4; ++t) {
+        const unsigned cv = (mv >> (8 * t)) & 0xffu;
+        const float fv = nu * srt[cv & 0x7fu];
+        bool inj = in[t];
+        if (FRESNEL) inj = inj && ((cu[t] ^ cv) & 0x7fu) == 0;
+        const float fu = inj ? nu * srt[cu[t] & 0x7fu] : 0.0f;
+        o[t] = fmaf(fu, su[t], (1.0f - fv) * sv[t]);
+        mvv[t] = fv * sv[t];
+      }
+      // X is not read again in this step: stream it past the caches
+      const f32x4 ov = {o[0], o[1], o[2], o[3]};
+      __builtin_nontemporal_store(ov, reinterpret_cast<f32x4*>(Xd + g));
+      acc.dom += (double(o[0]) + double(o[1])) + (double(o[2]) + double(o[3]));
+      // light that leaves: through the exit plane, then the x sides, then the c sides
+      if (last) {
+        acc.esc_a += (double(mvv[0]) + double(mvv[1])) + (double(mvv[2]) + double(mvv[3]));
+        continue;
+      }
+      const bool cexit = (unsigned)(pc + dcn) >= (unsigned)nf;
       const bool b1 = dbn > 0 && q == tq - 1, b0 = dbn < 0 && q == 0;
       if (b1) { acc.esc_b1 += double(mvv[3]); mvv[3] = 0.f; }
       if (b0) { acc.esc_b0 += double(mvv[0]); mvv[0] = 0.f; }
@@ -821,40 +873,35 @@ __device__ __forceinline__ void sweep_split_vec(const SweepArgs& A, const DevDir
         if (dcn > 0) acc.esc_c1 += t; else acc.esc_c0 += t;
       } else if (FRESNEL && (mv & 0x80808080u)) {
         // an interface voxel among the four: compare with its downwind voxel
-        const int x0 = 4 * q;
         const int vb = 4 * g;
         const int wofs = sign * 4 * sa4 + dbn + dcn * 4 * sc4;
 #pragma unroll
-        for (int j = 0; j < 4; ++j) {
-          if (!((mv >> (8 * j)) & 0x80u)) continue;
-          if ((j == 3 && b1) || (j == 0 && b0)) continue;   // left through an x side
-          const int x = x0 + j;
-          if ((unsigned)(x + dbn) >= (unsigned)nx) continue;
-          const unsigned cw = A.mat[vb + j + wofs];
-          if (((cw ^ (mv >> (8 * j))) & 0x7fu) != 0) {
-            A.icptF[size_t(A.islot[vb + j]) * A.ndir + d] = mvv[j];
-            acc.dom += double(mvv[j]);
+        for (int t = 0; t < 4; ++t) {
+          if (!((mv >> (8 * t)) & 0x80u)) continue;
+          if ((t == 3 && b1) || (t == 0 && b0)) continue;   // left through an x side
+          const unsigned cw = A.mat[vb + t + wofs];
+          if (((cw ^ (mv >> (8 * t))) & 0x7fu) != 0) {
+            A.icptF[size_t(A.islot[vb + t]) * A.ndir + d] = mvv[t];
+            acc.dom += double(mvv[t]);
           }
         }
       }
     }
-    q += dq;
-    int adv = drow;
-    if (q >= tq) { q -= tq; ++adv; }
-    yy += adv;
-    while (yy >= ny) { yy -= ny; ++zz; }
   }
 }
 
-// Split mode, an x-dominant direction, with index-class bytes: lanes run
-// across planes, so each lane's plane index, shifts and exit face are fixed and
-// only the row (y, z) changes; four rows per iteration with all loads issued
-// before the stores.  Arithmetic and tallies as in sweep_split_vec.
+// x-dominant: lanes run across planes, so each lane's plane index, shifts and
+// exit face are fixed and only the row (y, z) changes.  Bands of 4 x rpi rows
+// across z are walked along y, four rows per lane per item with all loads
+// issued before the stores.
 template <bool FRESNEL>
 __device__ __forceinline__ void sweep_split_rows0(const SweepArgs& A, const DevDir& D, int d,
-                                                  int rb, int re, const int8_t* __restrict__ db,
+                                                  int blk, int nblk,
+                                                  const int8_t* __restrict__ db,
                                                   const int8_t* __restrict__ dc,
-                                                  const float* __restrict__ srt, SweepAcc& acc) {
+                                                  const float* __restrict__ srt,
+                                                  const uint32_t* __restrict__ rbits,
+                                                  SweepAcc& acc) {
   const int nx = A.nx, ny = A.ny, nz = A.nz;
   const int nxy = nx * ny;
   const float* __restrict__ Yd = A.Y + size_t(d) * A.Vp;
@@ -866,75 +913,60 @@ __device__ __forceinline__ void sweep_split_rows0(const SweepArgs& A, const DevD
   if (rsub >= rpi) return;
   const int sign = D.sign;
   const float nu = D.nu;
+  constexpr int RB = 4;
+  const int TB = RB * rpi;
+  const int nb = (nz + TB - 1) / TB;
+  const long long T = (long long)nb * ny;
+  const int i0 = int(T * blk / nblk), i1 = int(T * (blk + 1) / nblk);
   for (int x = xs; x < nx; x += tpr) {
     const int k = sign > 0 ? x : nx - 1 - x;
     const int dbk = db[k], dck = dc[k], dbn = db[k + 1], dcn = dc[k + 1];
     const bool exit_a = k + 1 >= nx;
     const int uoff = -sign - dbk * nx - dck * nxy;
     const int woff = sign + dbn * nx + dcn * nxy;
-    constexpr int RB = 4;
-    int yy[RB], zz[RB];
-    {
-      const int row = rb + rsub;
-      zz[0] = row / ny;
-      yy[0] = row - zz[0] * ny;
-#pragma unroll
-      for (int i = 1; i < RB; ++i) {
-        yy[i] = yy[i - 1] + rpi;
-        zz[i] = zz[i - 1];
-        while (yy[i] >= ny) {
-          yy[i] -= ny;
-          ++zz[i];
-        }
-      }
-    }
-    for (int row0 = rb + rsub; row0 < re; row0 += RB * rpi) {
-      int v[RB];
+    for (int i = i0; i < i1; ++i) {
+      const int band = i / ny, y = i - band * ny;
+      const bool yin = k > 0 && (unsigned)(y - dbk) < (unsigned)ny;
+      const bool yexit = (unsigned)(y + dbn) >= (unsigned)ny;
+      int v[RB], zz[RB];
       bool live[RB], in[RB];
       float yv[RB], yu[RB];
       unsigned cv[RB], cu[RB];
 #pragma unroll
-      for (int i = 0; i < RB; ++i) {
-        const int row = row0 + i * rpi;
-        live[i] = row < re;
-        v[i] = row * nx + x;
-        in[i] = live[i] && k > 0 && (unsigned)(yy[i] - dbk) < (unsigned)ny &&
-                (unsigned)(zz[i] - dck) < (unsigned)nz;
-        yv[i] = live[i] ? Yd[v[i]] : 0.0f;
-        cv[i] = live[i] ? M[v[i]] : 0u;
-        yu[i] = in[i] ? Yd[v[i] + uoff] : 0.0f;
-        cu[i] = in[i] ? M[v[i] + uoff] : 0u;
+      for (int r = 0; r < RB; ++r) {
+        zz[r] = band * TB + rsub + r * rpi;
+        live[r] = zz[r] < nz;
+        v[r] = (zz[r] * ny + y) * nx + x;
+        in[r] = live[r] && yin && (unsigned)(zz[r] - dck) < (unsigned)nz;
+        yv[r] = live[r] ? Yd[v[r]] : 0.0f;
+        yu[r] = in[r] ? Yd[v[r] + uoff] : 0.0f;
+        // class bytes: the background class for rows the bitmap marks
+        const int row = zz[r] * ny + y, urow = row - dbk - dck * ny;
+        cv[r] = !live[r] ? 0u : (bg_row(rbits, row) ? A.bgcls : M[v[r]]);
+        cu[r] = !in[r] ? 0u : (bg_row(rbits, urow) ? A.bgcls : M[v[r] + uoff]);
       }
 #pragma unroll
-      for (int i = 0; i < RB; ++i) {
-        if (!live[i]) continue;
-        const float fv = nu * srt[cv[i] & 0x7fu];
-        bool inf = in[i];
-        if (FRESNEL) inf = inf && ((cu[i] ^ cv[i]) & 0x7fu) == 0;
-        const float fu = inf ? nu * srt[cu[i] & 0x7fu] : 0.0f;
-        const float out = fmaf(fu, yu[i], (1.0f - fv) * yv[i]);
-        Xd[v[i]] = out;
+      for (int r = 0; r < RB; ++r) {
+        if (!live[r]) continue;
+        const float fv = nu * srt[cv[r] & 0x7fu];
+        bool inf = in[r];
+        if (FRESNEL) inf = inf && ((cu[r] ^ cv[r]) & 0x7fu) == 0;
+        const float fu = inf ? nu * srt[cu[r] & 0x7fu] : 0.0f;
+        const float out = fmaf(fu, yu[r], (1.0f - fv) * yv[r]);
+        __builtin_nontemporal_store(out, Xd + v[r]);
         acc.dom += double(out);
-        const float mv = fv * yv[i];
+        const float mv = fv * yv[r];
         if (exit_a) {
           acc.esc_a += double(mv);
-        } else if ((unsigned)(yy[i] + dbn) >= (unsigned)ny) {
+        } else if (yexit) {
           if (dbn > 0) acc.esc_b1 += double(mv); else acc.esc_b0 += double(mv);
-        } else if ((unsigned)(zz[i] + dcn) >= (unsigned)nz) {
+        } else if ((unsigned)(zz[r] + dcn) >= (unsigned)nz) {
           if (dcn > 0) acc.esc_c1 += double(mv); else acc.esc_c0 += double(mv);
-        } else if (FRESNEL && (cv[i] & 0x80u)) {
-          if (((M[v[i] + woff] ^ cv[i]) & 0x7fu) != 0) {
-            A.icptF[size_t(A.islot[v[i]]) * A.ndir + d] = mv;
+        } else if (FRESNEL && (cv[r] & 0x80u)) {
+          if (((M[v[r] + woff] ^ cv[r]) & 0x7fu) != 0) {
+            A.icptF[size_t(A.islot[v[r]]) * A.ndir + d] = mv;
             acc.dom += double(mv);
           }
-        }
-      }
-#pragma unroll
-      for (int i = 0; i < RB; ++i) {
-        yy[i] += RB * rpi;
-        while (yy[i] >= ny) {
-          yy[i] -= ny;
-          ++zz[i];
         }
       }
     }
@@ -951,7 +983,7 @@ __device__ __forceinline__ void sweep_split_rows0(const SweepArgs& A, const DevD
 template <bool SPLIT, bool FRESNEL, bool FAST = false>
 __device__ __forceinline__ void sweep_block(const SweepArgs& A, int d, int blk, int nblk,
                                             int8_t (&sdelta)[2][kMaxExt + 2],
-                                            float* srt = nullptr) {
+                                            float* srt = nullptr, uint32_t* rbits = nullptr) {
   const DevDir D = A.dirs[d];
   const int m = *A.step_ctr;
   const float fph = SPLIT ? 1.0f : phase_move(D.nu64, m);
@@ -985,24 +1017,29 @@ __device__ __forceinline__ void sweep_block(const SweepArgs& A, int d, int blk, 
       sdelta[1][i] = A.delta[(size_t(d) * 2 + 1) * A.dstride + i];
     }
     const bool vec = D.axis != 0 && (A.nx & 3) == 0 && D.unitb;
-    const bool smat = FAST || (SPLIT && A.mat != nullptr && srt != nullptr);
+    const bool smat = FAST || (SPLIT && A.mat != nullptr && srt != nullptr && rbits != nullptr);
     const bool svec = smat && vec;
     if (smat && threadIdx.x < 128) srt[threadIdx.x] = A.rtab[threadIdx.x];
+    if (smat) {
+      const int R = A.ny * A.nz;
+      const int nw = ((R < kMaxRowBits ? R : kMaxRowBits) + 31) >> 5;
+      for (int i = threadIdx.x; i < nw; i += kThreads) rbits[i] = A.rowbits[i];
+    }
     __syncthreads();
     if (FAST) {
       if (D.axis == 0)
-        sweep_split_rows0<FRESNEL>(A, D, d, rb, re, sdelta[0], sdelta[1], srt, acc);
+        sweep_split_rows0<FRESNEL>(A, D, d, blk, nblk, sdelta[0], sdelta[1], srt, rbits, acc);
       else if (D.axis == 2)
-        sweep_split_vec<2, FRESNEL>(A, D, d, rb, re, sdelta[0], sdelta[1], srt, acc);
+        sweep_split_vec<2, FRESNEL>(A, D, d, blk, nblk, sdelta[0], sdelta[1], srt, rbits, acc);
       else
-        sweep_split_vec<1, FRESNEL>(A, D, d, rb, re, sdelta[0], sdelta[1], srt, acc);
+        sweep_split_vec<1, FRESNEL>(A, D, d, blk, nblk, sdelta[0], sdelta[1], srt, rbits, acc);
     } else if (smat && D.axis == 0) {
-      sweep_split_rows0<FRESNEL>(A, D, d, rb, re, sdelta[0], sdelta[1], srt, acc);
+      sweep_split_rows0<FRESNEL>(A, D, d, blk, nblk, sdelta[0], sdelta[1], srt, rbits, acc);
     } else if (svec) {
       if (D.axis == 2)
-        sweep_split_vec<2, FRESNEL>(A, D, d, rb, re, sdelta[0], sdelta[1], srt, acc);
+        sweep_split_vec<2, FRESNEL>(A, D, d, blk, nblk, sdelta[0], sdelta[1], srt, rbits, acc);
       else
-        sweep_split_vec<1, FRESNEL>(A, D, d, rb, re, sdelta[0], sdelta[1], srt, acc);
+        sweep_split_vec<1, FRESNEL>(A, D, d, blk, nblk, sdelta[0], sdelta[1], srt, rbits, acc);
     } else if (!SPLIT && D.axis != 0 && (A.nx & 3) == 0 && D.unitb) {
       if (D.axis == 2)
         sweep_phase_vec<2>(A, D, d, rb, re, sdelta[0], sdelta[1], acc);
@@ -1044,7 +1081,8 @@ template <bool SPLIT, bool FRESNEL, bool FAST>
 __global__ __launch_bounds__(kThreads) void sweep_kernel(SweepArgs A) {
   __shared__ int8_t sdelta[2][kMaxExt + 2];
   __shared__ float srt[128];
-  sweep_block<SPLIT, FRESNEL, FAST>(A, blockIdx.y, blockIdx.x, gridDim.x, sdelta, srt);
+  __shared__ uint32_t rbits[SPLIT ? kMaxRowBits / 32 : 1];
+  sweep_block<SPLIT, FRESNEL, FAST>(A, blockIdx.y, blockIdx.x, gridDim.x, sdelta, srt, rbits);
 }
 
 // Fresnel redistribution (Eq. 13-14): every target (direction, voxel) adds the

@@ -58,7 +58,9 @@ def closure_bound(b, ulps=1.0):
     # longer than a wavefront, and a one-vector row
     ("phase", 3, (20, 7, 9)), ("phase", 4, (264, 3, 4)), ("phase", 5, (4, 6, 5)),
     ("phase", 6, (12, 11, 3)), ("split", 7, (20, 7, 9)), ("split", 8, (264, 3, 4)),
-    ("split", 9, (12, 11, 3))])
+    ("split", 9, (12, 11, 3)), ("split", 10, (4, 6, 5)),
+    # several bands of rows in each direction class
+    ("split", 11, (64, 40, 6)), ("split", 12, (64, 6, 40))])
 def test_single_step_matches_oracle(advance, seed, shape):
     """One step from a random state: every (direction, voxel) of the field."""
     nx, ny, nz = shape
