@@ -178,6 +178,32 @@ def test_graph_replay_equals_single_steps():
         b.close()
 
 
+def test_phantom64_full_size_matches_stored_oracle(golden_dir):
+    """The 64^3 / 192-direction / 1000-step phantom in full, in the launch
+    configuration the benchmark times, against the FP64 oracle's per-step
+    detector records and budget (written by tests/golden/make_golden.py)."""
+    import os
+
+    from oracle import setup as osetup
+    z = np.load(os.path.join(golden_dir, "phantom64_oracle.npz"))
+    p = W.config2()
+    got = run_gpu(p)
+    assert got["steps"].shape == z["det"].shape
+    assert abs(got["info"].dt_ps - float(z["dt"])) < 1e-12
+    ref = z["det"]
+    assert rel_l2_above(got["steps"].ravel(), ref.ravel()) < 1e-4
+    Wm = osetup.rebin_matrix(ref.shape[1], float(z["dt"]), p.bin_ps, p.nbins)
+    rb = ref @ Wm
+    for k in range(p.ndet):
+        assert rel_l2_above(got["binned"][k], rb[k]) < 1e-4, k
+    b, ob = got["budget"], z["budget"]
+    assert np.allclose(b[:, 0], ob[:, 0], rtol=1e-6, atol=1e-15)
+    assert np.allclose(b[:, 1], ob[:, 1], rtol=1e-4, atol=1e-12)
+    assert np.allclose(b[:, 3:].sum(axis=1), ob[:, 2], rtol=1e-4, atol=1e-12)
+    assert np.allclose(b[:, 2], ob[:, 3], rtol=1e-4, atol=1e-12)
+    assert budget_closure(b) < closure_bound(b)
+
+
 def test_edge_cases():
     """nside 1 (12 directions), a one-voxel-thick slab, zero steps."""
     p = W.small_problem(nside=1, nx=5, ny=3, nz=1, mua=0.01, mus=1.0, g=0.3, steps=15,
