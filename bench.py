@@ -47,6 +47,22 @@ def kernel_rooflines(prof, prob, precision):
     return out
 
 
+def oracle_error(prob, det_steps):
+    """Relative L2 error of per-step detector records against the stored FP64
+    oracle run of the same phantom (bins above 1e-6 of the peak)."""
+    import numpy as np
+    path = os.path.join(ROOT, "tests", "golden", "phantom64_oracle.npz")
+    if not os.path.exists(path):
+        return None
+    ref = np.load(path)["det"]
+    k = min(ref.shape[1], det_steps.shape[1])
+    if k < ref.shape[1]:
+        return None
+    got, ref = det_steps[:, :k].ravel(), ref[:, :k].ravel()
+    mask = ref > 1e-6 * ref.max()
+    return float(np.linalg.norm(got[mask] - ref[mask]) / np.linalg.norm(ref[mask]))
+
+
 def timed_run(prob, steps, warmup, stream):
     import torch
 
@@ -65,6 +81,7 @@ def timed_run(prob, steps, warmup, stream):
         t1 = time.perf_counter()
         prof = m.profile_end()
         budget = m.read_budget()
+        det_steps = m.read_detector_steps()
         # the same steps replayed from captured graphs, no events
         m.reset()
         torch.cuda.synchronize()
@@ -76,7 +93,7 @@ def timed_run(prob, steps, warmup, stream):
         m.close()
     inj = budget[:, 0].sum()
     closure = abs(inj - budget[:, 1].sum() - budget[:, 3:].sum() - budget[-1, 2]) / max(inj, 1e-300)
-    return t1 - t0, g1 - g0, prof, closure
+    return t1 - t0, g1 - g0, prof, closure, det_steps
 
 
 def latency(prob, solves, stream):
@@ -97,6 +114,99 @@ def latency(prob, solves, stream):
             times.append((time.perf_counter() - t0) * 1e3)
         m.close()
     return float(np.percentile(times, 50)), float(np.percentile(times, 99))
+
+
+def serving(stream, count=16):
+    """Batched server on the first `count` requests of the seeded serving
+    stream (Poisson arrivals at 200/s, grids 32^3 .. 96^3, 192 directions,
+    500-1500 steps): p50/p99 latency with queueing, once at the offered rate
+    (far above capacity) and once with arrivals stretched to 0.8 x the
+    measured capacity."""
+    import numpy as np
+
+    from paper_2105_01028_amd import serve
+    from paper_2105_01028_amd import trinity as T
+    from paper_2105_01028_amd import workloads as W
+    import torch
+    reqs = W.serving_stream(count, seed=4)
+    work = [r.problem.nvox * 192 * r.problem.steps for r in reqs]
+    out = {"requests": count, "updates": float(sum(work))}
+    with torch.cuda.stream(stream):
+        srv = T.Server(nside=4, g=0.85, budget_bytes=32 << 30, max_slots=16)
+        sat = serve.run_stream(srv, reqs, chunk_steps=64)
+        cap = sum(work) / sat["wall_s"]
+        ts = 200.0 * (sum(work) / count) / (0.8 * cap)
+        low = serve.run_stream(srv, reqs, chunk_steps=64, time_scale=ts)
+        srv.close()
+    for key, r in (("offered_200_per_s", sat), ("offered_0.8_capacity", low)):
+        lat = r["latency_s"] * 1e3
+        out[key] = {"p50_ms": float(np.percentile(lat, 50)), "p99_ms": float(np.percentile(lat, 99)),
+                    "wall_s": r["wall_s"], "completed": r["completed"]}
+    out["capacity_updates_per_s"] = cap
+    out["arrival_stretch_0.8"] = ts
+    return out
+
+
+def adjoint_timing(stream):
+    """Forward solve with checkpoints every 50 steps and the adjoint, on the
+    64^3 / 192-direction / 500-step adjoint medium."""
+    import numpy as np
+    import torch
+
+    from paper_2105_01028_amd import trinity as T
+    from paper_2105_01028_amd import workloads as W
+    p = W.config5()
+    with torch.cuda.stream(stream):
+        m = T.Medium.from_problem(p)
+        m.solve_checkpointed(p.steps, 50)
+        y = m.read_detectors()
+        m.backward(np.ones_like(y))
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        m.solve_checkpointed(p.steps, 50)
+        y = m.read_detectors()
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        m.backward(np.ones_like(y))
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+        m.close()
+    upd = p.nvox * p.ndir * p.steps
+    return {"forward_ms": (t1 - t0) * 1e3, "backward_ms": (t2 - t1) * 1e3,
+            "backward_over_forward": (t2 - t1) / (t1 - t0),
+            "forward_updates_per_s": upd / (t1 - t0), "checkpoint_every": 50,
+            "workload": "64^3, 192 directions, 500 steps, three absorbing spheres"}
+
+
+def refraction128(stream, steps=20):
+    """The 128^3 / 768-direction heterogeneous medium with an air cylinder
+    (split advance, Fresnel interfaces): ms per step in FP32 and BF16-split."""
+    import torch
+
+    from paper_2105_01028_amd import trinity as T
+    from paper_2105_01028_amd import workloads as W
+    p = W.config3()
+    out = {"workload": "128^3, 768 directions (nside 8), air cylinder + 3 spheres, split advance",
+           "steps": steps}
+    for prec in ("fp32", "bf16split"):
+        q = p.copy(precision=prec)
+        with torch.cuda.stream(stream):
+            m = T.Medium.from_problem(q)
+            m.solve(3)
+            m.reset()
+            m.profile_begin(steps)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            m.step(steps)
+            m.synchronize()
+            t1 = time.perf_counter()
+            prof = m.profile_end()
+            m.close()
+        out[prec] = {"ms_per_step": (t1 - t0) / steps * 1e3,
+                     "updates_per_s": q.nvox * q.ndir * steps / (t1 - t0),
+                     "kernel_rooflines": kernel_rooflines(prof, q, prec),
+                     "kernels_ms": {k: v[0] / v[1] if v[1] else 0.0 for k, v in prof.items()}}
+    return out
 
 
 def cpu_baseline(prob, budget_s=15.0):
@@ -145,7 +255,7 @@ def main():
     stream = torch.cuda.Stream()
     prob = W.config2().copy(precision=args.precision)
     K, Wm = args.steps, args.warmup
-    el, el_graph, prof, closure = timed_run(prob, K, Wm, stream)
+    el, el_graph, prof, closure, det_steps = timed_run(prob, K, Wm, stream)
     updates = prob.nvox * prob.ndir * K
     roof = kernel_rooflines(prof, prob, args.precision)
     dom = max(("collide", "sweep"), key=lambda k: prof[k][0])
@@ -168,16 +278,21 @@ def main():
         "kernel_rooflines": roof,
         "graph_replay": {"value": updates / el_graph, "ms_per_step": el_graph / K * 1e3},
         "budget_closure": closure,
+        "rel_l2_vs_fp64_oracle": oracle_error(prob, det_steps),
     }
     if not args.no_extras:
         other = "bf16split" if args.precision == "fp32" else "fp32"
-        e2, g2, p2, c2 = timed_run(prob.copy(precision=other), K, Wm, stream)
+        e2, g2, p2, c2, d2 = timed_run(prob.copy(precision=other), K, Wm, stream)
         out[other] = {"value": updates / e2, "ms_per_step": e2 / K * 1e3,
                       "graph_value": updates / g2, "kernel_rooflines":
-                      kernel_rooflines(p2, prob, other), "budget_closure": c2}
+                      kernel_rooflines(p2, prob, other), "budget_closure": c2,
+                      "rel_l2_vs_fp64_oracle": oracle_error(prob, d2)}
         p50, p99 = latency(W.config1(), 30, stream)
         out["latency_uniform16"] = {"p50_ms": p50, "p99_ms": p99, "solves": 30,
                                     "workload": "16^3, 48 directions, 200 steps"}
+        out["serving"] = serving(stream)
+        out["adjoint"] = adjoint_timing(stream)
+        out["refraction128"] = refraction128(stream)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(prob)
     print(json.dumps(out), flush=True)
