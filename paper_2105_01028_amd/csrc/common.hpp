@@ -71,28 +71,35 @@ inline float bf16_bits_to_f32(unsigned short h) {
 
 // Rounding P to fp32 leaves each column sum (the light scattered out of one
 // incoming direction) off one by up to a few ulp of its largest entries, with a
-// bias that creates or destroys light at every scattering.  Nudge the smallest
-// entries of each column that can absorb the residual without changing sign:
-// each pass shrinks the residual to half an ulp of a small entry.
+// bias that creates or destroys light at every scattering.  Each pass moves the
+// residual into the largest entry of the column that absorbs at least half of
+// it, so that the relative change of any entry stays at the level of the
+// rounding itself (a small entry, such as a backward-scattering one, would
+// otherwise change by a large fraction of its value).
 inline void conserve_columns_f32(std::vector<float>& P, int n, int ld) {
   std::vector<int> order(n);
   for (int j = 0; j < n; ++j) {
     for (int i = 0; i < n; ++i) order[i] = i;
     std::sort(order.begin(), order.end(), [&](int p, int q) {
-      return P[size_t(p) * ld + j] < P[size_t(q) * ld + j];
+      return P[size_t(p) * ld + j] > P[size_t(q) * ld + j];
     });
-    for (int pass = 0; pass < 4; ++pass) {
+    for (int pass = 0; pass < 16; ++pass) {
       double s = 0;
       for (int i = 0; i < n; ++i) s += double(P[size_t(i) * ld + j]);
       const double r = 1.0 - s;
       if (r == 0.0) break;
+      bool moved = false;
       for (int i : order) {
         float& p = P[size_t(i) * ld + j];
-        if (double(p) > 64.0 * std::fabs(r)) {
-          p = float(double(p) + r);
+        const float np = float(double(p) + r);
+        const double rn = r - (double(np) - double(p));
+        if (np > 0.0f && std::fabs(rn) <= 0.5 * std::fabs(r)) {
+          p = np;
+          moved = true;
           break;
         }
       }
+      if (!moved) break;
     }
   }
 }
@@ -104,20 +111,27 @@ inline void conserve_columns_bf16(std::vector<uint16_t>& hi, std::vector<uint16_
   for (int j = 0; j < n; ++j) {
     for (int i = 0; i < n; ++i) order[i] = i;
     std::sort(order.begin(), order.end(), [&](int p, int q) {
-      return val(size_t(p) * ld + j) < val(size_t(q) * ld + j);
+      return val(size_t(p) * ld + j) > val(size_t(q) * ld + j);
     });
-    for (int pass = 0; pass < 8; ++pass) {
+    for (int pass = 0; pass < 16; ++pass) {
       double s = 0;
       for (int i = 0; i < n; ++i) s += val(size_t(i) * ld + j);
       const double r = 1.0 - s;
       if (r == 0.0) break;
+      bool moved = false;
       for (int i : order) {
         const size_t k = size_t(i) * ld + j;
-        if (val(k) > 64.0 * std::fabs(r)) {
-          lo[k] = f32_to_bf16_bits(float(double(bf16_bits_to_f32(lo[k])) + r));
+        const double l = double(bf16_bits_to_f32(lo[k]));
+        const uint16_t nl = f32_to_bf16_bits(float(l + r));
+        const double rn = r - (double(bf16_bits_to_f32(nl)) - l);
+        if (double(bf16_bits_to_f32(hi[k])) + double(bf16_bits_to_f32(nl)) > 0.0 &&
+            std::fabs(rn) <= 0.5 * std::fabs(r)) {
+          lo[k] = nl;
+          moved = true;
           break;
         }
       }
+      if (!moved) break;
     }
   }
 }

@@ -269,11 +269,133 @@ __global__ __launch_bounds__(512, 1) void collide_f32_res_kernel(CollideArgs A, 
   block_sums512(absorbed, total, A.part + blockIdx.x, A.part + gridDim.x + blockIdx.x);
 }
 
+// BF16-split collision with P_hi and P_lo resident in LDS (NP <= 192, 154 KB):
+// the persistent layout of collide_f32_res_kernel on v_mfma_f32_32x32x16_bf16.
+// A 16-deep K step takes 8 k per lane half; the k slots are mapped to physical
+// rows so that, over the two K steps of row block c, lane half h loads exactly
+// the 16 rows 32c + 8(s/4) + 4h + s%4 (s = 0..15) its accumulator holds, and
+// a_v X is again added as the rows arrive: slot j of K step t is row
+// 32c + 4h + 8(2t + j/4) + j%4, s = 8t + j.  P's columns are stored in LDS in
+// that slot order, so each lane's 8 k of a K step are one 16-byte read.
+template <int NP>
+__device__ __forceinline__ void load_p_bf16_lds(const uint16_t* __restrict__ Phi,
+                                                const uint16_t* __restrict__ Plo, uint16_t* Sh,
+                                                uint16_t* Sl) {
+  constexpr int LDK = NP + 8;
+  // groups of 4 slots: kappa = 32c + 16t + 8h + 4g2 holds physical columns
+  // 32c + 4h + 8(2t + g2) .. +3
+  for (int e = threadIdx.x; e < NP * (NP / 4); e += 512) {
+    const int r = e / (NP / 4), kap = (e - r * (NP / 4)) * 4;
+    const int c = kap >> 5, t = (kap >> 4) & 1, h = (kap >> 3) & 1, g2 = (kap >> 2) & 1;
+    const int ph = 32 * c + 4 * h + 8 * (2 * t + g2);
+    *reinterpret_cast<uint2*>(Sh + r * LDK + kap) =
+        *reinterpret_cast<const uint2*>(Phi + size_t(r) * NP + ph);
+    *reinterpret_cast<uint2*>(Sl + r * LDK + kap) =
+        *reinterpret_cast<const uint2*>(Plo + size_t(r) * NP + ph);
+  }
+}
+
+template <int NP>
+__device__ __forceinline__ void collide_bf16_res_tile(const CollideArgs& A,
+                                                      const uint16_t* Sh, const uint16_t* Sl,
+                                                      int tile, double& absorbed, double& total) {
+  constexpr int NQ = NP / 32;
+  constexpr int LDK = NP + 8;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int hl = lane >> 5, cl = lane & 31;
+  const size_t rowbytes = size_t(A.Vp) * sizeof(float);
+  const long long col = (long long)tile * 256 + wave * 32 + cl;
+  const unsigned voff = unsigned(size_t(col) * sizeof(float) + size_t(4 * hl) * rowbytes);
+  const char* __restrict__ xb0 = reinterpret_cast<const char*>(A.X);
+  const uint16_t* __restrict__ Ph = Sh + cl * LDK + 8 * hl;
+  const uint16_t* __restrict__ Pl = Sl + cl * LDK + 8 * hl;
+  const float av = A.a[col], bv = A.b[col];
+  floatx16 acc[NQ];
+#pragma unroll
+  for (int q = 0; q < NQ; ++q)
+#pragma unroll
+    for (int r = 0; r < 16; ++r) acc[q][r] = 0.0f;
+  auto ld = [&](int c, int s) {
+    const char* rb = xb0 + size_t(32 * c + 8 * (s >> 2) + (s & 3)) * rowbytes;
+    return *reinterpret_cast<const float*>(rb + voff);
+  };
+  float bcur[16], bnext[16];
+#pragma unroll
+  for (int s = 0; s < 16; ++s) bcur[s] = ld(0, s);
+  double colsum64 = 0.0;
+#pragma unroll 1
+  for (int c = 0; c < NQ; ++c) {
+    const int cn = c + 1 < NQ ? c + 1 : c;
+#pragma unroll
+    for (int s = 0; s < 16; ++s) bnext[s] = ld(cn, s);
+    float colsum = 0.0f;
+#pragma unroll
+    for (int s = 0; s < 16; ++s) colsum += bcur[s];
+    colsum64 += double(colsum);
+#pragma unroll
+    for (int q = 0; q < NQ; ++q)
+      if (q == c) {
+#pragma unroll
+        for (int s = 0; s < 16; ++s) acc[q][s] = fmaf(av, bcur[s], acc[q][s]);
+      }
+#pragma unroll
+    for (int t = 0; t < 2; ++t) {
+      bf16x8 xh, xl;
+#pragma unroll
+      for (int j = 0; j < 8; ++j) {
+        const float x = bcur[8 * t + j] * bv;
+        const unsigned short hi = bf16_bits(x);
+        xh[j] = __builtin_bit_cast(__bf16, hi);
+        xl[j] = __builtin_bit_cast(__bf16, bf16_bits(x - bf16_to_float(hi)));
+      }
+      const int kk = 32 * c + 16 * t;
+#pragma unroll
+      for (int q = 0; q < NQ; ++q) {
+        const bf16x8 ph = *reinterpret_cast<const bf16x8*>(Ph + q * 32 * LDK + kk);
+        const bf16x8 pl = *reinterpret_cast<const bf16x8*>(Pl + q * 32 * LDK + kk);
+        acc[q] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ph, xh, acc[q], 0, 0, 0);
+        acc[q] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ph, xl, acc[q], 0, 0, 0);
+        acc[q] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(pl, xh, acc[q], 0, 0, 0);
+        acc[q] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(pl, xl, acc[q], 0, 0, 0);
+      }
+    }
+#pragma unroll
+    for (int s = 0; s < 16; ++s) bcur[s] = bnext[s];
+  }
+  char* __restrict__ yb0 = reinterpret_cast<char*>(A.Y);
+#pragma unroll
+  for (int q = 0; q < NQ; ++q)
+#pragma unroll
+    for (int r = 0; r < 16; ++r)
+      *reinterpret_cast<float*>(yb0 + size_t(q * 32 + 8 * (r >> 2) + (r & 3)) * rowbytes + voff) =
+          acc[q][r];
+  absorbed += (1.0 - double(av) - double(bv)) * colsum64;
+  total += colsum64;
+}
+
+template <int NP>
+__global__ __launch_bounds__(512, 1) void collide_bf16_res_kernel(CollideArgs A, int ntiles) {
+  extern __shared__ uint16_t Sm[];
+  uint16_t* Sh = Sm;
+  uint16_t* Sl = Sm + NP * (NP + 8);
+  load_p_bf16_lds<NP>(A.Phi, A.Plo, Sh, Sl);
+  __syncthreads();
+  double absorbed = 0.0, total = 0.0;
+#pragma unroll 1
+  for (int tile = blockIdx.x; tile < ntiles; tile += gridDim.x)
+    collide_bf16_res_tile<NP>(A, Sh, Sl, tile, absorbed, total);
+  block_sums512(absorbed, total, A.part + blockIdx.x, A.part + gridDim.x + blockIdx.x);
+}
+
 // Same contraction with P and X each split into bf16 high and low parts,
-// X = X_hi + X_lo, P = P_hi + P_lo, and (P X) ~ P_hi X_hi + P_hi X_lo + P_lo X_hi
-// on v_mfma_f32_32x32x16_bf16 with fp32 accumulation (the dropped P_lo X_lo term
-// is below 2^-16 of the product).  P_hi / P_lo are staged through LDS as
-// [row][k] so each lane reads its 8 consecutive k in one 16-byte load.
+// X = X_hi + X_lo, P = P_hi + P_lo, and P X = (P_hi + P_lo)(X_hi + X_lo) as four
+// v_mfma_f32_32x32x16_bf16 products with fp32 accumulation.  The products of
+// bf16 values are exact in fp32, so the only errors are the two splits (2^-16
+// of each value) and the fp32 sums.  All four terms are kept: without
+// P_lo X_lo, whose column sums are not zero, the contraction would no longer
+// conserve the light of each incoming direction.  P_hi / P_lo are staged
+// through LDS as [row][k] so each lane reads its 8 consecutive k in one 16-byte
+// load.
 template <int MT>
 __global__ __launch_bounds__(kThreads, 2) void collide_bf16split_kernel(CollideArgs A) {
   constexpr int KC = 32;
@@ -321,6 +443,7 @@ __global__ __launch_bounds__(kThreads, 2) void collide_bf16split_kernel(CollideA
         acc[q] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ph, xh, acc[q], 0, 0, 0);
         acc[q] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ph, xl, acc[q], 0, 0, 0);
         acc[q] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(pl, xh, acc[q], 0, 0, 0);
+        acc[q] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(pl, xl, acc[q], 0, 0, 0);
       }
     }
   }
@@ -1396,24 +1519,36 @@ int resident_blocks() {
 }
 
 template <int NP>
-hipError_t prepare_res() {
-  const size_t lds = size_t(NP) * (NP + 4) * sizeof(float);
-  return hipFuncSetAttribute(reinterpret_cast<const void*>(&collide_f32_res_kernel<NP>),
-                             hipFuncAttributeMaxDynamicSharedMemorySize, int(lds));
+size_t res_lds(int bf16split) {
+  return bf16split ? 2 * size_t(NP) * (NP + 8) * sizeof(uint16_t)
+                   : size_t(NP) * (NP + 4) * sizeof(float);
 }
 
 template <int NP>
-hipError_t launch_res(const CollideArgs& a, const Field& f, hipStream_t s) {
-  const size_t lds = size_t(NP) * (NP + 4) * sizeof(float);
+hipError_t prepare_res(int bf16split) {
+  const void* k = bf16split ? reinterpret_cast<const void*>(&collide_bf16_res_kernel<NP>)
+                            : reinterpret_cast<const void*>(&collide_f32_res_kernel<NP>);
+  return hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize,
+                             int(res_lds<NP>(bf16split)));
+}
+
+template <int NP>
+hipError_t launch_res(const CollideArgs& a, const Field& f, int bf16split, hipStream_t s) {
+  const size_t lds = res_lds<NP>(bf16split);
   const int ntiles = int(f.Vp / 256);
   const int nb = ntiles < resident_blocks() ? ntiles : resident_blocks();
-  hipLaunchKernelGGL(collide_f32_res_kernel<NP>, dim3(unsigned(nb)), dim3(512), lds, s, a, ntiles);
+  if (bf16split)
+    hipLaunchKernelGGL(collide_bf16_res_kernel<NP>, dim3(unsigned(nb)), dim3(512), lds, s, a,
+                       ntiles);
+  else
+    hipLaunchKernelGGL(collide_f32_res_kernel<NP>, dim3(unsigned(nb)), dim3(512), lds, s, a,
+                       ntiles);
   return hipGetLastError();
 }
 
-// The resident kernel keeps 32-bit per-lane byte offsets of up to 5 rows.
-bool use_resident(const Field& f, int bf16split) {
-  return !bf16split && f.NP <= 192 && f.Vp * 4 * 5 < (1LL << 31);
+// The resident kernels keep 32-bit per-lane byte offsets of up to 5 rows.
+bool use_resident(const Field& f, int) {
+  return f.NP <= 192 && f.Vp * 4 * 5 < (1LL << 31);
 }
 
 }  // namespace
@@ -1421,12 +1556,12 @@ bool use_resident(const Field& f, int bf16split) {
 hipError_t prepare_collide(const Field& f, int bf16split) {
   if (!use_resident(f, bf16split)) return hipSuccess;
   switch (f.NP) {
-    case 32: return prepare_res<32>();
-    case 64: return prepare_res<64>();
-    case 96: return prepare_res<96>();
-    case 128: return prepare_res<128>();
-    case 160: return prepare_res<160>();
-    default: return prepare_res<192>();
+    case 32: return prepare_res<32>(bf16split);
+    case 64: return prepare_res<64>(bf16split);
+    case 96: return prepare_res<96>(bf16split);
+    case 128: return prepare_res<128>(bf16split);
+    case 160: return prepare_res<160>(bf16split);
+    default: return prepare_res<192>(bf16split);
   }
 }
 
@@ -1441,12 +1576,12 @@ int collide_nwg(const Field& f, int bf16split) {
 hipError_t launch_collide(const CollideArgs& a, const Field& f, int bf16split, int, hipStream_t s) {
   if (use_resident(f, bf16split)) {
     switch (f.NP) {
-      case 32: return launch_res<32>(a, f, s);
-      case 64: return launch_res<64>(a, f, s);
-      case 96: return launch_res<96>(a, f, s);
-      case 128: return launch_res<128>(a, f, s);
-      case 160: return launch_res<160>(a, f, s);
-      default: return launch_res<192>(a, f, s);
+      case 32: return launch_res<32>(a, f, bf16split, s);
+      case 64: return launch_res<64>(a, f, bf16split, s);
+      case 96: return launch_res<96>(a, f, bf16split, s);
+      case 128: return launch_res<128>(a, f, bf16split, s);
+      case 160: return launch_res<160>(a, f, bf16split, s);
+      default: return launch_res<192>(a, f, bf16split, s);
     }
   }
   switch (collide_mt(f.NP)) {

@@ -147,13 +147,18 @@ def test_refraction_air_cylinder():
     assert rel_l2_above(got["state"].ravel(), ref.state.ravel(), 0.0) < 1e-4
 
 
-def test_bf16split_matches_oracle():
-    p = W.small_problem(nside=4, nx=16, ny=12, nz=10, mua=0.01, mus=5.0, g=0.85, steps=60,
+@pytest.mark.parametrize("nside,shape", [(4, (16, 12, 10)), (2, (21, 14, 11)), (1, (9, 7, 5))])
+def test_bf16split_matches_oracle(nside, shape):
+    nx, ny, nz = shape
+    p = W.small_problem(nside=nside, nx=nx, ny=ny, nz=nz, mua=0.01, mus=5.0, g=0.85, steps=60,
                         seed=9, det_cone_deg=0.0, precision="bf16split")
     ref = solve.forward(p)
     got = run_gpu(p)
     assert rel_l2_above(got["steps"].ravel(), ref.det.ravel()) < 1e-4
-    assert budget_closure(got["budget"]) < closure_bound(got["budget"])
+    # every step stores each scattered value as x_hi + x_lo, off x by at most
+    # 2^-16 |x| (two round-to-nearest bf16 steps of 8 significant bits), and P's
+    # columns sum to one, so the budget closes to 2^-16 + 2^-23 per stored value
+    assert budget_closure(got["budget"]) < closure_bound(got["budget"], ulps=129.0)
 
 
 def test_graph_replay_equals_single_steps():
