@@ -21,29 +21,95 @@ sys.path.insert(0, ROOT)
 METRIC = ("voxel·direction·step updates/s (FP32 vs BF16-split); "
           "p50/p99 solve latency")
 PEAK_HBM_GBS = 8000.0
-PEAK_TFLOPS = {"fp32": 157.3, "bf16split": 2500.0}
+PEAK_TFLOPS = {"fp32": 157.3, "bf16split": 2500.0}   # dense MFMA peaks
 
 
-def kernel_rooflines(prof, prob, precision):
-    """Achieved rates of the collide (MFMA) and sweep (HBM) kernels from their
-    average launch durations and the algorithmic work per launch."""
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "hbm_traffic_collide_sweep.txt")
+
+
+def kernel_source_hash():
+    import hashlib
+    with open(os.path.join(ROOT, "paper_2105_01028_amd", "csrc", "kernels.hip"), "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()[:16]
+
+
+def measured_traffic(kernel, precision, workload):
+    """HBM bytes per launch of `kernel` from the committed rocprofv3 counter
+    summary (FETCH_SIZE and WRITE_SIZE per dispatch, each scaled by what the
+    counter reads for a plain copy of known size), or None when there is none
+    or the kernel source has changed since the counters were taken."""
+    if not os.path.exists(TRAFFIC_FILE):
+        return None
+    rows = {}
+    for line in open(TRAFFIC_FILE):
+        line = line.strip()
+        if not line or line.startswith("#"):
+            continue
+        kv = dict(item.split("=", 1) for item in line.split())
+        rows[(kv.get("workload"), kv.get("kernel"), kv.get("precision"))] = kv
+    kv = rows.get((workload, kernel, precision))
+    if kv is None or kv.get("source") != kernel_source_hash():
+        return None
+    return (float(kv["fetch_kib"]) * float(kv["fetch_scale"]) +
+            float(kv["write_kib"]) * float(kv["write_scale"])) * 1024.0
+
+
+def copy_probe(nbytes):
+    """A plain device copy of known size (the calibration of the HBM counters)."""
+    import torch
+    n = nbytes // 4
+    a = torch.ones(n, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    for _ in range(5):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_probe_bytes_read": n * 4, "copy_probe_bytes_written": n * 4,
+                      "copies": 5}), flush=True)
+
+
+def kernel_rooflines(prof, prob, precision, workload="phantom64"):
+    """Achieved rates of the collide and sweep kernels from their average
+    launch durations and the algorithmic work per launch.
+
+    collide, FP32: 2 N^2 V FLOP on the FP32 MFMA peak.  collide, BF16-split:
+    the four hi/lo products execute 8 N^2 V bf16 FLOP; at few directions the
+    kernel is bound by its 8 N V bytes (read X, write Y) instead, and the
+    binding roofline (the larger fraction) is reported, with the effective
+    FP32-equivalent rate 2 N^2 V / t beside it.  sweep: 8 N V bytes (read the
+    collided field once, write the new one once) on the HBM peak."""
     N, V = prob.ndir, prob.nvox
     out = {}
     ms, n = prof["collide"]
     if n:
         t = ms / n * 1e-3
-        flop = 2.0 * N * N * V * (3 if precision == "bf16split" else 1)
-        out["collide"] = {"bound": "mfma", "achieved": flop / t / 1e12,
-                          "peak": PEAK_TFLOPS[precision], "unit": "TFLOP/s",
-                          "frac": flop / t / 1e12 / PEAK_TFLOPS[precision],
-                          "avg_ms": ms / n, "work_per_launch": flop, "traffic": None}
+        if precision == "fp32":
+            flop = 2.0 * N * N * V
+            out["collide"] = {"bound": "mfma", "achieved": flop / t / 1e12, "peak": 157.3,
+                              "unit": "TFLOP/s", "frac": flop / t / 1e12 / 157.3,
+                              "avg_ms": ms / n, "work_per_launch": flop}
+        else:
+            flop = 8.0 * N * N * V
+            byt = 8.0 * N * V
+            f_mfma = flop / t / 1e12 / PEAK_TFLOPS["bf16split"]
+            f_hbm = byt / t / 1e9 / PEAK_HBM_GBS
+            if f_mfma >= f_hbm:
+                out["collide"] = {"bound": "mfma", "achieved": flop / t / 1e12,
+                                  "peak": PEAK_TFLOPS["bf16split"], "unit": "TFLOP/s",
+                                  "frac": f_mfma, "avg_ms": ms / n, "work_per_launch": flop}
+            else:
+                out["collide"] = {"bound": "hbm", "achieved": byt / t / 1e9, "peak": PEAK_HBM_GBS,
+                                  "unit": "GB/s", "frac": f_hbm, "avg_ms": ms / n,
+                                  "work_per_launch": byt}
+            out["collide"]["effective_fp32_equiv_tflops"] = 2.0 * N * N * V / t / 1e12
+        out["collide"]["traffic"] = measured_traffic("collide", precision, workload)
     ms, n = prof["sweep"]
     if n:
         t = ms / n * 1e-3
         byt = 8.0 * N * V
         out["sweep"] = {"bound": "hbm", "achieved": byt / t / 1e9, "peak": PEAK_HBM_GBS,
                         "unit": "GB/s", "frac": byt / t / 1e9 / PEAK_HBM_GBS,
-                        "avg_ms": ms / n, "work_per_launch": byt, "traffic": None}
+                        "avg_ms": ms / n, "work_per_launch": byt,
+                        "traffic": measured_traffic("sweep", precision, workload)}
     return out
 
 
@@ -178,7 +244,7 @@ def adjoint_timing(stream):
             "workload": "64^3, 192 directions, 500 steps, three absorbing spheres"}
 
 
-def refraction128(stream, steps=20):
+def refraction128(stream, steps=20, precisions=("fp32", "bf16split")):
     """The 128^3 / 768-direction heterogeneous medium with an air cylinder
     (split advance, Fresnel interfaces): ms per step in FP32 and BF16-split."""
     import torch
@@ -188,7 +254,7 @@ def refraction128(stream, steps=20):
     p = W.config3()
     out = {"workload": "128^3, 768 directions (nside 8), air cylinder + 3 spheres, split advance",
            "steps": steps}
-    for prec in ("fp32", "bf16split"):
+    for prec in precisions:
         q = p.copy(precision=prec)
         with torch.cuda.stream(stream):
             m = T.Medium.from_problem(q)
@@ -204,7 +270,7 @@ def refraction128(stream, steps=20):
             m.close()
         out[prec] = {"ms_per_step": (t1 - t0) / steps * 1e3,
                      "updates_per_s": q.nvox * q.ndir * steps / (t1 - t0),
-                     "kernel_rooflines": kernel_rooflines(prof, q, prec),
+                     "kernel_rooflines": kernel_rooflines(prof, q, prec, "refraction128"),
                      "kernels_ms": {k: v[0] / v[1] if v[1] else 0.0 for k, v in prof.items()}}
     return out
 
@@ -241,7 +307,19 @@ def main():
     ap.add_argument("--precision", default="fp32", choices=["fp32", "bf16split"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true")
+    ap.add_argument("--workload", default="phantom64", choices=["phantom64", "refraction128"],
+                    help="refraction128: only time the 128^3 x 768 medium (profiling runs)")
+    ap.add_argument("--copy-probe", type=int, default=0, metavar="BYTES",
+                    help="only run a plain device copy of BYTES (counter calibration)")
     args = ap.parse_args()
+    if args.copy_probe:
+        copy_probe(args.copy_probe)
+        return
+    if args.workload == "refraction128":
+        import torch
+        print(json.dumps(refraction128(torch.cuda.Stream(), args.steps, (args.precision,))),
+              flush=True)
+        return
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only; --gpus {args.gpus} is not supported "
               "(the multi-GPU z-slab decomposition is a design, not part of this build)",
@@ -262,7 +340,7 @@ def main():
     rl = dict(roof[dom])
     rl["kernel"] = dom
     rl = {k: rl[k] for k in ("bound", "achieved", "peak", "unit", "frac", "traffic", "kernel",
-                             "avg_ms", "work_per_launch")}
+                             "avg_ms", "work_per_launch") if k in rl}
     out = {
         "metric": METRIC, "value": updates / el, "unit": "updates/s", "n_gpus": 1,
         "steps": K, "warmup": Wm, "ms_per_step": el / K * 1e3, "higher_is_better": True,
