@@ -73,7 +73,8 @@ typedef struct {
                          steps the direction's phase selects (n must be uniform);
                          TR_ADVANCE_SPLIT: the fraction nu_d * min(n)/n_v moves each step */
   int precision;      /* TR_PREC_FP32 or TR_PREC_BF16SPLIT (P and N split into bf16 hi+lo,
-                         three bf16 MFMA products, fp32 accumulation) */
+                         the four bf16 MFMA products, fp32 accumulation; each value
+                         off by at most 2^-16 of itself) */
 } tr_grid_desc;
 
 typedef struct {
