@@ -174,7 +174,10 @@ tr_status tr_read_budget(tr_medium* m, double* out, size_t n_out);
 tr_status tr_read_energy(tr_medium* m, float* out, int on_device);
 
 /* Copy the photon field N[d][v] (ndir*nvox floats, direction-major) out of
- * or into the medium, in host or device memory.  For tests and restarts. */
+ * or into the medium, in host or device memory.  For tests and restarts.  The
+ * copy is queued on the medium's stream after its earlier work and waited for;
+ * device data that the caller wrote on another stream must be complete
+ * before the call. */
 tr_status tr_get_state(tr_medium* m, float* out, int on_device);
 tr_status tr_set_state(tr_medium* m, const float* in, int on_device);
 

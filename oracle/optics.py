@@ -95,6 +95,34 @@ def index_gradient(nidx, x, y, z):
             0.5 * (at(x, y, z + 1) - at(x, y, z - 1)))
 
 
+def intercept(lat, nidx, d, v, w):
+    """The interception of direction d's move from voxel v into voxel w, where
+    n differs: (R, d_reflected, d_refracted) as described for interceptions()."""
+    nz, ny, nx = nidx.shape
+    x, y, z = v % nx, (v // nx) % ny, v // (nx * ny)
+    wx, wy, wz = w % nx, (w // nx) % ny, w // (nx * ny)
+    gx, gy, gz = index_gradient(nidx, x, y, z)
+    gn = math.sqrt((gx * gx + gy * gy) + gz * gz)
+    if gn > 0.0:
+        h = (gx / gn, gy / gn, gz / gn)
+    else:
+        sx, sy, sz = float(wx - x), float(wy - y), float(wz - z)
+        sn = math.sqrt((sx * sx + sy * sy) + sz * sz)
+        h = (sx / sn, sy / sn, sz / sn)
+    om = tuple(lat.dirs[d])
+    if dot3(om, h) < 0.0:
+        h = (-h[0], -h[1], -h[2])
+    n1, n2 = float(nidx[z, y, x]), float(nidx[wz, wy, wx])
+    cos1 = dot3(om, h)
+    R = fresnel_reflectance(n1, n2, cos1)
+    dr = nearest_direction(lat.dirs, reflect(om, h))
+    t = refract(om, h, n1, n2)
+    if t is None:
+        R = 1.0
+    dt = -1 if R >= 1.0 else nearest_direction(lat.dirs, t)
+    return R, dr, dt
+
+
 def interceptions(lat, nidx):
     """All interface crossings of the lattice for index field nidx [z, y, x].
 
@@ -103,36 +131,15 @@ def interceptions(lat, nidx):
     R of Eq. (14), d_reflected the direction snapped from the mirror direction
     and d_refracted the one snapped from Snell's direction (-1 under total
     internal reflection)."""
-    nz, ny, nx = nidx.shape
     nflat = np.asarray(nidx, dtype=np.float64).ravel()
     out = []
     for d in range(len(lat.dirs)):
         dest, _ = lat.downwind(d)
         v_all = np.nonzero(dest >= 0)[0]
         diff = v_all[nflat[dest[v_all]] != nflat[v_all]]
-        om = tuple(lat.dirs[d])
         for v in diff:
             v = int(v)
             w = int(dest[v])
-            x, y, z = v % nx, (v // nx) % ny, v // (nx * ny)
-            gx, gy, gz = index_gradient(nidx, x, y, z)
-            gn = math.sqrt((gx * gx + gy * gy) + gz * gz)
-            if gn > 0.0:
-                h = (gx / gn, gy / gn, gz / gn)
-            else:
-                wx, wy, wz = w % nx, (w // nx) % ny, w // (nx * ny)
-                sx, sy, sz = float(wx - x), float(wy - y), float(wz - z)
-                sn = math.sqrt((sx * sx + sy * sy) + sz * sz)
-                h = (sx / sn, sy / sn, sz / sn)
-            if dot3(om, h) < 0.0:
-                h = (-h[0], -h[1], -h[2])
-            n1, n2 = nflat[v], nflat[w]
-            cos1 = dot3(om, h)
-            R = fresnel_reflectance(n1, n2, cos1)
-            dr = nearest_direction(lat.dirs, reflect(om, h))
-            t = refract(om, h, n1, n2)
-            if t is None:
-                R = 1.0
-            dt = -1 if R >= 1.0 else nearest_direction(lat.dirs, t)
+            R, dr, dt = intercept(lat, nidx, d, v, w)
             out.append((d, v, w, R, dr, dt))
     return out

@@ -330,9 +330,14 @@ tr_status tr_create_medium(const tr_grid_desc* desc, const float* mua, const flo
     hmua.resize(f.V);
     hmus.resize(f.V);
     m->nhost.resize(f.V);
-    hipError_t e = hipMemcpy(hmua.data(), mua, f.V * 4, hipMemcpyDeviceToHost);
-    if (e == hipSuccess) e = hipMemcpy(hmus.data(), mus, f.V * 4, hipMemcpyDeviceToHost);
-    if (e == hipSuccess) e = hipMemcpy(m->nhost.data(), n, f.V * 4, hipMemcpyDeviceToHost);
+    // on the given stream, after the work the caller queued there (which may
+    // be what wrote the arrays)
+    hipError_t e = hipMemcpyAsync(hmua.data(), mua, f.V * 4, hipMemcpyDeviceToHost, m->stream);
+    if (e == hipSuccess)
+      e = hipMemcpyAsync(hmus.data(), mus, f.V * 4, hipMemcpyDeviceToHost, m->stream);
+    if (e == hipSuccess)
+      e = hipMemcpyAsync(m->nhost.data(), n, f.V * 4, hipMemcpyDeviceToHost, m->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(m->stream);
     if (e != hipSuccess) {
       delete m;
       return fail(TR_EINVAL, std::string("reading device arrays: ") + hipGetErrorString(e));
@@ -822,8 +827,11 @@ tr_status tr_get_state(tr_medium* m, float* out, int on_device) {
   tr_status st = tr_synchronize(m);
   if (st != TR_OK) return st;
   if (!out) return fail(TR_EINVAL, "null output");
-  hipError_t e = hipMemcpy2D(out, m->f.V * 4, m->X, m->f.Vp * 4, m->f.V * 4, m->f.ndir,
-                             on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost);
+  // on the medium's stream, so that work the caller queued there is ordered with the copy
+  hipError_t e = hipMemcpy2DAsync(out, m->f.V * 4, m->X, m->f.Vp * 4, m->f.V * 4, m->f.ndir,
+                                  on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost,
+                                  m->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(m->stream);
   if (e != hipSuccess) return device_fail(m, e, "state read");
   return TR_OK;
 }
@@ -832,8 +840,10 @@ tr_status tr_set_state(tr_medium* m, const float* in, int on_device) {
   tr_status st = tr_synchronize(m);
   if (st != TR_OK) return st;
   if (!in) return fail(TR_EINVAL, "null input");
-  hipError_t e = hipMemcpy2D(m->X, m->f.Vp * 4, in, m->f.V * 4, m->f.V * 4, m->f.ndir,
-                             on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice);
+  hipError_t e = hipMemcpy2DAsync(m->X, m->f.Vp * 4, in, m->f.V * 4, m->f.V * 4, m->f.ndir,
+                                  on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice,
+                                  m->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(m->stream);
   if (e != hipSuccess) return device_fail(m, e, "state write");
   return TR_OK;
 }

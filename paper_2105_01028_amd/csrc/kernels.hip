@@ -1013,6 +1013,66 @@ __device__ __forceinline__ void sweep_split_vec(const SweepArgs& A, const DevDir
   }
 }
 
+// Phase mode, a moving x-dominant direction, in the band order of the split
+// paths: a lane's plane, shifts and exit face are fixed, bands of 4 x rpi rows
+// across z are walked along y, and the upwind rows a wave reads in pieces
+// (they differ lane by lane by a row in y or z) are still in L2 when the
+// neighbouring rows' waves read the rest of their cache lines.
+__device__ __forceinline__ void sweep_phase_band0(const SweepArgs& A, const DevDir& D, int d,
+                                                  int blk, int nblk,
+                                                  const int8_t* __restrict__ db,
+                                                  const int8_t* __restrict__ dc, SweepAcc& acc) {
+  const int nx = A.nx, ny = A.ny, nz = A.nz;
+  const int nxy = nx * ny;
+  const float* __restrict__ Yd = A.Y + size_t(d) * A.Vp;
+  float* __restrict__ Xd = A.X + size_t(d) * A.Vp;
+  const int tpr = nx < kThreads ? nx : kThreads;
+  const int rpi = kThreads / tpr;
+  const int xs = threadIdx.x % tpr, rsub = threadIdx.x / tpr;
+  if (rsub >= rpi) return;
+  const int sign = D.sign;
+  constexpr int RB = 4;
+  const int TB = RB * rpi;
+  const int nb = (nz + TB - 1) / TB;
+  const long long T = (long long)nb * ny;
+  const int i0 = int(T * blk / nblk), i1 = int(T * (blk + 1) / nblk);
+  for (int x = xs; x < nx; x += tpr) {
+    const int k = sign > 0 ? x : nx - 1 - x;
+    const int dbk = db[k], dck = dc[k], dbn = db[k + 1], dcn = dc[k + 1];
+    const bool exit_a = k + 1 >= nx;
+    const int uoff = -sign - dbk * nx - dck * nxy;
+    for (int i = i0; i < i1; ++i) {
+      const int band = i / ny, y = i - band * ny;
+      const bool yin = k > 0 && (unsigned)(y - dbk) < (unsigned)ny;
+      const bool yexit = (unsigned)(y + dbn) >= (unsigned)ny;
+      int v[RB], zz[RB];
+      bool live[RB];
+      float out[RB];
+#pragma unroll
+      for (int r = 0; r < RB; ++r) {
+        zz[r] = band * TB + rsub + r * rpi;
+        live[r] = zz[r] < nz;
+        v[r] = (zz[r] * ny + y) * nx + x;
+        const bool in = live[r] && yin && (unsigned)(zz[r] - dck) < (unsigned)nz;
+        out[r] = in ? Yd[v[r] + uoff] : 0.0f;
+      }
+#pragma unroll
+      for (int r = 0; r < RB; ++r) {
+        if (!live[r]) continue;
+        Xd[v[r]] = out[r];
+        acc.dom += double(out[r]);
+        if (exit_a) {
+          acc.esc_a += double(Yd[v[r]]);
+        } else if (yexit) {
+          if (dbn > 0) acc.esc_b1 += double(Yd[v[r]]); else acc.esc_b0 += double(Yd[v[r]]);
+        } else if ((unsigned)(zz[r] + dcn) >= (unsigned)nz) {
+          if (dcn > 0) acc.esc_c1 += double(Yd[v[r]]); else acc.esc_c0 += double(Yd[v[r]]);
+        }
+      }
+    }
+  }
+}
+
 // x-dominant: lanes run across planes, so each lane's plane index, shifts and
 // exit face are fixed and only the row (y, z) changes.  Bands of 4 x rpi rows
 // across z are walked along y, four rows per lane per item with all loads
@@ -1174,7 +1234,7 @@ __device__ __forceinline__ void sweep_block(const SweepArgs& A, int d, int blk, 
       else if (D.axis == 1)
         sweep_phase_rows<1>(A, D, d, rb, re, sdelta[0], sdelta[1], acc);
       else
-        sweep_phase_rows<0>(A, D, d, rb, re, sdelta[0], sdelta[1], acc);
+        sweep_phase_band0(A, D, d, blk, nblk, sdelta[0], sdelta[1], acc);
     } else if (D.axis == 2) {
       sweep_rows<2, SPLIT, FRESNEL>(A, D, d, rb, re, sdelta[0], sdelta[1], acc);
     } else if (D.axis == 1) {

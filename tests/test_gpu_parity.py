@@ -74,6 +74,26 @@ def test_single_step_matches_oracle(advance, seed, shape):
     assert np.allclose(got["budget"][0, 3:], ref.escaped[0], rtol=2e-6, atol=1e-9)
 
 
+@pytest.mark.parametrize("nside,precision,advance,shape", [
+    (5, "fp32", "phase", (12, 9, 7)), (8, "fp32", "phase", (9, 8, 6)),
+    (8, "fp32", "split", (12, 8, 6)), (5, "bf16split", "split", (12, 9, 7)),
+    (8, "bf16split", "phase", (9, 8, 6))])
+def test_single_step_many_directions(nside, precision, advance, shape):
+    """More than 192 directions (300 and 768): the collision kernels that
+    stream P through LDS in chunks, element by element after one step."""
+    nx, ny, nz = shape
+    p = W.small_problem(nside=nside, nx=nx, ny=ny, nz=nz, mua=0.05, mus=3.0, g=0.8, steps=1,
+                        seed=11, advance=advance, precision=precision, total_photons=0.0)
+    ndir = 12 * nside * nside
+    rng = np.random.default_rng(nside)
+    N0 = rng.uniform(0, 1, (ndir, p.nvox)).astype(np.float32)
+    ref = solve.forward(p, steps=1, state0=N0.astype(np.float64))
+    got = run_gpu(p, steps=1, state0=N0)
+    # fp32 sums of N products: the rounding grows like sqrt(N)
+    tol = 2e-6 * max(1.0, np.sqrt(ndir / 192.0)) if precision == "fp32" else 4e-5
+    assert np.abs(got["state"] - ref.state).max() <= tol * np.abs(ref.state).max()
+
+
 @pytest.mark.parametrize("shape,seed", [((13, 10, 9), 1), ((20, 12, 9), 2), ((8, 70, 5), 3)])
 def test_single_step_with_interfaces(shape, seed):
     """One split-mode step from a random state in a medium with an index blob
@@ -253,3 +273,74 @@ def test_errors_are_reported_not_raised_across_the_abi():
             m.step(-1)
         m.solve(2)
         m.close()
+
+
+@pytest.mark.parametrize("precision,tol", [("fp32", 2e-6), ("bf16split", 4e-5)])
+def test_refraction128_full_size_sampled_single_step(precision, tol):
+    """The 128^3 / 768-direction medium with the air cylinder and spheres, in
+    the launch configuration of a full solve: one step from a state that is
+    non-zero in small cubes around interface, inclusion, edge and interior
+    voxels, compared at every direction of the voxels around them with the
+    single-output oracle (oracle/pointwise.py).  fp32: 2e-6 of the largest
+    sampled value; BF16-split: each value split as hi + lo is off by at most
+    2^-16 of itself, 4e-5."""
+    import torch
+
+    from oracle import pointwise
+    p = W.config3().copy(precision=precision, total_photons=0.0)
+    nz, ny, nx = p.nz, p.ny, p.nx
+    n = np.asarray(p.n)
+    rng = np.random.default_rng(31)
+    jump = np.zeros(n.shape, bool)
+    jump[:, :, :-1] |= n[:, :, 1:] != n[:, :, :-1]
+    jump[:, :-1, :] |= n[:, 1:, :] != n[:, :-1, :]
+    jump[:-1, :, :] |= n[1:, :, :] != n[:-1, :, :]
+    iz, iy, ix = np.nonzero(jump)
+    pick = rng.choice(len(ix), 4, replace=False)
+    centres = [(int(ix[i]), int(iy[i]), int(iz[i])) for i in pick]
+    centres += [(60, 64, 32), (0, 0, 0), (127, 5, 127), (64, 127, 0), (33, 90, 70)]
+    ndir = 12 * p.nside ** 2
+    vox = set()
+    for cx, cy, cz in centres:
+        for dz in range(-2, 3):
+            for dy in range(-2, 3):
+                for dx in range(-2, 3):
+                    x, y, z = cx + dx, cy + dy, cz + dz
+                    if 0 <= x < nx and 0 <= y < ny and 0 <= z < nz:
+                        vox.add((z * ny + y) * nx + x)
+    vox = np.array(sorted(vox))
+    cols = rng.uniform(0.0, 1.0, (ndir, len(vox))).astype(np.float32)
+    where = {int(v): i for i, v in enumerate(vox)}
+    with torch.cuda.stream(_stream()):
+        m = T.Medium.from_problem(p)
+        state = torch.zeros((ndir, p.nvox), dtype=torch.float32, device="cuda")
+        state[:, torch.as_tensor(vox, device="cuda")] = torch.as_tensor(cols, device="cuda")
+        m.set_state(state)
+        m.step(1)
+        m.synchronize()
+        m.get_state(state)
+        torch.cuda.synchronize()
+        out_vox = []
+        for cx, cy, cz in centres:
+            for dz in range(-1, 2):
+                for dy in range(-1, 2):
+                    for dx in range(-1, 2):
+                        x, y, z = cx + dx, cy + dy, cz + dz
+                        if 0 <= x < nx and 0 <= y < ny and 0 <= z < nz:
+                            out_vox.append((z * ny + y) * nx + x)
+        out_vox = np.array(sorted(set(out_vox)))
+        got = state[:, torch.as_tensor(out_vox, device="cuda")].cpu().numpy()
+        info = m.info()
+        m.close()
+        del state
+    assert info.ninterceptions > 0
+    L = pointwise.build(p)
+    zero = np.zeros(ndir)
+
+    def column(w):
+        i = where.get(int(w))
+        return zero if i is None else cols[:, i].astype(np.float64)
+    ref = np.stack([pointwise.step_outputs(L, column, int(v)) for v in out_vox], axis=1)
+    scale = np.abs(ref).max()
+    assert scale > 0
+    assert np.abs(got - ref).max() <= tol * scale
