@@ -387,6 +387,243 @@ __global__ __launch_bounds__(512, 1) void collide_bf16_res_kernel(CollideArgs A,
   block_sums512(absorbed, total, A.part + blockIdx.x, A.part + gridDim.x + blockIdx.x);
 }
 
+// More directions than fit in LDS (NP > 192): the layout of the resident kernel
+// (512 threads, 256 voxel columns, lane half h holding the X rows
+// 32c + 8(s/4) + 4h + s%4 of row block c, which are the rows of its accumulator
+// block when block c lies in the workgroup's row tile), with the workgroup's MT
+// rows of P streamed through LDS in 32-column chunks, double-buffered: while
+// chunk c feeds the MFMAs, chunk c+1 of P and of X is loaded into registers,
+// and it goes to the other LDS buffer before the one barrier per chunk.
+// a_v X is added as the X rows of the workgroup's own row tile arrive, so the
+// epilogue only stores; the budget partials cover the tile's rows.
+template <int MT>
+__global__ __launch_bounds__(512, 1) void collide_f32_stream_kernel(CollideArgs A) {
+  constexpr int NQ = MT / 32;
+  constexpr int KC = 32, LDK = KC + 4;
+  constexpr int NPR = (MT * KC / 4 + 511) / 512;   // float4 of P per thread per chunk
+  extern __shared__ float Pbuf[];                   // [2][MT][LDK]
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int hl = lane >> 5, cl = lane & 31;
+  const int NC = A.NP / KC;
+  const int row0 = blockIdx.y * MT;
+  const size_t rowbytes = size_t(A.Vp) * sizeof(float);
+  const long long col = (long long)blockIdx.x * 256 + wave * 32 + cl;
+  const unsigned voff = unsigned(size_t(col) * sizeof(float) + size_t(4 * hl) * rowbytes);
+  const char* __restrict__ xb0 = reinterpret_cast<const char*>(A.X);
+  const float av = A.a[col], bv = A.b[col];
+  auto ld = [&](int c, int s) {
+    const char* rb = xb0 + size_t(32 * c + 8 * (s >> 2) + (s & 3)) * rowbytes;
+    return *reinterpret_cast<const float*>(rb + voff);
+  };
+  float4 preg[NPR];
+  auto stage = [&](int c) {
+#pragma unroll
+    for (int i = 0; i < NPR; ++i) {
+      const int e = tid + i * 512;
+      if (e < MT * KC / 4) {
+        const int r = e / (KC / 4), k4 = (e - r * (KC / 4)) * 4;
+        preg[i] = *reinterpret_cast<const float4*>(A.Prow + size_t(row0 + r) * A.NP + 32 * c + k4);
+      }
+    }
+  };
+  auto put = [&](int buf) {
+    float* Pb = Pbuf + buf * MT * LDK;
+#pragma unroll
+    for (int i = 0; i < NPR; ++i) {
+      const int e = tid + i * 512;
+      if (e < MT * KC / 4) {
+        const int r = e / (KC / 4), k4 = (e - r * (KC / 4)) * 4;
+        *reinterpret_cast<float4*>(Pb + r * LDK + k4) = preg[i];
+      }
+    }
+  };
+  floatx16 acc[NQ];
+#pragma unroll
+  for (int q = 0; q < NQ; ++q)
+#pragma unroll
+    for (int r = 0; r < 16; ++r) acc[q][r] = 0.0f;
+  float bcur[16], bnext[16];
+  stage(0);
+#pragma unroll
+  for (int s = 0; s < 16; ++s) bcur[s] = ld(0, s);
+  put(0);
+  __syncthreads();
+  double colsum64 = 0.0;
+#pragma unroll 1
+  for (int c = 0; c < NC; ++c) {
+    const int cn = c + 1 < NC ? c + 1 : c;   // the last chunk reloads itself (in bounds, unused)
+    stage(cn);
+#pragma unroll
+    for (int s = 0; s < 16; ++s) bnext[s] = ld(cn, s);
+    const int qc = c - row0 / 32;           // accumulator block of this chunk's rows, if in the tile
+    if (qc >= 0 && qc < NQ) {
+      float cs = 0.0f;
+#pragma unroll
+      for (int s = 0; s < 16; ++s) cs += bcur[s];
+      colsum64 += double(cs);
+#pragma unroll
+      for (int q = 0; q < NQ; ++q)
+        if (q == qc) {
+#pragma unroll
+          for (int s = 0; s < 16; ++s) acc[q][s] = fmaf(av, bcur[s], acc[q][s]);
+        }
+    }
+#pragma unroll
+    for (int s = 0; s < 16; ++s) bcur[s] *= bv;
+    const float* __restrict__ Pl = Pbuf + (c & 1) * MT * LDK + cl * LDK + 4 * hl;
+#pragma unroll
+    for (int s4 = 0; s4 < 16; s4 += 4) {
+      const int kk = 8 * (s4 >> 2);
+#pragma unroll
+      for (int q = 0; q < NQ; ++q) {
+        const float4 a4 = *reinterpret_cast<const float4*>(Pl + q * 32 * LDK + kk);
+        acc[q] = __builtin_amdgcn_mfma_f32_32x32x2f32(a4.x, bcur[s4 + 0], acc[q], 0, 0, 0);
+        acc[q] = __builtin_amdgcn_mfma_f32_32x32x2f32(a4.y, bcur[s4 + 1], acc[q], 0, 0, 0);
+        acc[q] = __builtin_amdgcn_mfma_f32_32x32x2f32(a4.z, bcur[s4 + 2], acc[q], 0, 0, 0);
+        acc[q] = __builtin_amdgcn_mfma_f32_32x32x2f32(a4.w, bcur[s4 + 3], acc[q], 0, 0, 0);
+      }
+    }
+    if (c + 1 < NC) put((c + 1) & 1);
+    __syncthreads();
+#pragma unroll
+    for (int s = 0; s < 16; ++s) bcur[s] = bnext[s];
+  }
+  char* __restrict__ yb0 = reinterpret_cast<char*>(A.Y);
+#pragma unroll
+  for (int q = 0; q < NQ; ++q)
+#pragma unroll
+    for (int r = 0; r < 16; ++r)
+      *reinterpret_cast<float*>(yb0 + size_t(row0 + q * 32 + 8 * (r >> 2) + (r & 3)) * rowbytes +
+                                voff) = acc[q][r];
+  const long long nwg = (long long)gridDim.x * gridDim.y;
+  const long long wg = (long long)blockIdx.y * gridDim.x + blockIdx.x;
+  block_sums512((1.0 - double(av) - double(bv)) * colsum64, colsum64, A.part + wg,
+                A.part + nwg + wg);
+}
+
+// BF16-split form of collide_f32_stream_kernel: P_hi and P_lo chunks of 32
+// columns in LDS, double-buffered, with each chunk's columns stored in the k
+// slot order of collide_bf16_res_kernel (slot 16t + 8h + j holds column
+// 4h + 8(2t + j/4) + j%4 of the chunk), so each lane's 8 k of a K step are one
+// 16-byte read and its X rows are its accumulator rows.
+template <int MT>
+__global__ __launch_bounds__(512, 1) void collide_bf16_stream_kernel(CollideArgs A) {
+  constexpr int NQ = MT / 32;
+  constexpr int KC = 32, LDK = KC + 8;             // bf16 per LDS row
+  constexpr int NG = MT * (KC / 4);                // 8-byte groups per matrix per chunk
+  constexpr int NPR = (NG + 511) / 512;
+  extern __shared__ uint16_t Sbuf[];               // [2][hi, lo][MT][LDK]
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int hl = lane >> 5, cl = lane & 31;
+  const int NC = A.NP / KC;
+  const int row0 = blockIdx.y * MT;
+  const size_t rowbytes = size_t(A.Vp) * sizeof(float);
+  const long long col = (long long)blockIdx.x * 256 + wave * 32 + cl;
+  const unsigned voff = unsigned(size_t(col) * sizeof(float) + size_t(4 * hl) * rowbytes);
+  const char* __restrict__ xb0 = reinterpret_cast<const char*>(A.X);
+  const float av = A.a[col], bv = A.b[col];
+  auto ld = [&](int c, int s) {
+    const char* rb = xb0 + size_t(32 * c + 8 * (s >> 2) + (s & 3)) * rowbytes;
+    return *reinterpret_cast<const float*>(rb + voff);
+  };
+  uint2 rh[NPR], rl[NPR];
+  auto stage = [&](int c) {
+#pragma unroll
+    for (int i = 0; i < NPR; ++i) {
+      const int e = tid + i * 512;
+      if (e < NG) {
+        const int r = e / (KC / 4), kap = (e - r * (KC / 4)) * 4;
+        const int t = (kap >> 4) & 1, h = (kap >> 3) & 1, g2 = (kap >> 2) & 1;
+        const size_t g = size_t(row0 + r) * A.NP + 32 * c + 4 * h + 8 * (2 * t + g2);
+        rh[i] = *reinterpret_cast<const uint2*>(A.Phi + g);
+        rl[i] = *reinterpret_cast<const uint2*>(A.Plo + g);
+      }
+    }
+  };
+  auto put = [&](int buf) {
+    uint16_t* Sh = Sbuf + buf * 2 * MT * LDK;
+    uint16_t* Sl = Sh + MT * LDK;
+#pragma unroll
+    for (int i = 0; i < NPR; ++i) {
+      const int e = tid + i * 512;
+      if (e < NG) {
+        const int r = e / (KC / 4), kap = (e - r * (KC / 4)) * 4;
+        *reinterpret_cast<uint2*>(Sh + r * LDK + kap) = rh[i];
+        *reinterpret_cast<uint2*>(Sl + r * LDK + kap) = rl[i];
+      }
+    }
+  };
+  floatx16 acc[NQ];
+#pragma unroll
+  for (int q = 0; q < NQ; ++q)
+#pragma unroll
+    for (int r = 0; r < 16; ++r) acc[q][r] = 0.0f;
+  float bcur[16], bnext[16];
+  stage(0);
+#pragma unroll
+  for (int s = 0; s < 16; ++s) bcur[s] = ld(0, s);
+  put(0);
+  __syncthreads();
+  double colsum64 = 0.0;
+#pragma unroll 1
+  for (int c = 0; c < NC; ++c) {
+    const int cn = c + 1 < NC ? c + 1 : c;   // the last chunk reloads itself (in bounds, unused)
+    stage(cn);
+#pragma unroll
+    for (int s = 0; s < 16; ++s) bnext[s] = ld(cn, s);
+    const int qc = c - row0 / 32;
+    if (qc >= 0 && qc < NQ) {
+      float cs = 0.0f;
+#pragma unroll
+      for (int s = 0; s < 16; ++s) cs += bcur[s];
+      colsum64 += double(cs);
+#pragma unroll
+      for (int q = 0; q < NQ; ++q)
+        if (q == qc) {
+#pragma unroll
+          for (int s = 0; s < 16; ++s) acc[q][s] = fmaf(av, bcur[s], acc[q][s]);
+        }
+    }
+    const uint16_t* __restrict__ Ph = Sbuf + (c & 1) * 2 * MT * LDK + cl * LDK + 8 * hl;
+    const uint16_t* __restrict__ Pl = Ph + MT * LDK;
+#pragma unroll
+    for (int t = 0; t < 2; ++t) {
+      bf16x8 xh, xl;
+#pragma unroll
+      for (int j = 0; j < 8; ++j) {
+        const float x = bcur[8 * t + j] * bv;
+        const unsigned short hi = bf16_bits(x);
+        xh[j] = __builtin_bit_cast(__bf16, hi);
+        xl[j] = __builtin_bit_cast(__bf16, bf16_bits(x - bf16_to_float(hi)));
+      }
+#pragma unroll
+      for (int q = 0; q < NQ; ++q) {
+        const bf16x8 ph = *reinterpret_cast<const bf16x8*>(Ph + q * 32 * LDK + 16 * t);
+        const bf16x8 pl = *reinterpret_cast<const bf16x8*>(Pl + q * 32 * LDK + 16 * t);
+        acc[q] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ph, xh, acc[q], 0, 0, 0);
+        acc[q] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ph, xl, acc[q], 0, 0, 0);
+        acc[q] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(pl, xh, acc[q], 0, 0, 0);
+        acc[q] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(pl, xl, acc[q], 0, 0, 0);
+      }
+    }
+    if (c + 1 < NC) put((c + 1) & 1);
+    __syncthreads();
+#pragma unroll
+    for (int s = 0; s < 16; ++s) bcur[s] = bnext[s];
+  }
+  char* __restrict__ yb0 = reinterpret_cast<char*>(A.Y);
+#pragma unroll
+  for (int q = 0; q < NQ; ++q)
+#pragma unroll
+    for (int r = 0; r < 16; ++r)
+      *reinterpret_cast<float*>(yb0 + size_t(row0 + q * 32 + 8 * (r >> 2) + (r & 3)) * rowbytes +
+                                voff) = acc[q][r];
+  const long long nwg = (long long)gridDim.x * gridDim.y;
+  const long long wg = (long long)blockIdx.y * gridDim.x + blockIdx.x;
+  block_sums512((1.0 - double(av) - double(bv)) * colsum64, colsum64, A.part + wg,
+                A.part + nwg + wg);
+}
+
 // Same contraction with P and X each split into bf16 high and low parts,
 // X = X_hi + X_lo, P = P_hi + P_lo, and P X = (P_hi + P_lo)(X_hi + X_lo) as four
 // v_mfma_f32_32x32x16_bf16 products with fp32 accumulation.  The products of
@@ -1555,14 +1792,43 @@ int collide_mt(int NP) {
 template <template <int> class K>
 struct Dummy;
 
+// The streamed kernel keeps 32-bit per-lane byte offsets of up to 5 rows.
+bool use_stream(const Field& f, int) {
+  return f.Vp * 4 * 5 < (1LL << 31);
+}
+
+template <int MT>
+size_t stream_lds(int bf16split) {
+  return bf16split ? 2 * 2 * size_t(MT) * (32 + 8) * sizeof(uint16_t)
+                   : 2 * size_t(MT) * (32 + 4) * sizeof(float);
+}
+
 template <int MT>
 hipError_t launch_collide_mt(const CollideArgs& a, const Field& f, int bf16split, hipStream_t s) {
+  if (use_stream(f, bf16split)) {
+    dim3 grid(unsigned(f.Vp / 256), unsigned(f.NP / MT));
+    if (bf16split)
+      hipLaunchKernelGGL(collide_bf16_stream_kernel<MT>, grid, dim3(512), stream_lds<MT>(1), s,
+                         a);
+    else
+      hipLaunchKernelGGL(collide_f32_stream_kernel<MT>, grid, dim3(512), stream_lds<MT>(0), s,
+                         a);
+    return hipGetLastError();
+  }
   dim3 grid(unsigned(f.Vp / 128), unsigned(f.NP / MT));
   if (bf16split)
     hipLaunchKernelGGL(collide_bf16split_kernel<MT>, grid, dim3(kThreads), 0, s, a);
   else
     hipLaunchKernelGGL(collide_f32_kernel<MT>, grid, dim3(kThreads), 0, s, a);
   return hipGetLastError();
+}
+
+template <int MT>
+hipError_t prepare_stream_mt(int bf16split) {
+  const void* k = bf16split ? reinterpret_cast<const void*>(&collide_bf16_stream_kernel<MT>)
+                            : reinterpret_cast<const void*>(&collide_f32_stream_kernel<MT>);
+  return hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize,
+                             int(stream_lds<MT>(bf16split)));
 }
 
 int resident_blocks() {
@@ -1614,7 +1880,19 @@ bool use_resident(const Field& f, int) {
 }  // namespace
 
 hipError_t prepare_collide(const Field& f, int bf16split) {
-  if (!use_resident(f, bf16split)) return hipSuccess;
+  if (!use_resident(f, bf16split)) {
+    if (!use_stream(f, bf16split)) return hipSuccess;
+    switch (collide_mt(f.NP)) {
+      case 256: return prepare_stream_mt<256>(bf16split);
+      case 224: return prepare_stream_mt<224>(bf16split);
+      case 192: return prepare_stream_mt<192>(bf16split);
+      case 160: return prepare_stream_mt<160>(bf16split);
+      case 128: return prepare_stream_mt<128>(bf16split);
+      case 96: return prepare_stream_mt<96>(bf16split);
+      case 64: return prepare_stream_mt<64>(bf16split);
+      default: return prepare_stream_mt<32>(bf16split);
+    }
+  }
   switch (f.NP) {
     case 32: return prepare_res<32>(bf16split);
     case 64: return prepare_res<64>(bf16split);
@@ -1630,6 +1908,7 @@ int collide_nwg(const Field& f, int bf16split) {
     const int ntiles = int(f.Vp / 256);
     return ntiles < resident_blocks() ? ntiles : resident_blocks();
   }
+  if (use_stream(f, bf16split)) return int(f.Vp / 256) * (f.NP / collide_mt(f.NP));
   return int(f.Vp / 128) * (f.NP / collide_mt(f.NP));
 }
 
