@@ -1539,8 +1539,18 @@ __device__ __forceinline__ void reduce_part(const ReduceArgs& A, int q, int nq) 
     src = A.spart + (long long)(q == 1 ? 6 : q - 2) * A.snwg;
     n = A.snwg;
   }
+  // eight loads in flight per thread, summed in a fixed order
   double s = 0;
-  for (long long i = tid; i < n; i += kThreads) s += src[i];
+  for (long long i0 = tid; i0 < n; i0 += 8 * kThreads) {
+    double v[8];
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+      const long long i = i0 + (long long)j * kThreads;
+      v[j] = i < n ? src[i] : 0.0;
+    }
+#pragma unroll
+    for (int j = 0; j < 8; ++j) s += v[j];
+  }
   red[tid] = s;
   __syncthreads();
   for (int w = kThreads / 2; w > 0; w >>= 1) {
