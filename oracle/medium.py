@@ -61,6 +61,23 @@ def collision_coefficients(mua, mus, n, dt_ps, coef="paper"):
     return a, b, omega, ell
 
 
+def implicit_weights(mua, mus, n, dt_ps):
+    """Per-voxel (a, w0, w1) of the implicit collision: Eq. (10) with S0 the
+    source of the incoming intensity and S1 that of the outgoing one, both by
+    Eq. (12) at the voxel, gives for the column of a voxel
+        N_c = a N + w0 P N + w1 P N_c,   a = e^-dtau, w0 = omega f0, w1 = omega f1,
+    f0, f1 the Eq. (9) weights.  (Sec. 2.4 Steps 3-6 iterate this relation to
+    convergence.)"""
+    mua = np.asarray(mua, dtype=np.float64)
+    mus = np.asarray(mus, dtype=np.float64)
+    ell = path_per_step(n, dt_ps)
+    mut = mua + mus
+    tau = mut * ell
+    omega = np.where(mut > 0.0, mus / np.where(mut > 0.0, mut, 1.0), 0.0)
+    f0, f1 = eq9_weights(tau)
+    return np.exp(-tau), omega * f0, omega * f1
+
+
 def coefficient_derivatives(mua, mus, n, dt_ps, coef="paper"):
     """Partial derivatives of (a, b) with respect to (mu_a, mu_s), voxel by voxel.
 

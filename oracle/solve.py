@@ -51,6 +51,9 @@ class Setup:
     det_face: List[int]
     det_acc: List[List[int]]
     icpt: list                 # interface interceptions (d, v, w, R, d_r, d_t)
+    source: str = "explicit"   # "explicit" | "implicit"
+    w0: Optional[np.ndarray] = None   # implicit source: omega f0, omega f1 per voxel
+    w1: Optional[np.ndarray] = None
 
 
 def build(prob, steps=None, coef=None) -> Setup:
@@ -85,11 +88,19 @@ def build(prob, steps=None, coef=None) -> Setup:
                for f, i, j in zip(prob.det_face, prob.det_i, prob.det_j)]
     det_acc = [setup.detector_acceptance(dirs, f, prob.det_cone_deg) for f in prob.det_face]
     icpt = optics.interceptions(lat, n) if mode == "split" and not uniform else []
+    source = getattr(prob, "source", "explicit")
+    w0 = w1 = None
+    if source == "implicit":
+        _, w0, w1 = medium.implicit_weights(prob.mua, prob.mus, n, dt)
+        w0, w1 = w0.ravel(), w1.ravel()
+    elif source != "explicit":
+        raise ValueError(source)
     return Setup(dirs=dirs, P=P, lat=lat, dt=dt, a=a.ravel(), b=b.ravel(),
                  omega=omega.ravel(), ell=ell.ravel(), nu=nu, r=r, mode=mode,
                  downwind=dw, exit_face=ef, src_vox=src_vox, src_dirs=src_dirs,
                  pulse=(prob.t0_ps, prob.fwhm_ps, prob.total_photons),
-                 det_vox=det_vox, det_face=list(prob.det_face), det_acc=det_acc, icpt=icpt)
+                 det_vox=det_vox, det_face=list(prob.det_face), det_acc=det_acc, icpt=icpt,
+                 source=source, w0=w0, w1=w1)
 
 
 def move_fraction(S: Setup, d, m):
@@ -112,10 +123,32 @@ def inject(S: Setup, N, m):
 def collide(S: Setup, N):
     """Collision of Eq. (10) with S1 := S0 and S from Eq. (12): every voxel's
     column N[:, v] becomes a_v N[:, v] + b_v (P N)[:, v].  Returns the new
-    state and the photons absorbed, sum_v (1 - a_v - b_v) sum_d N[d, v]."""
+    state and the photons absorbed, sum_v (1 - a_v - b_v) sum_d N[d, v].
+    With the implicit source, collide_implicit."""
+    if S.source == "implicit":
+        return collide_implicit(S, N)
     J = S.P @ N
     Nc = S.a[None, :] * N + S.b[None, :] * J
     absorbed = float(np.sum((1.0 - S.a - S.b) * N.sum(axis=0)))
+    return Nc, absorbed
+
+
+def collide_implicit(S: Setup, N, chunk=256):
+    """Collision with the implicit source: S1 in Eq. (10) is the source of the
+    outgoing intensity, so every voxel's column solves
+        (I - w1_v P) N_c = a_v N + w0_v P N,
+    the fixed point that Sec. 2.4 Steps 3-6 iterate towards; solved here
+    directly, voxel by voxel.  Returns the new state and the photons absorbed,
+    sum N - sum N_c."""
+    nd, nv = N.shape
+    rhs = S.a[None, :] * N + S.w0[None, :] * (S.P @ N)
+    Nc = np.empty_like(N)
+    eye = np.eye(nd)
+    for v0 in range(0, nv, chunk):
+        v1 = min(nv, v0 + chunk)
+        M = eye[None, :, :] - S.w1[v0:v1, None, None] * S.P[None, :, :]
+        Nc[:, v0:v1] = np.linalg.solve(M, rhs[:, v0:v1].T[:, :, None])[:, :, 0].T
+    absorbed = float(N.sum() - Nc.sum())
     return Nc, absorbed
 
 
