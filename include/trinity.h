@@ -57,6 +57,7 @@ enum { TR_HG_SINKHORN = 0, TR_HG_ROW = 1 };
 enum { TR_COEF_PAPER = 0, TR_COEF_ABS_EXACT = 1 };
 enum { TR_ADVANCE_AUTO = 0, TR_ADVANCE_PHASE = 1, TR_ADVANCE_SPLIT = 2 };
 enum { TR_PREC_FP32 = 0, TR_PREC_BF16SPLIT = 1 };
+enum { TR_SOURCE_EXPLICIT = 0, TR_SOURCE_IMPLICIT = 1 };
 
 typedef struct {
   int nx, ny, nz;     /* voxels per axis, each >= 1 and <= 4096 */
@@ -75,6 +76,13 @@ typedef struct {
   int precision;      /* TR_PREC_FP32 or TR_PREC_BF16SPLIT (P and N split into bf16 hi+lo,
                          the four bf16 MFMA products, fp32 accumulation; each value
                          off by at most 2^-16 of itself) */
+  int source;         /* TR_SOURCE_EXPLICIT: S1 := S0 in Eq. (10) (default);
+                         TR_SOURCE_IMPLICIT: S1 is the source of the outgoing intensity,
+                         the fixed point of Sec. 2.4 Steps 3-6, solved per voxel in
+                         closed form through P = V diag(lambda) V^T:
+                         N_c = V diag((a + w0 lambda)/(1 - w1 lambda)) V^T N,
+                         w0 = omega f0, w1 = omega f1 (Eq. 9).  Needs TR_HG_SINKHORN,
+                         TR_COEF_PAPER, TR_PREC_FP32 and at most 192 directions. */
 } tr_grid_desc;
 
 typedef struct {

@@ -47,6 +47,7 @@ struct tr_medium {
   uint8_t* iface = nullptr;
   float* nvox = nullptr;
   int* islot = nullptr;
+  float *V = nullptr, *lam = nullptr, *w0 = nullptr, *w1 = nullptr, *cimp = nullptr;  // implicit
   uint8_t* mat = nullptr;   // split mode: index class | interface bit << 7, or null
   uint32_t* rowbits = nullptr;  // split mode: rows of background class only
   unsigned bgcls = 0;
@@ -230,8 +231,11 @@ hipError_t queue_step(tr_medium* m) {
   }
   {
     KernelTimer t(m, TR_K_COLLIDE);
-    CollideArgs ca{m->X, m->Y, m->P, m->Prow, m->Phi, m->Plo, m->a, m->b, f.Vp, f.NP, m->cpart};
-    if ((e = launch_collide(ca, f, m->desc.precision, 0, m->stream)) != hipSuccess) return e;
+    CollideArgs ca{m->X,   m->Y, m->P,  m->Prow, m->Phi, m->Plo, m->a,   m->b,
+                   f.Vp,   f.NP, m->cpart, m->V, m->lam, m->w0,  m->w1, m->cimp};
+    e = m->V ? launch_collide_implicit(ca, f, m->stream)
+             : launch_collide(ca, f, m->desc.precision, 0, m->stream);
+    if (e != hipSuccess) return e;
   }
   const bool split = m->mode == TR_ADVANCE_SPLIT;
   {
@@ -303,6 +307,8 @@ size_t tr_bytes_required(const tr_grid_desc* desc, int ndet, int max_steps) {
   if (!valid_desc(desc, err) || ndet < 0 || max_steps < 0) return 0;
   Field f = field_of(desc);
   size_t b = fixed_bytes(f, desc->precision, 0);
+  if (desc->source == TR_SOURCE_IMPLICIT)   // V, its eigenvalues, w0, w1, c
+    b += (size_t(f.NP) * f.NP + f.NP + 3 * size_t(f.Vp)) * sizeof(float);
   long long cap = std::max(1024, max_steps);
   b += size_t(cap) * (9 + std::max(ndet, 1) + 1) * sizeof(double);
   b += size_t(f.ndir) * 8 * sizeof(int) + 4096;
@@ -524,6 +530,47 @@ tr_status tr_create_medium(const tr_grid_desc* desc, const float* mua, const flo
     if (e == hipSuccess) e = hipMemcpy(m->gptr, ptr.data(), ptr.size() * 4, hipMemcpyHostToDevice);
     if (e == hipSuccess) e = hipMemcpy(m->gsrc, src.data(), src.size() * 4, hipMemcpyHostToDevice);
     if (e == hipSuccess) e = hipMemcpy(m->gw, w.data(), w.size() * 4, hipMemcpyHostToDevice);
+    if (e != hipSuccess) {
+      delete m;
+      return fail(TR_EDEVICE, std::string("upload: ") + hipGetErrorString(e));
+    }
+  }
+  // ---- implicit source: eigen-decomposition of P and per-voxel weights
+  if (desc->source == TR_SOURCE_IMPLICIT) {
+    std::vector<double> P64, V64, lam64;
+    phase_matrix(m->dirs, desc->g, TR_HG_SINKHORN, P64);
+    const int n = f.ndir;
+    symmetric_eigen(P64, n, V64, lam64);
+    std::vector<float> Vf(size_t(f.NP) * f.NP, 0.0f), lf(f.NP, 0.0f);
+    for (int i = 0; i < n; ++i)
+      for (int k = 0; k < n; ++k) Vf[size_t(i) * f.NP + k] = float(V64[size_t(i) * n + k]);
+    for (int k = 0; k < n; ++k) lf[k] = float(lam64[k]);
+    std::vector<float> w0f(f.Vp, 0.0f), w1f(f.Vp, 0.0f), cf(f.Vp, 0.0f);
+    for (int v = 0; v < f.V; ++v) {
+      const double ell = kC0 * m->dt / double(pn[v]);
+      const double mt = double(pa[v]) + double(ps[v]);
+      const double om = mt > 0 ? double(ps[v]) / mt : 0.0;
+      double f0, f1;
+      eq9_weights(mt * ell, f0, f1);
+      w0f[v] = float(om * f0);
+      w1f[v] = float(om * f1);
+      cf[v] = float((m->co.a[v] + om * f0) / (1.0 - om * f1));
+    }
+    m->V = m->alloc<float>(Vf.size());
+    m->lam = m->alloc<float>(f.NP);
+    m->w0 = m->alloc<float>(f.Vp);
+    m->w1 = m->alloc<float>(f.Vp);
+    m->cimp = m->alloc<float>(f.Vp);
+    if (!m->V || !m->lam || !m->w0 || !m->w1 || !m->cimp) {
+      delete m;
+      return fail(TR_ENOMEM, "device allocation failed (implicit source)");
+    }
+    e = hipMemcpy(m->V, Vf.data(), Vf.size() * 4, hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(m->lam, lf.data(), lf.size() * 4, hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(m->w0, w0f.data(), w0f.size() * 4, hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(m->w1, w1f.data(), w1f.size() * 4, hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(m->cimp, cf.data(), cf.size() * 4, hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = prepare_collide_implicit(f);
     if (e != hipSuccess) {
       delete m;
       return fail(TR_EDEVICE, std::string("upload: ") + hipGetErrorString(e));
@@ -851,6 +898,7 @@ tr_status tr_set_state(tr_medium* m, const float* in, int on_device) {
 tr_status tr_solve_checkpointed(tr_medium* m, int nsteps, int ckpt_every) {
   tr_status st = check_medium(m);
   if (st != TR_OK) return st;
+  if (m->V) return fail(TR_EINVAL, "gradients are for the explicit source");
   if (nsteps < 1 || ckpt_every < 1) return fail(TR_EINVAL, "nsteps and ckpt_every must be >= 1");
   if ((st = tr_reset(m)) != TR_OK) return st;
   const Field& f = m->f;

@@ -41,6 +41,11 @@ inline bool valid_desc(const tr_grid_desc* d, std::string& err) {
   if (d->coef != 0 && d->coef != 1) return err = "bad coef", false;
   if (d->advance < 0 || d->advance > 2) return err = "bad advance", false;
   if (d->precision != 0 && d->precision != 1) return err = "bad precision", false;
+  if (d->source != 0 && d->source != 1) return err = "bad source", false;
+  if (d->source == 1 &&
+      (d->hg_norm != 0 || d->coef != 0 || d->precision != 0 || 12 * d->nside * d->nside > 192))
+    return err = "the implicit source needs the Sinkhorn phase matrix, the paper's "
+                 "coefficients, FP32 and at most 192 directions", false;
   return true;
 }
 

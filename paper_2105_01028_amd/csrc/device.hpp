@@ -48,6 +48,14 @@ struct CollideArgs {
   long long Vp;
   int NP;
   double* part;            // [2][nwg]: absorbed, total
+  // implicit source (null otherwise): eigenvectors V[i][k] of P, row-major
+  // [NP][NP], eigenvalues [NP], and per voxel w0 = omega f0, w1 = omega f1 and
+  // the column-total factor c = (a + w0) / (1 - w1)
+  const float* V;
+  const float* lam;
+  const float* w0;
+  const float* w1;
+  const float* cimp;
 };
 
 struct SweepArgs {
@@ -152,6 +160,9 @@ hipError_t launch_inject(const InjectArgs& a, hipStream_t s);
 hipError_t launch_collide(const CollideArgs& a, const Field& f, int bf16split, int nwg_cols,
                           hipStream_t s);
 int collide_nwg(const Field& f, int bf16split);
+// Implicit-source collision (A.V etc. set), NP <= 192, FP32.
+hipError_t launch_collide_implicit(const CollideArgs& a, const Field& f, hipStream_t s);
+hipError_t prepare_collide_implicit(const Field& f);
 hipError_t prepare_collide(const Field& f, int bf16split);   // once per process and shape
 // fast_split_ok: nx is a multiple of 4 and every direction's b shifts are unit
 // (then split mode with class bytes runs the fast kernel).

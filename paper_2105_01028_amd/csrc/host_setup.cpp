@@ -207,6 +207,65 @@ bool build_coefficients(int nvox, const float* mua, const float* mus, const floa
   return true;
 }
 
+void eq9_weights(double tau, double& f0, double& f1) {
+  if (tau >= 0.1) {
+    f1 = (tau + std::expm1(-tau)) / tau;
+  } else {
+    // tau - 1 + e^-tau = sum_{k>=2} (-tau)^k / k!
+    double term = tau / 2.0, sum = 0.0;
+    for (int k = 2; k < 20; ++k) {
+      sum += term;
+      term *= -tau / double(k + 1);
+    }
+    f1 = sum;
+  }
+  f0 = -std::expm1(-tau) - f1;
+}
+
+void symmetric_eigen(const std::vector<double>& A0, int n, std::vector<double>& V,
+                     std::vector<double>& lam) {
+  std::vector<double> A(A0);
+  V.assign(size_t(n) * n, 0.0);
+  for (int i = 0; i < n; ++i) V[size_t(i) * n + i] = 1.0;
+  auto at = [&](int i, int j) -> double& { return A[size_t(i) * n + j]; };
+  double scale = 0.0;
+  for (double x : A) scale = std::max(scale, std::fabs(x));
+  for (int sweep = 0; sweep < 100; ++sweep) {
+    double off = 0.0;
+    for (int i = 0; i < n; ++i)
+      for (int j = i + 1; j < n; ++j) off += at(i, j) * at(i, j);
+    if (std::sqrt(off) <= 1e-15 * scale * n) break;
+    for (int p = 0; p < n; ++p)
+      for (int q = p + 1; q < n; ++q) {
+        const double apq = at(p, q);
+        if (std::fabs(apq) <= 1e-300) continue;
+        // rotation that zeroes A[p][q]
+        const double theta = (at(q, q) - at(p, p)) / (2.0 * apq);
+        const double t = (theta >= 0 ? 1.0 : -1.0) / (std::fabs(theta) + std::sqrt(theta * theta + 1.0));
+        const double c = 1.0 / std::sqrt(t * t + 1.0), s = t * c;
+        for (int k = 0; k < n; ++k) {
+          const double akp = at(k, p), akq = at(k, q);
+          at(k, p) = c * akp - s * akq;
+          at(k, q) = s * akp + c * akq;
+        }
+        for (int k = 0; k < n; ++k) {
+          const double apk = at(p, k), aqk = at(q, k);
+          at(p, k) = c * apk - s * aqk;
+          at(q, k) = s * apk + c * aqk;
+        }
+        for (int k = 0; k < n; ++k) {
+          double& vkp = V[size_t(k) * n + p];
+          double& vkq = V[size_t(k) * n + q];
+          const double x = vkp, y = vkq;
+          vkp = c * x - s * y;
+          vkq = s * x + c * y;
+        }
+      }
+  }
+  lam.resize(n);
+  for (int i = 0; i < n; ++i) lam[i] = at(i, i);
+}
+
 std::vector<int> cone_set(const std::vector<Vec3>& dirs, const Vec3& axis, double cone_deg) {
   std::vector<int> in;
   const double cmin = std::cos(cone_deg * kPi / 180.0);

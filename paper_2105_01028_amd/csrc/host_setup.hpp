@@ -53,6 +53,14 @@ struct Coefficients {
 bool build_coefficients(int nvox, const float* mua, const float* mus, const float* n, double dx,
                         double dt_ps, int coef, Coefficients& out, std::string& err);
 
+// Eq. (9) weights of S0 and S1 for optical depth tau >= 0 (series below 0.1).
+void eq9_weights(double tau, double& f0, double& f1);
+
+// Eigen-decomposition of the symmetric n x n matrix A (row-major) by cyclic
+// Jacobi rotations: A = V diag(lam) V^T, V[i*n + k] = component i of vector k.
+void symmetric_eigen(const std::vector<double>& A, int n, std::vector<double>& V,
+                     std::vector<double>& lam);
+
 // Directions within cone_deg of axis (4 nearest when none), ascending index.
 std::vector<int> cone_set(const std::vector<Vec3>& dirs, const Vec3& axis, double cone_deg);
 

@@ -624,6 +624,116 @@ __global__ __launch_bounds__(512, 1) void collide_bf16_stream_kernel(CollideArgs
                 A.part + nwg + wg);
 }
 
+// Implicit source (the converged Steps 3-6 of Sec. 2.4): every voxel's column
+// solves (I - w1 P) N_c = a N + w0 P N, i.e. with P = V diag(lambda) V^T
+//   N_c = V diag(g) V^T N,   g_k = (a + w0 lambda_k) / (1 - w1 lambda_k).
+// Resident layout of collide_f32_res_kernel with V in LDS (V[i][k], padded
+// pitch): pass 1 forms Z = V^T X in the accumulators (A operand read down a
+// column of V, four 4-byte reads), scales row k of Z by g_k, and pass 2 forms
+// Y = V Z one 32-row output block at a time.  Z's accumulator rows for block c
+// are exactly the k slots of K block c of pass 2 (the row order in which X is
+// read), so Z feeds pass 2 from registers.
+template <int NP>
+__device__ __forceinline__ void collide_implicit_tile(const CollideArgs& A, const float* Vs,
+                                                      const float* lamS, int tile,
+                                                      double& absorbed, double& total) {
+  constexpr int NQ = NP / 32;
+  constexpr int LDK = NP + 4;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int hl = lane >> 5, cl = lane & 31;
+  const size_t rowbytes = size_t(A.Vp) * sizeof(float);
+  const long long col = (long long)tile * 256 + wave * 32 + cl;
+  const unsigned voff = unsigned(size_t(col) * sizeof(float) + size_t(4 * hl) * rowbytes);
+  const char* __restrict__ xb0 = reinterpret_cast<const char*>(A.X);
+  const float av = A.a[col], w0 = A.w0[col], w1 = A.w1[col], cv = A.cimp[col];
+  floatx16 z[NQ];
+#pragma unroll
+  for (int q = 0; q < NQ; ++q)
+#pragma unroll
+    for (int r = 0; r < 16; ++r) z[q][r] = 0.0f;
+  auto ld = [&](int c, int s) {
+    const char* rb = xb0 + size_t(32 * c + 8 * (s >> 2) + (s & 3)) * rowbytes;
+    return *reinterpret_cast<const float*>(rb + voff);
+  };
+  float bcur[16], bnext[16];
+#pragma unroll
+  for (int s = 0; s < 16; ++s) bcur[s] = ld(0, s);
+  double colsum64 = 0.0;
+  // pass 1: z = V^T X; A[k_out][i] = V[i][k_out], i the slot's row of X
+#pragma unroll 1
+  for (int c = 0; c < NQ; ++c) {
+    const int cn = c + 1 < NQ ? c + 1 : c;
+#pragma unroll
+    for (int s = 0; s < 16; ++s) bnext[s] = ld(cn, s);
+    float colsum = 0.0f;
+#pragma unroll
+    for (int s = 0; s < 16; ++s) colsum += bcur[s];
+    colsum64 += double(colsum);
+#pragma unroll
+    for (int s4 = 0; s4 < 16; s4 += 4) {
+      const int i0 = 32 * c + 8 * (s4 >> 2) + 4 * hl;
+#pragma unroll
+      for (int q = 0; q < NQ; ++q) {
+        const float* vc = Vs + size_t(i0) * LDK + q * 32 + cl;
+        z[q] = __builtin_amdgcn_mfma_f32_32x32x2f32(vc[0], bcur[s4 + 0], z[q], 0, 0, 0);
+        z[q] = __builtin_amdgcn_mfma_f32_32x32x2f32(vc[LDK], bcur[s4 + 1], z[q], 0, 0, 0);
+        z[q] = __builtin_amdgcn_mfma_f32_32x32x2f32(vc[2 * LDK], bcur[s4 + 2], z[q], 0, 0, 0);
+        z[q] = __builtin_amdgcn_mfma_f32_32x32x2f32(vc[3 * LDK], bcur[s4 + 3], z[q], 0, 0, 0);
+      }
+    }
+#pragma unroll
+    for (int s = 0; s < 16; ++s) bcur[s] = bnext[s];
+  }
+  // z[k] *= g_k for the lane's rows k = 32q + 8(r/4) + 4h + r%4
+#pragma unroll
+  for (int q = 0; q < NQ; ++q)
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+      const float lam = lamS[32 * q + 8 * (r >> 2) + 4 * hl + (r & 3)];
+      z[q][r] *= (av + w0 * lam) / (1.0f - w1 * lam);
+    }
+  // pass 2: Y = V z, block by block; K block c of z sits in z[c] in slot order
+  const float* __restrict__ Vl = Vs + cl * LDK + 4 * hl;
+  char* __restrict__ yb0 = reinterpret_cast<char*>(A.Y);
+#pragma unroll 1
+  for (int qo = 0; qo < NQ; ++qo) {
+    floatx16 acc;
+#pragma unroll
+    for (int r = 0; r < 16; ++r) acc[r] = 0.0f;
+    const float* __restrict__ Vq = Vl + qo * 32 * LDK;
+#pragma unroll
+    for (int c = 0; c < NQ; ++c)
+#pragma unroll
+      for (int s4 = 0; s4 < 16; s4 += 4) {
+        const float4 a4 = *reinterpret_cast<const float4*>(Vq + 32 * c + 8 * (s4 >> 2));
+        acc = __builtin_amdgcn_mfma_f32_32x32x2f32(a4.x, z[c][s4 + 0], acc, 0, 0, 0);
+        acc = __builtin_amdgcn_mfma_f32_32x32x2f32(a4.y, z[c][s4 + 1], acc, 0, 0, 0);
+        acc = __builtin_amdgcn_mfma_f32_32x32x2f32(a4.z, z[c][s4 + 2], acc, 0, 0, 0);
+        acc = __builtin_amdgcn_mfma_f32_32x32x2f32(a4.w, z[c][s4 + 3], acc, 0, 0, 0);
+      }
+#pragma unroll
+    for (int r = 0; r < 16; ++r)
+      *reinterpret_cast<float*>(yb0 + size_t(qo * 32 + 8 * (r >> 2) + (r & 3)) * rowbytes +
+                                voff) = acc[r];
+  }
+  absorbed += (1.0 - double(cv)) * colsum64;
+  total += colsum64;
+}
+
+template <int NP>
+__global__ __launch_bounds__(512, 1) void collide_implicit_kernel(CollideArgs A, int ntiles) {
+  extern __shared__ float Vsh[];
+  float* lamS = Vsh + NP * (NP + 4);
+  load_p_lds<NP>(A.V, Vsh);
+  for (int i = threadIdx.x; i < NP; i += 512) lamS[i] = A.lam[i];
+  __syncthreads();
+  double absorbed = 0.0, total = 0.0;
+#pragma unroll 1
+  for (int tile = blockIdx.x; tile < ntiles; tile += gridDim.x)
+    collide_implicit_tile<NP>(A, Vsh, lamS, tile, absorbed, total);
+  block_sums512(absorbed, total, A.part + blockIdx.x, A.part + gridDim.x + blockIdx.x);
+}
+
 // Same contraction with P and X each split into bf16 high and low parts,
 // X = X_hi + X_lo, P = P_hi + P_lo, and P X = (P_hi + P_lo)(X_hi + X_lo) as four
 // v_mfma_f32_32x32x16_bf16 products with fp32 accumulation.  The products of
@@ -1942,6 +2052,50 @@ hipError_t launch_collide(const CollideArgs& a, const Field& f, int bf16split, i
     case 96: return launch_collide_mt<96>(a, f, bf16split, s);
     case 64: return launch_collide_mt<64>(a, f, bf16split, s);
     default: return launch_collide_mt<32>(a, f, bf16split, s);
+  }
+}
+
+namespace {
+template <int NP>
+size_t implicit_lds() {
+  return (size_t(NP) * (NP + 4) + NP) * sizeof(float);
+}
+template <int NP>
+hipError_t prepare_implicit_np() {
+  return hipFuncSetAttribute(reinterpret_cast<const void*>(&collide_implicit_kernel<NP>),
+                             hipFuncAttributeMaxDynamicSharedMemorySize, int(implicit_lds<NP>()));
+}
+template <int NP>
+hipError_t launch_implicit_np(const CollideArgs& a, const Field& f, hipStream_t s) {
+  const int ntiles = int(f.Vp / 256);
+  const int nb = ntiles < resident_blocks() ? ntiles : resident_blocks();
+  hipLaunchKernelGGL(collide_implicit_kernel<NP>, dim3(unsigned(nb)), dim3(512), implicit_lds<NP>(),
+                     s, a, ntiles);
+  return hipGetLastError();
+}
+}  // namespace
+
+hipError_t prepare_collide_implicit(const Field& f) {
+  switch (f.NP) {
+    case 32: return prepare_implicit_np<32>();
+    case 64: return prepare_implicit_np<64>();
+    case 96: return prepare_implicit_np<96>();
+    case 128: return prepare_implicit_np<128>();
+    case 160: return prepare_implicit_np<160>();
+    case 192: return prepare_implicit_np<192>();
+    default: return hipErrorInvalidValue;
+  }
+}
+
+hipError_t launch_collide_implicit(const CollideArgs& a, const Field& f, hipStream_t s) {
+  switch (f.NP) {
+    case 32: return launch_implicit_np<32>(a, f, s);
+    case 64: return launch_implicit_np<64>(a, f, s);
+    case 96: return launch_implicit_np<96>(a, f, s);
+    case 128: return launch_implicit_np<128>(a, f, s);
+    case 160: return launch_implicit_np<160>(a, f, s);
+    case 192: return launch_implicit_np<192>(a, f, s);
+    default: return hipErrorInvalidValue;
   }
 }
 

@@ -22,6 +22,7 @@ HG = {"sinkhorn": 0, "row": 1}
 COEF = {"paper": 0, "abs_exact": 1}
 ADVANCE = {"auto": 0, "phase": 1, "split": 2}
 PRECISION = {"fp32": 0, "bf16split": 1}
+SOURCE = {"explicit": 0, "implicit": 1}
 MODE_NAMES = {1: "phase", 2: "split"}
 BUDGET_FIELDS = ("injected", "absorbed", "in_domain", "esc0", "esc1", "esc2", "esc3", "esc4",
                  "esc5")
@@ -37,7 +38,7 @@ class GridDesc(ctypes.Structure):
     _fields_ = [("nx", ctypes.c_int), ("ny", ctypes.c_int), ("nz", ctypes.c_int),
                 ("dx_mm", ctypes.c_double), ("nside", ctypes.c_int), ("g", ctypes.c_double),
                 ("dt_ps", ctypes.c_double), ("hg_norm", ctypes.c_int), ("coef", ctypes.c_int),
-                ("advance", ctypes.c_int), ("precision", ctypes.c_int)]
+                ("advance", ctypes.c_int), ("precision", ctypes.c_int), ("source", ctypes.c_int)]
 
 
 class Info(ctypes.Structure):
@@ -160,7 +161,7 @@ def _fptr(a):
 def grid_desc(prob) -> GridDesc:
     return GridDesc(prob.nx, prob.ny, prob.nz, float(prob.dx_mm), int(prob.nside), float(prob.g),
                     float(prob.dt_ps), HG[prob.hg_norm], COEF[prob.coef], ADVANCE[prob.advance],
-                    PRECISION[prob.precision])
+                    PRECISION[prob.precision], SOURCE[getattr(prob, "source", "explicit")])
 
 
 def current_stream() -> int:

@@ -344,3 +344,46 @@ def test_refraction128_full_size_sampled_single_step(precision, tol):
     scale = np.abs(ref).max()
     assert scale > 0
     assert np.abs(got - ref).max() <= tol * scale
+
+
+@pytest.mark.parametrize("advance,seed,shape", [("phase", 1, (13, 10, 9)), ("split", 2, (12, 9, 8)),
+                                                ("phase", 3, (64, 6, 5))])
+def test_implicit_source_single_step(advance, seed, shape):
+    """Implicit source (S1 from the outgoing intensity): one step from a random
+    state, every element against the oracle's per-voxel solve."""
+    nx, ny, nz = shape
+    p = W.small_problem(nside=2, nx=nx, ny=ny, nz=nz, mua=0.05, mus=3.0, g=0.8, steps=1,
+                        seed=seed, advance=advance, total_photons=0.0).copy(source="implicit")
+    rng = np.random.default_rng(seed)
+    N0 = rng.uniform(0, 1, (48, p.nvox)).astype(np.float32)
+    ref = solve.forward(p, steps=1, state0=N0.astype(np.float64))
+    got = run_gpu(p, steps=1, state0=N0)
+    assert np.abs(got["state"] - ref.state).max() <= 2e-6 * np.abs(ref.state).max()
+    assert abs(got["budget"][0, 1] - ref.absorbed[0]) <= 1e-5 * ref.absorbed[0]
+
+
+@pytest.mark.parametrize("nside,advance,shape", [(1, "phase", (9, 7, 5)), (2, "split", (15, 11, 9)),
+                                                 (4, "phase", (16, 12, 10))])
+def test_implicit_source_solve(nside, advance, shape):
+    nx, ny, nz = shape
+    p = W.small_problem(nside=nside, nx=nx, ny=ny, nz=nz, mua=0.01, mus=5.0, g=0.85, steps=50,
+                        seed=9, advance=advance, det_cone_deg=0.0).copy(source="implicit")
+    ref = solve.forward(p)
+    got = run_gpu(p)
+    assert rel_l2_above(got["steps"].ravel(), ref.det.ravel()) < 1e-4
+    # V is stored in fp32: each of the two products with it rounds every value
+    assert budget_closure(got["budget"]) < closure_bound(got["budget"], ulps=4.0)
+
+
+def test_implicit_source_rejected_where_unsupported():
+    import torch
+    p = W.small_problem(nside=2, steps=5).copy(source="implicit")
+    with torch.cuda.stream(_stream()):
+        for bad in (p.copy(precision="bf16split"), p.copy(hg_norm="row"), p.copy(nside=8)):
+            with pytest.raises(T.TrinityError) as e:
+                T.Medium.from_problem(bad)
+            assert e.value.status == T.TR_EINVAL
+        m = T.Medium.from_problem(p)
+        with pytest.raises(T.TrinityError):
+            m.solve_checkpointed(5, 2)
+        m.close()
