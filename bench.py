@@ -275,6 +275,39 @@ def refraction128(stream, steps=20, precisions=("fp32", "bf16split")):
     return out
 
 
+def implicit_source(stream, steps=200):
+    """The phantom with the implicit source (S1 of Eq. 10 from the outgoing
+    intensity, closed form per voxel): ms per step and kernel rooflines."""
+    import torch
+
+    from paper_2105_01028_amd import trinity as T
+    from paper_2105_01028_amd import workloads as W
+    p = W.config2().copy(source="implicit")
+    with torch.cuda.stream(stream):
+        m = T.Medium.from_problem(p)
+        m.solve(10)
+        m.reset()
+        m.profile_begin(steps)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        m.step(steps)
+        m.synchronize()
+        t1 = time.perf_counter()
+        prof = m.profile_end()
+        b = m.read_budget()
+        m.close()
+    inj = b[:, 0].sum()
+    ms, n = prof["collide"]
+    t = ms / n * 1e-3
+    flop = 4.0 * p.ndir * p.ndir * p.nvox      # two products with V
+    return {"ms_per_step": (t1 - t0) / steps * 1e3,
+            "updates_per_s": p.nvox * p.ndir * steps / (t1 - t0),
+            "collide": {"avg_ms": ms / n, "achieved_tflops": flop / t / 1e12, "peak": 157.3,
+                        "frac": flop / t / 1e12 / 157.3},
+            "budget_closure": abs(inj - b[:, 1].sum() - b[:, 3:].sum() - b[-1, 2]) / inj,
+            "workload": "phantom 64^3, 192 directions, implicit source, 200 steps"}
+
+
 def cpu_baseline(prob, budget_s=15.0):
     """The FP64 oracle on the host cores, on the first steps of the same workload."""
     from oracle import solve
@@ -371,6 +404,7 @@ def main():
         out["serving"] = serving(stream)
         out["adjoint"] = adjoint_timing(stream)
         out["refraction128"] = refraction128(stream)
+        out["implicit_source"] = implicit_source(stream)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(prob)
     print(json.dumps(out), flush=True)
