@@ -39,6 +39,72 @@ def healpix_ring(nside):
     return np.array(out, dtype=np.float64)
 
 
+def healpix_pixel_ring(nside, v):
+    """Index, in the order of healpix_ring(nside), of the HEALPix pixel
+    (Gorski et al. 2005) that contains the unit vector v.  With z = cos(theta)
+    and t = 2 phi / pi in [0, 4):
+    equatorial zone |z| <= 2/3: the pixel boundaries are the lines
+    nside (1/2 + t) -/+ (3/4) nside z = const, which give the ascending and
+    descending edge indices jp, jm, the ring ir = nside + 1 + jp - jm counted
+    from z = 2/3, and the pixel ((jp + jm - nside + shift + 1) / 2) mod 4 nside
+    counted from azimuth 0 (shift = 1 on even ir).  healpix_ring numbers the
+    rings with shift = 1 from azimuth pi / (2 nside) instead (j = 1 .. 4 nside
+    in its azimuth formula), one pixel later;
+    polar caps: with x = nside sqrt(3 (1 - |z|)) and the fractional part f of t,
+    jp = floor(f x), jm = floor((1 - f) x), the ring from the pole is
+    ir = jp + jm + 1, and the pixel is floor(t ir) in it."""
+    x, y, z = float(v[0]), float(v[1]), float(v[2])
+    phi = math.atan2(y, x)
+    if phi < 0.0:
+        phi += 2.0 * math.pi
+    t = (2.0 * phi / math.pi) % 4.0
+    za = abs(z)
+    npix = 12 * nside * nside
+    if za <= 2.0 / 3.0:
+        t1 = nside * (0.5 + t)
+        t2 = nside * z * 0.75
+        jp = int(math.floor(t1 - t2))
+        jm = int(math.floor(t1 + t2))
+        ir = nside + 1 + jp - jm
+        shift = 1 - (ir & 1)
+        ip = ((jp + jm - nside + shift + 1) // 2) % (4 * nside)
+        if shift:
+            ip = (ip - 1) % (4 * nside)
+        return 2 * nside * (nside - 1) + (ir - 1) * 4 * nside + ip
+    f = t - math.floor(t)
+    xx = nside * math.sqrt(3.0 * (1.0 - za))
+    jp = int(math.floor(f * xx))
+    jm = int(math.floor((1.0 - f) * xx))
+    ir = jp + jm + 1
+    ip = int(math.floor(t * ir)) % (4 * ir)
+    if z > 0.0:
+        return 2 * ir * (ir - 1) + ip
+    return npix - 2 * ir * (ir + 1) + ip
+
+
+def parents(nside, nside_scatter):
+    """For each direction of the fine grid (nside), the coarse direction
+    (nside_scatter) whose pixel contains it.  HEALPix is hierarchical, so each
+    coarse pixel holds exactly (nside / nside_scatter)^2 fine pixels."""
+    return np.array([healpix_pixel_ring(nside_scatter, v) for v in healpix_ring(nside)])
+
+
+def two_level_matrix(nside, nside_scatter, g, norm="sinkhorn"):
+    """Scattering on a coarser angular grid (Sec. 2.1: the source is computed
+    from the mean intensity over the 16 fine bins of each coarse bin).  In
+    photon numbers: the photons of a coarse bin are the sum over its children,
+    the coarse phase matrix scatters them, and each child of the target bin
+    receives an equal share:  P_eff = C P_c A  with A[J][i] = 1 for the parent
+    J of i and C[i][J] = 1 / (children per bin)."""
+    par = parents(nside, nside_scatter)
+    nc = 12 * nside_scatter * nside_scatter
+    Pc = phase_matrix(healpix_ring(nside_scatter), g, norm)
+    A = np.zeros((nc, len(par)))
+    A[par, np.arange(len(par))] = 1.0
+    C = A.T / (nside // nside_scatter) ** 2
+    return C @ Pc @ A
+
+
 def hg(mu, g):
     """Henyey-Greenstein phase function of the scattering cosine mu, Eq. (11)."""
     return (1.0 - g * g) / (FOUR_PI * (1.0 + g * g - 2.0 * g * mu) ** 1.5)

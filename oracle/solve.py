@@ -62,7 +62,11 @@ def build(prob, steps=None, coef=None) -> Setup:
     shape = (prob.nz, prob.ny, prob.nx)
     n = np.asarray(prob.n, dtype=np.float64)
     dirs = angles.healpix_ring(prob.nside)
-    P = angles.phase_matrix(dirs, prob.g, prob.hg_norm)
+    ns = getattr(prob, "nside_scatter", 0)
+    if ns and ns != prob.nside:
+        P = angles.two_level_matrix(prob.nside, ns, prob.g, prob.hg_norm)
+    else:
+        P = angles.phase_matrix(dirs, prob.g, prob.hg_norm)
     lat = lattice.RayLattice(dirs, shape)
     dt = medium.time_step(prob.dx_mm, n, prob.dt_ps)
     a, b, omega, ell = medium.collision_coefficients(prob.mua, prob.mus, n, dt,
