@@ -83,6 +83,14 @@ typedef struct {
                          N_c = V diag((a + w0 lambda)/(1 - w1 lambda)) V^T N,
                          w0 = omega f0, w1 = omega f1 (Eq. 9).  Needs TR_HG_SINKHORN,
                          TR_COEF_PAPER, TR_PREC_FP32 and at most 192 directions. */
+  int nside_scatter;  /* 0 (or nside): scatter on the transport directions.  Else the
+                         source is computed on the coarser HEALPix grid of this nside
+                         (nside / nside_scatter a power of two, at most 192 coarse
+                         directions; Sec. 2.1, 3072 transport and 192 scattering bins):
+                         the photons of a coarse bin are the sum over its fine
+                         children, are scattered by the coarse phase matrix, and each
+                         child of the target bin gets an equal share.  Needs the
+                         explicit source and FP32. */
 } tr_grid_desc;
 
 typedef struct {
@@ -317,6 +325,10 @@ tr_status tr_server_cancel(tr_server* s, long long id);
 
 /* HEALPix RING centres (Sec. 2.1), out[3*N]. */
 tr_status tr_host_directions(int nside, double* out);
+
+/* For every direction of nside, the direction of the coarser grid nside_c
+ * (nside / nside_c a power of two) whose pixel contains it, out[12 nside^2]. */
+tr_status tr_host_parents(int nside, int nside_c, int* out);
 
 /* Discrete phase matrix P[i*N + j] (Eq. 11-12) for directions of nside. */
 tr_status tr_host_phase_matrix(int nside, double g, int hg_norm, double* out);

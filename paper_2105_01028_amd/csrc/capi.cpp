@@ -48,6 +48,13 @@ struct tr_medium {
   float* nvox = nullptr;
   int* islot = nullptr;
   float *V = nullptr, *lam = nullptr, *w0 = nullptr, *w1 = nullptr, *cimp = nullptr;  // implicit
+  // two-level angular grid: coarse field of nc directions (NPc rows)
+  bool twolevel = false;
+  int nc = 0, NPc = 0, nkids = 0;
+  float *M = nullptr, *T = nullptr, *zero = nullptr;
+  int *children = nullptr, *parent = nullptr;
+  double* cpart2 = nullptr;
+  int cnwg2 = 0;
   uint8_t* mat = nullptr;   // split mode: index class | interface bit << 7, or null
   uint32_t* rowbits = nullptr;  // split mode: rows of background class only
   unsigned bgcls = 0;
@@ -231,10 +238,24 @@ hipError_t queue_step(tr_medium* m) {
   }
   {
     KernelTimer t(m, TR_K_COLLIDE);
-    CollideArgs ca{m->X,   m->Y, m->P,  m->Prow, m->Phi, m->Plo, m->a,   m->b,
-                   f.Vp,   f.NP, m->cpart, m->V, m->lam, m->w0,  m->w1, m->cimp};
-    e = m->V ? launch_collide_implicit(ca, f, m->stream)
-             : launch_collide(ca, f, m->desc.precision, 0, m->stream);
+    if (m->twolevel) {
+      TwoLevelArgs ta{m->X,        m->Y,      m->M,     m->T,     m->a,
+                      m->b,        m->children, m->parent, f.ndir, m->nc,
+                      m->nkids,    1.0f / float(m->nkids), f.Vp, f.V, m->cpart};
+      Field fc = f;
+      fc.ndir = m->nc;
+      fc.NP = m->NPc;
+      CollideArgs cc{m->M, m->T, m->P, m->Prow, nullptr, nullptr, m->zero, m->b,
+                     f.Vp, m->NPc, m->cpart2};
+      e = launch_coarse_sum(ta, m->stream);
+      if (e == hipSuccess) e = launch_collide(cc, fc, 0, 0, m->stream);
+      if (e == hipSuccess) e = launch_apply(ta, m->stream);
+    } else {
+      CollideArgs ca{m->X,   m->Y, m->P,  m->Prow, m->Phi, m->Plo, m->a,   m->b,
+                     f.Vp,   f.NP, m->cpart, m->V, m->lam, m->w0,  m->w1, m->cimp};
+      e = m->V ? launch_collide_implicit(ca, f, m->stream)
+               : launch_collide(ca, f, m->desc.precision, 0, m->stream);
+    }
     if (e != hipSuccess) return e;
   }
   const bool split = m->mode == TR_ADVANCE_SPLIT;
@@ -379,7 +400,16 @@ tr_status tr_create_medium(const tr_grid_desc* desc, const float* mua, const flo
     return fail(TR_EINVAL, "time step moves light more than one plane per step");
   }
   std::vector<float> P32, PT;
-  if (!build_p32(m->dirs, desc->g, desc->hg_norm, f.NP, P32, PT)) {
+  m->twolevel = desc->nside_scatter != 0 && desc->nside_scatter != desc->nside;
+  int NPm = f.NP;   // rows of the phase matrix the collide kernels use
+  if (m->twolevel) {
+    m->nc = 12 * desc->nside_scatter * desc->nside_scatter;
+    m->NPc = int(round_up(m->nc, 32));
+    m->nkids = f.ndir / m->nc;
+    NPm = m->NPc;
+  }
+  const std::vector<Vec3> pdirs = m->twolevel ? healpix_ring(desc->nside_scatter) : m->dirs;
+  if (!build_p32(pdirs, desc->g, desc->hg_norm, NPm, P32, PT)) {
     delete m;
     return fail(TR_EINVAL, "phase matrix scaling did not converge");
   }
@@ -392,8 +422,8 @@ tr_status tr_create_medium(const tr_grid_desc* desc, const float* mua, const flo
   const size_t NV = size_t(f.NP) * f.Vp;
   m->X = m->alloc<float>(NV);
   m->Y = m->alloc<float>(NV);
-  m->P = m->alloc<float>(size_t(f.NP) * f.NP);
-  m->Prow = m->alloc<float>(size_t(f.NP) * f.NP);
+  m->P = m->alloc<float>(size_t(NPm) * NPm);
+  m->Prow = m->alloc<float>(size_t(NPm) * NPm);
   m->a = m->alloc<float>(f.Vp);
   m->b = m->alloc<float>(f.Vp);
   m->r = m->alloc<float>(f.Vp);
@@ -533,6 +563,53 @@ tr_status tr_create_medium(const tr_grid_desc* desc, const float* mua, const flo
     if (e != hipSuccess) {
       delete m;
       return fail(TR_EDEVICE, std::string("upload: ") + hipGetErrorString(e));
+    }
+  }
+  // ---- two-level angular grid: children lists, coarse buffers
+  if (m->twolevel) {
+    const std::vector<int> par = healpix_parents(desc->nside, desc->nside_scatter);
+    std::vector<int> kids(size_t(m->nc) * m->nkids, -1), fill(m->nc, 0);
+    for (int i = 0; i < f.ndir; ++i) {
+      const int J = par[i];
+      if (J < 0 || J >= m->nc || fill[J] >= m->nkids) {
+        delete m;
+        return fail(TR_EINVAL, "inconsistent angular hierarchy");
+      }
+      kids[size_t(J) * m->nkids + fill[J]++] = i;
+    }
+    Field fc = f;
+    fc.ndir = m->nc;
+    fc.NP = m->NPc;
+    m->cnwg2 = collide_nwg(fc, 0);
+    m->M = m->alloc<float>(size_t(m->NPc) * f.Vp);
+    m->T = m->alloc<float>(size_t(m->NPc) * f.Vp);
+    m->zero = m->alloc<float>(f.Vp);
+    m->children = m->alloc<int>(kids.size());
+    m->parent = m->alloc<int>(par.size());
+    m->cpart2 = m->alloc<double>(2 * size_t(m->cnwg2));
+    if (!m->M || !m->T || !m->zero || !m->children || !m->parent || !m->cpart2) {
+      delete m;
+      return fail(TR_ENOMEM, "device allocation failed (two-level grid)");
+    }
+    e = hipMemset(m->M, 0, size_t(m->NPc) * f.Vp * 4);
+    if (e == hipSuccess) e = hipMemset(m->T, 0, size_t(m->NPc) * f.Vp * 4);
+    if (e == hipSuccess) e = hipMemset(m->zero, 0, f.Vp * 4);
+    if (e == hipSuccess) e = hipMemcpy(m->children, kids.data(), kids.size() * 4, hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(m->parent, par.data(), par.size() * 4, hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = prepare_collide(fc, 0);
+    if (e != hipSuccess) {
+      delete m;
+      return fail(TR_EDEVICE, std::string("upload: ") + hipGetErrorString(e));
+    }
+    // the budget partials come from the coarse sums, one pair per workgroup
+    TwoLevelArgs probe{};
+    probe.nc = m->nc;
+    m->release(m->cpart);
+    m->cnwg = int((f.V + 255) / 256) * coarse_sum_groups(probe);
+    m->cpart = m->alloc<double>(2 * size_t(m->cnwg));
+    if (!m->cpart) {
+      delete m;
+      return fail(TR_ENOMEM, "device allocation failed (two-level partials)");
     }
   }
   // ---- implicit source: eigen-decomposition of P and per-voxel weights
@@ -898,7 +975,8 @@ tr_status tr_set_state(tr_medium* m, const float* in, int on_device) {
 tr_status tr_solve_checkpointed(tr_medium* m, int nsteps, int ckpt_every) {
   tr_status st = check_medium(m);
   if (st != TR_OK) return st;
-  if (m->V) return fail(TR_EINVAL, "gradients are for the explicit source");
+  if (m->V || m->twolevel)
+    return fail(TR_EINVAL, "gradients are for the explicit source on one angular grid");
   if (nsteps < 1 || ckpt_every < 1) return fail(TR_EINVAL, "nsteps and ckpt_every must be >= 1");
   if ((st = tr_reset(m)) != TR_OK) return st;
   const Field& f = m->f;
@@ -1113,6 +1191,15 @@ tr_status tr_host_directions(int nside, double* out) {
     out[3 * i + 1] = d[i].y;
     out[3 * i + 2] = d[i].z;
   }
+  return TR_OK;
+}
+
+tr_status tr_host_parents(int nside, int nside_c, int* out) {
+  if (!out || nside < 1 || nside > 16 || nside_c < 1 || nside_c > nside || nside % nside_c ||
+      ((nside / nside_c) & (nside / nside_c - 1)))
+    return fail(TR_EINVAL, "bad nside pair");
+  const std::vector<int> par = healpix_parents(nside, nside_c);
+  std::copy(par.begin(), par.end(), out);
   return TR_OK;
 }
 

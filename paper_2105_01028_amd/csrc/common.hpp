@@ -42,6 +42,14 @@ inline bool valid_desc(const tr_grid_desc* d, std::string& err) {
   if (d->advance < 0 || d->advance > 2) return err = "bad advance", false;
   if (d->precision != 0 && d->precision != 1) return err = "bad precision", false;
   if (d->source != 0 && d->source != 1) return err = "bad source", false;
+  if (d->nside_scatter != 0 && d->nside_scatter != d->nside) {
+    const int ns = d->nside_scatter;
+    if (ns < 1 || ns > d->nside || d->nside % ns != 0 || ((d->nside / ns) & (d->nside / ns - 1)))
+      return err = "nside_scatter must divide nside by a power of two", false;
+    if (12 * ns * ns > 192 || d->source != 0 || d->precision != 0)
+      return err = "the two-level grid needs at most 192 scattering directions, the "
+                   "explicit source and FP32", false;
+  }
   if (d->source == 1 &&
       (d->hg_norm != 0 || d->coef != 0 || d->precision != 0 || 12 * d->nside * d->nside > 192))
     return err = "the implicit source needs the Sinkhorn phase matrix, the paper's "

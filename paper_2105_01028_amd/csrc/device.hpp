@@ -155,6 +155,27 @@ struct AdjArgs {
   int steps;
 };
 
+// Two-level angular grid: fine field X, Y [ndir][Vp]; coarse sums M and
+// coarse scattered light T [nc][Vp].
+struct TwoLevelArgs {
+  const float* X;
+  float* Y;
+  float* M;
+  const float* T;
+  const float* a;
+  const float* b;
+  const int* children;     // [nc][nkids] fine directions of each coarse bin
+  const int* parent;       // [ndir]
+  int ndir, nc, nkids;
+  float share;             // 1 / nkids
+  long long Vp;
+  int V;
+  double* part;            // [2][nwg] absorbed, total
+};
+int coarse_sum_groups(const TwoLevelArgs& a);   // nwg = ceil(V / 256) * groups
+hipError_t launch_coarse_sum(const TwoLevelArgs& a, hipStream_t s);
+hipError_t launch_apply(const TwoLevelArgs& a, hipStream_t s);
+
 // Launchers: queue the kernel on `s`.  Return the launch status.
 hipError_t launch_inject(const InjectArgs& a, hipStream_t s);
 hipError_t launch_collide(const CollideArgs& a, const Field& f, int bf16split, int nwg_cols,

@@ -207,6 +207,41 @@ bool build_coefficients(int nvox, const float* mua, const float* mus, const floa
   return true;
 }
 
+int healpix_pixel(int nside, const Vec3& v) {
+  const double z = std::max(-1.0, std::min(1.0, v.z));
+  double phi = std::atan2(v.y, v.x);
+  if (phi < 0) phi += 2.0 * kPi;
+  double t = std::fmod(phi / (0.5 * kPi), 4.0);   // azimuth in quarter turns
+  if (t < 0) t += 4.0;
+  const int npix = 12 * nside * nside;
+  if (std::fabs(z) <= 2.0 / 3.0) {
+    // belt: pixels are bounded by the lines nside (t + 1/2) -/+ (3/4) nside z = const
+    const double u = nside * (t + 0.5), w = 0.75 * nside * z;
+    const long long up = (long long)std::floor(u - w);   // ascending boundary index
+    const long long dn = (long long)std::floor(u + w);   // descending boundary index
+    const int ring_b = int(nside + 1 + up - dn);           // 1 .. 2 nside + 1 from z = 2/3
+    const int odd_start = (ring_b % 2 == 0) ? 1 : 0;      // rings whose first pixel is at azimuth 0
+    long long in_ring = (up + dn - nside + odd_start + 1) / 2;
+    in_ring = ((in_ring % (4 * nside)) + 4 * nside) % (4 * nside);
+    // healpix_ring starts those rings one pixel later, at azimuth pi / (2 nside)
+    if (odd_start) in_ring = (in_ring + 4 * nside - 1) % (4 * nside);
+    return 2 * nside * (nside - 1) + (ring_b - 1) * 4 * nside + int(in_ring);
+  }
+  const double frac = t - std::floor(t);
+  const double x = nside * std::sqrt(3.0 * (1.0 - std::fabs(z)));
+  const int a = int(std::floor(frac * x)), b = int(std::floor((1.0 - frac) * x));
+  const int ring = a + b + 1;                              // counted from the nearer pole
+  const int in_ring = int(std::floor(t * ring)) % (4 * ring);
+  return z > 0 ? 2 * ring * (ring - 1) + in_ring : npix - 2 * ring * (ring + 1) + in_ring;
+}
+
+std::vector<int> healpix_parents(int nside, int nside_c) {
+  const std::vector<Vec3> d = healpix_ring(nside);
+  std::vector<int> par(d.size());
+  for (size_t i = 0; i < d.size(); ++i) par[i] = healpix_pixel(nside_c, d[i]);
+  return par;
+}
+
 void eq9_weights(double tau, double& f0, double& f1) {
   if (tau >= 0.1) {
     f1 = (tau + std::expm1(-tau)) / tau;

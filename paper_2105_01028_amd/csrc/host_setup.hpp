@@ -53,6 +53,13 @@ struct Coefficients {
 bool build_coefficients(int nvox, const float* mua, const float* mus, const float* n, double dx,
                         double dt_ps, int coef, Coefficients& out, std::string& err);
 
+// The pixel of the HEALPix grid of nside (numbered as healpix_ring) that
+// contains the unit vector v.
+int healpix_pixel(int nside, const Vec3& v);
+
+// Parent (coarse pixel of nside_c) of every pixel of nside (a power-of-two multiple).
+std::vector<int> healpix_parents(int nside, int nside_c);
+
 // Eq. (9) weights of S0 and S1 for optical depth tau >= 0 (series below 0.1).
 void eq9_weights(double tau, double& f0, double& f1);
 

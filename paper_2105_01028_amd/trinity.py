@@ -38,7 +38,8 @@ class GridDesc(ctypes.Structure):
     _fields_ = [("nx", ctypes.c_int), ("ny", ctypes.c_int), ("nz", ctypes.c_int),
                 ("dx_mm", ctypes.c_double), ("nside", ctypes.c_int), ("g", ctypes.c_double),
                 ("dt_ps", ctypes.c_double), ("hg_norm", ctypes.c_int), ("coef", ctypes.c_int),
-                ("advance", ctypes.c_int), ("precision", ctypes.c_int), ("source", ctypes.c_int)]
+                ("advance", ctypes.c_int), ("precision", ctypes.c_int), ("source", ctypes.c_int),
+                ("nside_scatter", ctypes.c_int)]
 
 
 class Info(ctypes.Structure):
@@ -110,6 +111,7 @@ _SIGS = {
     "tr_server_result": [_P, ctypes.c_longlong, _PD, ctypes.c_size_t, _PD, ctypes.c_size_t],
     "tr_server_cancel": [_P, ctypes.c_longlong],
     "tr_host_directions": [_I, _PD],
+    "tr_host_parents": [_I, _I, _PI],
     "tr_host_phase_matrix": [_I, _D, _I, _PD],
     "tr_host_lattice": [_I, _I, _I, _I, _PI, _PI, _PI],
     "tr_host_coefficients": [ctypes.POINTER(GridDesc), _PF, _PF, _PF, _PD, _PD, _PD, _PD],
@@ -161,7 +163,8 @@ def _fptr(a):
 def grid_desc(prob) -> GridDesc:
     return GridDesc(prob.nx, prob.ny, prob.nz, float(prob.dx_mm), int(prob.nside), float(prob.g),
                     float(prob.dt_ps), HG[prob.hg_norm], COEF[prob.coef], ADVANCE[prob.advance],
-                    PRECISION[prob.precision], SOURCE[getattr(prob, "source", "explicit")])
+                    PRECISION[prob.precision], SOURCE[getattr(prob, "source", "explicit")],
+                    int(getattr(prob, "nside_scatter", 0)))
 
 
 def current_stream() -> int:
@@ -435,6 +438,12 @@ def host_directions(nside):
     out = np.zeros(12 * nside * nside * 3)
     _check(lib().tr_host_directions(nside, _dptr(out)))
     return out.reshape(-1, 3)
+
+
+def host_parents(nside, nside_c):
+    out = np.zeros(12 * nside * nside, np.int32)
+    _check(lib().tr_host_parents(nside, nside_c, _iptr(out)))
+    return out
 
 
 def host_phase_matrix(nside, g, hg_norm="sinkhorn"):

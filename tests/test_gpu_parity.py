@@ -387,3 +387,43 @@ def test_implicit_source_rejected_where_unsupported():
         with pytest.raises(T.TrinityError):
             m.solve_checkpointed(5, 2)
         m.close()
+
+
+@pytest.mark.parametrize("nside,nsc,advance,shape", [(4, 1, "phase", (12, 9, 7)), (4, 2, "split", (11, 8, 9)),
+                                                     (8, 2, "phase", (9, 8, 6))])
+def test_two_level_single_step(nside, nsc, advance, shape):
+    """Scattering on a coarser angular grid: one step from a random state,
+    every element against the oracle (coarse sums, coarse P, equal shares)."""
+    nx, ny, nz = shape
+    p = W.small_problem(nside=nside, nx=nx, ny=ny, nz=nz, mua=0.05, mus=3.0, g=0.8, steps=1,
+                        seed=nside + nsc, advance=advance, total_photons=0.0)
+    p = p.copy(nside_scatter=nsc)
+    ndir = 12 * nside * nside
+    rng = np.random.default_rng(nsc)
+    N0 = rng.uniform(0, 1, (ndir, p.nvox)).astype(np.float32)
+    ref = solve.forward(p, steps=1, state0=N0.astype(np.float64))
+    got = run_gpu(p, steps=1, state0=N0)
+    assert np.abs(got["state"] - ref.state).max() <= 2e-6 * np.abs(ref.state).max()
+    assert abs(got["budget"][0, 1] - ref.absorbed[0]) <= 1e-5 * ref.absorbed[0]
+
+
+@pytest.mark.parametrize("nside,nsc,shape", [(4, 1, (16, 12, 10)), (8, 2, (12, 10, 8))])
+def test_two_level_solve(nside, nsc, shape):
+    nx, ny, nz = shape
+    p = W.small_problem(nside=nside, nx=nx, ny=ny, nz=nz, mua=0.01, mus=5.0, g=0.9, steps=40,
+                        seed=4, det_cone_deg=0.0).copy(nside_scatter=nsc)
+    ref = solve.forward(p)
+    got = run_gpu(p)
+    assert rel_l2_above(got["steps"].ravel(), ref.det.ravel()) < 1e-4
+    assert budget_closure(got["budget"]) < closure_bound(got["budget"])
+
+
+def test_two_level_rejected_where_unsupported():
+    import torch
+    p = W.small_problem(nside=4, steps=5).copy(nside_scatter=1)
+    with torch.cuda.stream(_stream()):
+        for bad in (p.copy(precision="bf16split"), p.copy(source="implicit"),
+                    p.copy(nside_scatter=3), p.copy(nside=16, nside_scatter=8)):
+            with pytest.raises(T.TrinityError) as e:
+                T.Medium.from_problem(bad)
+            assert e.value.status == T.TR_EINVAL

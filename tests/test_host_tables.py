@@ -114,3 +114,9 @@ def test_invalid_descriptor_is_rejected():
                                           mua.ctypes.data, 0, 0, ctypes.byref(h)))
     assert e.value.status == T.TR_EINVAL
     assert "nside" in str(e.value)
+
+
+@pytest.mark.parametrize("nf,nc", [(2, 1), (4, 1), (8, 2), (16, 4), (16, 16)])
+def test_host_parents_match_oracle(nf, nc):
+    from oracle import angles
+    assert np.array_equal(T.host_parents(nf, nc), angles.parents(nf, nc))
