@@ -308,6 +308,41 @@ def implicit_source(stream, steps=200):
             "workload": "phantom 64^3, 192 directions, implicit source, 200 steps"}
 
 
+def two_level(stream, steps=20):
+    """The paper's fiducial angular set-up on the phantom: transport on 3072
+    directions (nside 16), scattering on 192 (nside 4)."""
+    import torch
+
+    from paper_2105_01028_amd import trinity as T
+    from paper_2105_01028_amd import workloads as W
+    p = W.config2().copy(nside=16, nside_scatter=4)
+    with torch.cuda.stream(stream):
+        t0 = time.perf_counter()
+        m = T.Medium.from_problem(p)
+        t1 = time.perf_counter()
+        m.solve(3)
+        m.reset()
+        m.profile_begin(steps)
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+        m.step(steps)
+        m.synchronize()
+        t3 = time.perf_counter()
+        prof = m.profile_end()
+        b = m.read_budget()
+        m.close()
+    nd = 12 * 16 * 16
+    inj = b[:, 0].sum()
+    sw_ms, sw_n = prof["sweep"]
+    return {"workload": "phantom 64^3, transport 3072 directions (nside 16), scattering 192 "
+                        "(nside 4)", "setup_s": t1 - t0,
+            "ms_per_step": (t3 - t2) / steps * 1e3,
+            "updates_per_s": p.nvox * nd * steps / (t3 - t2),
+            "kernels_ms": {k: v[0] / v[1] if v[1] else 0.0 for k, v in prof.items()},
+            "sweep_gbs": 8.0 * nd * p.nvox / (sw_ms / sw_n * 1e-3) / 1e9,
+            "budget_closure": abs(inj - b[:, 1].sum() - b[:, 3:].sum() - b[-1, 2]) / max(inj, 1e-300)}
+
+
 def cpu_baseline(prob, budget_s=15.0):
     """The FP64 oracle on the host cores, on the first steps of the same workload."""
     from oracle import solve
@@ -405,6 +440,7 @@ def main():
         out["adjoint"] = adjoint_timing(stream)
         out["refraction128"] = refraction128(stream)
         out["implicit_source"] = implicit_source(stream)
+        out["two_level_3072_192"] = two_level(stream)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(prob)
     print(json.dumps(out), flush=True)
