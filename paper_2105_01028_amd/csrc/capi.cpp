@@ -604,8 +604,9 @@ tr_status tr_create_medium(const tr_grid_desc* desc, const float* mua, const flo
     // the budget partials come from the coarse sums, one pair per workgroup
     TwoLevelArgs probe{};
     probe.nc = m->nc;
+    probe.V = f.V;
     m->release(m->cpart);
-    m->cnwg = int((f.V + 255) / 256) * coarse_sum_groups(probe);
+    m->cnwg = int(coarse_sum_workgroups(probe));
     m->cpart = m->alloc<double>(2 * size_t(m->cnwg));
     if (!m->cpart) {
       delete m;

@@ -172,7 +172,7 @@ struct TwoLevelArgs {
   int V;
   double* part;            // [2][nwg] absorbed, total
 };
-int coarse_sum_groups(const TwoLevelArgs& a);   // nwg = ceil(V / 256) * groups
+long long coarse_sum_workgroups(const TwoLevelArgs& a);   // budget partial pairs written
 hipError_t launch_coarse_sum(const TwoLevelArgs& a, hipStream_t s);
 hipError_t launch_apply(const TwoLevelArgs& a, hipStream_t s);
 

@@ -30,26 +30,64 @@ __device__ double tl_block_sum(double v, double* red) {
   return s;
 }
 
-// Workgroup (voxel block bx, coarse group by): coarse bins J = by, by + gy, ...
+// Lanes hold four consecutive voxels (16-byte loads; rows start on 1 KiB
+// boundaries because Vp is a multiple of 256).  The one quad that straddles V
+// takes the scalar path.
+__device__ __forceinline__ float4 ld4(const float* p) {
+  return *reinterpret_cast<const float4*>(p);
+}
+__device__ __forceinline__ void st4(float* p, float4 v) {
+  *reinterpret_cast<float4*>(p) = v;
+}
+
+// The children table is never written on the device: reading it through the
+// constant address space lets the uniform index loads go to scalar registers
+// instead of a vector load and a wait in front of every batch.
+typedef const __attribute__((address_space(4))) int* const_ints;
+__device__ __forceinline__ const_ints kids_of(const TwoLevelArgs& A, int J) {
+  return (const_ints)(A.children + size_t(J) * A.nkids);
+}
+
+// Workgroup (quad block bx, coarse group by): coarse bins J = by, by + gy, ...
 // of the block's voxels; the budget partials cover the fine rows of those bins.
 __global__ __launch_bounds__(kTwoThreads) void coarse_sum_kernel(TwoLevelArgs A) {
   __shared__ double red[kTwoThreads / 64];
-  const long long v = (long long)blockIdx.x * kTwoThreads + threadIdx.x;
-  double colsum = 0.0;
-  float av = 0.f, bv = 0.f;
-  if (v < A.V) {
-    av = A.a[v];
-    bv = A.b[v];
+  const long long v0 = 4 * ((long long)blockIdx.x * kTwoThreads + threadIdx.x);
+  double col[4] = {0.0, 0.0, 0.0, 0.0};
+  double ab = 0.0;
+  if (v0 + 4 <= A.V) {
     for (int J = blockIdx.y; J < A.nc; J += gridDim.y) {
-      const int* kids = A.children + size_t(J) * A.nkids;
-      float s = 0.0f;
-      for (int k = 0; k < A.nkids; ++k) s += A.X[size_t(kids[k]) * A.Vp + v];
-      A.M[size_t(J) * A.Vp + v] = s;
-      colsum += double(s);
+      const const_ints kids = kids_of(A, J);
+      float4 s = make_float4(0.f, 0.f, 0.f, 0.f);
+#pragma unroll 8
+      for (int k = 0; k < A.nkids; ++k) {
+        const float4 x = ld4(A.X + size_t(kids[k]) * A.Vp + v0);
+        s.x += x.x;
+        s.y += x.y;
+        s.z += x.z;
+        s.w += x.w;
+      }
+      st4(A.M + size_t(J) * A.Vp + v0, s);
+      col[0] += double(s.x);
+      col[1] += double(s.y);
+      col[2] += double(s.z);
+      col[3] += double(s.w);
+    }
+  } else if (v0 < A.V) {
+    for (int J = blockIdx.y; J < A.nc; J += gridDim.y) {
+      const const_ints kids = kids_of(A, J);
+      for (long long v = v0; v < A.V; ++v) {
+        float s = 0.0f;
+        for (int k = 0; k < A.nkids; ++k) s += A.X[size_t(kids[k]) * A.Vp + v];
+        A.M[size_t(J) * A.Vp + v] = s;
+        col[v - v0] += double(s);
+      }
     }
   }
-  const double ab = tl_block_sum((1.0 - double(av) - double(bv)) * colsum, red);
-  const double tt = tl_block_sum(colsum, red);
+  for (int e = 0; e < 4; ++e)
+    if (v0 + e < A.V) ab += (1.0 - double(A.a[v0 + e]) - double(A.b[v0 + e])) * col[e];
+  ab = tl_block_sum(ab, red);
+  const double tt = tl_block_sum(col[0] + col[1] + col[2] + col[3], red);
   const long long nwg = (long long)gridDim.x * gridDim.y;
   const long long wg = (long long)blockIdx.y * gridDim.x + blockIdx.x;
   if (threadIdx.x == 0) {
@@ -58,31 +96,83 @@ __global__ __launch_bounds__(kTwoThreads) void coarse_sum_kernel(TwoLevelArgs A)
   }
 }
 
+// Workgroup (quad block bx, coarse group by): the fine rows of coarse bins
+// J = by, by + gy, ...; T[J] is read once for all of J's children.
 __global__ __launch_bounds__(kTwoThreads) void apply_kernel(TwoLevelArgs A) {
-  const long long v = (long long)blockIdx.x * kTwoThreads + threadIdx.x;
-  if (v >= A.V) return;
-  const float av = A.a[v];
-  for (int i = blockIdx.y; i < A.ndir; i += gridDim.y) {
-    const size_t k = size_t(i) * A.Vp + v;
-    A.Y[k] = fmaf(av, A.X[k], A.T[size_t(A.parent[i]) * A.Vp + v] * A.share);
+  const long long v0 = 4 * ((long long)blockIdx.x * kTwoThreads + threadIdx.x);
+  if (v0 >= A.V) return;
+  if (v0 + 4 <= A.V) {
+    const float4 av = ld4(A.a + v0);
+    for (int J = blockIdx.y; J < A.nc; J += gridDim.y) {
+      const const_ints kids = kids_of(A, J);
+      float4 t = ld4(A.T + size_t(J) * A.Vp + v0);
+      t.x *= A.share;
+      t.y *= A.share;
+      t.z *= A.share;
+      t.w *= A.share;
+      // four children per batch: all loads are issued before the first store
+      // (X and Y may alias as far as the compiler knows)
+      int k = 0;
+      for (; k + 4 <= A.nkids; k += 4) {
+        size_t o[4];
+        float4 x[4];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          o[j] = size_t(kids[k + j]) * A.Vp + v0;
+          x[j] = ld4(A.X + o[j]);
+        }
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+          st4(A.Y + o[j], make_float4(fmaf(av.x, x[j].x, t.x), fmaf(av.y, x[j].y, t.y),
+                                      fmaf(av.z, x[j].z, t.z), fmaf(av.w, x[j].w, t.w)));
+      }
+      for (; k < A.nkids; ++k) {
+        const size_t o = size_t(kids[k]) * A.Vp + v0;
+        const float4 x = ld4(A.X + o);
+        st4(A.Y + o, make_float4(fmaf(av.x, x.x, t.x), fmaf(av.y, x.y, t.y),
+                                 fmaf(av.z, x.z, t.z), fmaf(av.w, x.w, t.w)));
+      }
+    }
+  } else {
+    for (int J = blockIdx.y; J < A.nc; J += gridDim.y) {
+      const const_ints kids = kids_of(A, J);
+      for (long long v = v0; v < A.V; ++v) {
+        const float t = A.T[size_t(J) * A.Vp + v] * A.share;
+        for (int k = 0; k < A.nkids; ++k) {
+          const size_t o = size_t(kids[k]) * A.Vp + v;
+          A.Y[o] = fmaf(A.a[v], A.X[o], t);
+        }
+      }
+    }
   }
 }
 
 }  // namespace
 
-int coarse_sum_groups(const TwoLevelArgs& a) {
-  return a.nc < 16 ? a.nc : 16;
+namespace {
+
+unsigned quad_blocks(const TwoLevelArgs& a) {
+  return unsigned((a.V + 4 * kTwoThreads - 1) / (4 * kTwoThreads));
+}
+
+unsigned coarse_sum_groups(const TwoLevelArgs& a) {
+  return unsigned(a.nc < 16 ? a.nc : 16);
+}
+
+}  // namespace
+
+long long coarse_sum_workgroups(const TwoLevelArgs& a) {
+  return (long long)quad_blocks(a) * coarse_sum_groups(a);
 }
 
 hipError_t launch_coarse_sum(const TwoLevelArgs& a, hipStream_t s) {
-  dim3 grid(unsigned((a.V + kTwoThreads - 1) / kTwoThreads), unsigned(coarse_sum_groups(a)));
+  dim3 grid(quad_blocks(a), coarse_sum_groups(a));
   hipLaunchKernelGGL(coarse_sum_kernel, grid, dim3(kTwoThreads), 0, s, a);
   return hipGetLastError();
 }
 
 hipError_t launch_apply(const TwoLevelArgs& a, hipStream_t s) {
-  const int gy = a.ndir < 64 ? a.ndir : 64;
-  dim3 grid(unsigned((a.V + kTwoThreads - 1) / kTwoThreads), unsigned(gy));
+  dim3 grid(quad_blocks(a), coarse_sum_groups(a));
   hipLaunchKernelGGL(apply_kernel, grid, dim3(kTwoThreads), 0, s, a);
   return hipGetLastError();
 }
