@@ -27,9 +27,11 @@ PEAK_TFLOPS = {"fp32": 157.3, "bf16split": 2500.0}   # dense MFMA peaks
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "hbm_traffic_collide_sweep.txt")
 
 
-def kernel_source_hash():
+def kernel_source_hash(kernel="collide"):
+    """First 16 hex digits of the sha256 of the source file that holds `kernel`."""
     import hashlib
-    with open(os.path.join(ROOT, "paper_2105_01028_amd", "csrc", "kernels.hip"), "rb") as f:
+    src = "twolevel.hip" if kernel in ("coarse_sum", "apply") else "kernels.hip"
+    with open(os.path.join(ROOT, "paper_2105_01028_amd", "csrc", src), "rb") as f:
         return hashlib.sha256(f.read()).hexdigest()[:16]
 
 
@@ -48,7 +50,7 @@ def measured_traffic(kernel, precision, workload):
         kv = dict(item.split("=", 1) for item in line.split())
         rows[(kv.get("workload"), kv.get("kernel"), kv.get("precision"))] = kv
     kv = rows.get((workload, kernel, precision))
-    if kv is None or kv.get("source") != kernel_source_hash():
+    if kv is None or kv.get("source") != kernel_source_hash(kernel):
         return None
     return (float(kv["fetch_kib"]) * float(kv["fetch_scale"]) +
             float(kv["write_kib"]) * float(kv["write_scale"])) * 1024.0
@@ -308,6 +310,34 @@ def implicit_source(stream, steps=200):
             "workload": "phantom 64^3, 192 directions, implicit source, 200 steps"}
 
 
+def two_level_rooflines(prof, prob, nc):
+    """Rates of the kernels of a two-level step (N fine, nc coarse directions):
+    coarse_sum reads the fine field and writes the coarse one (4 V (N + nc)
+    bytes); the coarse contraction is 2 nc^2 V FLOP on the FP32 MFMA peak;
+    apply reads the fine and coarse fields and writes the fine one
+    (4 V (2 N + nc) bytes); sweep is 8 N V bytes as in the one-level step."""
+    N, V = prob.ndir, prob.nvox
+    work = {"coarse_sum": ("hbm", 4.0 * V * (N + nc)),
+            "collide": ("mfma", 2.0 * nc * nc * V),
+            "apply": ("hbm", 4.0 * V * (2 * N + nc)),
+            "sweep": ("hbm", 8.0 * N * V)}
+    out = {}
+    for k, (bound, w) in work.items():
+        ms, n = prof[k]
+        if not n:
+            continue
+        t = ms / n * 1e-3
+        if bound == "hbm":
+            out[k] = {"bound": "hbm", "achieved": w / t / 1e9, "peak": PEAK_HBM_GBS,
+                      "unit": "GB/s", "frac": w / t / 1e9 / PEAK_HBM_GBS}
+        else:
+            out[k] = {"bound": "mfma", "achieved": w / t / 1e12, "peak": 157.3,
+                      "unit": "TFLOP/s", "frac": w / t / 1e12 / 157.3}
+        out[k].update({"avg_ms": ms / n, "work_per_launch": w,
+                       "traffic": measured_traffic(k, "fp32", "twolevel64")})
+    return out
+
+
 def two_level(stream, steps=20):
     """The paper's fiducial angular set-up on the phantom: transport on 3072
     directions (nside 16), scattering on 192 (nside 4)."""
@@ -322,24 +352,24 @@ def two_level(stream, steps=20):
         t1 = time.perf_counter()
         m.solve(3)
         m.reset()
-        m.profile_begin(steps)
         torch.cuda.synchronize()
         t2 = time.perf_counter()
         m.step(steps)
         m.synchronize()
         t3 = time.perf_counter()
+        m.reset()
+        m.profile_begin(steps)
+        m.step(steps)
         prof = m.profile_end()
         b = m.read_budget()
         m.close()
-    nd = 12 * 16 * 16
     inj = b[:, 0].sum()
-    sw_ms, sw_n = prof["sweep"]
     return {"workload": "phantom 64^3, transport 3072 directions (nside 16), scattering 192 "
-                        "(nside 4)", "setup_s": t1 - t0,
+                        "(nside 4)", "setup_s": t1 - t0, "steps": steps,
             "ms_per_step": (t3 - t2) / steps * 1e3,
-            "updates_per_s": p.nvox * nd * steps / (t3 - t2),
-            "kernels_ms": {k: v[0] / v[1] if v[1] else 0.0 for k, v in prof.items()},
-            "sweep_gbs": 8.0 * nd * p.nvox / (sw_ms / sw_n * 1e-3) / 1e9,
+            "updates_per_s": p.nvox * p.ndir * steps / (t3 - t2),
+            "kernels_ms": {k: v[0] / v[1] for k, v in prof.items() if v[1]},
+            "kernel_rooflines": two_level_rooflines(prof, p, 12 * 4 * 4),
             "budget_closure": abs(inj - b[:, 1].sum() - b[:, 3:].sum() - b[-1, 2]) / max(inj, 1e-300)}
 
 
@@ -375,13 +405,18 @@ def main():
     ap.add_argument("--precision", default="fp32", choices=["fp32", "bf16split"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true")
-    ap.add_argument("--workload", default="phantom64", choices=["phantom64", "refraction128"],
-                    help="refraction128: only time the 128^3 x 768 medium (profiling runs)")
+    ap.add_argument("--workload", default="phantom64",
+                    choices=["phantom64", "refraction128", "twolevel64"],
+                    help="refraction128, twolevel64: only time that medium (profiling runs)")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="BYTES",
                     help="only run a plain device copy of BYTES (counter calibration)")
     args = ap.parse_args()
     if args.copy_probe:
         copy_probe(args.copy_probe)
+        return
+    if args.workload == "twolevel64":
+        import torch
+        print(json.dumps(two_level(torch.cuda.Stream(), args.steps)), flush=True)
         return
     if args.workload == "refraction128":
         import torch

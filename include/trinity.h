@@ -220,9 +220,12 @@ tr_status tr_backward(tr_medium* m, const double* dL_dbins, float* dmua, float* 
 
 /* ---- kernel timing ------------------------------------------------------ */
 
-/* Kernel kinds reported by tr_profile_end. */
+/* Kernel kinds reported by tr_profile_end.  With a two-level angular grid,
+ * TR_K_COLLIDE is the contraction on the coarse directions alone; the sums
+ * over children and the return to the fine directions are TR_K_COARSE_SUM and
+ * TR_K_APPLY (no launches otherwise). */
 enum { TR_K_INJECT = 0, TR_K_COLLIDE = 1, TR_K_SWEEP = 2, TR_K_GATHER = 3, TR_K_REDUCE = 4,
-       TR_K_COUNT = 5 };
+       TR_K_COARSE_SUM = 5, TR_K_APPLY = 6, TR_K_COUNT = 7 };
 
 /* Start timing: the next steps (up to max_steps of them) are queued one kernel
  * at a time with a pair of HIP events on the medium's stream around every

@@ -236,26 +236,33 @@ hipError_t queue_step(tr_medium* m) {
     InjectArgs ia{m->X, f.Vp, m->src_pairs, m->npairs, m->qdev, m->cap, m->step_ctr, m->budget};
     if ((e = launch_inject(ia, m->stream)) != hipSuccess) return e;
   }
-  {
-    KernelTimer t(m, TR_K_COLLIDE);
-    if (m->twolevel) {
-      TwoLevelArgs ta{m->X,        m->Y,      m->M,     m->T,     m->a,
-                      m->b,        m->children, m->parent, f.ndir, m->nc,
-                      m->nkids,    1.0f / float(m->nkids), f.Vp, f.V, m->cpart};
-      Field fc = f;
-      fc.ndir = m->nc;
-      fc.NP = m->NPc;
-      CollideArgs cc{m->M, m->T, m->P, m->Prow, nullptr, nullptr, m->zero, m->b,
-                     f.Vp, m->NPc, m->cpart2};
-      e = launch_coarse_sum(ta, m->stream);
-      if (e == hipSuccess) e = launch_collide(cc, fc, 0, 0, m->stream);
-      if (e == hipSuccess) e = launch_apply(ta, m->stream);
-    } else {
-      CollideArgs ca{m->X,   m->Y, m->P,  m->Prow, m->Phi, m->Plo, m->a,   m->b,
-                     f.Vp,   f.NP, m->cpart, m->V, m->lam, m->w0,  m->w1, m->cimp};
-      e = m->V ? launch_collide_implicit(ca, f, m->stream)
-               : launch_collide(ca, f, m->desc.precision, 0, m->stream);
+  if (m->twolevel) {
+    TwoLevelArgs ta{m->X,     m->Y,          m->M,                   m->T,  m->a,
+                    m->b,     m->children,   m->parent,              f.ndir, m->nc,
+                    m->nkids, 1.0f / float(m->nkids), f.Vp,          f.V,   m->cpart};
+    Field fc = f;
+    fc.ndir = m->nc;
+    fc.NP = m->NPc;
+    CollideArgs cc{m->M, m->T, m->P, m->Prow, nullptr, nullptr, m->zero, m->b,
+                   f.Vp, m->NPc, m->cpart2};
+    {
+      KernelTimer t(m, TR_K_COARSE_SUM);
+      if ((e = launch_coarse_sum(ta, m->stream)) != hipSuccess) return e;
     }
+    {
+      KernelTimer t(m, TR_K_COLLIDE);
+      if ((e = launch_collide(cc, fc, 0, 0, m->stream)) != hipSuccess) return e;
+    }
+    {
+      KernelTimer t(m, TR_K_APPLY);
+      if ((e = launch_apply(ta, m->stream)) != hipSuccess) return e;
+    }
+  } else {
+    KernelTimer t(m, TR_K_COLLIDE);
+    CollideArgs ca{m->X,   m->Y, m->P,  m->Prow, m->Phi, m->Plo, m->a,   m->b,
+                   f.Vp,   f.NP, m->cpart, m->V, m->lam, m->w0,  m->w1, m->cimp};
+    e = m->V ? launch_collide_implicit(ca, f, m->stream)
+             : launch_collide(ca, f, m->desc.precision, 0, m->stream);
     if (e != hipSuccess) return e;
   }
   const bool split = m->mode == TR_ADVANCE_SPLIT;

@@ -59,7 +59,7 @@ __global__ __launch_bounds__(kTwoThreads) void coarse_sum_kernel(TwoLevelArgs A)
     for (int J = blockIdx.y; J < A.nc; J += gridDim.y) {
       const const_ints kids = kids_of(A, J);
       float4 s = make_float4(0.f, 0.f, 0.f, 0.f);
-#pragma unroll 8
+#pragma unroll 16
       for (int k = 0; k < A.nkids; ++k) {
         const float4 x = ld4(A.X + size_t(kids[k]) * A.Vp + v0);
         s.x += x.x;

@@ -289,15 +289,15 @@ class Medium:
         return dmua.reshape(shape), dmus.reshape(shape)
 
     # ---- kernel timing
-    KERNELS = ("inject", "collide", "sweep", "gather", "reduce")
+    KERNELS = ("inject", "collide", "sweep", "gather", "reduce", "coarse_sum", "apply")
 
     def profile_begin(self, max_steps: int):
         _check(lib().tr_profile_begin(self._h, int(max_steps)))
 
     def profile_end(self):
         """Summed device ms and launch count per kernel kind since profile_begin."""
-        ms = np.zeros(5)
-        n = np.zeros(5, np.int32)
+        ms = np.zeros(len(self.KERNELS))
+        n = np.zeros(len(self.KERNELS), np.int32)
         _check(lib().tr_profile_end(self._h, _dptr(ms), _iptr(n)))
         return {k: (float(ms[i]), int(n[i])) for i, k in enumerate(self.KERNELS)}
 
