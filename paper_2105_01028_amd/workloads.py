@@ -41,7 +41,7 @@ class Problem:
     dt_ps: float = 0.0       # 0 => derived from the medium
     hg_norm: str = "sinkhorn"   # "sinkhorn" | "row"
     coef: str = "paper"         # "paper" | "abs_exact"
-    advance: str = "auto"       # "auto" | "phase" | "split"
+    advance: str = "auto"       # "auto" | "phase" | "split" | "retarded" (Courant < 1 history)
     precision: str = "fp32"     # "fp32" | "bf16split"
     source: str = "explicit"    # "explicit" | "implicit" (S1 from the new intensity, Eq. 9-10)
     nside_scatter: int = 0      # 0: scatter on the transport directions; else a coarser
