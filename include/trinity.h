@@ -55,7 +55,7 @@ typedef enum {
 
 enum { TR_HG_SINKHORN = 0, TR_HG_ROW = 1 };
 enum { TR_COEF_PAPER = 0, TR_COEF_ABS_EXACT = 1 };
-enum { TR_ADVANCE_AUTO = 0, TR_ADVANCE_PHASE = 1, TR_ADVANCE_SPLIT = 2 };
+enum { TR_ADVANCE_AUTO = 0, TR_ADVANCE_PHASE = 1, TR_ADVANCE_SPLIT = 2, TR_ADVANCE_RETARDED = 3 };
 enum { TR_PREC_FP32 = 0, TR_PREC_BF16SPLIT = 1 };
 enum { TR_SOURCE_EXPLICIT = 0, TR_SOURCE_IMPLICIT = 1 };
 
@@ -72,7 +72,21 @@ typedef struct {
   int advance;        /* TR_ADVANCE_AUTO: phase if n is uniform, else split;
                          TR_ADVANCE_PHASE: all photons of a direction move one plane on the
                          steps the direction's phase selects (n must be uniform);
-                         TR_ADVANCE_SPLIT: the fraction nu_d * min(n)/n_v moves each step */
+                         TR_ADVANCE_SPLIT: the fraction nu_d * min(n)/n_v moves each step;
+                         TR_ADVANCE_RETARDED: time steps below the crossing time (Sec. 2.1,
+                         the retarded formal solution; Sec. 2.2 and 3.1 run at a tenth and
+                         a fifth of it).  The hop between planes of direction d,
+                         dr_d = dx/|Omega_a|, takes D_d = dr_d n/(c0 dt) >= 1 steps; every
+                         step collides the field with the hop's coefficients
+                         a = e^{-mu_t dr_d}, b = omega (1 - a) into a history of the last
+                         floor(max D_d) + 1 collided fields, and a voxel takes its upwind
+                         voxel's collided value at the retarded step m + 1 - D_d (linear
+                         between the two nearest steps).  A voxel's photons cross a plane at
+                         1/D_d of them per step: the source puts D_d times its per-step
+                         photons into its voxels, and escape, detector and absorption
+                         tallies count 1/D_d of the content per step.  Needs uniform n, FP32,
+                         the explicit source, TR_COEF_PAPER, one angular grid and at most
+                         192 directions; tr_set_state, the adjoint and the server refuse it */
   int precision;      /* TR_PREC_FP32 or TR_PREC_BF16SPLIT (P and N split into bf16 hi+lo,
                          the four bf16 MFMA products, fp32 accumulation; each value
                          off by at most 2^-16 of itself) */
@@ -96,11 +110,12 @@ typedef struct {
 typedef struct {
   int ndir;           /* N = 12 nside^2 */
   int nvox;           /* nx*ny*nz */
-  int mode;           /* TR_ADVANCE_PHASE or TR_ADVANCE_SPLIT as resolved */
+  int mode;           /* TR_ADVANCE_PHASE, TR_ADVANCE_SPLIT or TR_ADVANCE_RETARDED as resolved */
   int ninterceptions; /* (direction, voxel) pairs whose move crosses an index jump */
   double dt_ps;       /* time step as resolved */
   long long steps_done;
   size_t device_bytes;  /* device memory the medium holds */
+  int history;        /* TR_ADVANCE_RETARDED: collided fields kept (floor(max D_d) + 1); else 0 */
 } tr_info;
 
 /* ---- medium life cycle ------------------------------------------------- */
@@ -121,7 +136,8 @@ tr_status tr_create_medium(const tr_grid_desc* desc, const float* mua, const flo
 
 /* Device bytes tr_create_medium would allocate for this descriptor with
  * ndet detectors and room for max_steps steps (for admission by HBM budget).
- * Returns 0 for an invalid descriptor. */
+ * Returns 0 for an invalid descriptor, and for TR_ADVANCE_RETARDED, whose
+ * history length depends on n. */
 size_t tr_bytes_required(const tr_grid_desc* desc, int ndet, int max_steps);
 
 /* Release every resource of the medium; waits for its queued work. NULL is OK. */
@@ -193,7 +209,8 @@ tr_status tr_read_energy(tr_medium* m, float* out, int on_device);
  * or into the medium, in host or device memory.  For tests and restarts.  The
  * copy is queued on the medium's stream after its earlier work and waited for;
  * device data that the caller wrote on another stream must be complete
- * before the call. */
+ * before the call.  With TR_ADVANCE_RETARDED the state also holds the history
+ * of collided fields, so tr_set_state returns TR_EINVAL. */
 tr_status tr_get_state(tr_medium* m, float* out, int on_device);
 tr_status tr_set_state(tr_medium* m, const float* in, int on_device);
 

@@ -48,6 +48,10 @@ struct tr_medium {
   float* nvox = nullptr;
   int* islot = nullptr;
   float *V = nullptr, *lam = nullptr, *w0 = nullptr, *w1 = nullptr, *cimp = nullptr;  // implicit
+  // retarded advance: history ring of H collided fields, per-voxel mu_t dx and
+  // omega, per-row 1/|Omega_a| and 1/D
+  float *ring = nullptr, *mutdx = nullptr, *omega = nullptr, *hinvc = nullptr, *hinvD = nullptr;
+  int H = 0;
   // two-level angular grid: coarse field of nc directions (NPc rows)
   bool twolevel = false;
   int nc = 0, NPc = 0, nkids = 0;
@@ -233,7 +237,8 @@ hipError_t queue_step(tr_medium* m) {
   hipError_t e;
   if (m->npairs > 0) {
     KernelTimer t(m, TR_K_INJECT);
-    InjectArgs ia{m->X, f.Vp, m->src_pairs, m->npairs, m->qdev, m->cap, m->step_ctr, m->budget};
+    InjectArgs ia{m->X,   f.Vp,        m->src_pairs, m->npairs, m->qdev,
+                  m->cap, m->step_ctr, m->budget,    m->ddirs,  m->ring != nullptr};
     if ((e = launch_inject(ia, m->stream)) != hipSuccess) return e;
   }
   if (m->twolevel) {
@@ -257,6 +262,22 @@ hipError_t queue_step(tr_medium* m) {
       KernelTimer t(m, TR_K_APPLY);
       if ((e = launch_apply(ta, m->stream)) != hipSuccess) return e;
     }
+  } else if (m->ring) {
+    KernelTimer t(m, TR_K_COLLIDE);
+    CollideArgs ca{};
+    ca.X = m->X;
+    ca.Prow = m->Prow;
+    ca.Vp = f.Vp;
+    ca.NP = f.NP;
+    ca.part = m->cpart;
+    ca.ring = m->ring;
+    ca.H = m->H;
+    ca.step_ctr = m->step_ctr;
+    ca.mutdx = m->mutdx;
+    ca.omega = m->omega;
+    ca.hinvc = m->hinvc;
+    ca.hinvD = m->hinvD;
+    if ((e = launch_collide_hop(ca, f, m->stream)) != hipSuccess) return e;
   } else {
     KernelTimer t(m, TR_K_COLLIDE);
     CollideArgs ca{m->X,   m->Y, m->P,  m->Prow, m->Phi, m->Plo, m->a,   m->b,
@@ -270,10 +291,10 @@ hipError_t queue_step(tr_medium* m) {
     KernelTimer t(m, TR_K_SWEEP);
     SweepArgs sa{m->Y, m->X, f.Vp, f.V, f.nx, f.ny, f.nz, m->ddirs, m->delta, m->dstride,
                  m->r, m->iface, m->nvox, m->islot, m->icptF, f.ndir, m->step_ctr, m->spart,
-                 m->mat, m->rtab, m->rowbits, m->bgcls};
-    if ((e = launch_sweep(sa, f, split, m->fresnel, m->sweep_bpd, m->stream, m->fast_split)) !=
-        hipSuccess)
-      return e;
+                 m->mat, m->rtab, m->rowbits, m->bgcls, m->ring, m->H, (long long)f.NP * f.Vp};
+    e = m->ring ? launch_sweep_retarded(sa, f, m->sweep_bpd, m->stream)
+                : launch_sweep(sa, f, split, m->fresnel, m->sweep_bpd, m->stream, m->fast_split);
+    if (e != hipSuccess) return e;
   }
   if (m->fresnel) {
     KernelTimer t(m, TR_K_GATHER);
@@ -283,7 +304,8 @@ hipError_t queue_step(tr_medium* m) {
   KernelTimer t(m, TR_K_REDUCE);
   ReduceArgs ra{m->cpart, m->cnwg, m->spart, m->snwg, m->Y, f.Vp, m->det_pairs, m->det_first,
                 m->det_vox_dev, m->ndet, m->ddirs, m->r, split ? 1 : 0, m->step_ctr, m->budget,
-                m->det_steps, m->cap, m->flag, m->rscratch, m->rdone};
+                m->det_steps, m->cap, m->flag, m->rscratch, m->rdone,
+                m->ring, m->H, (long long)f.NP * f.Vp};
   return launch_reduce(ra, m->stream);
 }
 
@@ -333,6 +355,7 @@ const char* tr_last_error(void) { return last_error().c_str(); }
 size_t tr_bytes_required(const tr_grid_desc* desc, int ndet, int max_steps) {
   std::string err;
   if (!valid_desc(desc, err) || ndet < 0 || max_steps < 0) return 0;
+  if (desc->advance == TR_ADVANCE_RETARDED) return 0;   // the history length depends on n
   Field f = field_of(desc);
   size_t b = fixed_bytes(f, desc->precision, 0);
   if (desc->source == TR_SOURCE_IMPLICIT)   // V, its eigenvalues, w0, w1, c
@@ -397,6 +420,10 @@ tr_status tr_create_medium(const tr_grid_desc* desc, const float* mua, const flo
   if (mode == TR_ADVANCE_PHASE && !m->co.uniform_n) {
     delete m;
     return fail(TR_EINVAL, "phase advance needs a uniform refractive index");
+  }
+  if (mode == TR_ADVANCE_RETARDED && !m->co.uniform_n) {
+    delete m;
+    return fail(TR_EINVAL, "the retarded advance needs a uniform refractive index");
   }
   m->mode = mode;
   double maxspeed = 0, maxr = 0;
@@ -480,6 +507,15 @@ tr_status tr_create_medium(const tr_grid_desc* desc, const float* mua, const flo
         dl[(size_t(d) * 2 + q) * m->dstride + k] = int8_t(s);
         if (q == 0 && (s < -1 || s > 1)) dd[d].unitb = 0;
       }
+  }
+  // retarded advance: a hop takes D_d = dx / (|Omega_a| l_ref) = 1 / nu_d steps
+  for (int d = 0; d < f.ndir; ++d) {
+    const double D = 1.0 / dd[d].nu64;
+    const int lag = int(std::floor(D + 1e-12));
+    dd[d].rlag = lag;
+    dd[d].rphi = float(std::max(D - lag, 0.0));
+    dd[d].rD = float(D);
+    dd[d].rinvD = float(1.0 / D);
   }
   m->fast_split = f.nx % 4 == 0;
   for (const DevDir& D : dd) m->fast_split = m->fast_split && D.unitb;
@@ -618,6 +654,43 @@ tr_status tr_create_medium(const tr_grid_desc* desc, const float* mua, const flo
     if (!m->cpart) {
       delete m;
       return fail(TR_ENOMEM, "device allocation failed (two-level partials)");
+    }
+  }
+  // ---- retarded advance: history ring of collided fields and hop tables
+  if (m->mode == TR_ADVANCE_RETARDED) {
+    int maxlag = 0;
+    std::vector<float> ic(f.NP, 0.0f), iD(f.NP, 0.0f);
+    for (int d = 0; d < f.ndir; ++d) {
+      maxlag = std::max(maxlag, dd[d].rlag);
+      ic[d] = float(1.0 / m->lat.speed[d]);
+      iD[d] = dd[d].rinvD;
+    }
+    m->H = maxlag + 1;
+    std::vector<float> mx(f.Vp, 0.0f), om(f.Vp, 0.0f);
+    for (int v = 0; v < f.V; ++v) {
+      const double mt = double(m->mua_host[v]) + double(m->mus_host[v]);
+      mx[v] = float(mt * desc->dx_mm);
+      om[v] = mt > 0.0 ? float(double(m->mus_host[v]) / mt) : 0.0f;
+    }
+    const size_t nring = size_t(m->H) * f.NP * f.Vp;
+    m->ring = m->alloc<float>(nring);
+    m->mutdx = m->alloc<float>(f.Vp);
+    m->omega = m->alloc<float>(f.Vp);
+    m->hinvc = m->alloc<float>(f.NP);
+    m->hinvD = m->alloc<float>(f.NP);
+    if (!m->ring || !m->mutdx || !m->omega || !m->hinvc || !m->hinvD) {
+      delete m;
+      return fail(TR_ENOMEM, "device allocation failed (history of the retarded advance)");
+    }
+    e = hipMemset(m->ring, 0, nring * 4);
+    if (e == hipSuccess) e = hipMemcpy(m->mutdx, mx.data(), mx.size() * 4, hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(m->omega, om.data(), om.size() * 4, hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(m->hinvc, ic.data(), ic.size() * 4, hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(m->hinvD, iD.data(), iD.size() * 4, hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = prepare_collide_hop(f);
+    if (e != hipSuccess) {
+      delete m;
+      return fail(TR_EDEVICE, std::string("upload: ") + hipGetErrorString(e));
     }
   }
   // ---- implicit source: eigen-decomposition of P and per-voxel weights
@@ -828,6 +901,8 @@ tr_status tr_reset(tr_medium* m) {
   const Field& f = m->f;
   hipError_t e = hipMemsetAsync(m->X, 0, size_t(f.NP) * f.Vp * 4, m->stream);
   if (e == hipSuccess) e = hipMemsetAsync(m->Y, 0, size_t(f.NP) * f.Vp * 4, m->stream);
+  if (e == hipSuccess && m->ring)
+    e = hipMemsetAsync(m->ring, 0, size_t(m->H) * f.NP * f.Vp * 4, m->stream);
   if (e == hipSuccess) e = hipMemsetAsync(m->budget, 0, size_t(m->cap) * 9 * 8, m->stream);
   if (e == hipSuccess && m->ndet > 0)
     e = hipMemsetAsync(m->det_steps, 0, size_t(m->ndet) * m->cap * 8, m->stream);
@@ -972,6 +1047,9 @@ tr_status tr_set_state(tr_medium* m, const float* in, int on_device) {
   tr_status st = tr_synchronize(m);
   if (st != TR_OK) return st;
   if (!in) return fail(TR_EINVAL, "null input");
+  if (m->ring)
+    return fail(TR_EINVAL, "the retarded advance keeps a history of collided fields; "
+                           "its state cannot be set");
   hipError_t e = hipMemcpy2DAsync(m->X, m->f.Vp * 4, in, m->f.V * 4, m->f.V * 4, m->f.ndir,
                                   on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice,
                                   m->stream);
@@ -983,8 +1061,9 @@ tr_status tr_set_state(tr_medium* m, const float* in, int on_device) {
 tr_status tr_solve_checkpointed(tr_medium* m, int nsteps, int ckpt_every) {
   tr_status st = check_medium(m);
   if (st != TR_OK) return st;
-  if (m->V || m->twolevel)
-    return fail(TR_EINVAL, "gradients are for the explicit source on one angular grid");
+  if (m->V || m->twolevel || m->ring)
+    return fail(TR_EINVAL, "gradients are for the explicit source on one angular grid, "
+                           "stepped at or below the crossing time without history");
   if (nsteps < 1 || ckpt_every < 1) return fail(TR_EINVAL, "nsteps and ckpt_every must be >= 1");
   if ((st = tr_reset(m)) != TR_OK) return st;
   const Field& f = m->f;
@@ -1186,6 +1265,7 @@ tr_status tr_get_info(tr_medium* m, tr_info* out) {
   out->dt_ps = m->dt;
   out->steps_done = m->steps_done;
   out->device_bytes = m->bytes;
+  out->history = m->H;
   return TR_OK;
 }
 

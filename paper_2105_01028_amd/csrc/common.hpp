@@ -39,7 +39,12 @@ inline bool valid_desc(const tr_grid_desc* d, std::string& err) {
   if (!(d->dt_ps >= 0) || !std::isfinite(d->dt_ps)) return err = "dt_ps must be >= 0", false;
   if (d->hg_norm != 0 && d->hg_norm != 1) return err = "bad hg_norm", false;
   if (d->coef != 0 && d->coef != 1) return err = "bad coef", false;
-  if (d->advance < 0 || d->advance > 2) return err = "bad advance", false;
+  if (d->advance < 0 || d->advance > 3) return err = "bad advance", false;
+  if (d->advance == 3 && (d->precision != 0 || d->source != 0 || d->coef != 0 ||
+                          (d->nside_scatter != 0 && d->nside_scatter != d->nside) ||
+                          12 * d->nside * d->nside > 192))
+    return err = "the retarded advance needs FP32, the explicit source, the paper's "
+                 "coefficients, one angular grid and at most 192 directions", false;
   if (d->precision != 0 && d->precision != 1) return err = "bad precision", false;
   if (d->source != 0 && d->source != 1) return err = "bad source", false;
   if (d->nside_scatter != 0 && d->nside_scatter != d->nside) {

@@ -14,6 +14,10 @@ struct DevDir {
   float nu;                   // planes advanced per step at the reference path (split mode)
   int unitb;                  // 1 if every plane-to-plane shift along b is -1, 0 or +1
   double nu64;                // same, FP64, for the phase-mode move rule
+  // retarded stepping (below Courant one): a hop between planes takes
+  // rD = rlag + rphi steps; rinvD = 1 / rD
+  int rlag;
+  float rphi, rD, rinvD;
 };
 
 // The photon field lives in N[d][v] buffers of NP rows (directions, padded to a
@@ -34,6 +38,8 @@ struct InjectArgs {
   int cap;                 // length of q and of the budget
   const int* step_ctr;
   double* budget;          // [cap][9]
+  const DevDir* dirs;      // retarded stepping: a pair of direction d gets rD times its share
+  int retarded;
 };
 
 struct CollideArgs {
@@ -56,6 +62,16 @@ struct CollideArgs {
   const float* w0;
   const float* w1;
   const float* cimp;
+  // retarded stepping (null otherwise): history ring [H][NP][Vp] (slot = step
+  // mod H), per voxel mu_t dx and omega, per direction row 1/|Omega_a| and 1/D
+  // (zero on padding rows)
+  float* ring;
+  int H;
+  const int* step_ctr;
+  const float* mutdx;
+  const float* omega;
+  const float* hinvc;
+  const float* hinvD;
 };
 
 struct SweepArgs {
@@ -80,6 +96,9 @@ struct SweepArgs {
                             // when all its voxels have class bgcls and none starts an
                             // interception
   unsigned bgcls;           // the class of most voxels
+  const float* ring;        // retarded stepping: history ring [H][NP][Vp], slot = step mod H
+  int H;
+  long long slot;           // NP * Vp
 };
 
 constexpr int kMaxRowBits = 65536;   // rows covered by the uniform-row bitmap (8 KB)
@@ -117,6 +136,9 @@ struct ReduceArgs {
   int* flag;               // bit 0: non-finite budget, bit 1: step beyond capacity
   double* scratch;         // [8] per-quantity sums of the current step
   int* done;               // workgroups finished (reset by the last one)
+  const float* ring;       // retarded stepping: detectors read the history ring
+  int H;
+  long long slot;
 };
 
 // One request of the batched server: its argument blocks as the single-medium
@@ -182,6 +204,13 @@ hipError_t launch_collide(const CollideArgs& a, const Field& f, int bf16split, i
                           hipStream_t s);
 int collide_nwg(const Field& f, int bf16split);
 // Implicit-source collision (A.V etc. set), NP <= 192, FP32.
+// Retarded stepping below Courant one: collision with per-direction hop
+// coefficients into the history ring, and the sweep that reads the ring at
+// the retarded time.
+hipError_t prepare_collide_hop(const Field& f);
+hipError_t launch_collide_hop(const CollideArgs& a, const Field& f, hipStream_t s);
+hipError_t launch_sweep_retarded(const SweepArgs& a, const Field& f, int blocks_per_dir,
+                                 hipStream_t s);
 hipError_t launch_collide_implicit(const CollideArgs& a, const Field& f, hipStream_t s);
 hipError_t prepare_collide_implicit(const Field& f);
 hipError_t prepare_collide(const Field& f, int bf16split);   // once per process and shape

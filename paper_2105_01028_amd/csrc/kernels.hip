@@ -75,7 +75,7 @@ __device__ __forceinline__ void inject_body(const InjectArgs& A) {
   const float share = float(q / double(A.npairs));
   for (int i = threadIdx.x; i < A.npairs; i += blockDim.x) {
     const int d = A.pairs[2 * i], v = A.pairs[2 * i + 1];
-    A.X[size_t(d) * A.Vp + v] += share;
+    A.X[size_t(d) * A.Vp + v] += A.retarded ? share * A.dirs[d].rD : share;
   }
   if (threadIdx.x == 0 && m < A.cap) A.budget[size_t(m) * 9 + 0] = double(share) * A.npairs;
 }
@@ -266,6 +266,126 @@ __global__ __launch_bounds__(512, 1) void collide_f32_res_kernel(CollideArgs A, 
 #pragma unroll 1
   for (int tile = blockIdx.x; tile < ntiles; tile += gridDim.x)
     collide_res_tile<NP>(A, Ps, tile, absorbed, total);
+  block_sums512(absorbed, total, A.part + blockIdx.x, A.part + gridDim.x + blockIdx.x);
+}
+
+// Collision over one hop, for stepping below Courant one (Sec. 2.1, the
+// retarded form of Eq. 10 with S1 := S0).  Direction i hops dr_i = dx/|Omega_a|
+// between planes, so its coefficients depend on the row as well as the voxel:
+//   a[i][v] = exp(-mu_t(v) dr_i),  b[i][v] = omega_v (1 - a[i][v]).
+// The B operand is omega_v X (the per-voxel factor of b), so the accumulator
+// holds omega_v (P X)[i][v], and the epilogue forms
+//   C[i][v] = a X[i][v] + (1 - a) acc
+// with X re-read (a tile's rows were read moments before).  C goes to the
+// history slot of the current step.  Absorbed per step, with the light of a
+// hop spread over its D_i steps: (1 - a)(1 - omega) X[i][v] / D_i.
+template <int NP>
+__device__ __forceinline__ void collide_hop_tile(const CollideArgs& A, const float* Ps,
+                                                 const float* sinvc, const float* sinvD,
+                                                 float* __restrict__ Cout, int tile,
+                                                 double& absorbed, double& total) {
+  constexpr int NQ = NP / 32;
+  constexpr int LDK = NP + 4;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int hl = lane >> 5, cl = lane & 31;
+  const size_t rowbytes = size_t(A.Vp) * sizeof(float);
+  const float* __restrict__ Pl = Ps + cl * LDK + 4 * hl;
+  const long long col = (long long)tile * 256 + wave * 32 + cl;
+  const unsigned voff = unsigned(size_t(col) * sizeof(float) + size_t(4 * hl) * rowbytes);
+  const char* __restrict__ xb0 = reinterpret_cast<const char*>(A.X);
+  const float mx = A.mutdx[col], om = A.omega[col];
+  floatx16 acc[NQ];
+#pragma unroll
+  for (int q = 0; q < NQ; ++q)
+#pragma unroll
+    for (int r = 0; r < 16; ++r) acc[q][r] = 0.0f;
+  auto ld = [&](int c, int s) {
+    const char* rb = xb0 + size_t(32 * c + 8 * (s >> 2) + (s & 3)) * rowbytes;
+    return *reinterpret_cast<const float*>(rb + voff);
+  };
+  float bcur[16], bnext[16];
+#pragma unroll
+  for (int s = 0; s < 16; ++s) bcur[s] = ld(0, s);
+#pragma unroll 1
+  for (int c = 0; c < NQ; ++c) {
+    const int cn = c + 1 < NQ ? c + 1 : c;
+#pragma unroll
+    for (int s = 0; s < 16; ++s) bnext[s] = ld(cn, s);
+#pragma unroll
+    for (int s = 0; s < 16; ++s) bcur[s] *= om;
+#pragma unroll
+    for (int s4 = 0; s4 < 16; s4 += 4) {
+      const int kk = 32 * c + 8 * (s4 >> 2);
+#pragma unroll
+      for (int q = 0; q < NQ; ++q) {
+        const float4 a4 = *reinterpret_cast<const float4*>(Pl + q * 32 * LDK + kk);
+        acc[q] = __builtin_amdgcn_mfma_f32_32x32x2f32(a4.x, bcur[s4 + 0], acc[q], 0, 0, 0);
+        acc[q] = __builtin_amdgcn_mfma_f32_32x32x2f32(a4.y, bcur[s4 + 1], acc[q], 0, 0, 0);
+        acc[q] = __builtin_amdgcn_mfma_f32_32x32x2f32(a4.z, bcur[s4 + 2], acc[q], 0, 0, 0);
+        acc[q] = __builtin_amdgcn_mfma_f32_32x32x2f32(a4.w, bcur[s4 + 3], acc[q], 0, 0, 0);
+      }
+    }
+#pragma unroll
+    for (int s = 0; s < 16; ++s) bcur[s] = bnext[s];
+  }
+  // keep the epilogue's re-reads of X after the K loop (hoisted, they would
+  // hold 96 more registers across it)
+  __asm__ volatile("" ::: "memory");
+  char* __restrict__ cb0 = reinterpret_cast<char*>(Cout);
+  // exp(-mu_t dx / |Omega_a|) = exp2(-(mu_t dx log2 e) / |Omega_a|) on the
+  // hardware exp2
+  const float ml2 = mx * 1.44269504088896341f;
+  // the lane half's rows of the hop tables: one base, constant offsets
+  const float* __restrict__ ic = sinvc + 4 * hl;
+  const float* __restrict__ iD = sinvD + 4 * hl;
+  double colsum = 0.0, lost = 0.0;
+  // rows of accumulator block q: 32q + 8(r/4) + r%4 (+ 4h in voff); addresses
+  // from the block's base and the 16 in-block offsets, so that the compiler
+  // does not keep 96 row offsets live across the tile loop
+#pragma unroll
+  for (int q = 0; q < NQ; ++q) {
+    const char* xq = xb0 + size_t(32 * q) * rowbytes + voff;
+    char* cq = cb0 + size_t(32 * q) * rowbytes + voff;
+#pragma unroll
+    for (int r4 = 0; r4 < 16; r4 += 4) {
+      const size_t o4 = size_t(8 * (r4 >> 2)) * rowbytes;
+      float x[4];
+#pragma unroll
+      for (int j = 0; j < 4; ++j)
+        x[j] = *reinterpret_cast<const float*>(xq + o4 + size_t(j) * rowbytes);
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const int r = r4 + j;
+        const int ro = q * 32 + 8 * (r >> 2) + (r & 3);   // row minus 4h
+        const float a = __builtin_amdgcn_exp2f(-ml2 * ic[ro]);
+        const float oma = 1.0f - a;
+        *reinterpret_cast<float*>(cq + o4 + size_t(j) * rowbytes) = fmaf(a, x[j], oma * acc[q][r]);
+        colsum += double(x[j]);
+        lost += double(oma * x[j]) * double(iD[ro]);
+      }
+    }
+  }
+  absorbed += (1.0 - double(om)) * lost;
+  total += colsum;
+}
+
+template <int NP>
+__global__ __launch_bounds__(512, 1) void collide_hop_kernel(CollideArgs A, int ntiles) {
+  extern __shared__ float Ps[];
+  float* sinvc = Ps + NP * (NP + 4);
+  float* sinvD = sinvc + NP;
+  load_p_lds<NP>(A.Prow, Ps);
+  for (int i = threadIdx.x; i < NP; i += 512) {
+    sinvc[i] = A.hinvc[i];
+    sinvD[i] = A.hinvD[i];
+  }
+  __syncthreads();
+  const int m = *A.step_ctr;
+  float* Cout = A.ring + size_t(m % A.H) * size_t(NP) * size_t(A.Vp);
+  double absorbed = 0.0, total = 0.0;
+#pragma unroll 1
+  for (int tile = blockIdx.x; tile < ntiles; tile += gridDim.x)
+    collide_hop_tile<NP>(A, Ps, sinvc, sinvD, Cout, tile, absorbed, total);
   block_sums512(absorbed, total, A.part + blockIdx.x, A.part + gridDim.x + blockIdx.x);
 }
 
@@ -832,6 +952,49 @@ struct SweepAcc {
   double esc_a = 0, esc_b0 = 0, esc_b1 = 0, esc_c0 = 0, esc_c1 = 0, dom = 0;
 };
 
+// The collided field a moving sweep reads for one direction: one field, or,
+// when stepping below Courant one, the blend of two past collided fields at
+// the retarded time, w_late C^{m+1-n} + w_early C^{m-n}.
+struct OneField {
+  const float* __restrict__ p;
+  __device__ __forceinline__ float operator[](long long i) const { return p[i]; }
+  __device__ __forceinline__ float4 q4(long long q) const {
+    return reinterpret_cast<const float4*>(p)[q];
+  }
+};
+
+struct TwoFields {
+  const float* __restrict__ late;
+  const float* __restrict__ early;
+  float wl, we;
+  __device__ __forceinline__ float operator[](long long i) const {
+    return fmaf(we, early[i], wl * late[i]);
+  }
+  __device__ __forceinline__ float4 q4(long long q) const {
+    const float4 l = reinterpret_cast<const float4*>(late)[q];
+    const float4 e = reinterpret_cast<const float4*>(early)[q];
+    return make_float4(fmaf(we, e.x, wl * l.x), fmaf(we, e.y, wl * l.y), fmaf(we, e.z, wl * l.z),
+                       fmaf(we, e.w, wl * l.w));
+  }
+};
+
+// Direction d's rows at the retarded time m + 1 - D_d, D_d = rlag + rphi: slot
+// (m + 1 - rlag) mod H with weight 1 - rphi and slot (m - rlag) mod H with
+// weight rphi.  Slots of steps before the first are zero (the ring is cleared
+// at reset and a slot is written only at its own step).  With rphi = 0 both
+// point at the same row.
+__device__ __forceinline__ TwoFields retarded_rows(const float* ring, int H, long long slot,
+                                                   long long Vp, const DevDir& D, int d, int m) {
+  const int sl = ((m + 1 - D.rlag) % H + H) % H;
+  const int se = ((m - D.rlag) % H + H) % H;
+  TwoFields t;
+  t.late = ring + sl * slot + size_t(d) * Vp;
+  t.early = D.rphi > 0.0f ? ring + se * slot + size_t(d) * Vp : t.late;
+  t.wl = 1.0f - D.rphi;
+  t.we = D.rphi;
+  return t;
+}
+
 constexpr int kMaxExt = 4096;   // largest grid extent (the C-ABI rejects larger)
 #ifndef TRINITY_SWEEP_ROWS
 #define TRINITY_SWEEP_ROWS 4
@@ -964,9 +1127,10 @@ __device__ __forceinline__ void sweep_rows(const SweepArgs& A, const DevDir& D, 
 // its upwind voxel's value, light in the exit plane (or crossing a side of the
 // box) leaves.  Per-row (or, for x-dominant directions, per-lane) quantities
 // are hoisted; indices are 32-bit (the C-ABI limits a grid to 2^30 voxels).
-template <int AX>
-__device__ __forceinline__ void sweep_phase_rows(const SweepArgs& A, const DevDir& D, int d,
-                                                 int rb, int re, const int8_t* __restrict__ db,
+template <int AX, class Src>
+__device__ __forceinline__ void sweep_phase_rows(const SweepArgs& A, const Src& Yd,
+                                                 const DevDir& D, int d, int rb, int re,
+                                                 const int8_t* __restrict__ db,
                                                  const int8_t* __restrict__ dc, SweepAcc& acc) {
   const int nx = A.nx, ny = A.ny, nz = A.nz;
   const int nxy = nx * ny;
@@ -975,7 +1139,6 @@ __device__ __forceinline__ void sweep_phase_rows(const SweepArgs& A, const DevDi
   const int ec = CX == 1 ? ny : nz;
   const int sa = AX == 0 ? 1 : (AX == 1 ? nx : nxy);
   const int sc = CX == 1 ? nx : nxy;
-  const float* __restrict__ Yd = A.Y + size_t(d) * A.Vp;
   float* __restrict__ Xd = A.X + size_t(d) * A.Vp;
   const int tpr = nx < kThreads ? nx : kThreads;
   const int rpi = kThreads / tpr;
@@ -1114,9 +1277,10 @@ __device__ __forceinline__ void sweep_phase_rows(const SweepArgs& A, const DevDi
 // the next four voxels over comes from its neighbour lane (or, at the edge of
 // the wave, from memory).  Same tallies, in the same order of precedence, as
 // the scalar path.
-template <int AX>
-__device__ __forceinline__ void sweep_phase_vec(const SweepArgs& A, const DevDir& D, int d,
-                                                int rb, int re, const int8_t* __restrict__ db,
+template <int AX, class Src>
+__device__ __forceinline__ void sweep_phase_vec(const SweepArgs& A, const Src& Ysrc,
+                                                const DevDir& D, int d, int rb, int re,
+                                                const int8_t* __restrict__ db,
                                                 const int8_t* __restrict__ dc, SweepAcc& acc) {
   static_assert(AX == 1 || AX == 2, "rows run along x");
   constexpr int CX = AX == 2 ? 1 : 2;
@@ -1126,9 +1290,7 @@ __device__ __forceinline__ void sweep_phase_vec(const SweepArgs& A, const DevDir
   const int tq = nx >> 2;                              // float4 per row
   const int sa4 = AX == 1 ? tq : tq * ny;              // plane stride in float4
   const int sc4 = CX == 1 ? tq : tq * ny;
-  const float4* __restrict__ Yd = reinterpret_cast<const float4*>(A.Y + size_t(d) * A.Vp);
   float4* __restrict__ Xd = reinterpret_cast<float4*>(A.X + size_t(d) * A.Vp);
-  const float* __restrict__ Ys = A.Y + size_t(d) * A.Vp;
   const int sign = D.sign;
   const int lane = threadIdx.x & 63;
   const int ge = re * tq;
@@ -1144,18 +1306,18 @@ __device__ __forceinline__ void sweep_phase_vec(const SweepArgs& A, const DevDir
     const int dbk = db[k], dck = dc[k], dbn = db[k + 1], dcn = dc[k + 1];
     const bool rowin = k > 0 && (unsigned)(pc - dck) < (unsigned)ec;
     const int u = g - sign * sa4 - dck * sc4;
-    const float4 y = rowin ? Yd[u] : make_float4(0.f, 0.f, 0.f, 0.f);
+    const float4 y = rowin ? Ysrc.q4(u) : make_float4(0.f, 0.f, 0.f, 0.f);
     // the neighbour lane holds the next four voxels of the same row (q > 0 / q < tq - 1)
     const float prev_w = __shfl_up(y.w, 1);
     const float next_x = __shfl_down(y.x, 1);
     float4 o = y;
     if (dbk > 0) {
       float w = 0.f;
-      if (rowin && q > 0) w = lane > 0 ? prev_w : Ys[4 * u - 1];
+      if (rowin && q > 0) w = lane > 0 ? prev_w : Ysrc[4 * u - 1];
       o = make_float4(w, y.x, y.y, y.z);
     } else if (dbk < 0) {
       float x = 0.f;
-      if (rowin && q < tq - 1) x = lane < 63 ? next_x : Ys[4 * u + 4];
+      if (rowin && q < tq - 1) x = lane < 63 ? next_x : Ysrc[4 * u + 4];
       o = make_float4(y.y, y.z, y.w, x);
     }
     Xd[g] = o;
@@ -1165,7 +1327,7 @@ __device__ __forceinline__ void sweep_phase_vec(const SweepArgs& A, const DevDir
     const bool bx = !last && ((dbn > 0 && q == tq - 1) || (dbn < 0 && q == 0));
     const bool cexit = !last && (unsigned)(pc + dcn) >= (unsigned)ec;
     if (last || bx || cexit) {
-      const float4 s4 = Yd[g];
+      const float4 s4 = Ysrc.q4(g);
       if (last) {
         acc.esc_a += (double(s4.x) + double(s4.y)) + (double(s4.z) + double(s4.w));
       } else {
@@ -1365,13 +1527,13 @@ __device__ __forceinline__ void sweep_split_vec(const SweepArgs& A, const DevDir
 // across z are walked along y, and the upwind rows a wave reads in pieces
 // (they differ lane by lane by a row in y or z) are still in L2 when the
 // neighbouring rows' waves read the rest of their cache lines.
-__device__ __forceinline__ void sweep_phase_band0(const SweepArgs& A, const DevDir& D, int d,
-                                                  int blk, int nblk,
+template <class Src>
+__device__ __forceinline__ void sweep_phase_band0(const SweepArgs& A, const Src& Yd,
+                                                  const DevDir& D, int d, int blk, int nblk,
                                                   const int8_t* __restrict__ db,
                                                   const int8_t* __restrict__ dc, SweepAcc& acc) {
   const int nx = A.nx, ny = A.ny, nz = A.nz;
   const int nxy = nx * ny;
-  const float* __restrict__ Yd = A.Y + size_t(d) * A.Vp;
   float* __restrict__ Xd = A.X + size_t(d) * A.Vp;
   const int tpr = nx < kThreads ? nx : kThreads;
   const int rpi = kThreads / tpr;
@@ -1505,6 +1667,48 @@ __device__ __forceinline__ void sweep_split_rows0(const SweepArgs& A, const DevD
 
 }  // namespace
 
+// Every photon of direction d moves one plane: 16-byte rows for y- and
+// z-dominant directions on grids with nx a multiple of 4, else rows of single
+// voxels, or, x-dominant, lanes across planes in band order.
+template <class Src>
+__device__ __forceinline__ void sweep_moving(const SweepArgs& A, const Src& Y, const DevDir& D,
+                                             int d, int blk, int nblk, int rb, int re,
+                                             int8_t (&sdelta)[2][kMaxExt + 2], SweepAcc& acc) {
+  if (D.axis != 0 && (A.nx & 3) == 0 && D.unitb) {
+    if (D.axis == 2)
+      sweep_phase_vec<2>(A, Y, D, d, rb, re, sdelta[0], sdelta[1], acc);
+    else
+      sweep_phase_vec<1>(A, Y, D, d, rb, re, sdelta[0], sdelta[1], acc);
+  } else if (D.axis == 2) {
+    sweep_phase_rows<2>(A, Y, D, d, rb, re, sdelta[0], sdelta[1], acc);
+  } else if (D.axis == 1) {
+    sweep_phase_rows<1>(A, Y, D, d, rb, re, sdelta[0], sdelta[1], acc);
+  } else {
+    sweep_phase_band0(A, Y, D, d, blk, nblk, sdelta[0], sdelta[1], acc);
+  }
+}
+
+// The 7 partial sums of block blk of direction d (escape per face scaled by
+// esc_scale, light in the box) to A.part[q * ndir * nblk + d * nblk + blk].
+__device__ __forceinline__ void store_sweep_partials(const SweepArgs& A, const DevDir& D, int d,
+                                                     int blk, int nblk, const SweepAcc& acc,
+                                                     double esc_scale = 1.0) {
+  double face[6];
+  const int fa = 2 * D.axis + (D.sign > 0 ? 1 : 0);
+#pragma unroll
+  for (int f = 0; f < 6; ++f) {
+    double s = 0;
+    if (f == fa) s += acc.esc_a;
+    if (f == 2 * D.bax) s += acc.esc_b0;
+    if (f == 2 * D.bax + 1) s += acc.esc_b1;
+    if (f == 2 * D.cax) s += acc.esc_c0;
+    if (f == 2 * D.cax + 1) s += acc.esc_c1;
+    face[f] = s * esc_scale;
+  }
+  const double vals[7] = {face[0], face[1], face[2], face[3], face[4], face[5], acc.dom};
+  block_sums<7>(vals, A.part + (long long)d * nblk + blk, (long long)A.ndir * nblk);
+}
+
 // Block blk of nblk row slabs of direction d; writes the block's 7 partial sums
 // (escape per face, light in the box) to A.part[q * ndir * nblk + d * nblk + blk].
 // FAST: every direction takes one of the class-byte split paths (x-dominant
@@ -1570,18 +1774,8 @@ __device__ __forceinline__ void sweep_block(const SweepArgs& A, int d, int blk, 
         sweep_split_vec<2, FRESNEL>(A, D, d, blk, nblk, sdelta[0], sdelta[1], srt, rbits, acc);
       else
         sweep_split_vec<1, FRESNEL>(A, D, d, blk, nblk, sdelta[0], sdelta[1], srt, rbits, acc);
-    } else if (!SPLIT && D.axis != 0 && (A.nx & 3) == 0 && D.unitb) {
-      if (D.axis == 2)
-        sweep_phase_vec<2>(A, D, d, rb, re, sdelta[0], sdelta[1], acc);
-      else
-        sweep_phase_vec<1>(A, D, d, rb, re, sdelta[0], sdelta[1], acc);
     } else if (!SPLIT) {
-      if (D.axis == 2)
-        sweep_phase_rows<2>(A, D, d, rb, re, sdelta[0], sdelta[1], acc);
-      else if (D.axis == 1)
-        sweep_phase_rows<1>(A, D, d, rb, re, sdelta[0], sdelta[1], acc);
-      else
-        sweep_phase_band0(A, D, d, blk, nblk, sdelta[0], sdelta[1], acc);
+      sweep_moving(A, OneField{A.Y + size_t(d) * A.Vp}, D, d, blk, nblk, rb, re, sdelta, acc);
     } else if (D.axis == 2) {
       sweep_rows<2, SPLIT, FRESNEL>(A, D, d, rb, re, sdelta[0], sdelta[1], acc);
     } else if (D.axis == 1) {
@@ -1590,20 +1784,7 @@ __device__ __forceinline__ void sweep_block(const SweepArgs& A, int d, int blk, 
       sweep_rows<0, SPLIT, FRESNEL>(A, D, d, rb, re, sdelta[0], sdelta[1], acc);
     }
   }
-  double face[6];
-  const int fa = 2 * D.axis + (D.sign > 0 ? 1 : 0);
-#pragma unroll
-  for (int f = 0; f < 6; ++f) {
-    double s = 0;
-    if (f == fa) s += acc.esc_a;
-    if (f == 2 * D.bax) s += acc.esc_b0;
-    if (f == 2 * D.bax + 1) s += acc.esc_b1;
-    if (f == 2 * D.cax) s += acc.esc_c0;
-    if (f == 2 * D.cax + 1) s += acc.esc_c1;
-    face[f] = s;
-  }
-  const double vals[7] = {face[0], face[1], face[2], face[3], face[4], face[5], acc.dom};
-  block_sums<7>(vals, A.part + (long long)d * nblk + blk, (long long)A.ndir * nblk);
+  store_sweep_partials(A, D, d, blk, nblk, acc);
   __syncthreads();   // LDS (shift tables, partial sums) is reused by the next block of work
 }
 
@@ -1613,6 +1794,31 @@ __global__ __launch_bounds__(kThreads) void sweep_kernel(SweepArgs A) {
   __shared__ float srt[128];
   __shared__ uint32_t rbits[SPLIT ? kMaxRowBits / 32 : 1];
   sweep_block<SPLIT, FRESNEL, FAST>(A, blockIdx.y, blockIdx.x, gridDim.x, sdelta, srt, rbits);
+}
+
+// Retarded stepping below Courant one (Sec. 2.1, the upwind value at the
+// retarded time t - dr/c): every direction moves each step, and a voxel takes
+// its upwind voxel's collided value at step m + 1 - D_d, blended from two
+// history slots.  Light leaving the box crosses the face at its content over
+// D_d per step.
+__global__ __launch_bounds__(kThreads) void sweep_retarded_kernel(SweepArgs A) {
+  __shared__ int8_t sdelta[2][kMaxExt + 2];
+  const int d = blockIdx.y, blk = blockIdx.x, nblk = gridDim.x;
+  const DevDir D = A.dirs[d];
+  const int m = *A.step_ctr;
+  const int ea = D.axis == 0 ? A.nx : (D.axis == 1 ? A.ny : A.nz);
+  for (int i = threadIdx.x; i <= ea; i += kThreads) {
+    sdelta[0][i] = A.delta[(size_t(d) * 2 + 0) * A.dstride + i];
+    sdelta[1][i] = A.delta[(size_t(d) * 2 + 1) * A.dstride + i];
+  }
+  __syncthreads();
+  const int R = A.ny * A.nz;
+  const int rb = int((long long)R * blk / nblk);
+  const int re = int((long long)R * (blk + 1) / nblk);
+  SweepAcc acc;
+  sweep_moving(A, retarded_rows(A.ring, A.H, A.slot, A.Vp, D, d, m), D, d, blk, nblk, rb, re,
+               sdelta, acc);
+  store_sweep_partials(A, D, d, blk, nblk, acc, double(D.rinvD));
 }
 
 // Fresnel redistribution (Eq. 13-14): every target (direction, voxel) adds the
@@ -1675,8 +1881,12 @@ __device__ __forceinline__ void reduce_part(const ReduceArgs& A, int q, int nq) 
       for (int p = A.det_first[k]; p < A.det_first[k + 1]; ++p) {
         const int d = A.det_pairs[2 * p + 1];
         const DevDir D = A.dirs[d];
-        const float f = A.split ? D.nu * A.r[v] : phase_move(D.nu64, m);
-        sd += double(f * A.Y[size_t(d) * A.Vp + v]);
+        if (A.ring) {
+          sd += double(D.rinvD * retarded_rows(A.ring, A.H, A.slot, A.Vp, D, d, m)[v]);
+        } else {
+          const float f = A.split ? D.nu * A.r[v] : phase_move(D.nu64, m);
+          sd += double(f * A.Y[size_t(d) * A.Vp + v]);
+        }
       }
       if (ok) A.det_steps[size_t(k) * A.cap + m] = sd;
     }
@@ -2074,6 +2284,56 @@ hipError_t launch_implicit_np(const CollideArgs& a, const Field& f, hipStream_t 
   return hipGetLastError();
 }
 }  // namespace
+
+namespace {
+template <int NP>
+size_t hop_lds() {
+  return (size_t(NP) * (NP + 4) + 2 * NP) * sizeof(float);
+}
+template <int NP>
+hipError_t prepare_hop_np() {
+  return hipFuncSetAttribute(reinterpret_cast<const void*>(&collide_hop_kernel<NP>),
+                             hipFuncAttributeMaxDynamicSharedMemorySize, int(hop_lds<NP>()));
+}
+template <int NP>
+hipError_t launch_hop_np(const CollideArgs& a, const Field& f, hipStream_t s) {
+  const int ntiles = int(f.Vp / 256);
+  const int nb = ntiles < resident_blocks() ? ntiles : resident_blocks();
+  hipLaunchKernelGGL(collide_hop_kernel<NP>, dim3(unsigned(nb)), dim3(512), hop_lds<NP>(), s, a,
+                     ntiles);
+  return hipGetLastError();
+}
+}  // namespace
+
+hipError_t prepare_collide_hop(const Field& f) {
+  switch (f.NP) {
+    case 32: return prepare_hop_np<32>();
+    case 64: return prepare_hop_np<64>();
+    case 96: return prepare_hop_np<96>();
+    case 128: return prepare_hop_np<128>();
+    case 160: return prepare_hop_np<160>();
+    case 192: return prepare_hop_np<192>();
+    default: return hipErrorInvalidValue;
+  }
+}
+
+hipError_t launch_collide_hop(const CollideArgs& a, const Field& f, hipStream_t s) {
+  switch (f.NP) {
+    case 32: return launch_hop_np<32>(a, f, s);
+    case 64: return launch_hop_np<64>(a, f, s);
+    case 96: return launch_hop_np<96>(a, f, s);
+    case 128: return launch_hop_np<128>(a, f, s);
+    case 160: return launch_hop_np<160>(a, f, s);
+    case 192: return launch_hop_np<192>(a, f, s);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+hipError_t launch_sweep_retarded(const SweepArgs& a, const Field& f, int bpd, hipStream_t s) {
+  hipLaunchKernelGGL(sweep_retarded_kernel, dim3(unsigned(bpd), unsigned(f.ndir)),
+                     dim3(kThreads), 0, s, a);
+  return hipGetLastError();
+}
 
 hipError_t prepare_collide_implicit(const Field& f) {
   switch (f.NP) {

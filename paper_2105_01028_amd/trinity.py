@@ -20,7 +20,7 @@ STATUS_NAMES = {0: "TR_OK", -1: "TR_EINVAL", -2: "TR_ENOMEM", -3: "TR_EDEVICE",
                 -4: "TR_ENUMERIC", -5: "TR_ESTATE"}
 HG = {"sinkhorn": 0, "row": 1}
 COEF = {"paper": 0, "abs_exact": 1}
-ADVANCE = {"auto": 0, "phase": 1, "split": 2}
+ADVANCE = {"auto": 0, "phase": 1, "split": 2, "retarded": 3}
 PRECISION = {"fp32": 0, "bf16split": 1}
 SOURCE = {"explicit": 0, "implicit": 1}
 MODE_NAMES = {1: "phase", 2: "split"}
@@ -45,7 +45,8 @@ class GridDesc(ctypes.Structure):
 class Info(ctypes.Structure):
     _fields_ = [("ndir", ctypes.c_int), ("nvox", ctypes.c_int), ("mode", ctypes.c_int),
                 ("ninterceptions", ctypes.c_int), ("dt_ps", ctypes.c_double),
-                ("steps_done", ctypes.c_longlong), ("device_bytes", ctypes.c_size_t)]
+                ("steps_done", ctypes.c_longlong), ("device_bytes", ctypes.c_size_t),
+                ("history", ctypes.c_int)]
 
 
 class ServerDesc(ctypes.Structure):
