@@ -670,7 +670,8 @@ tr_status tr_create_medium(const tr_grid_desc* desc, const float* mua, const flo
     for (int v = 0; v < f.V; ++v) {
       const double mt = double(m->mua_host[v]) + double(m->mus_host[v]);
       mx[v] = float(mt * desc->dx_mm);
-      om[v] = mt > 0.0 ? float(double(m->mus_host[v]) / mt) : 0.0f;
+      // below 2^-20 optical depth per voxel the hop kernel takes a = 1, b = 0
+      om[v] = mt * desc->dx_mm >= 0x1p-20 ? float(double(m->mus_host[v]) / mt) : 0.0f;
     }
     const size_t nring = size_t(m->H) * f.NP * f.Vp;
     m->ring = m->alloc<float>(nring);

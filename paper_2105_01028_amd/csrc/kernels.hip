@@ -273,12 +273,14 @@ __global__ __launch_bounds__(512, 1) void collide_f32_res_kernel(CollideArgs A, 
 // retarded form of Eq. 10 with S1 := S0).  Direction i hops dr_i = dx/|Omega_a|
 // between planes, so its coefficients depend on the row as well as the voxel:
 //   a[i][v] = exp(-mu_t(v) dr_i),  b[i][v] = omega_v (1 - a[i][v]).
-// The B operand is omega_v X (the per-voxel factor of b), so the accumulator
-// holds omega_v (P X)[i][v], and the epilogue forms
-//   C[i][v] = a X[i][v] + (1 - a) acc
-// with X re-read (a tile's rows were read moments before).  C goes to the
-// history slot of the current step.  Absorbed per step, with the light of a
-// hop spread over its D_i steps: (1 - a)(1 - omega) X[i][v] / D_i.
+// With e = 1 - a the result is C = e (w X + omega P X), w = a / e: the B
+// operand is omega_v X, and w X is added to the accumulator as the lane's own
+// rows of X arrive (the row order of collide_res_tile), so X is read once.
+// The factor e cancels on the X term (e * (a/e) = a up to rounding), and the
+// P X term carries the absolute error of e, 2^-25.  Voxels with
+// mu_t dx < 2^-20 come with omega = 0 from the host and take C = X (a = 1).
+// C goes to the history slot of the current step.  Absorbed per step, with the
+// light of a hop spread over its D_i steps: e (1 - omega) X[i][v] / D_i.
 template <int NP>
 __device__ __forceinline__ void collide_hop_tile(const CollideArgs& A, const float* Ps,
                                                  const float* sinvc, const float* sinvD,
@@ -294,6 +296,11 @@ __device__ __forceinline__ void collide_hop_tile(const CollideArgs& A, const flo
   const unsigned voff = unsigned(size_t(col) * sizeof(float) + size_t(4 * hl) * rowbytes);
   const char* __restrict__ xb0 = reinterpret_cast<const char*>(A.X);
   const float mx = A.mutdx[col], om = A.omega[col];
+  // exp(-mu_t dx / |Omega_a|) = exp2(-(mu_t dx log2 e) / |Omega_a|) on the hardware exp2
+  const float ml2 = mx * 1.44269504088896341f;
+  // the lane half's rows of the hop tables: one base, constant offsets
+  const float* __restrict__ ic = sinvc + 4 * hl;
+  const float* __restrict__ iD = sinvD + 4 * hl;
   floatx16 acc[NQ];
 #pragma unroll
   for (int q = 0; q < NQ; ++q)
@@ -306,11 +313,29 @@ __device__ __forceinline__ void collide_hop_tile(const CollideArgs& A, const flo
   float bcur[16], bnext[16];
 #pragma unroll
   for (int s = 0; s < 16; ++s) bcur[s] = ld(0, s);
+  double colsum = 0.0, lost = 0.0;
 #pragma unroll 1
   for (int c = 0; c < NQ; ++c) {
     const int cn = c + 1 < NQ ? c + 1 : c;
 #pragma unroll
     for (int s = 0; s < 16; ++s) bnext[s] = ld(cn, s);
+    // w X for the rows of accumulator block c (uniform branch); the chunk's
+    // tallies in FP32, then into the FP64 sums
+    float csum = 0.0f, clost = 0.0f;
+#pragma unroll
+    for (int s = 0; s < 16; ++s) {
+      const int ro = 32 * c + 8 * (s >> 2) + (s & 3);   // row minus 4h
+      const float a = __builtin_amdgcn_exp2f(-ml2 * ic[ro]);
+      const float e = 1.0f - a;
+      const float w = e > 0.0f ? a * __builtin_amdgcn_rcpf(e) : 1.0f;
+      csum += bcur[s];
+      clost = fmaf(e * bcur[s], iD[ro], clost);
+#pragma unroll
+      for (int q = 0; q < NQ; ++q)
+        if (q == c) acc[q][s] = fmaf(w, bcur[s], acc[q][s]);
+    }
+    colsum += double(csum);
+    lost += double(clost);
 #pragma unroll
     for (int s = 0; s < 16; ++s) bcur[s] *= om;
 #pragma unroll
@@ -328,41 +353,16 @@ __device__ __forceinline__ void collide_hop_tile(const CollideArgs& A, const flo
 #pragma unroll
     for (int s = 0; s < 16; ++s) bcur[s] = bnext[s];
   }
-  // keep the epilogue's re-reads of X after the K loop (hoisted, they would
-  // hold 96 more registers across it)
-  __asm__ volatile("" ::: "memory");
   char* __restrict__ cb0 = reinterpret_cast<char*>(Cout);
-  // exp(-mu_t dx / |Omega_a|) = exp2(-(mu_t dx log2 e) / |Omega_a|) on the
-  // hardware exp2
-  const float ml2 = mx * 1.44269504088896341f;
-  // the lane half's rows of the hop tables: one base, constant offsets
-  const float* __restrict__ ic = sinvc + 4 * hl;
-  const float* __restrict__ iD = sinvD + 4 * hl;
-  double colsum = 0.0, lost = 0.0;
-  // rows of accumulator block q: 32q + 8(r/4) + r%4 (+ 4h in voff); addresses
-  // from the block's base and the 16 in-block offsets, so that the compiler
-  // does not keep 96 row offsets live across the tile loop
 #pragma unroll
   for (int q = 0; q < NQ; ++q) {
-    const char* xq = xb0 + size_t(32 * q) * rowbytes + voff;
     char* cq = cb0 + size_t(32 * q) * rowbytes + voff;
 #pragma unroll
-    for (int r4 = 0; r4 < 16; r4 += 4) {
-      const size_t o4 = size_t(8 * (r4 >> 2)) * rowbytes;
-      float x[4];
-#pragma unroll
-      for (int j = 0; j < 4; ++j)
-        x[j] = *reinterpret_cast<const float*>(xq + o4 + size_t(j) * rowbytes);
-#pragma unroll
-      for (int j = 0; j < 4; ++j) {
-        const int r = r4 + j;
-        const int ro = q * 32 + 8 * (r >> 2) + (r & 3);   // row minus 4h
-        const float a = __builtin_amdgcn_exp2f(-ml2 * ic[ro]);
-        const float oma = 1.0f - a;
-        *reinterpret_cast<float*>(cq + o4 + size_t(j) * rowbytes) = fmaf(a, x[j], oma * acc[q][r]);
-        colsum += double(x[j]);
-        lost += double(oma * x[j]) * double(iD[ro]);
-      }
+    for (int r = 0; r < 16; ++r) {
+      const int ro = q * 32 + 8 * (r >> 2) + (r & 3);
+      const float e = 1.0f - __builtin_amdgcn_exp2f(-ml2 * ic[ro]);
+      *reinterpret_cast<float*>(cq + size_t(8 * (r >> 2) + (r & 3)) * rowbytes) =
+          (e > 0.0f ? e : 1.0f) * acc[q][r];
     }
   }
   absorbed += (1.0 - double(om)) * lost;
