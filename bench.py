@@ -525,8 +525,8 @@ def main():
     rl = {k: rl[k] for k in ("bound", "achieved", "peak", "unit", "frac", "traffic", "kernel",
                              "avg_ms", "work_per_launch") if k in rl}
     out = {
-        "metric": METRIC, "value": updates / el, "unit": "updates/s", "n_gpus": 1,
-        "steps": K, "warmup": Wm, "ms_per_step": el / K * 1e3, "higher_is_better": True,
+        "metric": METRIC, "value": updates / el_graph, "unit": "updates/s", "n_gpus": 1,
+        "steps": K, "warmup": Wm, "ms_per_step": el_graph / K * 1e3, "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None,
         "dtype": "f32" if args.precision == "fp32" else "bf16x3-f32acc",
         "data": "synthetic",
@@ -537,15 +537,18 @@ def main():
         "kernels": {k: {"avg_ms": v[0] / v[1] if v[1] else 0.0, "launches": v[1]}
                     for k, v in prof.items()},
         "kernel_rooflines": roof,
-        "graph_replay": {"value": updates / el_graph, "ms_per_step": el_graph / K * 1e3},
+        "timing": "value: the K steps as the library runs them (tr_step replays captured "
+                  "graphs); kernel durations: the same K steps queued kernel by kernel with "
+                  "HIP events on the medium's stream (instrumented below)",
+        "instrumented": {"value": updates / el, "ms_per_step": el / K * 1e3},
         "budget_closure": closure,
         "rel_l2_vs_fp64_oracle": oracle_error(prob, det_steps),
     }
     if not args.no_extras:
         other = "bf16split" if args.precision == "fp32" else "fp32"
         e2, g2, p2, c2, d2 = timed_run(prob.copy(precision=other), K, Wm, stream)
-        out[other] = {"value": updates / e2, "ms_per_step": e2 / K * 1e3,
-                      "graph_value": updates / g2, "kernel_rooflines":
+        out[other] = {"value": updates / g2, "ms_per_step": g2 / K * 1e3,
+                      "instrumented_value": updates / e2, "kernel_rooflines":
                       kernel_rooflines(p2, prob, other), "budget_closure": c2,
                       "rel_l2_vs_fp64_oracle": oracle_error(prob, d2)}
         p50, p99 = latency(W.config1(), 30, stream)
