@@ -54,6 +54,8 @@ struct tr_medium {
   int H = 0;
   // two-level angular grid: coarse field of nc directions (NPc rows)
   bool twolevel = false;
+  bool tlfused = false;     // two-level phase stepping: the sweep forms the collided value, the
+                            // field alternates between X (even steps) and Y (odd steps)
   int nc = 0, NPc = 0, nkids = 0;
   float *M = nullptr, *T = nullptr, *zero = nullptr;
   int *children = nullptr, *parent = nullptr;
@@ -217,6 +219,10 @@ tr_status ensure_capacity(tr_medium* m, long long need) {
   return TR_OK;
 }
 
+// The buffer that holds the field after the steps done so far: X, except in
+// two-level phase stepping, where the field alternates and odd steps end in Y.
+float* state_field(tr_medium* m) { return m->tlfused && (m->steps_done & 1) ? m->Y : m->X; }
+
 // Event pair around one kernel while timing is active (no-op otherwise).
 struct KernelTimer {
   tr_medium* m;
@@ -238,13 +244,15 @@ hipError_t queue_step(tr_medium* m) {
   if (m->npairs > 0) {
     KernelTimer t(m, TR_K_INJECT);
     InjectArgs ia{m->X,   f.Vp,        m->src_pairs, m->npairs, m->qdev,
-                  m->cap, m->step_ctr, m->budget,    m->ddirs,  m->ring != nullptr};
+                  m->cap, m->step_ctr, m->budget,    m->ddirs,  m->ring != nullptr,
+                  m->tlfused ? m->Y : nullptr};
     if ((e = launch_inject(ia, m->stream)) != hipSuccess) return e;
   }
   if (m->twolevel) {
     TwoLevelArgs ta{m->X,     m->Y,          m->M,                   m->T,  m->a,
                     m->b,     m->children,   m->parent,              f.ndir, m->nc,
-                    m->nkids, 1.0f / float(m->nkids), f.Vp,          f.V,   m->cpart};
+                    m->nkids, 1.0f / float(m->nkids), f.Vp,          f.V,   m->cpart,
+                    m->tlfused ? m->Y : nullptr, m->step_ctr};
     Field fc = f;
     fc.ndir = m->nc;
     fc.NP = m->NPc;
@@ -258,7 +266,7 @@ hipError_t queue_step(tr_medium* m) {
       KernelTimer t(m, TR_K_COLLIDE);
       if ((e = launch_collide(cc, fc, 0, 0, m->stream)) != hipSuccess) return e;
     }
-    {
+    if (!m->tlfused) {
       KernelTimer t(m, TR_K_APPLY);
       if ((e = launch_apply(ta, m->stream)) != hipSuccess) return e;
     }
@@ -292,8 +300,20 @@ hipError_t queue_step(tr_medium* m) {
     SweepArgs sa{m->Y, m->X, f.Vp, f.V, f.nx, f.ny, f.nz, m->ddirs, m->delta, m->dstride,
                  m->r, m->iface, m->nvox, m->islot, m->icptF, f.ndir, m->step_ctr, m->spart,
                  m->mat, m->rtab, m->rowbits, m->bgcls, m->ring, m->H, (long long)f.NP * f.Vp};
-    e = m->ring ? launch_sweep_retarded(sa, f, m->sweep_bpd, m->stream)
-                : launch_sweep(sa, f, split, m->fresnel, m->sweep_bpd, m->stream, m->fast_split);
+    if (m->tlfused) {
+      sa.tlT = m->T;
+      sa.tlparent = m->parent;
+      sa.tla = m->a;
+      sa.tlshare = 1.0f / float(m->nkids);
+      sa.pp0 = m->X;
+      sa.pp1 = m->Y;
+      sa.dorder = m->children;   // the children of each coarse bin together
+      e = launch_sweep_twolevel(sa, f, m->sweep_bpd, m->stream);
+    } else if (m->ring) {
+      e = launch_sweep_retarded(sa, f, m->sweep_bpd, m->stream);
+    } else {
+      e = launch_sweep(sa, f, split, m->fresnel, m->sweep_bpd, m->stream, m->fast_split);
+    }
     if (e != hipSuccess) return e;
   }
   if (m->fresnel) {
@@ -306,6 +326,14 @@ hipError_t queue_step(tr_medium* m) {
                 m->det_vox_dev, m->ndet, m->ddirs, m->r, split ? 1 : 0, m->step_ctr, m->budget,
                 m->det_steps, m->cap, m->flag, m->rscratch, m->rdone,
                 m->ring, m->H, (long long)f.NP * f.Vp};
+  if (m->tlfused) {
+    ra.tlT = m->T;
+    ra.tlparent = m->parent;
+    ra.tla = m->a;
+    ra.tlshare = 1.0f / float(m->nkids);
+    ra.pp0 = m->X;
+    ra.pp1 = m->Y;
+  }
   return launch_reduce(ra, m->stream);
 }
 
@@ -435,6 +463,7 @@ tr_status tr_create_medium(const tr_grid_desc* desc, const float* mua, const flo
   }
   std::vector<float> P32, PT;
   m->twolevel = desc->nside_scatter != 0 && desc->nside_scatter != desc->nside;
+  m->tlfused = m->twolevel && mode == TR_ADVANCE_PHASE;
   int NPm = f.NP;   // rows of the phase matrix the collide kernels use
   if (m->twolevel) {
     m->nc = 12 * desc->nside_scatter * desc->nside_scatter;
@@ -1023,7 +1052,7 @@ tr_status tr_read_energy(tr_medium* m, float* out, int on_device) {
   if (!out) return fail(TR_EINVAL, "null output");
   float* E = on_device ? out : m->alloc<float>(m->f.V);
   if (!E) return fail(TR_ENOMEM, "device allocation failed");
-  hipError_t e = launch_energy(m->X, m->f.Vp, m->f.ndir, m->f.V, E, m->stream);
+  hipError_t e = launch_energy(state_field(m), m->f.Vp, m->f.ndir, m->f.V, E, m->stream);
   if (e == hipSuccess) e = hipStreamSynchronize(m->stream);
   if (e == hipSuccess && !on_device) e = hipMemcpy(out, E, m->f.V * 4, hipMemcpyDeviceToHost);
   if (!on_device) m->release(E);
@@ -1036,7 +1065,8 @@ tr_status tr_get_state(tr_medium* m, float* out, int on_device) {
   if (st != TR_OK) return st;
   if (!out) return fail(TR_EINVAL, "null output");
   // on the medium's stream, so that work the caller queued there is ordered with the copy
-  hipError_t e = hipMemcpy2DAsync(out, m->f.V * 4, m->X, m->f.Vp * 4, m->f.V * 4, m->f.ndir,
+  hipError_t e = hipMemcpy2DAsync(out, m->f.V * 4, state_field(m), m->f.Vp * 4, m->f.V * 4,
+                                  m->f.ndir,
                                   on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost,
                                   m->stream);
   if (e == hipSuccess) e = hipStreamSynchronize(m->stream);
@@ -1051,7 +1081,8 @@ tr_status tr_set_state(tr_medium* m, const float* in, int on_device) {
   if (m->ring)
     return fail(TR_EINVAL, "the retarded advance keeps a history of collided fields; "
                            "its state cannot be set");
-  hipError_t e = hipMemcpy2DAsync(m->X, m->f.Vp * 4, in, m->f.V * 4, m->f.V * 4, m->f.ndir,
+  hipError_t e = hipMemcpy2DAsync(state_field(m), m->f.Vp * 4, in, m->f.V * 4, m->f.V * 4,
+                                  m->f.ndir,
                                   on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice,
                                   m->stream);
   if (e == hipSuccess) e = hipStreamSynchronize(m->stream);

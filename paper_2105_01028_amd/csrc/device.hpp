@@ -40,6 +40,8 @@ struct InjectArgs {
   double* budget;          // [cap][9]
   const DevDir* dirs;      // retarded stepping: a pair of direction d gets rD times its share
   int retarded;
+  float* X2;               // two-level phase stepping: the field alternates between X (even
+                           // steps) and X2 (odd steps); null otherwise
 };
 
 struct CollideArgs {
@@ -99,6 +101,17 @@ struct SweepArgs {
   const float* ring;        // retarded stepping: history ring [H][NP][Vp], slot = step mod H
   int H;
   long long slot;           // NP * Vp
+  // two-level phase stepping (null otherwise): the sweep forms the collided
+  // value a X + T[parent] share as it reads, from the field of this step's
+  // parity (pp[m & 1]) into the other one; directions are taken in the order
+  // dorder (the children of each coarse bin together)
+  const float* tlT;
+  const int* tlparent;
+  const float* tla;
+  float tlshare;
+  float* pp0;
+  float* pp1;
+  const int* dorder;
 };
 
 constexpr int kMaxRowBits = 65536;   // rows covered by the uniform-row bitmap (8 KB)
@@ -139,6 +152,14 @@ struct ReduceArgs {
   const float* ring;       // retarded stepping: detectors read the history ring
   int H;
   long long slot;
+  // two-level phase stepping: detectors read a X + T[parent] share from the
+  // field of this step's parity
+  const float* tlT;
+  const int* tlparent;
+  const float* tla;
+  float tlshare;
+  const float* pp0;
+  const float* pp1;
 };
 
 // One request of the batched server: its argument blocks as the single-medium
@@ -193,6 +214,8 @@ struct TwoLevelArgs {
   long long Vp;
   int V;
   double* part;            // [2][nwg] absorbed, total
+  const float* X2;         // alternating field (see InjectArgs::X2), null otherwise
+  const int* step_ctr;
 };
 long long coarse_sum_workgroups(const TwoLevelArgs& a);   // budget partial pairs written
 hipError_t launch_coarse_sum(const TwoLevelArgs& a, hipStream_t s);
@@ -210,6 +233,9 @@ int collide_nwg(const Field& f, int bf16split);
 hipError_t prepare_collide_hop(const Field& f);
 hipError_t launch_collide_hop(const CollideArgs& a, const Field& f, hipStream_t s);
 hipError_t launch_sweep_retarded(const SweepArgs& a, const Field& f, int blocks_per_dir,
+                                 hipStream_t s);
+// Two-level phase stepping: the sweep with the collided value formed as it reads.
+hipError_t launch_sweep_twolevel(const SweepArgs& a, const Field& f, int blocks_per_dir,
                                  hipStream_t s);
 hipError_t launch_collide_implicit(const CollideArgs& a, const Field& f, hipStream_t s);
 hipError_t prepare_collide_implicit(const Field& f);

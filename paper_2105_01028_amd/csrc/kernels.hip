@@ -73,9 +73,10 @@ __device__ __forceinline__ void inject_body(const InjectArgs& A) {
   const int m = *A.step_ctr;
   const double q = m < A.cap ? A.q[m] : 0.0;
   const float share = float(q / double(A.npairs));
+  float* X = A.X2 && (m & 1) ? A.X2 : A.X;
   for (int i = threadIdx.x; i < A.npairs; i += blockDim.x) {
     const int d = A.pairs[2 * i], v = A.pairs[2 * i + 1];
-    A.X[size_t(d) * A.Vp + v] += A.retarded ? share * A.dirs[d].rD : share;
+    X[size_t(d) * A.Vp + v] += A.retarded ? share * A.dirs[d].rD : share;
   }
   if (threadIdx.x == 0 && m < A.cap) A.budget[size_t(m) * 9 + 0] = double(share) * A.npairs;
 }
@@ -978,6 +979,25 @@ struct TwoFields {
   }
 };
 
+// Two-level angular grid: the collided row of fine direction i formed as it is
+// read, a_v X[i][v] + T[parent(i)][v] share (the same rounding as apply_kernel).
+struct TwoLevelRow {
+  const float* __restrict__ x;
+  const float* __restrict__ t;
+  const float* __restrict__ a;
+  float share;
+  __device__ __forceinline__ float operator[](long long i) const {
+    return fmaf(a[i], x[i], t[i] * share);
+  }
+  __device__ __forceinline__ float4 q4(long long q) const {
+    const float4 xv = reinterpret_cast<const float4*>(x)[q];
+    const float4 tv = reinterpret_cast<const float4*>(t)[q];
+    const float4 av = reinterpret_cast<const float4*>(a)[q];
+    return make_float4(fmaf(av.x, xv.x, tv.x * share), fmaf(av.y, xv.y, tv.y * share),
+                       fmaf(av.z, xv.z, tv.z * share), fmaf(av.w, xv.w, tv.w * share));
+  }
+};
+
 // Direction d's rows at the retarded time m + 1 - D_d, D_d = rlag + rphi: slot
 // (m + 1 - rlag) mod H with weight 1 - rphi and slot (m - rlag) mod H with
 // weight rphi.  Slots of steps before the first are zero (the ring is cleared
@@ -1667,6 +1687,29 @@ __device__ __forceinline__ void sweep_split_rows0(const SweepArgs& A, const DevD
 
 }  // namespace
 
+// Phase mode, direction d does not move at this step: the collided field of
+// rows [rb, re) passes through.
+template <class Src>
+__device__ __forceinline__ void sweep_still(const SweepArgs& A, const Src& Y, int d, int rb,
+                                            int re, SweepAcc& acc) {
+  float4* __restrict__ Xd = reinterpret_cast<float4*>(A.X + size_t(d) * A.Vp);
+  const long long v0 = (long long)rb * A.nx, v1 = (long long)re * A.nx;
+  // whole float4s inside [v0, v1) are copied as vectors, the ragged ends one by one
+  const long long q0 = (v0 + 3) / 4, q1 = v1 / 4;
+  for (long long q = q0 + threadIdx.x; q < q1; q += kThreads) {
+    const float4 y = Y.q4(q);
+    Xd[q] = y;
+    acc.dom += (double(y.x) + double(y.y)) + (double(y.z) + double(y.w));
+  }
+  float* Xs = A.X + size_t(d) * A.Vp;
+  for (long long v = v0 + threadIdx.x; v < v1; v += kThreads) {
+    if (v >= 4 * q0 && v < 4 * q1) continue;
+    const float y = Y[v];
+    Xs[v] = y;
+    acc.dom += double(y);
+  }
+}
+
 // Every photon of direction d moves one plane: 16-byte rows for y- and
 // z-dominant directions on grids with nx a multiple of 4, else rows of single
 // voxels, or, x-dominant, lanes across planes in band order.
@@ -1726,24 +1769,7 @@ __device__ __forceinline__ void sweep_block(const SweepArgs& A, int d, int blk, 
   const int re = int((long long)R * (blk + 1) / nblk);
   SweepAcc acc;
   if (fph == 0.0f) {
-    // phase mode, this direction does not move at step m: the field passes through
-    const float4* __restrict__ Yd = reinterpret_cast<const float4*>(A.Y + size_t(d) * A.Vp);
-    float4* __restrict__ Xd = reinterpret_cast<float4*>(A.X + size_t(d) * A.Vp);
-    const long long v0 = (long long)rb * A.nx, v1 = (long long)re * A.nx;
-    // whole float4s inside [v0, v1) are copied as vectors, the ragged ends one by one
-    const long long q0 = (v0 + 3) / 4, q1 = v1 / 4;
-    for (long long q = q0 + threadIdx.x; q < q1; q += kThreads) {
-      const float4 y = Yd[q];
-      Xd[q] = y;
-      acc.dom += (double(y.x) + double(y.y)) + (double(y.z) + double(y.w));
-    }
-    const float* Ys = A.Y + size_t(d) * A.Vp;
-    float* Xs = A.X + size_t(d) * A.Vp;
-    for (long long v = v0 + threadIdx.x; v < v1; v += kThreads) {
-      if (v >= 4 * q0 && v < 4 * q1) continue;
-      Xs[v] = Ys[v];
-      acc.dom += double(Ys[v]);
-    }
+    sweep_still(A, OneField{A.Y + size_t(d) * A.Vp}, d, rb, re, acc);
   } else {
     const int ea = D.axis == 0 ? A.nx : (D.axis == 1 ? A.ny : A.nz);
     for (int i = threadIdx.x; i <= ea; i += kThreads) {
@@ -1821,6 +1847,39 @@ __global__ __launch_bounds__(kThreads) void sweep_retarded_kernel(SweepArgs A) {
   store_sweep_partials(A, D, d, blk, nblk, acc, double(D.rinvD));
 }
 
+// Two-level angular grid, phase mode: the sweep of fine direction d reads the
+// collided value a X + T[parent(d)] share of the field of this step's parity
+// and writes the other field, so the collided field is never stored.  Blocks
+// take the directions in the order dorder, the children of each coarse bin
+// together, so that a row of T is read from HBM about once.
+__global__ __launch_bounds__(kThreads) void sweep_twolevel_kernel(SweepArgs A) {
+  __shared__ int8_t sdelta[2][kMaxExt + 2];
+  const int d = A.dorder[blockIdx.y];
+  const int blk = blockIdx.x, nblk = gridDim.x;
+  const DevDir D = A.dirs[d];
+  const int m = *A.step_ctr;
+  SweepArgs B = A;
+  B.X = (m & 1) ? A.pp0 : A.pp1;
+  const TwoLevelRow Y{((m & 1) ? A.pp1 : A.pp0) + size_t(d) * A.Vp,
+                      A.tlT + size_t(A.tlparent[d]) * A.Vp, A.tla, A.tlshare};
+  const int R = A.ny * A.nz;
+  const int rb = int((long long)R * blk / nblk);
+  const int re = int((long long)R * (blk + 1) / nblk);
+  SweepAcc acc;
+  if (phase_move(D.nu64, m) == 0.0f) {
+    sweep_still(B, Y, d, rb, re, acc);
+  } else {
+    const int ea = D.axis == 0 ? A.nx : (D.axis == 1 ? A.ny : A.nz);
+    for (int i = threadIdx.x; i <= ea; i += kThreads) {
+      sdelta[0][i] = A.delta[(size_t(d) * 2 + 0) * A.dstride + i];
+      sdelta[1][i] = A.delta[(size_t(d) * 2 + 1) * A.dstride + i];
+    }
+    __syncthreads();
+    sweep_moving(B, Y, D, d, blk, nblk, rb, re, sdelta, acc);
+  }
+  store_sweep_partials(A, D, d, blk, nblk, acc);
+}
+
 // Fresnel redistribution (Eq. 13-14): every target (direction, voxel) adds the
 // reflected or refracted share of the light intercepted at an index jump.
 __global__ void gather_kernel(GatherArgs A) {
@@ -1883,6 +1942,11 @@ __device__ __forceinline__ void reduce_part(const ReduceArgs& A, int q, int nq) 
         const DevDir D = A.dirs[d];
         if (A.ring) {
           sd += double(D.rinvD * retarded_rows(A.ring, A.H, A.slot, A.Vp, D, d, m)[v]);
+        } else if (A.tlT) {
+          const float* x = (m & 1) ? A.pp1 : A.pp0;
+          const TwoLevelRow Y{x + size_t(d) * A.Vp, A.tlT + size_t(A.tlparent[d]) * A.Vp, A.tla,
+                              A.tlshare};
+          sd += double(phase_move(D.nu64, m) * Y[v]);
         } else {
           const float f = A.split ? D.nu * A.r[v] : phase_move(D.nu64, m);
           sd += double(f * A.Y[size_t(d) * A.Vp + v]);
@@ -2327,6 +2391,12 @@ hipError_t launch_collide_hop(const CollideArgs& a, const Field& f, hipStream_t 
     case 192: return launch_hop_np<192>(a, f, s);
     default: return hipErrorInvalidValue;
   }
+}
+
+hipError_t launch_sweep_twolevel(const SweepArgs& a, const Field& f, int bpd, hipStream_t s) {
+  hipLaunchKernelGGL(sweep_twolevel_kernel, dim3(unsigned(bpd), unsigned(f.ndir)),
+                     dim3(kThreads), 0, s, a);
+  return hipGetLastError();
 }
 
 hipError_t launch_sweep_retarded(const SweepArgs& a, const Field& f, int bpd, hipStream_t s) {

@@ -52,6 +52,8 @@ __device__ __forceinline__ const_ints kids_of(const TwoLevelArgs& A, int J) {
 // of the block's voxels; the budget partials cover the fine rows of those bins.
 __global__ __launch_bounds__(kTwoThreads) void coarse_sum_kernel(TwoLevelArgs A) {
   __shared__ double red[kTwoThreads / 64];
+  // the field of this step's parity when it alternates between two buffers
+  if (A.X2 && (*A.step_ctr & 1)) A.X = A.X2;
   const long long v0 = 4 * ((long long)blockIdx.x * kTwoThreads + threadIdx.x);
   double col[4] = {0.0, 0.0, 0.0, 0.0};
   double ab = 0.0;

@@ -418,6 +418,28 @@ def test_two_level_solve(nside, nsc, shape):
     assert budget_closure(got["budget"]) < closure_bound(got["budget"])
 
 
+@pytest.mark.parametrize("steps", [1, 2, 21])
+def test_two_level_state_after_odd_and_even_steps(steps):
+    """Two-level phase stepping keeps the field in two alternating buffers;
+    the state read back after any number of steps (graph replays of 16 steps
+    and single steps mixed) is the oracle's, and so is the energy."""
+    p = W.small_problem(nside=4, nx=12, ny=9, nz=7, mua=0.05, mus=3.0, g=0.8, steps=steps,
+                        seed=11, advance="phase").copy(nside_scatter=2)
+    rng = np.random.default_rng(steps)
+    N0 = rng.uniform(0, 1, (192, p.nvox)).astype(np.float32)
+    ref = solve.forward(p, steps=steps, state0=N0.astype(np.float64))
+    import torch
+    with torch.cuda.stream(_stream()):
+        m = T.Medium.from_problem(p)
+        m.set_state(N0)
+        m.solve(steps)
+        got = m.get_state()
+        energy = m.read_energy()
+        m.close()
+    assert np.abs(got - ref.state).max() <= 1e-5 * np.abs(ref.state).max()
+    assert np.allclose(energy.ravel(), ref.state.sum(axis=0), rtol=1e-5, atol=1e-6)
+
+
 def test_two_level_rejected_where_unsupported():
     import torch
     p = W.small_problem(nside=4, steps=5).copy(nside_scatter=1)
