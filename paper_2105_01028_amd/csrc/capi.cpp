@@ -388,6 +388,12 @@ size_t tr_bytes_required(const tr_grid_desc* desc, int ndet, int max_steps) {
   size_t b = fixed_bytes(f, desc->precision, 0);
   if (desc->source == TR_SOURCE_IMPLICIT)   // V, its eigenvalues, w0, w1, c
     b += (size_t(f.NP) * f.NP + f.NP + 3 * size_t(f.Vp)) * sizeof(float);
+  if (desc->nside_scatter != 0 && desc->nside_scatter != desc->nside) {
+    // coarse fields M and T, a zero row, children and parents, partials
+    const long long NPc = round_up(12LL * desc->nside_scatter * desc->nside_scatter, 32);
+    b += (2 * size_t(NPc) + 1) * f.Vp * sizeof(float) + 2 * size_t(f.ndir) * sizeof(int);
+    b += 4 * (size_t(f.Vp / 256) + 64) * 16 * sizeof(double);
+  }
   long long cap = std::max(1024, max_steps);
   b += size_t(cap) * (9 + std::max(ndet, 1) + 1) * sizeof(double);
   b += size_t(f.ndir) * 8 * sizeof(int) + 4096;

@@ -102,3 +102,30 @@ def test_retarded_rejected_where_unsupported():
         with pytest.raises(T.TrinityError):
             m.solve_checkpointed(5, 2)
         m.close()
+
+
+def test_retarded_phantom64_full_size_matches_stored_oracle(golden_dir):
+    """The 64^3 / 192-direction phantom at a fifth of the crossing time (nine
+    history fields), in the launch configuration the benchmark times, against
+    the FP64 oracle's per-step detector records and budget (written by
+    tests/golden/make_golden.py)."""
+    import os
+    z = np.load(os.path.join(golden_dir, "retarded64_oracle.npz"))
+    steps = int(z["steps"])
+    p = W.config2()
+    p = p.copy(advance="retarded", dt_ps=0.2 * p.dx_mm * float(p.n.flat[0]) / C0)
+    got = run_gpu(p, steps)
+    assert abs(got["info"].dt_ps - float(z["dt"])) < 1e-12
+    assert got["info"].history == int(z["history"])
+    ref = z["det"]
+    assert got["steps"][:, :steps].shape == ref.shape
+    assert rel_l2_above(got["steps"][:, :steps].ravel(), ref.ravel()) < 1e-4
+    for k in range(p.ndet):
+        if ref[k].max() > 1e-6 * ref.max():
+            assert rel_l2_above(got["steps"][k, :steps], ref[k]) < 1e-4, k
+    b, ob = got["budget"][:steps], z["budget"]
+    assert np.allclose(b[:, 0], ob[:, 0], rtol=1e-6, atol=1e-15)
+    for col, ocol in ((1, 1), (2, 3)):
+        assert np.abs(b[:, col] - ob[:, ocol]).max() <= 1e-4 * np.abs(ob[:, ocol]).max()
+    esc = b[:, 3:].sum(axis=1)
+    assert np.abs(esc - ob[:, 2]).max() <= 1e-4 * np.abs(ob[:, 2]).max()
