@@ -17,7 +17,12 @@ read as in optics.py):
                                             (1 - R) f_d'(u') Nc[d'][u']
 
 with Nc[:, w] = a_w N[:, w] + b_w (P N[:, w]) and f the move fraction of the
-advance mode.  Only the columns of N at v and its lattice neighbours are read.
+advance mode.  With scattering on a coarser angular grid (Sec. 2.1) P is the
+effective fine-grid matrix of angles.two_level_matrix; with the implicit
+source (Eq. 9-10 with S1 from the outgoing intensity, the fixed point of
+Sec. 2.4 Steps 3-6) Nc[:, w] solves (I - w1_w P) Nc = a_w N + w0_w P N, as in
+solve.collide_implicit.  Only the columns of N at v and its lattice neighbours
+are read.
 The lattice neighbours are found from the same per-plane offsets R(k t) that
 lattice.RayLattice.downwind uses, one voxel at a time.
 
@@ -42,6 +47,9 @@ class LocalSetup:
     n: np.ndarray          # [nz, ny, nx]
     mode: str
     dt: float
+    source: str = "explicit"
+    w0: np.ndarray = None      # implicit source: omega f0, omega f1 per voxel, flat
+    w1: np.ndarray = None
 
 
 def build(prob) -> LocalSetup:
@@ -50,7 +58,11 @@ def build(prob) -> LocalSetup:
     shape = (prob.nz, prob.ny, prob.nx)
     n = np.asarray(prob.n, dtype=np.float64)
     dirs = angles.healpix_ring(prob.nside)
-    P = angles.phase_matrix(dirs, prob.g, prob.hg_norm)
+    ns = getattr(prob, "nside_scatter", 0)
+    if ns and ns != prob.nside:
+        P = angles.two_level_matrix(prob.nside, ns, prob.g, prob.hg_norm)
+    else:
+        P = angles.phase_matrix(dirs, prob.g, prob.hg_norm)
     lat = lattice.RayLattice(dirs, shape)
     dt = medium.time_step(prob.dx_mm, n, prob.dt_ps)
     a, b, _, _ = medium.collision_coefficients(prob.mua, prob.mus, n, dt, prob.coef)
@@ -59,8 +71,14 @@ def build(prob) -> LocalSetup:
     n_ref = medium.reference_index(n)
     ell_ref = medium.C0_MM_PER_PS * dt / n_ref
     nu = lat.plane_speed(ell_ref, prob.dx_mm)
+    source = getattr(prob, "source", "explicit")
+    w0 = w1 = None
+    if source == "implicit":
+        _, w0, w1 = medium.implicit_weights(prob.mua, prob.mus, n, dt)
+        w0, w1 = w0.ravel(), w1.ravel()
     return LocalSetup(dirs=dirs, P=P, lat=lat, a=a.ravel(), b=b.ravel(),
-                      r=(n_ref / n).ravel(), nu=nu, n=n, mode=mode, dt=dt)
+                      r=(n_ref / n).ravel(), nu=nu, n=n, mode=mode, dt=dt, source=source,
+                      w0=w0, w1=w1)
 
 
 def _coords(L: LocalSetup, v):
@@ -139,7 +157,11 @@ def step_outputs(L: LocalSetup, column: Callable[[int], np.ndarray], v, m=0):
     def nc(w):
         if w not in cache:
             x = np.asarray(column(w), dtype=np.float64)
-            cache[w] = L.a[w] * x + L.b[w] * (L.P @ x)
+            if L.source == "implicit":
+                rhs = L.a[w] * x + L.w0[w] * (L.P @ x)
+                cache[w] = np.linalg.solve(np.eye(nd) - L.w1[w] * L.P, rhs)
+            else:
+                cache[w] = L.a[w] * x + L.b[w] * (L.P @ x)
         return cache[w]
 
     out = np.zeros(nd)

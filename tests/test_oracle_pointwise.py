@@ -35,16 +35,22 @@ def _interface_problem(shape, seed):
     return p
 
 
-@pytest.mark.parametrize("case", ["phase", "split", "interfaces"])
+@pytest.mark.parametrize("case", ["phase", "split", "interfaces", "twolevel", "implicit"])
 def test_outputs_match_whole_field_step(case):
     if case == "interfaces":
         p = _interface_problem((10, 9, 8), 3)
+    elif case == "twolevel":
+        p = W.small_problem(nside=4, nx=7, ny=6, nz=5, mua=0.05, mus=3.0, g=0.8, steps=1,
+                            seed=4, advance="phase", total_photons=0.0).copy(nside_scatter=2)
+    elif case == "implicit":
+        p = W.small_problem(nside=2, nx=9, ny=8, nz=7, mua=0.05, mus=3.0, g=0.8, steps=1,
+                            seed=4, advance="split", total_photons=0.0).copy(source="implicit")
     else:
         p = W.small_problem(nside=2, nx=9, ny=8, nz=7, mua=0.05, mus=3.0, g=0.8, steps=1,
                             seed=4, advance=case, total_photons=0.0)
     rng = np.random.default_rng(5)
-    N0 = rng.uniform(0, 1, (48, p.nvox))
-    m = 3 if case == "phase" else 0
+    N0 = rng.uniform(0, 1, (p.ndir, p.nvox))
+    m = 3 if case in ("phase", "twolevel") else 0
     ref = solve.forward(p, steps=1, state0=N0, start_step=m).state
     L = pointwise.build(p)
     if case == "interfaces":
