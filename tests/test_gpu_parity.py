@@ -449,3 +449,65 @@ def test_two_level_rejected_where_unsupported():
             with pytest.raises(T.TrinityError) as e:
                 T.Medium.from_problem(bad)
             assert e.value.status == T.TR_EINVAL
+
+
+def _sampled_single_step(p, centres, tol, seed):
+    """One step at full size from a state that is non-zero in 5^3 cubes around
+    the centres, compared at every direction of the 3^3 voxels around them with
+    the single-output oracle (oracle/pointwise.py)."""
+    import torch
+
+    from oracle import pointwise
+    nz, ny, nx = p.nz, p.ny, p.nx
+    ndir = p.ndir
+    rng = np.random.default_rng(seed)
+
+    def cube(r):
+        out = set()
+        for cx, cy, cz in centres:
+            for dz in range(-r, r + 1):
+                for dy in range(-r, r + 1):
+                    for dx in range(-r, r + 1):
+                        x, y, z = cx + dx, cy + dy, cz + dz
+                        if 0 <= x < nx and 0 <= y < ny and 0 <= z < nz:
+                            out.add((z * ny + y) * nx + x)
+        return np.array(sorted(out))
+    vox, out_vox = cube(2), cube(1)
+    cols = rng.uniform(0.0, 1.0, (ndir, len(vox))).astype(np.float32)
+    where = {int(v): i for i, v in enumerate(vox)}
+    with torch.cuda.stream(_stream()):
+        m = T.Medium.from_problem(p)
+        state = torch.zeros((ndir, p.nvox), dtype=torch.float32, device="cuda")
+        state[:, torch.as_tensor(vox, device="cuda")] = torch.as_tensor(cols, device="cuda")
+        m.set_state(state)
+        m.step(1)
+        m.synchronize()
+        m.get_state(state)
+        torch.cuda.synchronize()
+        got = state[:, torch.as_tensor(out_vox, device="cuda")].cpu().numpy()
+        m.close()
+        del state
+    L = pointwise.build(p)
+    zero = np.zeros(ndir)
+
+    def column(w):
+        i = where.get(int(w))
+        return zero if i is None else cols[:, i].astype(np.float64)
+    ref = np.stack([pointwise.step_outputs(L, column, int(v)) for v in out_vox], axis=1)
+    scale = np.abs(ref).max()
+    assert scale > 0
+    assert np.abs(got - ref).max() <= tol * scale
+
+
+def test_two_level_full_size_sampled_single_step():
+    """The paper's fiducial angular set-up at the phantom's full size: 3072
+    transport and 192 scattering directions on 64^3 voxels, the benchmark's
+    launch configuration (sweep forming the collided value as it reads)."""
+    p = W.config2().copy(nside=16, nside_scatter=4, total_photons=0.0)
+    _sampled_single_step(p, [(31, 31, 0), (0, 0, 0), (63, 20, 40), (30, 45, 20)], 2e-6, 41)
+
+
+def test_implicit_source_full_size_sampled_single_step():
+    """The implicit source on the full 64^3 x 192 phantom."""
+    p = W.config2().copy(source="implicit", total_photons=0.0)
+    _sampled_single_step(p, [(31, 31, 0), (0, 63, 0), (63, 20, 40), (30, 45, 20)], 2e-6, 42)
