@@ -36,6 +36,9 @@ Readings (each one is what the paper leaves open):
     a fifth of the crossing time, where D_d reaches 5 sqrt(3).
   * Uniform refractive index only (one D_d per direction, no Fresnel
     interception).
+  * With the source on a coarser angular grid, P is the effective fine-grid
+    matrix of angles.two_level_matrix, and the hop coefficients are those of
+    each fine direction.
 
 Test infrastructure only (see the package docstring)."""
 from dataclasses import dataclass
@@ -106,6 +109,11 @@ def build(prob, dirs=None, P=None) -> RetardedSetup:
         raise ValueError("retarded stepping needs a uniform refractive index")
     if dirs is None:
         dirs = angles.healpix_ring(prob.nside)
+    ns = getattr(prob, "nside_scatter", 0)
+    if P is None and ns and ns != prob.nside:
+        # the source on a coarser angular grid (Sec. 2.1): the effective
+        # fine-grid matrix, as in solve.build
+        P = angles.two_level_matrix(prob.nside, ns, prob.g, prob.hg_norm)
     if P is None:
         P = angles.phase_matrix(dirs, prob.g, prob.hg_norm)
     lat = lattice.RayLattice(dirs, shape)

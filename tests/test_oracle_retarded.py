@@ -213,3 +213,20 @@ def test_unequal_hops_conserve_light_to_second_order():
         assert res.in_domain[-1] < 1e-12 * inj
         loss.append((inj - res.absorbed.sum() - res.escaped.sum()) / inj)
     assert 3.5 < loss[0] / loss[1] < 4.5
+
+
+def test_two_level_source_uses_the_effective_matrix():
+    """With nside_scatter the retarded collision scatters with C P_c A: one
+    collision of a random field equals a N + b (P_eff N), and P_eff keeps
+    column sums of one, so scattering alone conserves the content."""
+    from oracle import angles
+    p = W.small_problem(nside=4, nx=5, ny=4, nz=3, mua=0.0, mus=1.5, g=0.7, n=1.2, steps=1,
+                        seed=8).copy(nside_scatter=2, dt_ps=0.2 * 1.2 / C0)
+    S = retarded.build(p)
+    Pe = angles.two_level_matrix(4, 2, p.g, p.hg_norm)
+    assert np.abs(S.P - Pe).max() == 0.0
+    rng = np.random.default_rng(9)
+    N = rng.uniform(0.0, 1.0, (192, p.nvox))
+    C, _ = retarded.collide(S, N)
+    assert np.abs(C - (S.a * N + S.b * (Pe @ N))).max() < 1e-14
+    assert np.allclose(Pe.sum(axis=0), 1.0, atol=1e-13)
