@@ -85,8 +85,10 @@ typedef struct {
                          1/D_d of them per step: the source puts D_d times its per-step
                          photons into its voxels, and escape, detector and absorption
                          tallies count 1/D_d of the content per step.  Needs uniform n, FP32,
-                         the explicit source, TR_COEF_PAPER, one angular grid and at most
-                         192 directions; tr_set_state, the adjoint and the server refuse it */
+                         the explicit source, TR_COEF_PAPER, and at most 192 directions
+                         unless nside_scatter puts the source on a coarser grid (then
+                         a = e^{-mu_t dr_d} per fine direction and b (P N) comes from the
+                         coarse bins); tr_set_state, the adjoint and the server refuse it */
   int precision;      /* TR_PREC_FP32 or TR_PREC_BF16SPLIT (P and N split into bf16 hi+lo,
                          the four bf16 MFMA products, fp32 accumulation; each value
                          off by at most 2^-16 of itself) */

@@ -256,8 +256,10 @@ hipError_t queue_step(tr_medium* m) {
     Field fc = f;
     fc.ndir = m->nc;
     fc.NP = m->NPc;
-    CollideArgs cc{m->M, m->T, m->P, m->Prow, nullptr, nullptr, m->zero, m->b,
-                   f.Vp, m->NPc, m->cpart2};
+    // coarse source T = b (P_c M); with the retarded history the factor is
+    // omega, and each fine direction's (1 - a) comes in apply_hop
+    CollideArgs cc{m->M, m->T, m->P, m->Prow, nullptr, nullptr, m->zero,
+                   m->ring ? m->omega : m->b, f.Vp, m->NPc, m->cpart2};
     {
       KernelTimer t(m, TR_K_COARSE_SUM);
       if ((e = launch_coarse_sum(ta, m->stream)) != hipSuccess) return e;
@@ -266,7 +268,17 @@ hipError_t queue_step(tr_medium* m) {
       KernelTimer t(m, TR_K_COLLIDE);
       if ((e = launch_collide(cc, fc, 0, 0, m->stream)) != hipSuccess) return e;
     }
-    if (!m->tlfused) {
+    if (m->ring) {
+      KernelTimer t(m, TR_K_APPLY);
+      ta.ring = m->ring;
+      ta.H = m->H;
+      ta.slot = (long long)f.NP * f.Vp;
+      ta.mutdx = m->mutdx;
+      ta.omega = m->omega;
+      ta.hinvc = m->hinvc;
+      ta.hinvD = m->hinvD;
+      if ((e = launch_apply_hop(ta, m->stream)) != hipSuccess) return e;
+    } else if (!m->tlfused) {
       KernelTimer t(m, TR_K_APPLY);
       if ((e = launch_apply(ta, m->stream)) != hipSuccess) return e;
     }
@@ -723,7 +735,8 @@ tr_status tr_create_medium(const tr_grid_desc* desc, const float* mua, const flo
     if (e == hipSuccess) e = hipMemcpy(m->omega, om.data(), om.size() * 4, hipMemcpyHostToDevice);
     if (e == hipSuccess) e = hipMemcpy(m->hinvc, ic.data(), ic.size() * 4, hipMemcpyHostToDevice);
     if (e == hipSuccess) e = hipMemcpy(m->hinvD, iD.data(), iD.size() * 4, hipMemcpyHostToDevice);
-    if (e == hipSuccess) e = prepare_collide_hop(f);
+    // (on a two-level grid the hop collision is apply_hop's, from the coarse source)
+    if (e == hipSuccess && !m->twolevel) e = prepare_collide_hop(f);
     if (e != hipSuccess) {
       delete m;
       return fail(TR_EDEVICE, std::string("upload: ") + hipGetErrorString(e));

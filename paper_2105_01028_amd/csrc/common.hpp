@@ -41,10 +41,11 @@ inline bool valid_desc(const tr_grid_desc* d, std::string& err) {
   if (d->coef != 0 && d->coef != 1) return err = "bad coef", false;
   if (d->advance < 0 || d->advance > 3) return err = "bad advance", false;
   if (d->advance == 3 && (d->precision != 0 || d->source != 0 || d->coef != 0 ||
-                          (d->nside_scatter != 0 && d->nside_scatter != d->nside) ||
-                          12 * d->nside * d->nside > 192))
+                          ((d->nside_scatter == 0 || d->nside_scatter == d->nside) &&
+                           12 * d->nside * d->nside > 192)))
     return err = "the retarded advance needs FP32, the explicit source, the paper's "
-                 "coefficients, one angular grid and at most 192 directions", false;
+                 "coefficients, and at most 192 directions unless the source is on a "
+                 "coarser angular grid", false;
   if (d->precision != 0 && d->precision != 1) return err = "bad precision", false;
   if (d->source != 0 && d->source != 1) return err = "bad source", false;
   if (d->nside_scatter != 0 && d->nside_scatter != d->nside) {

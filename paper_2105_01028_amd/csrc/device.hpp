@@ -216,10 +216,24 @@ struct TwoLevelArgs {
   double* part;            // [2][nwg] absorbed, total
   const float* X2;         // alternating field (see InjectArgs::X2), null otherwise
   const int* step_ctr;
+  // retarded stepping (apply_hop): history ring [H][NP][Vp] (slot = step mod
+  // H, NP * Vp floats each), per voxel mu_t dx and omega, per fine row
+  // 1/|Omega_a| and 1/D
+  float* ring;
+  int H;
+  long long slot;
+  const float* mutdx;
+  const float* omega;
+  const float* hinvc;
+  const float* hinvD;
 };
 long long coarse_sum_workgroups(const TwoLevelArgs& a);   // budget partial pairs written
 hipError_t launch_coarse_sum(const TwoLevelArgs& a, hipStream_t s);
 hipError_t launch_apply(const TwoLevelArgs& a, hipStream_t s);
+// Retarded stepping on the two-level grid: the hop collision of every fine
+// direction from the coarse source, into the history slot of the step; writes
+// the budget partials (the layout of launch_coarse_sum, which it replaces).
+hipError_t launch_apply_hop(const TwoLevelArgs& a, hipStream_t s);
 
 // Launchers: queue the kernel on `s`.  Return the launch status.
 hipError_t launch_inject(const InjectArgs& a, hipStream_t s);

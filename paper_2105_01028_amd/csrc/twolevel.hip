@@ -149,6 +149,85 @@ __global__ __launch_bounds__(kTwoThreads) void apply_kernel(TwoLevelArgs A) {
   }
 }
 
+// Retarded stepping on the two-level grid (the hop collision of the retarded
+// form of Eq. 10 with the source from the coarse bins): fine direction i hops
+// dx/|Omega_a|_i, so
+//   C[i][v] = a X[i][v] + (1 - a) T[J(i)][v] / r^2,  a = exp(-mu_t(v) dx / |Omega_a|_i),
+// with T = omega (P_c M) from the coarse collide; C goes to the history slot
+// of the step.  The budget partials (absorbed (1 - a)(1 - omega) X / D_i per
+// element, total X) replace those coarse_sum wrote, in the same layout.
+__global__ __launch_bounds__(kTwoThreads) void apply_hop_kernel(TwoLevelArgs A) {
+  __shared__ double red[kTwoThreads / 64];
+  const long long v0 = 4 * ((long long)blockIdx.x * kTwoThreads + threadIdx.x);
+  const int m = *A.step_ctr;
+  float* __restrict__ C = A.ring + size_t(m % A.H) * size_t(A.slot);
+  typedef const __attribute__((address_space(4))) float* const_floats;
+  const const_floats ic = (const_floats)A.hinvc;
+  const const_floats iD = (const_floats)A.hinvD;
+  constexpr float kLog2e = 1.44269504088896341f;
+  double lost[4] = {0.0, 0.0, 0.0, 0.0}, tot[4] = {0.0, 0.0, 0.0, 0.0};
+  float om[4] = {0.f, 0.f, 0.f, 0.f};
+  if (v0 < A.V) {
+    const int ne = v0 + 4 <= A.V ? 4 : int(A.V - v0);
+    float ml2[4] = {0.f, 0.f, 0.f, 0.f};
+    for (int e = 0; e < ne; ++e) {
+      ml2[e] = A.mutdx[v0 + e] * kLog2e;
+      om[e] = A.omega[v0 + e];
+    }
+    for (int J = blockIdx.y; J < A.nc; J += gridDim.y) {
+      const const_ints kids = kids_of(A, J);
+      float t[4] = {0.f, 0.f, 0.f, 0.f};
+      for (int e = 0; e < ne; ++e) t[e] = A.T[size_t(J) * A.Vp + v0 + e] * A.share;
+      float lf[4] = {0.f, 0.f, 0.f, 0.f}, tf[4] = {0.f, 0.f, 0.f, 0.f};
+      for (int k = 0; k < A.nkids; ++k) {
+        const int i = kids[k];
+        const size_t o = size_t(i) * A.Vp + v0;
+        const float c = ic[i], w = iD[i];
+        float x[4] = {0.f, 0.f, 0.f, 0.f};
+        if (ne == 4) {
+          const float4 x4 = ld4(A.X + o);
+          x[0] = x4.x;
+          x[1] = x4.y;
+          x[2] = x4.z;
+          x[3] = x4.w;
+        } else {
+          for (int e = 0; e < ne; ++e) x[e] = A.X[o + e];
+        }
+        float y[4];
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          const float a = __builtin_amdgcn_exp2f(-ml2[e] * c);
+          const float oma = 1.0f - a;
+          y[e] = fmaf(a, x[e], oma * t[e]);
+          lf[e] = fmaf(oma * x[e], w, lf[e]);
+          tf[e] += x[e];
+        }
+        if (ne == 4)
+          st4(C + o, make_float4(y[0], y[1], y[2], y[3]));
+        else
+          for (int e = 0; e < ne; ++e) C[o + e] = y[e];
+      }
+      for (int e = 0; e < 4; ++e) {
+        lost[e] += double(lf[e]);
+        tot[e] += double(tf[e]);
+      }
+    }
+  }
+  double ab = 0.0, tt = 0.0;
+  for (int e = 0; e < 4; ++e) {
+    ab += (1.0 - double(om[e])) * lost[e];
+    tt += tot[e];
+  }
+  ab = tl_block_sum(ab, red);
+  tt = tl_block_sum(tt, red);
+  const long long nwg = (long long)gridDim.x * gridDim.y;
+  const long long wg = (long long)blockIdx.y * gridDim.x + blockIdx.x;
+  if (threadIdx.x == 0) {
+    A.part[wg] = ab;
+    A.part[nwg + wg] = tt;
+  }
+}
+
 }  // namespace
 
 namespace {
@@ -170,6 +249,12 @@ long long coarse_sum_workgroups(const TwoLevelArgs& a) {
 hipError_t launch_coarse_sum(const TwoLevelArgs& a, hipStream_t s) {
   dim3 grid(quad_blocks(a), coarse_sum_groups(a));
   hipLaunchKernelGGL(coarse_sum_kernel, grid, dim3(kTwoThreads), 0, s, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_apply_hop(const TwoLevelArgs& a, hipStream_t s) {
+  dim3 grid(quad_blocks(a), coarse_sum_groups(a));
+  hipLaunchKernelGGL(apply_hop_kernel, grid, dim3(kTwoThreads), 0, s, a);
   return hipGetLastError();
 }
 

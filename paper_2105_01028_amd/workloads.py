@@ -142,6 +142,25 @@ def config2(seed: int = 2) -> Problem:
                    nbins=5004, name="phantom 64^3 +-5% noise, 192 dirs, 1000 steps")
 
 
+def fiducial101(seed: int = 2) -> Problem:
+    """The paper's fiducial phantom run at its own size (Sec. 3.1 and the
+    timing of Sec. 4): a 4 cm box at 0.4 mm (101^3 voxels), 3072 transport
+    directions with the source on 192, time step 0.4 ps (a fifth of the
+    crossing time at n = 1.5), 8680 steps.  The medium takes the values of the
+    64^3 phantom (+-5 % voxel noise)."""
+    nx = ny = nz = 101
+    rng = np.random.default_rng(seed)
+    shape = (nz, ny, nx)
+    mua = (0.005 * _noise(rng, shape)).astype(np.float32)
+    mus = (8.0 * _noise(rng, shape)).astype(np.float32)
+    n = np.full(shape, 1.5, np.float32)
+    f, i, j = surface_line_detectors(nx, nz, 0.4, 20.0, 20.0, np.arange(5.0, 41.0, 5.0))
+    return Problem(nx=nx, ny=ny, nz=nz, dx_mm=0.4, nside=16, nside_scatter=4, g=0.85, mua=mua,
+                   mus=mus, n=n, steps=8680, dt_ps=0.4, advance="retarded", src_ix=49,
+                   src_iy=49, src_w=2, det_face=f, det_i=i, det_j=j, nbins=3500,
+                   name="fiducial phantom 101^3 at 0.4 mm, 3072/192 directions, 0.4 ps")
+
+
 def _voxel_centres(nx, ny, nz, dx):
     z, y, x = np.meshgrid((np.arange(nz) + 0.5) * dx, (np.arange(ny) + 0.5) * dx,
                           (np.arange(nx) + 0.5) * dx, indexing="ij")

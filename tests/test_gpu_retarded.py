@@ -84,6 +84,15 @@ def test_retarded_long_run_through_graph_replays():
     assert ref.in_domain[-1] < 0.5 * ref.in_domain.max()
 
 
+@pytest.mark.parametrize("nside,nsc,shape", [(4, 2, (12, 9, 7)), (4, 1, (9, 8, 6)),
+                                              (8, 2, (10, 8, 6))])
+def test_retarded_two_level_matches_oracle(nside, nsc, shape):
+    """The paper's combination: transport on a fine grid below the crossing
+    time, source from coarse bins (hop coefficients per fine direction)."""
+    p = _problem(nside, shape, 0.2, 8, 40).copy(nside_scatter=nsc)
+    _compare(p, 40)
+
+
 def test_retarded_rejected_where_unsupported():
     import torch
     p = _problem(2, (9, 8, 7), 0.2, 7, 5)
@@ -92,7 +101,7 @@ def test_retarded_rejected_where_unsupported():
     with torch.cuda.stream(_stream()):
         for bad in (p.copy(precision="bf16split"), p.copy(source="implicit"),
                     p.copy(coef="abs_exact"), p.copy(nside=8), p.copy(n=n2),
-                    p.copy(nside=4, nside_scatter=2)):
+                    p.copy(nside=16, nside_scatter=8)):
             with pytest.raises(T.TrinityError) as e:
                 T.Medium.from_problem(bad)
             assert e.value.status == T.TR_EINVAL
