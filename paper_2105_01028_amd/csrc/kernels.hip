@@ -1143,149 +1143,87 @@ __device__ __forceinline__ void sweep_rows(const SweepArgs& A, const DevDir& D, 
   }
 }
 
-// Phase mode, a direction that moves at this step (f = 1): every voxel takes
-// its upwind voxel's value, light in the exit plane (or crossing a side of the
-// box) leaves.  Per-row (or, for x-dominant directions, per-lane) quantities
-// are hoisted; indices are 32-bit (the C-ABI limits a grid to 2^30 voxels).
+// Phase mode, a moving direction whose dominant axis is y or z, any nx: the
+// voxels of rows [rb, re) in flat order, kThreads apart, four per thread per
+// pass with all loads issued before the stores, so that every lane works
+// whatever the row length.  Same tallies, in the same order of precedence, as
+// the row paths.
 template <int AX, class Src>
-__device__ __forceinline__ void sweep_phase_rows(const SweepArgs& A, const Src& Yd,
+__device__ __forceinline__ void sweep_phase_flat(const SweepArgs& A, const Src& Yd,
                                                  const DevDir& D, int d, int rb, int re,
                                                  const int8_t* __restrict__ db,
                                                  const int8_t* __restrict__ dc, SweepAcc& acc) {
-  const int nx = A.nx, ny = A.ny, nz = A.nz;
-  const int nxy = nx * ny;
+  static_assert(AX == 1 || AX == 2, "rows run along x");
   constexpr int CX = AX == 2 ? 1 : 2;
-  const int ea = AX == 0 ? nx : (AX == 1 ? ny : nz);
+  constexpr int U = 4;
+  const int nx = A.nx, ny = A.ny, nz = A.nz;
+  const int ea = AX == 1 ? ny : nz;
   const int ec = CX == 1 ? ny : nz;
-  const int sa = AX == 0 ? 1 : (AX == 1 ? nx : nxy);
-  const int sc = CX == 1 ? nx : nxy;
+  const int sa = AX == 1 ? nx : nx * ny;
+  const int sc = CX == 1 ? nx : nx * ny;
   float* __restrict__ Xd = A.X + size_t(d) * A.Vp;
-  const int tpr = nx < kThreads ? nx : kThreads;
-  const int rpi = kThreads / tpr;
-  const int xs = threadIdx.x % tpr, rsub = threadIdx.x / tpr;
-  if (rsub >= rpi) return;
   const int sign = D.sign;
-  if (AX == 0) {
-    // lanes run across planes: the plane index and its shifts are per lane
-    for (int x = xs; x < nx; x += tpr) {
-      const int k = sign > 0 ? x : nx - 1 - x;
-      const int dbk = db[k], dck = dc[k], dbn = db[k + 1], dcn = dc[k + 1];
-      const bool exit_a = k + 1 >= nx;
-      const int uoff = -sign - dbk * nx - dck * nxy;
-      constexpr int RB = 4;
-      int yy[RB], zz[RB];
-      {
-        const int row = rb + rsub;
-        zz[0] = row / ny;
-        yy[0] = row - zz[0] * ny;
+  const int ve = re * nx;
+  const int drow = kThreads / nx, dxs = kThreads - drow * nx;
+  // slot j of a pass takes flat index g0 + j kThreads: its (x, y, z)
+  int xs[U], yys[U], zzs[U];
+  {
+    const int g = rb * nx + threadIdx.x;
+    const int row = g / nx;
+    xs[0] = g - row * nx;
+    zzs[0] = row / ny;
+    yys[0] = row - zzs[0] * ny;
 #pragma unroll
-        for (int i = 1; i < RB; ++i) {
-          yy[i] = yy[i - 1] + rpi;
-          zz[i] = zz[i - 1];
-          while (yy[i] >= ny) {
-            yy[i] -= ny;
-            ++zz[i];
-          }
-        }
-      }
-      for (int row0 = rb + rsub; row0 < re; row0 += RB * rpi) {
-        float out[RB];
-        int v[RB];
-        bool live[RB];
+    for (int j = 1; j < U; ++j) {
+      xs[j] = xs[j - 1] + dxs;
+      yys[j] = yys[j - 1] + drow;
+      zzs[j] = zzs[j - 1];
+      if (xs[j] >= nx) { xs[j] -= nx; ++yys[j]; }
+      while (yys[j] >= ny) { yys[j] -= ny; ++zzs[j]; }
+    }
+  }
+  const int drowU = U * kThreads / nx, dxU = U * kThreads - drowU * nx;
+  for (int g0 = rb * nx + threadIdx.x; g0 < ve; g0 += U * kThreads) {
+    float out[U];
+    int kk[U], dbn[U], dcn[U];
+    bool live[U];
 #pragma unroll
-        for (int i = 0; i < RB; ++i) {
-          const int row = row0 + i * rpi;
-          live[i] = row < re;
-          v[i] = row * nx + x;
-          const bool in = live[i] && k > 0 && (unsigned)(yy[i] - dbk) < (unsigned)ny &&
-                          (unsigned)(zz[i] - dck) < (unsigned)nz;
-          out[i] = in ? Yd[v[i] + uoff] : 0.0f;
-        }
+    for (int j = 0; j < U; ++j) {
+      const int v = g0 + j * kThreads;
+      live[j] = v < ve;
+      const int pa = AX == 1 ? yys[j] : zzs[j];
+      const int pc = CX == 1 ? yys[j] : zzs[j];
+      kk[j] = sign > 0 ? pa : ea - 1 - pa;
+      const int kc = live[j] ? kk[j] : 0;   // slots past the end read in-range tables
+      const int dbk = db[kc], dck = dc[kc];
+      dbn[j] = db[kc + 1];
+      dcn[j] = dc[kc + 1];
+      const bool in = live[j] && kk[j] > 0 && (unsigned)(pc - dck) < (unsigned)ec &&
+                      (unsigned)(xs[j] - dbk) < (unsigned)nx;
+      out[j] = in ? Yd[v - sign * sa - dck * sc - dbk] : 0.0f;
+    }
 #pragma unroll
-        for (int i = 0; i < RB; ++i) {
-          if (!live[i]) continue;
-          Xd[v[i]] = out[i];
-          acc.dom += double(out[i]);
-          if (exit_a) {
-            acc.esc_a += double(Yd[v[i]]);
-          } else if ((unsigned)(yy[i] + dbn) >= (unsigned)ny) {
-            if (dbn > 0) acc.esc_b1 += double(Yd[v[i]]); else acc.esc_b0 += double(Yd[v[i]]);
-          } else if ((unsigned)(zz[i] + dcn) >= (unsigned)nz) {
-            if (dcn > 0) acc.esc_c1 += double(Yd[v[i]]); else acc.esc_c0 += double(Yd[v[i]]);
-          }
-        }
-#pragma unroll
-        for (int i = 0; i < RB; ++i) {
-          yy[i] += RB * rpi;
-          while (yy[i] >= ny) {
-            yy[i] -= ny;
-            ++zz[i];
-          }
-        }
+    for (int j = 0; j < U; ++j) {
+      if (!live[j]) continue;
+      const int v = g0 + j * kThreads;
+      const int pc = CX == 1 ? yys[j] : zzs[j];
+      Xd[v] = out[j];
+      acc.dom += double(out[j]);
+      if (kk[j] + 1 >= ea) {
+        acc.esc_a += double(Yd[v]);
+      } else if ((unsigned)(xs[j] + dbn[j]) >= (unsigned)nx) {
+        if (dbn[j] > 0) acc.esc_b1 += double(Yd[v]); else acc.esc_b0 += double(Yd[v]);
+      } else if ((unsigned)(pc + dcn[j]) >= (unsigned)ec) {
+        if (dcn[j] > 0) acc.esc_c1 += double(Yd[v]); else acc.esc_c0 += double(Yd[v]);
       }
     }
-  } else {
-    // four rows per iteration, all loads issued before the stores
-    constexpr int RB = 4;
-    int yy[RB], zz[RB];
-    {
-      const int row = rb + rsub;
-      zz[0] = row / ny;
-      yy[0] = row - zz[0] * ny;
 #pragma unroll
-      for (int i = 1; i < RB; ++i) {
-        yy[i] = yy[i - 1] + rpi;
-        zz[i] = zz[i - 1];
-        while (yy[i] >= ny) {
-          yy[i] -= ny;
-          ++zz[i];
-        }
-      }
-    }
-    for (int row0 = rb + rsub; row0 < re; row0 += RB * rpi) {
-      for (int x = xs; x < nx; x += tpr) {
-        int v[RB], k[RB], dbn[RB], dcn[RB];
-        bool live[RB], last[RB], cexit[RB];
-        float out[RB];
-#pragma unroll
-        for (int i = 0; i < RB; ++i) {
-          const int row = row0 + i * rpi;
-          live[i] = row < re;
-          const int pa = AX == 1 ? yy[i] : zz[i];
-          const int pc = CX == 1 ? yy[i] : zz[i];
-          k[i] = sign > 0 ? pa : ea - 1 - pa;
-          const int dbk = db[k[i]], dck = dc[k[i]];
-          dbn[i] = db[k[i] + 1];
-          dcn[i] = dc[k[i] + 1];
-          const bool in = live[i] && k[i] > 0 && (unsigned)(pc - dck) < (unsigned)ec &&
-                          (unsigned)(x - dbk) < (unsigned)nx;
-          last[i] = k[i] + 1 >= ea;
-          cexit[i] = !last[i] && (unsigned)(pc + dcn[i]) >= (unsigned)ec;
-          v[i] = row * nx + x;
-          out[i] = in ? Yd[v[i] - sign * sa - dck * sc - dbk] : 0.0f;
-        }
-#pragma unroll
-        for (int i = 0; i < RB; ++i) {
-          if (!live[i]) continue;
-          Xd[v[i]] = out[i];
-          acc.dom += double(out[i]);
-          if (last[i]) {
-            acc.esc_a += double(Yd[v[i]]);
-          } else if ((unsigned)(x + dbn[i]) >= (unsigned)nx) {
-            if (dbn[i] > 0) acc.esc_b1 += double(Yd[v[i]]); else acc.esc_b0 += double(Yd[v[i]]);
-          } else if (cexit[i]) {
-            if (dcn[i] > 0) acc.esc_c1 += double(Yd[v[i]]); else acc.esc_c0 += double(Yd[v[i]]);
-          }
-        }
-      }
-#pragma unroll
-      for (int i = 0; i < RB; ++i) {
-        yy[i] += RB * rpi;
-        while (yy[i] >= ny) {
-          yy[i] -= ny;
-          ++zz[i];
-        }
-      }
+    for (int j = 0; j < U; ++j) {
+      xs[j] += dxU;
+      int adv = drowU;
+      if (xs[j] >= nx) { xs[j] -= nx; ++adv; }
+      yys[j] += adv;
+      while (yys[j] >= ny) { yys[j] -= ny; ++zzs[j]; }
     }
   }
 }
@@ -1723,9 +1661,9 @@ __device__ __forceinline__ void sweep_moving(const SweepArgs& A, const Src& Y, c
     else
       sweep_phase_vec<1>(A, Y, D, d, rb, re, sdelta[0], sdelta[1], acc);
   } else if (D.axis == 2) {
-    sweep_phase_rows<2>(A, Y, D, d, rb, re, sdelta[0], sdelta[1], acc);
+    sweep_phase_flat<2>(A, Y, D, d, rb, re, sdelta[0], sdelta[1], acc);
   } else if (D.axis == 1) {
-    sweep_phase_rows<1>(A, Y, D, d, rb, re, sdelta[0], sdelta[1], acc);
+    sweep_phase_flat<1>(A, Y, D, d, rb, re, sdelta[0], sdelta[1], acc);
   } else {
     sweep_phase_band0(A, Y, D, d, blk, nblk, sdelta[0], sdelta[1], acc);
   }
