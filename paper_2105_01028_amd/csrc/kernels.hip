@@ -1760,6 +1760,18 @@ __global__ __launch_bounds__(kThreads) void sweep_kernel(SweepArgs A) {
   sweep_block<SPLIT, FRESNEL, FAST>(A, blockIdx.y, blockIdx.x, gridDim.x, sdelta, srt, rbits);
 }
 
+// The split fast paths held to 64 registers, eight waves per SIMD: at 68-70
+// registers (seven waves) the 128^3 x 768 sweep took 3.13 ms, at 64 (a 12-byte
+// spill) 2.87 ms.
+template <bool FRESNEL>
+__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(8, 8)))
+void sweep_fast_kernel(SweepArgs A) {
+  __shared__ int8_t sdelta[2][kMaxExt + 2];
+  __shared__ float srt[128];
+  __shared__ uint32_t rbits[kMaxRowBits / 32];
+  sweep_block<true, FRESNEL, true>(A, blockIdx.y, blockIdx.x, gridDim.x, sdelta, srt, rbits);
+}
+
 // Retarded stepping below Courant one (Sec. 2.1, the upwind value at the
 // retarded time t - dr/c): every direction moves each step, and a voxel takes
 // its upwind voxel's collided value at step m + 1 - D_d, blended from two
@@ -2386,11 +2398,11 @@ hipError_t launch_sweep(const SweepArgs& a, const Field& f, int split, int fresn
   // split mode: fast kernel when every direction has a class-byte path
   const bool fast = split && a.mat != nullptr && fast_split_ok;
   if (split && fresnel && fast)
-    hipLaunchKernelGGL((sweep_kernel<true, true, true>), grid, dim3(kThreads), 0, s, a);
+    hipLaunchKernelGGL((sweep_fast_kernel<true>), grid, dim3(kThreads), 0, s, a);
   else if (split && fresnel)
     hipLaunchKernelGGL((sweep_kernel<true, true, false>), grid, dim3(kThreads), 0, s, a);
   else if (split && fast)
-    hipLaunchKernelGGL((sweep_kernel<true, false, true>), grid, dim3(kThreads), 0, s, a);
+    hipLaunchKernelGGL((sweep_fast_kernel<false>), grid, dim3(kThreads), 0, s, a);
   else if (split)
     hipLaunchKernelGGL((sweep_kernel<true, false, false>), grid, dim3(kThreads), 0, s, a);
   else
