@@ -522,6 +522,10 @@ __global__ __launch_bounds__(512, 1) void collide_f32_stream_kernel(CollideArgs 
   constexpr int NQ = MT / 32;
   constexpr int KC = 32, LDK = KC + 4;
   constexpr int NPR = (MT * KC / 4 + 511) / 512;   // float4 of P per thread per chunk
+  // every thread has NPR float4 when they divide evenly, else all but the last;
+  // every slot is filled unconditionally and only the LDS store of a partial
+  // slot is guarded (a guarded fill kept preg in scratch)
+  constexpr bool kFull = (MT * KC / 4) % 512 == 0;
   extern __shared__ float Pbuf[];                   // [2][MT][LDK]
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int hl = lane >> 5, cl = lane & 31;
@@ -536,44 +540,42 @@ __global__ __launch_bounds__(512, 1) void collide_f32_stream_kernel(CollideArgs 
     const char* rb = xb0 + size_t(32 * c + 8 * (s >> 2) + (s & 3)) * rowbytes;
     return *reinterpret_cast<const float*>(rb + voff);
   };
+  // P chunk staging, written out in place (no lambda holding preg by
+  // reference, which kept it in scratch)
   float4 preg[NPR];
-  auto stage = [&](int c) {
-#pragma unroll
-    for (int i = 0; i < NPR; ++i) {
-      const int e = tid + i * 512;
-      if (e < MT * KC / 4) {
-        const int r = e / (KC / 4), k4 = (e - r * (KC / 4)) * 4;
-        preg[i] = *reinterpret_cast<const float4*>(A.Prow + size_t(row0 + r) * A.NP + 32 * c + k4);
-      }
-    }
-  };
-  auto put = [&](int buf) {
-    float* Pb = Pbuf + buf * MT * LDK;
-#pragma unroll
-    for (int i = 0; i < NPR; ++i) {
-      const int e = tid + i * 512;
-      if (e < MT * KC / 4) {
-        const int r = e / (KC / 4), k4 = (e - r * (KC / 4)) * 4;
-        *reinterpret_cast<float4*>(Pb + r * LDK + k4) = preg[i];
-      }
-    }
-  };
+#define TRINITY_STAGE_P(cc)                                                                   \
+  _Pragma("unroll") for (int i = 0; i < NPR; ++i) {                                           \
+    /* a partial last slot reads element 0 again (in range, not stored) */                    \
+    const int e0 = tid + i * 512;                                                             \
+    const int e = (kFull || i + 1 < NPR || e0 < MT * KC / 4) ? e0 : 0;                        \
+    const int r = e / (KC / 4), k4 = (e - r * (KC / 4)) * 4;                                  \
+    preg[i] = *reinterpret_cast<const float4*>(A.Prow + size_t(row0 + r) * A.NP + 32 * (cc) + \
+                                               k4);                                           \
+  }
+#define TRINITY_PUT_P(buf)                                                                    \
+  _Pragma("unroll") for (int i = 0; i < NPR; ++i) {                                           \
+    const int e = tid + i * 512;                                                              \
+    if (kFull || i + 1 < NPR || e < MT * KC / 4) {                                            \
+      const int r = e / (KC / 4), k4 = (e - r * (KC / 4)) * 4;                                \
+      *reinterpret_cast<float4*>(Pbuf + (buf) * MT * LDK + r * LDK + k4) = preg[i];           \
+    }                                                                                         \
+  }
   floatx16 acc[NQ];
 #pragma unroll
   for (int q = 0; q < NQ; ++q)
 #pragma unroll
     for (int r = 0; r < 16; ++r) acc[q][r] = 0.0f;
   float bcur[16], bnext[16];
-  stage(0);
+  TRINITY_STAGE_P(0)
 #pragma unroll
   for (int s = 0; s < 16; ++s) bcur[s] = ld(0, s);
-  put(0);
+  TRINITY_PUT_P(0)
   __syncthreads();
   double colsum64 = 0.0;
 #pragma unroll 1
   for (int c = 0; c < NC; ++c) {
     const int cn = c + 1 < NC ? c + 1 : c;   // the last chunk reloads itself (in bounds, unused)
-    stage(cn);
+    TRINITY_STAGE_P(cn)
 #pragma unroll
     for (int s = 0; s < 16; ++s) bnext[s] = ld(cn, s);
     const int qc = c - row0 / 32;           // accumulator block of this chunk's rows, if in the tile
@@ -604,7 +606,9 @@ __global__ __launch_bounds__(512, 1) void collide_f32_stream_kernel(CollideArgs 
         acc[q] = __builtin_amdgcn_mfma_f32_32x32x2f32(a4.w, bcur[s4 + 3], acc[q], 0, 0, 0);
       }
     }
-    if (c + 1 < NC) put((c + 1) & 1);
+    if (c + 1 < NC) {
+      TRINITY_PUT_P((c + 1) & 1)
+    }
     __syncthreads();
 #pragma unroll
     for (int s = 0; s < 16; ++s) bcur[s] = bnext[s];
@@ -620,6 +624,8 @@ __global__ __launch_bounds__(512, 1) void collide_f32_stream_kernel(CollideArgs 
   const long long wg = (long long)blockIdx.y * gridDim.x + blockIdx.x;
   block_sums512((1.0 - double(av) - double(bv)) * colsum64, colsum64, A.part + wg,
                 A.part + nwg + wg);
+#undef TRINITY_STAGE_P
+#undef TRINITY_PUT_P
 }
 
 // BF16-split form of collide_f32_stream_kernel: P_hi and P_lo chunks of 32
