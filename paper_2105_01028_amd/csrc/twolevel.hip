@@ -4,7 +4,10 @@
 //   M[J][v] = sum over children i of J of X[i][v]         (coarse_sum_kernel)
 //   T = b (P_c M)            (the resident collide kernel on the coarse field)
 //   Y[i][v] = a_v X[i][v] + T[parent(i)][v] / r^2          (apply_kernel)
-// Both kernels are bound by HBM: each reads the fine field once, with lanes
+// With the phase advance the sweep forms Y as it reads (kernels.hip) and
+// apply_kernel is not used; with the retarded history apply_hop_kernel writes
+// the hop collision of every fine direction into the history instead.  The
+// kernels here are bound by HBM: each reads the fine field once, with lanes
 // running along the voxels of one direction.
 #include <hip/hip_runtime.h>
 
