@@ -203,6 +203,8 @@ def serving(stream, count=16):
         srv = T.Server(nside=4, g=0.85, budget_bytes=32 << 30, max_slots=16)
         sat = serve.run_stream(srv, reqs, chunk_steps=64)
         cap = sum(work) / sat["wall_s"]
+        print(f"serving: {count} requests at the offered rate in {sat['wall_s']:.1f} s",
+              file=sys.stderr, flush=True)
         ts = 200.0 * (sum(work) / count) / (0.8 * cap)
         low = serve.run_stream(srv, reqs, chunk_steps=64, time_scale=ts)
         srv.close()
@@ -523,14 +525,20 @@ def main():
     ap.add_argument("--no-extras", action="store_true")
     ap.add_argument("--workload", default="phantom64",
                     choices=["phantom64", "refraction128", "twolevel64", "retarded64",
-                             "fiducial101"],
+                             "fiducial101", "serving"],
                     help="refraction128, twolevel64, retarded64: only time that medium "
                          "(profiling runs)")
+    ap.add_argument("--serving-requests", type=int, default=16,
+                    help="requests of the serving stream (workload 'serving' or the extra)")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="BYTES",
                     help="only run a plain device copy of BYTES (counter calibration)")
     args = ap.parse_args()
     if args.copy_probe:
         copy_probe(args.copy_probe)
+        return
+    if args.workload == "serving":
+        import torch
+        print(json.dumps(serving(torch.cuda.Stream(), args.serving_requests)), flush=True)
         return
     if args.workload == "fiducial101":
         import torch
@@ -600,7 +608,7 @@ def main():
         p50, p99 = latency(W.config1(), 30, stream)
         out["latency_uniform16"] = {"p50_ms": p50, "p99_ms": p99, "solves": 30,
                                     "workload": "16^3, 48 directions, 200 steps"}
-        out["serving"] = serving(stream)
+        out["serving"] = serving(stream, args.serving_requests)
         out["adjoint"] = adjoint_timing(stream)
         out["refraction128"] = refraction128(stream)
         out["implicit_source"] = implicit_source(stream)
