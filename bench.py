@@ -1,7 +1,7 @@
 """Benchmark of the TRINITY time step on one MI355X.
 
 A step is one pass of the whole hot path (inject, scattering contraction,
-transport sweep, tallies) over the phantom-scale workload: a 64^3 voxel grid
+transport, tallies) over the phantom-scale workload: a 64^3 voxel grid
 with +-5% voxel noise, 192 HEALPix directions (the Sec. 3.1 phantom shape on
 synthetic data).  The metric is voxel x direction x step updates per second,
 with the state resident in HBM.  Kernel durations come from HIP events
@@ -71,7 +71,9 @@ def copy_probe(nbytes):
 
 def kernel_rooflines(prof, prob, precision, workload="phantom64"):
     """Achieved rates of the collide and sweep kernels from their average
-    launch durations and the algorithmic work per launch.
+    launch durations and the algorithmic work per launch.  With the phase
+    moves in the collision kernel there is no sweep kernel: the collide kernel
+    also moves every value to its downwind voxel, within the same 8 N V bytes.
 
     collide, FP32: 2 N^2 V FLOP on the FP32 MFMA peak.  collide, BF16-split:
     the four hi/lo products execute 8 N^2 V bf16 FLOP; at few directions the
@@ -137,6 +139,7 @@ def timed_run(prob, steps, warmup, stream):
     from paper_2105_01028_amd import trinity as T
     with torch.cuda.stream(stream):
         m = T.Medium.from_problem(prob)
+        fused = m.info().moves_fused
         m.solve(warmup)
         # instrumented timed region: HIP events around every kernel
         m.reset()
@@ -161,7 +164,7 @@ def timed_run(prob, steps, warmup, stream):
         m.close()
     inj = budget[:, 0].sum()
     closure = abs(inj - budget[:, 1].sum() - budget[:, 3:].sum() - budget[-1, 2]) / max(inj, 1e-300)
-    return t1 - t0, g1 - g0, prof, closure, det_steps
+    return t1 - t0, g1 - g0, prof, closure, det_steps, fused
 
 
 def latency(prob, solves, stream):
@@ -570,7 +573,7 @@ def main():
     stream = torch.cuda.Stream()
     prob = W.config2().copy(precision=args.precision)
     K, Wm = args.steps, args.warmup
-    el, el_graph, prof, closure, det_steps = timed_run(prob, K, Wm, stream)
+    el, el_graph, prof, closure, det_steps, fused = timed_run(prob, K, Wm, stream)
     updates = prob.nvox * prob.ndir * K
     roof = kernel_rooflines(prof, prob, args.precision)
     dom = max(("collide", "sweep"), key=lambda k: prof[k][0])
@@ -586,7 +589,8 @@ def main():
         "data": "synthetic",
         "config": {"workload": "phantom 64^3, 1 mm voxels, +-5% noise, 192 directions "
                                "(nside 4), phase advance", "grid": [64, 64, 64], "ndir": 192,
-                   "precision": args.precision},
+                   "precision": args.precision,
+                   "transport": "moves in the collision kernel" if fused else "sweep kernel"},
         "roofline": rl,
         "kernels": {k: {"avg_ms": v[0] / v[1] if v[1] else 0.0, "launches": v[1]}
                     for k, v in prof.items()},
@@ -600,11 +604,18 @@ def main():
     }
     if not args.no_extras:
         other = "bf16split" if args.precision == "fp32" else "fp32"
-        e2, g2, p2, c2, d2 = timed_run(prob.copy(precision=other), K, Wm, stream)
+        e2, g2, p2, c2, d2, _ = timed_run(prob.copy(precision=other), K, Wm, stream)
         out[other] = {"value": updates / g2, "ms_per_step": g2 / K * 1e3,
                       "instrumented_value": updates / e2, "kernel_rooflines":
                       kernel_rooflines(p2, prob, other), "budget_closure": c2,
                       "rel_l2_vs_fp64_oracle": oracle_error(prob, d2)}
+        # the same steps with the separate sweep kernel (TR_TRANSPORT_SWEEP)
+        for pr in (args.precision, other):
+            e3, g3, p3, _, _, _ = timed_run(prob.copy(precision=pr, transport="sweep"), K, Wm,
+                                            stream)
+            out["separate_sweep_" + pr] = {
+                "value": updates / g3, "ms_per_step": g3 / K * 1e3,
+                "kernels_ms": {k: v[0] / v[1] for k, v in p3.items() if v[1]}}
         p50, p99 = latency(W.config1(), 30, stream)
         out["latency_uniform16"] = {"p50_ms": p50, "p99_ms": p99, "solves": 30,
                                     "workload": "16^3, 48 directions, 200 steps"}

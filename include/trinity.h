@@ -58,6 +58,7 @@ enum { TR_COEF_PAPER = 0, TR_COEF_ABS_EXACT = 1 };
 enum { TR_ADVANCE_AUTO = 0, TR_ADVANCE_PHASE = 1, TR_ADVANCE_SPLIT = 2, TR_ADVANCE_RETARDED = 3 };
 enum { TR_PREC_FP32 = 0, TR_PREC_BF16SPLIT = 1 };
 enum { TR_SOURCE_EXPLICIT = 0, TR_SOURCE_IMPLICIT = 1 };
+enum { TR_TRANSPORT_AUTO = 0, TR_TRANSPORT_SWEEP = 1 };
 
 typedef struct {
   int nx, ny, nz;     /* voxels per axis, each >= 1 and <= 4096 */
@@ -107,6 +108,12 @@ typedef struct {
                          children, are scattered by the coarse phase matrix, and each
                          child of the target bin gets an equal share.  Needs the
                          explicit source and FP32. */
+  int transport;      /* TR_TRANSPORT_AUTO (0): in phase advance with the explicit source on
+                         one angular grid and at most 192 directions (and both fields
+                         within 2 GiB, each extent <= 1023), the collision kernel moves
+                         each collided value straight to its downwind voxel: one kernel
+                         per step instead of a collision and a sweep, same field values.
+                         TR_TRANSPORT_SWEEP (1): always the separate sweep kernel. */
 } tr_grid_desc;
 
 typedef struct {
@@ -118,6 +125,7 @@ typedef struct {
   long long steps_done;
   size_t device_bytes;  /* device memory the medium holds */
   int history;        /* TR_ADVANCE_RETARDED: collided fields kept (floor(max D_d) + 1); else 0 */
+  int moves_fused;    /* 1 if the collision kernel also does the moves (see transport) */
 } tr_info;
 
 /* ---- medium life cycle ------------------------------------------------- */

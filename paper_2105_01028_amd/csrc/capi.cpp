@@ -57,6 +57,13 @@ struct tr_medium {
   bool tlfused = false;     // two-level phase stepping: the sweep forms the collided value, the
                             // field alternates between X (even steps) and Y (odd steps)
   int nc = 0, NPc = 0, nkids = 0;
+  // phase advance with the moves in the collision kernel (launch_collide_move):
+  // the field alternates between X (even steps) and Y (odd steps); X and Y are
+  // the two halves of one allocation
+  bool mfused = false;
+  int* mvtab = nullptr;
+  int* mvdir = nullptr;
+  int mvext = 0;
   float *M = nullptr, *T = nullptr, *zero = nullptr;
   int *children = nullptr, *parent = nullptr;
   double* cpart2 = nullptr;
@@ -172,7 +179,10 @@ size_t fixed_bytes(const Field& f, int precision, size_t niface_guess) {
   b += size_t(f.ndir) * sizeof(DevDir);
   b += size_t(f.ndir) * 2 * (std::max(f.nx, std::max(f.ny, f.nz)) + 2);
   const int cn = collide_nwg(f, precision), sn = sweep_blocks_per_dir(f) * f.ndir;
-  b += (2 * size_t(cn) + 7 * size_t(sn)) * sizeof(double);
+  b += (2 * size_t(cn) + 7 * size_t(std::max(sn, cn))) * sizeof(double);
+  // move tables of the phase moves in the collision
+  const int S = std::max(f.nx, std::max(f.ny, f.nz));
+  b += (size_t(f.NP + 1) * S * 2 + f.NP) * sizeof(int);
   b += niface_guess * f.ndir * sizeof(float);
   return b;
 }
@@ -220,8 +230,11 @@ tr_status ensure_capacity(tr_medium* m, long long need) {
 }
 
 // The buffer that holds the field after the steps done so far: X, except in
-// two-level phase stepping, where the field alternates and odd steps end in Y.
-float* state_field(tr_medium* m) { return m->tlfused && (m->steps_done & 1) ? m->Y : m->X; }
+// two-level phase stepping and with the moves in the collision, where the
+// field alternates and odd steps end in Y.
+float* state_field(tr_medium* m) {
+  return (m->tlfused || m->mfused) && (m->steps_done & 1) ? m->Y : m->X;
+}
 
 // Event pair around one kernel while timing is active (no-op otherwise).
 struct KernelTimer {
@@ -245,7 +258,7 @@ hipError_t queue_step(tr_medium* m) {
     KernelTimer t(m, TR_K_INJECT);
     InjectArgs ia{m->X,   f.Vp,        m->src_pairs, m->npairs, m->qdev,
                   m->cap, m->step_ctr, m->budget,    m->ddirs,  m->ring != nullptr,
-                  m->tlfused ? m->Y : nullptr};
+                  m->tlfused || m->mfused ? m->Y : nullptr};
     if ((e = launch_inject(ia, m->stream)) != hipSuccess) return e;
   }
   if (m->twolevel) {
@@ -298,6 +311,30 @@ hipError_t queue_step(tr_medium* m) {
     ca.hinvc = m->hinvc;
     ca.hinvD = m->hinvD;
     if ((e = launch_collide_hop(ca, f, m->stream)) != hipSuccess) return e;
+  } else if (m->mfused) {
+    KernelTimer t(m, TR_K_COLLIDE);
+    CollideArgs ca{};
+    ca.Prow = m->Prow;
+    ca.Phi = m->Phi;
+    ca.Plo = m->Plo;
+    ca.a = m->a;
+    ca.b = m->b;
+    ca.Vp = f.Vp;
+    ca.NP = f.NP;
+    ca.part = m->cpart;
+    ca.step_ctr = m->step_ctr;
+    ca.pp = m->X;
+    ca.mvtab = m->mvtab;
+    ca.mvdir = m->mvdir;
+    ca.dirs = m->ddirs;
+    ca.ndir = f.ndir;
+    ca.nx = f.nx;
+    ca.ny = f.ny;
+    ca.nz = f.nz;
+    ca.nvox = f.V;
+    ca.mvext = m->mvext;
+    ca.spart = m->spart;
+    if ((e = launch_collide_move(ca, f, m->desc.precision, m->stream)) != hipSuccess) return e;
   } else {
     KernelTimer t(m, TR_K_COLLIDE);
     CollideArgs ca{m->X,   m->Y, m->P,  m->Prow, m->Phi, m->Plo, m->a,   m->b,
@@ -307,7 +344,7 @@ hipError_t queue_step(tr_medium* m) {
     if (e != hipSuccess) return e;
   }
   const bool split = m->mode == TR_ADVANCE_SPLIT;
-  {
+  if (!m->mfused) {
     KernelTimer t(m, TR_K_SWEEP);
     SweepArgs sa{m->Y, m->X, f.Vp, f.V, f.nx, f.ny, f.nz, m->ddirs, m->delta, m->dstride,
                  m->r, m->iface, m->nvox, m->islot, m->icptF, f.ndir, m->step_ctr, m->spart,
@@ -343,6 +380,12 @@ hipError_t queue_step(tr_medium* m) {
     ra.tlparent = m->parent;
     ra.tla = m->a;
     ra.tlshare = 1.0f / float(m->nkids);
+    ra.pp0 = m->X;
+    ra.pp1 = m->Y;
+  }
+  if (m->mfused) {
+    ra.snwg = m->cnwg;   // the transport partials come from the collision's workgroups
+    ra.mvfused = 1;
     ra.pp0 = m->X;
     ra.pp1 = m->Y;
   }
@@ -501,8 +544,8 @@ tr_status tr_create_medium(const tr_grid_desc* desc, const float* mua, const flo
 
   // ---- device buffers
   const size_t NV = size_t(f.NP) * f.Vp;
-  m->X = m->alloc<float>(NV);
-  m->Y = m->alloc<float>(NV);
+  m->X = m->alloc<float>(2 * NV);
+  m->Y = m->X ? m->X + NV : nullptr;
   m->P = m->alloc<float>(size_t(NPm) * NPm);
   m->Prow = m->alloc<float>(size_t(NPm) * NPm);
   m->a = m->alloc<float>(f.Vp);
@@ -519,7 +562,7 @@ tr_status tr_create_medium(const tr_grid_desc* desc, const float* mua, const flo
   m->sweep_bpd = sweep_blocks_per_dir(f);
   m->snwg = m->sweep_bpd * f.ndir;
   m->cpart = m->alloc<double>(2 * size_t(m->cnwg));
-  m->spart = m->alloc<double>(7 * size_t(m->snwg));
+  m->spart = m->alloc<double>(7 * size_t(std::max(m->snwg, m->cnwg)));
   if (desc->precision == 1) {
     m->Phi = m->alloc<uint16_t>(size_t(f.NP) * f.NP);
     m->Plo = m->alloc<uint16_t>(size_t(f.NP) * f.NP);
@@ -592,6 +635,70 @@ tr_status tr_create_medium(const tr_grid_desc* desc, const float* mua, const flo
   if (e != hipSuccess) {
     delete m;
     return fail(TR_EDEVICE, std::string("upload: ") + hipGetErrorString(e));
+  }
+
+  // ---- phase moves in the collision: per direction and coordinate p along
+  // its dominant axis, the flat offset to the downwind voxel, the faces a voxel
+  // there may leave through (dominant-axis face fa always, the b / c face fb /
+  // fc where the shift into the next plane is not zero) and the faces through
+  // which nothing flows in (the opposite ones, with the shift into the plane)
+  m->mfused = mode == TR_ADVANCE_PHASE && !m->twolevel && desc->source == TR_SOURCE_EXPLICIT &&
+              desc->transport == TR_TRANSPORT_AUTO && use_collide_move(f);
+  if (m->mfused) {
+    const int ext[3] = {f.nx, f.ny, f.nz};
+    const long long st[3] = {1, f.nx, (long long)f.nx * f.ny};
+    const int S = std::max(f.nx, std::max(f.ny, f.nz));
+    std::vector<int> tab(size_t(f.NP + 1) * S * 2, 0), dir(f.NP, 0);
+    auto shift = [&](int d, int q, int k) { return int(dl[(size_t(d) * 2 + q) * m->dstride + k]); };
+    for (int d = 0; d < f.ndir && m->mfused; ++d) {
+      const int a = dd[d].axis, b = dd[d].bax, c = dd[d].cax, sg = dd[d].sign;
+      // the b (c) shifts must be -1, 0 or +1 and of one sign along the ray
+      int sb = 0, sc = 0;
+      for (int k = 1; k < ext[a]; ++k) {
+        const int s0 = shift(d, 0, k), s1 = shift(d, 1, k);
+        if (s0 < -1 || s0 > 1 || s1 < -1 || s1 > 1 || (s0 && sb && s0 != sb) ||
+            (s1 && sc && s1 != sc)) {
+          m->mfused = false;
+          break;
+        }
+        if (s0) sb = s0;
+        if (s1) sc = s1;
+      }
+      const int fa = 2 * a + (sg > 0 ? 1 : 0), fb = 2 * b + (sb > 0 ? 1 : 0),
+                fc = 2 * c + (sc > 0 ? 1 : 0);
+      dir[d] = 10 * a | fa << 8 | fb << 11 | fc << 14;
+      for (int p = 0; p < ext[a]; ++p) {
+        const int k = sg > 0 ? p : ext[a] - 1 - p;
+        unsigned mk = 1u << fa, in = 1u << (fa ^ 1);
+        long long off = 0;
+        if (k + 1 < ext[a]) {
+          const int dbn = shift(d, 0, k + 1), dcn = shift(d, 1, k + 1);
+          if (dbn) mk |= 1u << fb;
+          if (dcn) mk |= 1u << fc;
+          off = sg * st[a] + dbn * st[b] + dcn * st[c];
+        }
+        if (k > 0 && shift(d, 0, k)) in |= 1u << (fb ^ 1);
+        if (k > 0 && shift(d, 1, k)) in |= 1u << (fc ^ 1);
+        tab[(size_t(d) * S + p) * 2] = int(off);
+        tab[(size_t(d) * S + p) * 2 + 1] = int(mk | in << 6);
+      }
+    }
+    if (m->mfused) {
+      m->mvext = S;
+      m->mvtab = m->alloc<int>(tab.size());
+      m->mvdir = m->alloc<int>(dir.size());
+      if (!m->mvtab || !m->mvdir) {
+        delete m;
+        return fail(TR_ENOMEM, "device allocation failed (move tables)");
+      }
+      e = hipMemcpy(m->mvtab, tab.data(), tab.size() * 4, hipMemcpyHostToDevice);
+      if (e == hipSuccess) e = hipMemcpy(m->mvdir, dir.data(), dir.size() * 4, hipMemcpyHostToDevice);
+      if (e == hipSuccess) e = prepare_collide_move(f, desc->precision);
+      if (e != hipSuccess) {
+        delete m;
+        return fail(TR_EDEVICE, std::string("upload: ") + hipGetErrorString(e));
+      }
+    }
   }
 
   // ---- Fresnel interface tables
@@ -1126,7 +1233,8 @@ tr_status tr_solve_checkpointed(tr_medium* m, int nsteps, int ckpt_every) {
   m->ckpt_steps = 0;
   if (!m->ckpt) return fail(TR_ENOMEM, "no device memory for the checkpoints");
   for (int seg = 0; seg < nseg; ++seg) {
-    hipError_t e = hipMemcpyAsync(m->ckpt + NV * seg, m->X, NV * 4, hipMemcpyDeviceToDevice, m->stream);
+    hipError_t e =
+        hipMemcpyAsync(m->ckpt + NV * seg, state_field(m), NV * 4, hipMemcpyDeviceToDevice, m->stream);
     if (e != hipSuccess) return device_fail(m, e, "checkpoint");
     if ((st = tr_step(m, std::min(ckpt_every, nsteps - seg * ckpt_every))) != TR_OK) return st;
   }
@@ -1180,7 +1288,7 @@ tr_status tr_backward(tr_medium* m, const double* dL_dbins, float* dmua, float* 
     cleanup();
     return fail(TR_ENOMEM, "no device memory for the adjoint");
   }
-  e = hipMemcpyAsync(keep, m->X, NV * 4, hipMemcpyDeviceToDevice, m->stream);
+  e = hipMemcpyAsync(keep, state_field(m), NV * 4, hipMemcpyDeviceToDevice, m->stream);
   if (e == hipSuccess) e = hipMemsetAsync(lam, 0, NV * 4, m->stream);
   if (e == hipSuccess) e = hipMemsetAsync(mu, 0, NV * 4, m->stream);
   if (e == hipSuccess) e = hipMemsetAsync(seg, 0, NV * 4 * size_t(K), m->stream);
@@ -1226,7 +1334,7 @@ tr_status tr_backward(tr_medium* m, const double* dL_dbins, float* dmua, float* 
     }
   }
   std::vector<double> hga(f.V), hgb(f.V);
-  if (e == hipSuccess) e = hipMemcpyAsync(m->X, keep, NV * 4, hipMemcpyDeviceToDevice, m->stream);
+  if (e == hipSuccess) e = hipMemcpyAsync(state_field(m), keep, NV * 4, hipMemcpyDeviceToDevice, m->stream);
   if (e == hipSuccess) e = hipStreamSynchronize(m->stream);
   if (e == hipSuccess) {
     const int sd_steps = int(steps);
@@ -1317,6 +1425,7 @@ tr_status tr_get_info(tr_medium* m, tr_info* out) {
   out->steps_done = m->steps_done;
   out->device_bytes = m->bytes;
   out->history = m->H;
+  out->moves_fused = m->mfused ? 1 : 0;
   return TR_OK;
 }
 

@@ -74,6 +74,21 @@ struct CollideArgs {
   const float* omega;
   const float* hinvc;
   const float* hinvD;
+  // phase moves in the collision's epilogue (launch_collide_move; null otherwise):
+  // the field alternates between the two halves of pp ([2][NP][Vp]), step m
+  // reads half m & 1 and writes the other.  mvtab[d][p] (NP + 1 rows of mvext
+  // int pairs, row NP all zero for directions that stay) holds, for a voxel at
+  // coordinate p along d's dominant axis, the flat offset to its downwind voxel
+  // and two face masks: bits 0-5 the faces it may leave through, bits 6-11 the
+  // faces through which nothing flows in (face 2 axis + side, side 1 the high
+  // face); mvdir[d] = 10 axis | fa << 8 | fb << 11 | fc << 14 (exit faces
+  // along a, b, c).  spart: [7][nwg] escape per face and light in the box.
+  float* pp;
+  const int* mvtab;
+  const int* mvdir;
+  const DevDir* dirs;
+  int ndir, nx, ny, nz, nvox, mvext;
+  double* spart;
 };
 
 struct SweepArgs {
@@ -160,6 +175,9 @@ struct ReduceArgs {
   float tlshare;
   const float* pp0;
   const float* pp1;
+  // phase moves in the collision (launch_collide_move): detectors read the
+  // exiting light that the collision left in the field of this step's parity
+  int mvfused;
 };
 
 // One request of the batched server: its argument blocks as the single-medium
@@ -252,6 +270,13 @@ hipError_t launch_sweep_retarded(const SweepArgs& a, const Field& f, int blocks_
 hipError_t launch_sweep_twolevel(const SweepArgs& a, const Field& f, int blocks_per_dir,
                                  hipStream_t s);
 hipError_t launch_collide_implicit(const CollideArgs& a, const Field& f, hipStream_t s);
+// Phase stepping with the moves in the collision's epilogue (the A.pp fields
+// set); needs use_collide_move(f).  Writes the collision partials to A.part
+// ([2][nwg]) and the transport partials to A.spart ([7][nwg]), nwg =
+// collide_nwg(f, bf16split).
+bool use_collide_move(const Field& f);
+hipError_t prepare_collide_move(const Field& f, int bf16split);
+hipError_t launch_collide_move(const CollideArgs& a, const Field& f, int bf16split, hipStream_t s);
 hipError_t prepare_collide_implicit(const Field& f);
 hipError_t prepare_collide(const Field& f, int bf16split);   // once per process and shape
 // fast_split_ok: nx is a multiple of 4 and every direction's b shifts are unit

@@ -165,11 +165,14 @@ __device__ __forceinline__ void load_p_lds(const float* __restrict__ Prow, float
   }
 }
 
-// One 256-column tile (eight wavefronts of 32 columns); adds this thread's share
-// of the tile's budget sums to absorbed and total.
+// One 256-column tile (eight wavefronts of 32 columns) into the accumulators:
+// lane (h, c) of wavefront w holds column 256 tile + 32 w + c and, in acc[q][s],
+// row 32q + 8(s/4) + 4h + s%4.  Adds this thread's share of the tile's budget
+// sums to absorbed and total.
 template <int NP>
-__device__ __forceinline__ void collide_res_tile(const CollideArgs& A, const float* Ps, int tile,
-                                                 double& absorbed, double& total) {
+__device__ __forceinline__ void collide_res_acc(const CollideArgs& A, const float* Ps, int tile,
+                                                floatx16 (&acc)[NP / 32], double& absorbed,
+                                                double& total) {
   constexpr int NQ = NP / 32;
   constexpr int LDK = NP + 4;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -181,7 +184,6 @@ __device__ __forceinline__ void collide_res_tile(const CollideArgs& A, const flo
   const unsigned voff = unsigned(size_t(col) * sizeof(float) + size_t(4 * hl) * rowbytes);
   const char* __restrict__ xb0 = reinterpret_cast<const char*>(A.X);
   const float av = A.a[col], bv = A.b[col];
-  floatx16 acc[NQ];
 #pragma unroll
   for (int q = 0; q < NQ; ++q)
 #pragma unroll
@@ -229,6 +231,19 @@ __device__ __forceinline__ void collide_res_tile(const CollideArgs& A, const flo
 #pragma unroll
     for (int s = 0; s < 16; ++s) bcur[s] = bnext[s];
   }
+  absorbed += (1.0 - double(av) - double(bv)) * colsum64;
+  total += colsum64;
+}
+
+// Stores a tile's accumulators (the layout of collide_res_acc) to Y.
+template <int NQ>
+__device__ __forceinline__ void store_res_tile(const CollideArgs& A, const floatx16 (&acc)[NQ],
+                                               int tile) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int hl = lane >> 5, cl = lane & 31;
+  const size_t rowbytes = size_t(A.Vp) * sizeof(float);
+  const long long col = (long long)tile * 256 + wave * 32 + cl;
+  const unsigned voff = unsigned(size_t(col) * sizeof(float) + size_t(4 * hl) * rowbytes);
   char* __restrict__ yb0 = reinterpret_cast<char*>(A.Y);
 #pragma unroll
   for (int q = 0; q < NQ; ++q)
@@ -236,8 +251,14 @@ __device__ __forceinline__ void collide_res_tile(const CollideArgs& A, const flo
     for (int r = 0; r < 16; ++r)
       *reinterpret_cast<float*>(yb0 + size_t(q * 32 + 8 * (r >> 2) + (r & 3)) * rowbytes + voff) =
           acc[q][r];
-  absorbed += (1.0 - double(av) - double(bv)) * colsum64;
-  total += colsum64;
+}
+
+template <int NP>
+__device__ __forceinline__ void collide_res_tile(const CollideArgs& A, const float* Ps, int tile,
+                                                 double& absorbed, double& total) {
+  floatx16 acc[NP / 32];
+  collide_res_acc<NP>(A, Ps, tile, acc, absorbed, total);
+  store_res_tile<NP / 32>(A, acc, tile);
 }
 
 // Sums of two doubles over a 512-thread workgroup, written by thread 0 and 1.
@@ -417,9 +438,10 @@ __device__ __forceinline__ void load_p_bf16_lds(const uint16_t* __restrict__ Phi
 }
 
 template <int NP>
-__device__ __forceinline__ void collide_bf16_res_tile(const CollideArgs& A,
-                                                      const uint16_t* Sh, const uint16_t* Sl,
-                                                      int tile, double& absorbed, double& total) {
+__device__ __forceinline__ void collide_bf16_res_acc(const CollideArgs& A, const uint16_t* Sh,
+                                                     const uint16_t* Sl, int tile,
+                                                     floatx16 (&acc)[NP / 32], double& absorbed,
+                                                     double& total) {
   constexpr int NQ = NP / 32;
   constexpr int LDK = NP + 8;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -431,7 +453,6 @@ __device__ __forceinline__ void collide_bf16_res_tile(const CollideArgs& A,
   const uint16_t* __restrict__ Ph = Sh + cl * LDK + 8 * hl;
   const uint16_t* __restrict__ Pl = Sl + cl * LDK + 8 * hl;
   const float av = A.a[col], bv = A.b[col];
-  floatx16 acc[NQ];
 #pragma unroll
   for (int q = 0; q < NQ; ++q)
 #pragma unroll
@@ -483,15 +504,17 @@ __device__ __forceinline__ void collide_bf16_res_tile(const CollideArgs& A,
 #pragma unroll
     for (int s = 0; s < 16; ++s) bcur[s] = bnext[s];
   }
-  char* __restrict__ yb0 = reinterpret_cast<char*>(A.Y);
-#pragma unroll
-  for (int q = 0; q < NQ; ++q)
-#pragma unroll
-    for (int r = 0; r < 16; ++r)
-      *reinterpret_cast<float*>(yb0 + size_t(q * 32 + 8 * (r >> 2) + (r & 3)) * rowbytes + voff) =
-          acc[q][r];
   absorbed += (1.0 - double(av) - double(bv)) * colsum64;
   total += colsum64;
+}
+
+template <int NP>
+__device__ __forceinline__ void collide_bf16_res_tile(const CollideArgs& A, const uint16_t* Sh,
+                                                      const uint16_t* Sl, int tile,
+                                                      double& absorbed, double& total) {
+  floatx16 acc[NP / 32];
+  collide_bf16_res_acc<NP>(A, Sh, Sl, tile, acc, absorbed, total);
+  store_res_tile<NP / 32>(A, acc, tile);
 }
 
 template <int NP>
@@ -506,6 +529,191 @@ __global__ __launch_bounds__(512, 1) void collide_bf16_res_kernel(CollideArgs A,
   for (int tile = blockIdx.x; tile < ntiles; tile += gridDim.x)
     collide_bf16_res_tile<NP>(A, Sh, Sl, tile, absorbed, total);
   block_sums512(absorbed, total, A.part + blockIdx.x, A.part + gridDim.x + blockIdx.x);
+}
+
+// ---------------------------------------------------------------------------
+// Phase stepping with the moves in the collision's epilogue.  In phase mode a
+// direction either stays this step (the collided value is the new value) or
+// moves all its photons one plane along its characteristic (Sec. 2.1, the ray
+// lattice), so the transport is a permutation of the collided field plus the
+// light that leaves the box.  After the MFMA main loop a lane holds the
+// collided values of its voxel for 16 rows per row block; it writes each one
+// straight to the downwind voxel in the other field, and the collided field is
+// never stored and read back.
+//   * The moves of a direction are one-to-one (the transverse shift at a plane
+//     is the same for the whole plane): a destination gets one value or none,
+//     and a voxel with no upwind voxel in the box gets a zero from its own lane.
+//   * Light leaves and inflow is missing only at voxels on the box surface.  A
+//     voxel on one face sends all its leaving light through that face, so one
+//     FP32 sum per lane suffices; a wavefront holding an edge voxel (two or
+//     more faces) applies the sweep's precedence (dominant axis, then b, then c)
+//     value by value.
+//   * A value that leaves is written over the lane's own column of the input
+//     field, which no other workgroup reads; the detectors read it there.
+
+struct MoveLane {
+  unsigned P;    // x | y << 10 | z << 20
+  unsigned LF;   // faces the voxel lies on (bit 2 axis + side); all six on padding columns
+};
+
+__device__ __forceinline__ MoveLane move_lane(const CollideArgs& A, long long col) {
+  MoveLane L{0u, 0x3Fu};
+  if (col < A.nvox) {
+    const int nxy = A.nx * A.ny;
+    const int v = int(col);
+    const int z = v / nxy, rem = v - z * nxy;
+    const int y = rem / A.nx, x = rem - y * A.nx;
+    L.P = unsigned(x) | unsigned(y) << 10 | unsigned(z) << 20;
+    L.LF = unsigned(x == 0) | unsigned(x == A.nx - 1) << 1 | unsigned(y == 0) << 2 |
+           unsigned(y == A.ny - 1) << 3 | unsigned(z == 0) << 4 | unsigned(z == A.nz - 1) << 5;
+  }
+  return L;
+}
+
+// Buffer resource over `bytes` bytes at p (gfx9 layout: raw, no stride).  A
+// buffer store whose offset is at or beyond `bytes` is dropped by the hardware.
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t raw_rsrc(const void* p, unsigned bytes) {
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(p), 0, int(bytes), 0x00020000);
+}
+constexpr unsigned kDropOffset = 0x80000000u;   // above every resource made here
+
+// The scatter of one tile's accumulators (the layout of collide_res_acc).
+// fld: both fields; ssv / dsv: byte offsets of the lane's column in this
+// step's input and output halves (with the lane half's 4-row shift).  Adds
+// this lane's escape per face and light in the box.
+template <int NQ, bool EDGE>
+__device__ __forceinline__ void move_tile(const int2* sdesc, __amdgpu_buffer_rsrc_t tab,
+                                          __amdgpu_buffer_rsrc_t fld, const floatx16 (&acc)[NQ],
+                                          const MoveLane& L, unsigned ssv, unsigned dsv,
+                                          unsigned rowbytes, int hl, double (&esc)[6],
+                                          double& dom) {
+  const unsigned LF6 = L.LF << 6;
+  double lesc = 0.0;
+#pragma unroll
+  for (int q = 0; q < NQ; ++q) {
+    float fdom = 0.0f, fesc = 0.0f;
+    float fe6[6] = {0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+    for (int r0 = 0; r0 < 16; r0 += 8) {
+      int w[8][2];
+#pragma unroll
+      for (int j = 0; j < 8; ++j) {
+        const int r = r0 + j;
+        const int2 dsc = sdesc[q * 32 + 8 * (r >> 2) + (r & 3) + 4 * hl];
+        const unsigned p = __builtin_amdgcn_ubfe(L.P, unsigned(dsc.y) & 31u, 10u);
+        const auto t =
+            __builtin_amdgcn_raw_buffer_load_b64(tab, int(unsigned(dsc.x) + (p << 3)), 0, 0);
+        w[j][0] = int(t[0]);
+        w[j][1] = int(t[1]);
+      }
+#pragma unroll
+      for (int j = 0; j < 8; ++j) {
+        const int r = r0 + j;
+        const float val = acc[q][r];
+        const unsigned mk = unsigned(w[j][1]);
+        const unsigned hits = mk & L.LF;
+        const bool ex = hits != 0u;
+        const unsigned ro = unsigned(32 * q + 8 * (r >> 2) + (r & 3)) * rowbytes;
+        const unsigned vo = ro + (ex ? ssv : dsv + 4u * unsigned(w[j][0]));
+        __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(val), fld, int(vo), 0, 0);
+        const unsigned zo = (mk & LF6) ? ro + dsv : kDropOffset;
+        __builtin_amdgcn_raw_buffer_store_b32(0u, fld, int(zo), 0, 0);
+        const float e = ex ? val : 0.0f;
+        fdom += val - e;
+        if (EDGE) {
+          const unsigned dy = unsigned(sdesc[q * 32 + 8 * (r >> 2) + (r & 3) + 4 * hl].y);
+          const unsigned fa = (dy >> 8) & 7u, fb = (dy >> 11) & 7u, fc = (dy >> 14) & 7u;
+          const unsigned f = ((hits >> fa) & 1u) ? fa : (((hits >> fb) & 1u) ? fb : fc);
+#pragma unroll
+          for (int i = 0; i < 6; ++i) fe6[i] += f == unsigned(i) ? e : 0.0f;
+        } else {
+          fesc += e;
+        }
+      }
+    }
+    dom += double(fdom);
+    if (EDGE) {
+#pragma unroll
+      for (int i = 0; i < 6; ++i) esc[i] += double(fe6[i]);
+    } else {
+      lesc += double(fesc);
+    }
+  }
+  if (!EDGE) {
+    // at most one face: all of this lane's leaving light went through it
+    const int face = L.LF ? __builtin_ctz(L.LF) : 6;
+#pragma unroll
+    for (int i = 0; i < 6; ++i) esc[i] += face == i ? lesc : 0.0;
+  }
+}
+
+// P resident in LDS (FP32, or the bf16 hi/lo pair), then per step direction
+// descriptors (table row, coordinate shift and exit faces) after it.
+template <int NP, bool BF16>
+__global__ __launch_bounds__(512, 1) void collide_move_kernel(CollideArgs A, int ntiles) {
+  extern __shared__ float Pm[];
+  constexpr size_t kPB = BF16 ? 2 * size_t(NP) * (NP + 8) * sizeof(uint16_t)
+                              : size_t(NP) * (NP + 4) * sizeof(float);
+  int2* sdesc = reinterpret_cast<int2*>(reinterpret_cast<char*>(Pm) + kPB);
+  uint16_t* Sh = reinterpret_cast<uint16_t*>(Pm);
+  uint16_t* Sl = Sh + NP * (NP + 8);
+  if (BF16)
+    load_p_bf16_lds<NP>(A.Phi, A.Plo, Sh, Sl);
+  else
+    load_p_lds<NP>(A.Prow, Pm);
+  const int m = *A.step_ctr;
+  for (int d = threadIdx.x; d < NP; d += 512) {
+    const bool mv = d < A.ndir && phase_move(A.dirs[d].nu64, m) != 0.0f;
+    sdesc[d] = make_int2((mv ? d : NP) * A.mvext * 8, A.mvdir[d]);
+  }
+  __syncthreads();
+  const size_t half = size_t(NP) * size_t(A.Vp) * sizeof(float);
+  const unsigned so = (m & 1) ? unsigned(half) : 0u;
+  const unsigned dso = (m & 1) ? 0u : unsigned(half);
+  const __amdgpu_buffer_rsrc_t fld = raw_rsrc(A.pp, unsigned(2 * half));
+  const __amdgpu_buffer_rsrc_t tab =
+      raw_rsrc(A.mvtab, unsigned(size_t(NP + 1) * size_t(A.mvext) * 2 * sizeof(int)));
+  CollideArgs B = A;
+  B.X = reinterpret_cast<const float*>(reinterpret_cast<const char*>(A.pp) + so);
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int hl = lane >> 5, cl = lane & 31;
+  const size_t rowbytes = size_t(A.Vp) * sizeof(float);
+  double absorbed = 0.0, total = 0.0, dom = 0.0;
+  double esc[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+#pragma unroll 1
+  for (int tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+    floatx16 acc[NP / 32];
+    if (BF16)
+      collide_bf16_res_acc<NP>(B, Sh, Sl, tile, acc, absorbed, total);
+    else
+      collide_res_acc<NP>(B, Pm, tile, acc, absorbed, total);
+    const long long col = (long long)tile * 256 + wave * 32 + cl;
+    const unsigned voff = unsigned(size_t(col) * sizeof(float) + size_t(4 * hl) * rowbytes);
+    const MoveLane L = move_lane(A, col);
+    if (__any(__builtin_popcount(L.LF) > 1))
+      move_tile<NP / 32, true>(sdesc, tab, fld, acc, L, so + voff, dso + voff, unsigned(rowbytes),
+                               hl, esc, dom);
+    else
+      move_tile<NP / 32, false>(sdesc, tab, fld, acc, L, so + voff, dso + voff, unsigned(rowbytes),
+                                hl, esc, dom);
+  }
+  // workgroup sums: absorbed, total -> part; escape per face, in the box -> spart
+  __shared__ double red9[9][8];
+  const double v9[9] = {absorbed, total, esc[0], esc[1], esc[2], esc[3], esc[4], esc[5], dom};
+#pragma unroll
+  for (int i = 0; i < 9; ++i) {
+    const double t = wave_sum(v9[i]);
+    if (lane == 0) red9[i][wave] = t;
+  }
+  __syncthreads();
+  if (threadIdx.x < 9) {
+    double t = 0.0;
+    for (int w = 0; w < 8; ++w) t += red9[threadIdx.x][w];
+    const int i = threadIdx.x;
+    double* o = i < 2 ? A.part + (long long)i * gridDim.x + blockIdx.x
+                      : A.spart + (long long)(i < 8 ? i - 2 : 6) * gridDim.x + blockIdx.x;
+    *o = t;
+  }
 }
 
 // More directions than fit in LDS (NP > 192): the layout of the resident kernel
@@ -1904,8 +2112,11 @@ __device__ __forceinline__ void reduce_part(const ReduceArgs& A, int q, int nq) 
                               A.tlshare};
           sd += double(phase_move(D.nu64, m) * Y[v]);
         } else {
+          // with the moves in the collision, the light that left is in the
+          // input field of this step, at the voxel it left from
+          const float* Y = A.mvfused ? ((m & 1) ? A.pp1 : A.pp0) : A.Y;
           const float f = A.split ? D.nu * A.r[v] : phase_move(D.nu64, m);
-          sd += double(f * A.Y[size_t(d) * A.Vp + v]);
+          sd += double(f * Y[size_t(d) * A.Vp + v]);
         }
       }
       if (ok) A.det_steps[size_t(k) * A.cap + m] = sd;
@@ -2282,6 +2493,65 @@ hipError_t launch_collide(const CollideArgs& a, const Field& f, int bf16split, i
     case 96: return launch_collide_mt<96>(a, f, bf16split, s);
     case 64: return launch_collide_mt<64>(a, f, bf16split, s);
     default: return launch_collide_mt<32>(a, f, bf16split, s);
+  }
+}
+
+namespace {
+template <int NP>
+const void* move_kernel(int bf16split) {
+  return bf16split ? reinterpret_cast<const void*>(&collide_move_kernel<NP, true>)
+                   : reinterpret_cast<const void*>(&collide_move_kernel<NP, false>);
+}
+template <int NP>
+size_t move_lds(int bf16split) {
+  return res_lds<NP>(bf16split) + size_t(NP) * sizeof(int2);
+}
+template <int NP>
+hipError_t prepare_move_np(int bf16split) {
+  return hipFuncSetAttribute(move_kernel<NP>(bf16split),
+                             hipFuncAttributeMaxDynamicSharedMemorySize, int(move_lds<NP>(bf16split)));
+}
+template <int NP>
+hipError_t launch_move_np(const CollideArgs& a, const Field& f, int bf16split, hipStream_t s) {
+  const int ntiles = int(f.Vp / 256);
+  const int nb = ntiles < resident_blocks() ? ntiles : resident_blocks();
+  if (bf16split)
+    hipLaunchKernelGGL((collide_move_kernel<NP, true>), dim3(unsigned(nb)), dim3(512),
+                       move_lds<NP>(bf16split), s, a, ntiles);
+  else
+    hipLaunchKernelGGL((collide_move_kernel<NP, false>), dim3(unsigned(nb)), dim3(512),
+                       move_lds<NP>(bf16split), s, a, ntiles);
+  return hipGetLastError();
+}
+}  // namespace
+
+// The epilogue addresses both fields through one buffer resource, with 32-bit
+// offsets below the drop offset 2^31.
+bool use_collide_move(const Field& f) {
+  return use_resident(f, 0) && (long long)(2 * f.NP + 32) * f.Vp * 4 < (1LL << 31) && f.nx <= 1023 &&
+         f.ny <= 1023 && f.nz <= 1023;
+}
+
+hipError_t prepare_collide_move(const Field& f, int bf16split) {
+  switch (f.NP) {
+    case 32: return prepare_move_np<32>(bf16split);
+    case 64: return prepare_move_np<64>(bf16split);
+    case 96: return prepare_move_np<96>(bf16split);
+    case 128: return prepare_move_np<128>(bf16split);
+    case 160: return prepare_move_np<160>(bf16split);
+    default: return prepare_move_np<192>(bf16split);
+  }
+}
+
+hipError_t launch_collide_move(const CollideArgs& a, const Field& f, int bf16split, hipStream_t s) {
+  if (!use_collide_move(f)) return hipErrorInvalidValue;
+  switch (f.NP) {
+    case 32: return launch_move_np<32>(a, f, bf16split, s);
+    case 64: return launch_move_np<64>(a, f, bf16split, s);
+    case 96: return launch_move_np<96>(a, f, bf16split, s);
+    case 128: return launch_move_np<128>(a, f, bf16split, s);
+    case 160: return launch_move_np<160>(a, f, bf16split, s);
+    default: return launch_move_np<192>(a, f, bf16split, s);
   }
 }
 

@@ -23,6 +23,7 @@ COEF = {"paper": 0, "abs_exact": 1}
 ADVANCE = {"auto": 0, "phase": 1, "split": 2, "retarded": 3}
 PRECISION = {"fp32": 0, "bf16split": 1}
 SOURCE = {"explicit": 0, "implicit": 1}
+TRANSPORT = {"auto": 0, "sweep": 1}
 MODE_NAMES = {1: "phase", 2: "split"}
 BUDGET_FIELDS = ("injected", "absorbed", "in_domain", "esc0", "esc1", "esc2", "esc3", "esc4",
                  "esc5")
@@ -39,14 +40,14 @@ class GridDesc(ctypes.Structure):
                 ("dx_mm", ctypes.c_double), ("nside", ctypes.c_int), ("g", ctypes.c_double),
                 ("dt_ps", ctypes.c_double), ("hg_norm", ctypes.c_int), ("coef", ctypes.c_int),
                 ("advance", ctypes.c_int), ("precision", ctypes.c_int), ("source", ctypes.c_int),
-                ("nside_scatter", ctypes.c_int)]
+                ("nside_scatter", ctypes.c_int), ("transport", ctypes.c_int)]
 
 
 class Info(ctypes.Structure):
     _fields_ = [("ndir", ctypes.c_int), ("nvox", ctypes.c_int), ("mode", ctypes.c_int),
                 ("ninterceptions", ctypes.c_int), ("dt_ps", ctypes.c_double),
                 ("steps_done", ctypes.c_longlong), ("device_bytes", ctypes.c_size_t),
-                ("history", ctypes.c_int)]
+                ("history", ctypes.c_int), ("moves_fused", ctypes.c_int)]
 
 
 class ServerDesc(ctypes.Structure):
@@ -165,7 +166,8 @@ def grid_desc(prob) -> GridDesc:
     return GridDesc(prob.nx, prob.ny, prob.nz, float(prob.dx_mm), int(prob.nside), float(prob.g),
                     float(prob.dt_ps), HG[prob.hg_norm], COEF[prob.coef], ADVANCE[prob.advance],
                     PRECISION[prob.precision], SOURCE[getattr(prob, "source", "explicit")],
-                    int(getattr(prob, "nside_scatter", 0)))
+                    int(getattr(prob, "nside_scatter", 0)),
+                    TRANSPORT[getattr(prob, "transport", "auto")])
 
 
 def current_stream() -> int:

@@ -46,6 +46,8 @@ class Problem:
     source: str = "explicit"    # "explicit" | "implicit" (S1 from the new intensity, Eq. 9-10)
     nside_scatter: int = 0      # 0: scatter on the transport directions; else a coarser
                                 # HEALPix grid (nside / nside_scatter a power of two)
+    transport: str = "auto"     # "auto": phase moves in the collision kernel where it
+                                # applies | "sweep": always the separate sweep kernel
     src_ix: int = 0
     src_iy: int = 0
     src_w: int = 2           # 1 = one top-face voxel, 2 = the 2x2 block at (ix..ix+1, iy..iy+1)

@@ -102,6 +102,11 @@ def test_interceptions_match_oracle():
 
 def test_invalid_descriptor_is_rejected():
     p = W.small_problem()
+    assert T.bytes_required(T.grid_desc(p)) > 0
+    assert T.bytes_required(T.grid_desc(p.copy(transport="sweep"))) > 0
+    bad = T.grid_desc(p)
+    bad.transport = 2
+    assert T.bytes_required(bad) == 0
     bad = T.grid_desc(p)
     bad.nside = 0
     assert T.bytes_required(bad) == 0
