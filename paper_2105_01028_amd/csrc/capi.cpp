@@ -64,6 +64,7 @@ struct tr_medium {
   int* mvtab = nullptr;
   int* mvdir = nullptr;
   int mvext = 0;
+  int mvscramble = 1;
   float *M = nullptr, *T = nullptr, *zero = nullptr;
   int *children = nullptr, *parent = nullptr;
   double* cpart2 = nullptr;
@@ -333,6 +334,7 @@ hipError_t queue_step(tr_medium* m) {
     ca.nz = f.nz;
     ca.nvox = f.V;
     ca.mvext = m->mvext;
+    ca.mvscramble = m->mvscramble;
     ca.spart = m->spart;
     if ((e = launch_collide_move(ca, f, m->desc.precision, m->stream)) != hipSuccess) return e;
   } else {
@@ -666,7 +668,7 @@ tr_status tr_create_medium(const tr_grid_desc* desc, const float* mua, const flo
       }
       const int fa = 2 * a + (sg > 0 ? 1 : 0), fb = 2 * b + (sb > 0 ? 1 : 0),
                 fc = 2 * c + (sc > 0 ? 1 : 0);
-      dir[d] = 10 * a | fa << 8 | fb << 11 | fc << 14;
+      dir[d] = 10 * a | (3 << (2 * a)) << 8;
       for (int p = 0; p < ext[a]; ++p) {
         const int k = sg > 0 ? p : ext[a] - 1 - p;
         unsigned mk = 1u << fa, in = 1u << (fa ^ 1);
@@ -685,6 +687,14 @@ tr_status tr_create_medium(const tr_grid_desc* desc, const float* mua, const flo
     }
     if (m->mfused) {
       m->mvext = S;
+      // tile order multiplier: the first of these primes that does not divide ntiles
+      const long long ntiles = f.Vp / 256;
+      for (int pr : {257, 263, 269, 271}) {
+        if (ntiles % pr != 0) {
+          m->mvscramble = pr;
+          break;
+        }
+      }
       m->mvtab = m->alloc<int>(tab.size());
       m->mvdir = m->alloc<int>(dir.size());
       if (!m->mvtab || !m->mvdir) {

@@ -81,13 +81,15 @@ struct CollideArgs {
   // coordinate p along d's dominant axis, the flat offset to its downwind voxel
   // and two face masks: bits 0-5 the faces it may leave through, bits 6-11 the
   // faces through which nothing flows in (face 2 axis + side, side 1 the high
-  // face); mvdir[d] = 10 axis | fa << 8 | fb << 11 | fc << 14 (exit faces
-  // along a, b, c).  spart: [7][nwg] escape per face and light in the box.
+  // face); mvdir[d] = 10 axis | 3 << (2 axis + 8) (the coordinate's shift in
+  // a packed x | y << 10 | z << 20, and both faces of the dominant axis).
+  // spart: [7][nwg] escape per face and light in the box.
   float* pp;
   const int* mvtab;
   const int* mvdir;
   const DevDir* dirs;
   int ndir, nx, ny, nz, nvox, mvext;
+  int mvscramble;          // tile order multiplier, prime to the number of 256-voxel tiles
   double* spart;
 };
 

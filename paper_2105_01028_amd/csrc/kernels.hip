@@ -621,9 +621,11 @@ __device__ __forceinline__ void move_tile(const int2* sdesc, __amdgpu_buffer_rsr
         const float e = ex ? val : 0.0f;
         fdom += val - e;
         if (EDGE) {
+          // the sweep's precedence: the dominant-axis face, else the face on the
+          // lowest axis hit (b < c); hits holds one face per axis at most
           const unsigned dy = unsigned(sdesc[q * 32 + 8 * (r >> 2) + (r & 3) + 4 * hl].y);
-          const unsigned fa = (dy >> 8) & 7u, fb = (dy >> 11) & 7u, fc = (dy >> 14) & 7u;
-          const unsigned f = ((hits >> fa) & 1u) ? fa : (((hits >> fb) & 1u) ? fb : fc);
+          const unsigned ha = hits & (dy >> 8);
+          const unsigned f = unsigned(__builtin_ctz((ha ? ha : hits) | 64u));
 #pragma unroll
           for (int i = 0; i < 6; ++i) fe6[i] += f == unsigned(i) ? e : 0.0f;
         } else {
@@ -648,7 +650,7 @@ __device__ __forceinline__ void move_tile(const int2* sdesc, __amdgpu_buffer_rsr
 }
 
 // P resident in LDS (FP32, or the bf16 hi/lo pair), then per step direction
-// descriptors (table row, coordinate shift and exit faces) after it.
+// descriptors (table row, coordinate shift, dominant-axis faces) after it.
 template <int NP, bool BF16>
 __global__ __launch_bounds__(512, 1) void collide_move_kernel(CollideArgs A, int ntiles) {
   extern __shared__ float Pm[];
@@ -680,8 +682,16 @@ __global__ __launch_bounds__(512, 1) void collide_move_kernel(CollideArgs A, int
   const size_t rowbytes = size_t(A.Vp) * sizeof(float);
   double absorbed = 0.0, total = 0.0, dom = 0.0;
   double esc[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+  // a contiguous range of s per workgroup, tile = s * A.mvscramble mod ntiles
+  // (a bijection: the multiplier is prime to ntiles), so that the tiles holding
+  // edges of the box, which take the per-value face precedence, are spread
+  // over the workgroups instead of recurring on the same ones
+  const int per = (ntiles + int(gridDim.x) - 1) / int(gridDim.x);
 #pragma unroll 1
-  for (int tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+  for (int i = 0; i < per; ++i) {
+    const int s = int(blockIdx.x) * per + i;
+    if (s >= ntiles) break;
+    const int tile = int((long long)s * A.mvscramble % ntiles);
     floatx16 acc[NP / 32];
     if (BF16)
       collide_bf16_res_acc<NP>(B, Sh, Sl, tile, acc, absorbed, total);

@@ -73,7 +73,9 @@ def test_moves_in_collision_equal_separate_sweep(nside, precision, shape, steps)
     assert np.array_equal(a["det"], b["det"])
     ba, bb = a["budget"], b["budget"]
     scale = ba[:, 2].max()
-    assert np.array_equal(ba[:, :2], bb[:, :2])              # injected, absorbed
+    assert np.array_equal(ba[:, 0], bb[:, 0])                # injected
+    # absorbed: the same per-tile FP64 partials, summed in another tile order
+    assert np.allclose(ba[:, 1], bb[:, 1], rtol=1e-12, atol=1e-15 * ba[:, 1].max())
     # in box, escape: the collision kernel sums 16 values per lane in FP32 before
     # FP64, each partial within 15 * 2^-24 < 1e-6 of itself; the sweep sums in FP64
     assert np.allclose(ba[:, 2:], bb[:, 2:], rtol=1e-6, atol=1e-12 * scale)
