@@ -524,6 +524,8 @@ def main():
     ap.add_argument("--steps", type=int, default=1000)
     ap.add_argument("--warmup", type=int, default=50)
     ap.add_argument("--precision", default="fp32", choices=["fp32", "bf16split"])
+    ap.add_argument("--transport", default="auto", choices=["auto", "sweep"],
+                    help="auto: phase moves in the collision kernel; sweep: separate sweep kernel")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true")
     ap.add_argument("--workload", default="phantom64",
@@ -571,11 +573,11 @@ def main():
     from paper_2105_01028_amd import workloads as W
     assert torch.cuda.is_available(), "bench.py needs the GPU"
     stream = torch.cuda.Stream()
-    prob = W.config2().copy(precision=args.precision)
+    prob = W.config2().copy(precision=args.precision, transport=args.transport)
     K, Wm = args.steps, args.warmup
     el, el_graph, prof, closure, det_steps, fused = timed_run(prob, K, Wm, stream)
     updates = prob.nvox * prob.ndir * K
-    roof = kernel_rooflines(prof, prob, args.precision)
+    roof = kernel_rooflines(prof, prob, args.precision, "phantom64" if fused else "phantom64-sweep")
     dom = max(("collide", "sweep"), key=lambda k: prof[k][0])
     rl = dict(roof[dom])
     rl["kernel"] = dom
@@ -606,6 +608,7 @@ def main():
         other = "bf16split" if args.precision == "fp32" else "fp32"
         e2, g2, p2, c2, d2, _ = timed_run(prob.copy(precision=other), K, Wm, stream)
         out[other] = {"value": updates / g2, "ms_per_step": g2 / K * 1e3,
+                      "kernels_ms": {k: v[0] / v[1] for k, v in p2.items() if v[1]},
                       "instrumented_value": updates / e2, "kernel_rooflines":
                       kernel_rooflines(p2, prob, other), "budget_closure": c2,
                       "rel_l2_vs_fp64_oracle": oracle_error(prob, d2)}
