@@ -65,6 +65,7 @@ struct tr_medium {
   int* mvdir = nullptr;
   int mvext = 0;
   int mvscramble = 1;
+  unsigned* mvdet = nullptr;   // bit per voxel column: a detector's voxel
   float *M = nullptr, *T = nullptr, *zero = nullptr;
   int *children = nullptr, *parent = nullptr;
   double* cpart2 = nullptr;
@@ -181,9 +182,9 @@ size_t fixed_bytes(const Field& f, int precision, size_t niface_guess) {
   b += size_t(f.ndir) * 2 * (std::max(f.nx, std::max(f.ny, f.nz)) + 2);
   const int cn = collide_nwg(f, precision), sn = sweep_blocks_per_dir(f) * f.ndir;
   b += (2 * size_t(cn) + 7 * size_t(std::max(sn, cn))) * sizeof(double);
-  // move tables of the phase moves in the collision
+  // move tables and detector bitmap of the phase moves in the collision
   const int S = std::max(f.nx, std::max(f.ny, f.nz));
-  b += (size_t(f.NP + 1) * S * 2 + f.NP) * sizeof(int);
+  b += (size_t(f.NP + 1) * S * 2 + f.NP) * sizeof(int) + size_t(f.Vp / 32) * 4;
   b += niface_guess * f.ndir * sizeof(float);
   return b;
 }
@@ -335,6 +336,7 @@ hipError_t queue_step(tr_medium* m) {
     ca.nvox = f.V;
     ca.mvext = m->mvext;
     ca.mvscramble = m->mvscramble;
+    ca.mvdet = m->mvdet;
     ca.spart = m->spart;
     if ((e = launch_collide_move(ca, f, m->desc.precision, m->stream)) != hipSuccess) return e;
   } else {
@@ -418,6 +420,11 @@ tr_status upload_detector_pairs(tr_medium* m, const std::vector<std::vector<int>
   hipError_t e = hipMemcpy(dp, pairs.data(), pairs.size() * sizeof(int), hipMemcpyHostToDevice);
   if (e == hipSuccess) e = hipMemcpy(df, first.data(), first.size() * sizeof(int), hipMemcpyHostToDevice);
   if (e == hipSuccess) e = hipMemcpy(dv, m->det_vox.data(), m->ndet * sizeof(int), hipMemcpyHostToDevice);
+  if (e == hipSuccess && m->mvdet) {
+    std::vector<unsigned> bits(size_t(m->f.Vp / 32), 0u);
+    for (int v : m->det_vox) bits[size_t(v) >> 5] |= 1u << (v & 31);
+    e = hipMemcpy(m->mvdet, bits.data(), bits.size() * 4, hipMemcpyHostToDevice);
+  }
   if (e != hipSuccess) return device_fail(m, e, "detector upload");
   m->det_pairs = dp;
   m->det_first = df;
@@ -697,12 +704,14 @@ tr_status tr_create_medium(const tr_grid_desc* desc, const float* mua, const flo
       }
       m->mvtab = m->alloc<int>(tab.size());
       m->mvdir = m->alloc<int>(dir.size());
-      if (!m->mvtab || !m->mvdir) {
+      m->mvdet = m->alloc<unsigned>(size_t(f.Vp / 32));
+      if (!m->mvtab || !m->mvdir || !m->mvdet) {
         delete m;
         return fail(TR_ENOMEM, "device allocation failed (move tables)");
       }
       e = hipMemcpy(m->mvtab, tab.data(), tab.size() * 4, hipMemcpyHostToDevice);
       if (e == hipSuccess) e = hipMemcpy(m->mvdir, dir.data(), dir.size() * 4, hipMemcpyHostToDevice);
+      if (e == hipSuccess) e = hipMemset(m->mvdet, 0, size_t(f.Vp / 32) * 4);
       if (e == hipSuccess) e = prepare_collide_move(f, desc->precision);
       if (e != hipSuccess) {
         delete m;

@@ -90,6 +90,8 @@ struct CollideArgs {
   const DevDir* dirs;
   int ndir, nx, ny, nz, nvox, mvext;
   int mvscramble;          // tile order multiplier, prime to the number of 256-voxel tiles
+  const unsigned* mvdet;   // bit per voxel column: a detector's voxel (light that leaves
+                           // there is kept for the read-out; elsewhere it is only tallied)
   double* spart;
 };
 

@@ -548,8 +548,9 @@ __global__ __launch_bounds__(512, 1) void collide_bf16_res_kernel(CollideArgs A,
 //     FP32 sum per lane suffices; a wavefront holding an edge voxel (two or
 //     more faces) applies the sweep's precedence (dominant axis, then b, then c)
 //     value by value.
-//   * A value that leaves is written over the lane's own column of the input
-//     field, which no other workgroup reads; the detectors read it there.
+//   * A value that leaves a detector's voxel is written over the lane's own
+//     column of the input field, which no other workgroup reads; the
+//     detectors read it there.  Elsewhere leaving light is only tallied.
 
 struct MoveLane {
   unsigned P;    // x | y << 10 | z << 20
@@ -579,7 +580,8 @@ constexpr unsigned kDropOffset = 0x80000000u;   // above every resource made her
 
 // The scatter of one tile's accumulators (the layout of collide_res_acc).
 // fld: both fields; ssv / dsv: byte offsets of the lane's column in this
-// step's input and output halves (with the lane half's 4-row shift).  Adds
+// step's input and output halves (with the lane half's 4-row shift; ssv the
+// drop offset where leaving light is not kept).  Adds
 // this lane's escape per face and light in the box.
 template <int NQ, bool EDGE>
 __device__ __forceinline__ void move_tile(const int2* sdesc, __amdgpu_buffer_rsrc_t tab,
@@ -700,12 +702,16 @@ __global__ __launch_bounds__(512, 1) void collide_move_kernel(CollideArgs A, int
     const long long col = (long long)tile * 256 + wave * 32 + cl;
     const unsigned voff = unsigned(size_t(col) * sizeof(float) + size_t(4 * hl) * rowbytes);
     const MoveLane L = move_lane(A, col);
+    // light leaving a detector's voxel is kept where the read-out finds it;
+    // elsewhere the store is dropped (it is only tallied)
+    const bool det = (A.mvdet[col >> 5] >> (col & 31)) & 1u;
+    const unsigned ssv = det ? so + voff : kDropOffset;
     if (__any(__builtin_popcount(L.LF) > 1))
-      move_tile<NP / 32, true>(sdesc, tab, fld, acc, L, so + voff, dso + voff, unsigned(rowbytes),
-                               hl, esc, dom);
+      move_tile<NP / 32, true>(sdesc, tab, fld, acc, L, ssv, dso + voff, unsigned(rowbytes), hl,
+                               esc, dom);
     else
-      move_tile<NP / 32, false>(sdesc, tab, fld, acc, L, so + voff, dso + voff, unsigned(rowbytes),
-                                hl, esc, dom);
+      move_tile<NP / 32, false>(sdesc, tab, fld, acc, L, ssv, dso + voff, unsigned(rowbytes), hl,
+                                esc, dom);
   }
   // workgroup sums: absorbed, total -> part; escape per face, in the box -> spart
   __shared__ double red9[9][8];
