@@ -647,10 +647,10 @@ tr_status tr_create_medium(const tr_grid_desc* desc, const float* mua, const flo
   }
 
   // ---- phase moves in the collision: per direction and coordinate p along
-  // its dominant axis, the flat offset to the downwind voxel, the faces a voxel
-  // there may leave through (dominant-axis face fa always, the b / c face fb /
-  // fc where the shift into the next plane is not zero) and the faces through
-  // which nothing flows in (the opposite ones, with the shift into the plane)
+  // its dominant axis, the flat offset of the move (shifts into the next plane,
+  // also past the last one) and the faces a voxel there may leave through
+  // (dominant-axis face fa always, the b / c face fb / fc where the shift into
+  // the next plane is not zero)
   m->mfused = mode == TR_ADVANCE_PHASE && !m->twolevel && desc->source == TR_SOURCE_EXPLICIT &&
               desc->transport == TR_TRANSPORT_AUTO && use_collide_move(f);
   if (m->mfused) {
@@ -663,7 +663,7 @@ tr_status tr_create_medium(const tr_grid_desc* desc, const float* mua, const flo
       const int a = dd[d].axis, b = dd[d].bax, c = dd[d].cax, sg = dd[d].sign;
       // the b (c) shifts must be -1, 0 or +1 and of one sign along the ray
       int sb = 0, sc = 0;
-      for (int k = 1; k < ext[a]; ++k) {
+      for (int k = 1; k <= ext[a]; ++k) {
         const int s0 = shift(d, 0, k), s1 = shift(d, 1, k);
         if (s0 < -1 || s0 > 1 || s1 < -1 || s1 > 1 || (s0 && sb && s0 != sb) ||
             (s1 && sc && s1 != sc)) {
@@ -678,18 +678,12 @@ tr_status tr_create_medium(const tr_grid_desc* desc, const float* mua, const flo
       dir[d] = 10 * a | (3 << (2 * a)) << 8;
       for (int p = 0; p < ext[a]; ++p) {
         const int k = sg > 0 ? p : ext[a] - 1 - p;
-        unsigned mk = 1u << fa, in = 1u << (fa ^ 1);
-        long long off = 0;
-        if (k + 1 < ext[a]) {
-          const int dbn = shift(d, 0, k + 1), dcn = shift(d, 1, k + 1);
-          if (dbn) mk |= 1u << fb;
-          if (dcn) mk |= 1u << fc;
-          off = sg * st[a] + dbn * st[b] + dcn * st[c];
-        }
-        if (k > 0 && shift(d, 0, k)) in |= 1u << (fb ^ 1);
-        if (k > 0 && shift(d, 1, k)) in |= 1u << (fc ^ 1);
-        tab[(size_t(d) * S + p) * 2] = int(off);
-        tab[(size_t(d) * S + p) * 2 + 1] = int(mk | in << 6);
+        const int dbn = shift(d, 0, k + 1), dcn = shift(d, 1, k + 1);
+        unsigned mk = 1u << fa;
+        if (dbn) mk |= 1u << fb;
+        if (dcn) mk |= 1u << fc;
+        tab[(size_t(d) * S + p) * 2] = int(sg * st[a] + dbn * st[b] + dcn * st[c]);
+        tab[(size_t(d) * S + p) * 2 + 1] = int(mk);
       }
     }
     if (m->mfused) {

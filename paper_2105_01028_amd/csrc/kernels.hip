@@ -541,8 +541,9 @@ __global__ __launch_bounds__(512, 1) void collide_bf16_res_kernel(CollideArgs A,
 // straight to the downwind voxel in the other field, and the collided field is
 // never stored and read back.
 //   * The moves of a direction are one-to-one (the transverse shift at a plane
-//     is the same for the whole plane): a destination gets one value or none,
-//     and a voxel with no upwind voxel in the box gets a zero from its own lane.
+//     is the same for the whole plane): a destination gets one value or none.
+//     Wrapped around the box they map it onto itself, so a value that leaves
+//     sends a zero to its wrapped destination, a voxel that nothing flows into.
 //   * Light leaves and inflow is missing only at voxels on the box surface.  A
 //     voxel on one face sends all its leaving light through that face, so one
 //     FP32 sum per lane suffices; a wavefront holding an edge voxel (two or
@@ -579,17 +580,30 @@ __device__ __forceinline__ __amdgpu_buffer_rsrc_t raw_rsrc(const void* p, unsign
 constexpr unsigned kDropOffset = 0x80000000u;   // above every resource made here
 
 // The scatter of one tile's accumulators (the layout of collide_res_acc).
-// fld: both fields; ssv / dsv: byte offsets of the lane's column in this
-// step's input and output halves (with the lane half's 4-row shift; ssv the
-// drop offset where leaving light is not kept).  Adds
-// this lane's escape per face and light in the box.
-template <int NQ, bool EDGE>
+// fld: both fields; dsv: byte offset of the lane's column in this step's
+// output half (with the lane half's 4-row shift); wrap4[f]: the byte offset
+// that takes a move out through face f back around the box.  A value that
+// stays in the box goes to its downwind voxel.  A value that leaves sends a
+// zero to its downwind voxel wrapped around the box: with unit shifts the
+// wrapped moves map the box one-to-one onto itself, so the wrapped
+// destinations of the values that leave are exactly the voxels that nothing
+// flows into, and every voxel of the new field is written once.
+// SLOW, for wavefronts holding a voxel on two or more faces, a detector's
+// voxel or a padding column: face precedence and wrap per value, the light
+// leaving a detector's voxel kept at ssv (the drop offset elsewhere), nothing
+// stored for padding columns.  Adds this lane's escape per face and light in
+// the box.
+template <int NQ, bool SLOW>
 __device__ __forceinline__ void move_tile(const int2* sdesc, __amdgpu_buffer_rsrc_t tab,
                                           __amdgpu_buffer_rsrc_t fld, const floatx16 (&acc)[NQ],
-                                          const MoveLane& L, unsigned ssv, unsigned dsv,
-                                          unsigned rowbytes, int hl, double (&esc)[6],
-                                          double& dom) {
-  const unsigned LF6 = L.LF << 6;
+                                          const MoveLane& L, const int (&wrap4)[6], unsigned ssv,
+                                          unsigned dsv, bool live, unsigned rowbytes, int hl,
+                                          double (&esc)[6], double& dom) {
+  // a lane on one face leaves through it only
+  const int face = L.LF ? __builtin_ctz(L.LF) : 6;
+  int wo4 = 0;
+#pragma unroll
+  for (int i = 0; i < 6; ++i) wo4 = face == i ? wrap4[i] : wo4;
   double lesc = 0.0;
 #pragma unroll
   for (int q = 0; q < NQ; ++q) {
@@ -612,17 +626,26 @@ __device__ __forceinline__ void move_tile(const int2* sdesc, __amdgpu_buffer_rsr
       for (int j = 0; j < 8; ++j) {
         const int r = r0 + j;
         const float val = acc[q][r];
-        const unsigned mk = unsigned(w[j][1]);
-        const unsigned hits = mk & L.LF;
+        const unsigned hits = unsigned(w[j][1]) & L.LF;
         const bool ex = hits != 0u;
         const unsigned ro = unsigned(32 * q + 8 * (r >> 2) + (r & 3)) * rowbytes;
-        const unsigned vo = ro + (ex ? ssv : dsv + 4u * unsigned(w[j][0]));
-        __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(val), fld, int(vo), 0, 0);
-        const unsigned zo = (mk & LF6) ? ro + dsv : kDropOffset;
-        __builtin_amdgcn_raw_buffer_store_b32(0u, fld, int(zo), 0, 0);
+        const unsigned dst = ro + dsv + 4u * unsigned(w[j][0]);
+        unsigned off;
+        if (SLOW) {
+          int wr = 0;
+#pragma unroll
+          for (int i = 0; i < 6; ++i) wr += ((hits >> i) & 1u) ? wrap4[i] : 0;
+          off = live ? dst - unsigned(wr) : kDropOffset;
+        } else {
+          off = ex ? dst - unsigned(wo4) : dst;
+        }
+        __builtin_amdgcn_raw_buffer_store_b32(ex ? 0u : __float_as_uint(val), fld, int(off), 0, 0);
+        if (SLOW)
+          __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(val), fld,
+                                                int(ex ? ro + ssv : kDropOffset), 0, 0);
         const float e = ex ? val : 0.0f;
         fdom += val - e;
-        if (EDGE) {
+        if (SLOW) {
           // the sweep's precedence: the dominant-axis face, else the face on the
           // lowest axis hit (b < c); hits holds one face per axis at most
           const unsigned dy = unsigned(sdesc[q * 32 + 8 * (r >> 2) + (r & 3) + 4 * hl].y);
@@ -636,16 +659,14 @@ __device__ __forceinline__ void move_tile(const int2* sdesc, __amdgpu_buffer_rsr
       }
     }
     dom += double(fdom);
-    if (EDGE) {
+    if (SLOW) {
 #pragma unroll
       for (int i = 0; i < 6; ++i) esc[i] += double(fe6[i]);
     } else {
       lesc += double(fesc);
     }
   }
-  if (!EDGE) {
-    // at most one face: all of this lane's leaving light went through it
-    const int face = L.LF ? __builtin_ctz(L.LF) : 6;
+  if (!SLOW) {
 #pragma unroll
     for (int i = 0; i < 6; ++i) esc[i] += face == i ? lesc : 0.0;
   }
@@ -682,6 +703,15 @@ __global__ __launch_bounds__(512, 1) void collide_move_kernel(CollideArgs A, int
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int hl = lane >> 5, cl = lane & 31;
   const size_t rowbytes = size_t(A.Vp) * sizeof(float);
+  // byte offset of a move out through face f (2 axis + side) back around the box
+  int wrap4[6];
+#pragma unroll
+  for (int f = 0; f < 6; ++f) {
+    const int ax = f >> 1;
+    const int ext = ax == 0 ? A.nx : (ax == 1 ? A.ny : A.nz);
+    const int stride = ax == 0 ? 1 : (ax == 1 ? A.nx : A.nx * A.ny);
+    wrap4[f] = (f & 1 ? 4 : -4) * ext * stride;
+  }
   double absorbed = 0.0, total = 0.0, dom = 0.0;
   double esc[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
   // a contiguous range of s per workgroup, tile = s * A.mvscramble mod ntiles
@@ -703,15 +733,16 @@ __global__ __launch_bounds__(512, 1) void collide_move_kernel(CollideArgs A, int
     const unsigned voff = unsigned(size_t(col) * sizeof(float) + size_t(4 * hl) * rowbytes);
     const MoveLane L = move_lane(A, col);
     // light leaving a detector's voxel is kept where the read-out finds it;
-    // elsewhere the store is dropped (it is only tallied)
+    // elsewhere it is only tallied
     const bool det = (A.mvdet[col >> 5] >> (col & 31)) & 1u;
+    const bool live = col < A.nvox;
     const unsigned ssv = det ? so + voff : kDropOffset;
-    if (__any(__builtin_popcount(L.LF) > 1))
-      move_tile<NP / 32, true>(sdesc, tab, fld, acc, L, ssv, dso + voff, unsigned(rowbytes), hl,
-                               esc, dom);
+    if (__any(__builtin_popcount(L.LF) > 1 || det || !live))
+      move_tile<NP / 32, true>(sdesc, tab, fld, acc, L, wrap4, ssv, dso + voff, live,
+                               unsigned(rowbytes), hl, esc, dom);
     else
-      move_tile<NP / 32, false>(sdesc, tab, fld, acc, L, ssv, dso + voff, unsigned(rowbytes), hl,
-                                esc, dom);
+      move_tile<NP / 32, false>(sdesc, tab, fld, acc, L, wrap4, ssv, dso + voff, live,
+                                unsigned(rowbytes), hl, esc, dom);
   }
   // workgroup sums: absorbed, total -> part; escape per face, in the box -> spart
   __shared__ double red9[9][8];
