@@ -117,6 +117,22 @@ def kernel_rooflines(prof, prob, precision, workload="phantom64"):
     return out
 
 
+def step_roofline(prob, precision, ms_per_step):
+    """The whole step against its own bound: the larger of the contraction's
+    2 N^2 V FLOP on the FP32 MFMA peak (FP32; BF16-split executes 8 N^2 V bf16
+    FLOP on the bf16 peak) and the transport's 8 N V bytes on the HBM peak
+    (read the field once, write it once), whatever kernels the step runs."""
+    N, V = prob.ndir, prob.nvox
+    if precision == "fp32":
+        t_mfma = 2.0 * N * N * V / (PEAK_TFLOPS["fp32"] * 1e12)
+    else:
+        t_mfma = 8.0 * N * N * V / (PEAK_TFLOPS["bf16split"] * 1e12)
+    t_hbm = 8.0 * N * V / (PEAK_HBM_GBS * 1e9)
+    t_min = max(t_mfma, t_hbm)
+    return {"bound": "mfma" if t_mfma >= t_hbm else "hbm", "min_ms": t_min * 1e3,
+            "ms_per_step": ms_per_step, "frac": t_min * 1e3 / ms_per_step}
+
+
 def oracle_error(prob, det_steps):
     """Relative L2 error of per-step detector records against the stored FP64
     oracle run of the same phantom (bins above 1e-6 of the peak)."""
@@ -597,6 +613,7 @@ def main():
         "kernels": {k: {"avg_ms": v[0] / v[1] if v[1] else 0.0, "launches": v[1]}
                     for k, v in prof.items()},
         "kernel_rooflines": roof,
+        "step_roofline": step_roofline(prob, args.precision, el_graph / K * 1e3),
         "timing": "value: the K steps as the library runs them (tr_step replays captured "
                   "graphs); kernel durations: the same K steps queued kernel by kernel with "
                   "HIP events on the medium's stream (instrumented below)",
@@ -608,6 +625,7 @@ def main():
         other = "bf16split" if args.precision == "fp32" else "fp32"
         e2, g2, p2, c2, d2, _ = timed_run(prob.copy(precision=other), K, Wm, stream)
         out[other] = {"value": updates / g2, "ms_per_step": g2 / K * 1e3,
+                      "step_roofline": step_roofline(prob, other, g2 / K * 1e3),
                       "kernels_ms": {k: v[0] / v[1] for k, v in p2.items() if v[1]},
                       "instrumented_value": updates / e2, "kernel_rooflines":
                       kernel_rooflines(p2, prob, other), "budget_closure": c2,
@@ -618,6 +636,7 @@ def main():
                                             stream)
             out["separate_sweep_" + pr] = {
                 "value": updates / g3, "ms_per_step": g3 / K * 1e3,
+                "step_roofline": step_roofline(prob, pr, g3 / K * 1e3),
                 "kernels_ms": {k: v[0] / v[1] for k, v in p3.items() if v[1]}}
         p50, p99 = latency(W.config1(), 30, stream)
         out["latency_uniform16"] = {"p50_ms": p50, "p99_ms": p99, "solves": 30,
