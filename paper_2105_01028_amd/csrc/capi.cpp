@@ -646,46 +646,13 @@ tr_status tr_create_medium(const tr_grid_desc* desc, const float* mua, const flo
     return fail(TR_EDEVICE, std::string("upload: ") + hipGetErrorString(e));
   }
 
-  // ---- phase moves in the collision: per direction and coordinate p along
-  // its dominant axis, the flat offset of the move (shifts into the next plane,
-  // also past the last one) and the faces a voxel there may leave through
-  // (dominant-axis face fa always, the b / c face fb / fc where the shift into
-  // the next plane is not zero)
+  // ---- phase moves in the collision (tables: build_move_tables)
   m->mfused = mode == TR_ADVANCE_PHASE && !m->twolevel && desc->source == TR_SOURCE_EXPLICIT &&
               desc->transport == TR_TRANSPORT_AUTO && use_collide_move(f);
-  if (m->mfused) {
-    const int ext[3] = {f.nx, f.ny, f.nz};
-    const long long st[3] = {1, f.nx, (long long)f.nx * f.ny};
-    const int S = std::max(f.nx, std::max(f.ny, f.nz));
-    std::vector<int> tab(size_t(f.NP + 1) * S * 2, 0), dir(f.NP, 0);
-    auto shift = [&](int d, int q, int k) { return int(dl[(size_t(d) * 2 + q) * m->dstride + k]); };
-    for (int d = 0; d < f.ndir && m->mfused; ++d) {
-      const int a = dd[d].axis, b = dd[d].bax, c = dd[d].cax, sg = dd[d].sign;
-      // the b (c) shifts must be -1, 0 or +1 and of one sign along the ray
-      int sb = 0, sc = 0;
-      for (int k = 1; k <= ext[a]; ++k) {
-        const int s0 = shift(d, 0, k), s1 = shift(d, 1, k);
-        if (s0 < -1 || s0 > 1 || s1 < -1 || s1 > 1 || (s0 && sb && s0 != sb) ||
-            (s1 && sc && s1 != sc)) {
-          m->mfused = false;
-          break;
-        }
-        if (s0) sb = s0;
-        if (s1) sc = s1;
-      }
-      const int fa = 2 * a + (sg > 0 ? 1 : 0), fb = 2 * b + (sb > 0 ? 1 : 0),
-                fc = 2 * c + (sc > 0 ? 1 : 0);
-      dir[d] = 10 * a | (3 << (2 * a)) << 8;
-      for (int p = 0; p < ext[a]; ++p) {
-        const int k = sg > 0 ? p : ext[a] - 1 - p;
-        const int dbn = shift(d, 0, k + 1), dcn = shift(d, 1, k + 1);
-        unsigned mk = 1u << fa;
-        if (dbn) mk |= 1u << fb;
-        if (dcn) mk |= 1u << fc;
-        tab[(size_t(d) * S + p) * 2] = int(sg * st[a] + dbn * st[b] + dcn * st[c]);
-        tab[(size_t(d) * S + p) * 2 + 1] = int(mk);
-      }
-    }
+  std::vector<int> tab, dir;
+  if (m->mfused) m->mfused = build_move_tables(m->lat, dl, m->dstride, f.NP, tab, dir);
+  {
+    const int S = m->lat.maxext;
     if (m->mfused) {
       m->mvext = S;
       // tile order multiplier: the first of these primes that does not divide ntiles

@@ -142,6 +142,42 @@ Lattice build_lattice(const std::vector<Vec3>& dirs, int nx, int ny, int nz) {
   return L;
 }
 
+bool build_move_tables(const Lattice& lat, const std::vector<int8_t>& dl, int dstride, int NP,
+                       std::vector<int>& tab, std::vector<int>& dir) {
+  const int* ext = lat.ext;
+  const long long st[3] = {1, ext[0], (long long)ext[0] * ext[1]};
+  const int S = lat.maxext;
+  tab.assign(size_t(NP + 1) * S * 2, 0);
+  dir.assign(size_t(NP), 0);
+  auto shift = [&](int d, int q, int k) { return int(dl[(size_t(d) * 2 + q) * dstride + k]); };
+  for (int d = 0; d < lat.ndir; ++d) {
+    const int a = lat.axis[d], b = lat.bax[d], c = lat.cax[d], sg = lat.sign[d];
+    // the b (c) shifts must be -1, 0 or +1 and of one sign along the ray
+    int sb = 0, sc = 0;
+    for (int k = 1; k <= ext[a]; ++k) {
+      const int s0 = shift(d, 0, k), s1 = shift(d, 1, k);
+      if (s0 < -1 || s0 > 1 || s1 < -1 || s1 > 1 || (s0 && sb && s0 != sb) ||
+          (s1 && sc && s1 != sc))
+        return false;
+      if (s0) sb = s0;
+      if (s1) sc = s1;
+    }
+    const int fa = 2 * a + (sg > 0 ? 1 : 0), fb = 2 * b + (sb > 0 ? 1 : 0),
+              fc = 2 * c + (sc > 0 ? 1 : 0);
+    dir[d] = 10 * a | (3 << (2 * a)) << 8;
+    for (int p = 0; p < ext[a]; ++p) {
+      const int k = sg > 0 ? p : ext[a] - 1 - p;
+      const int dbn = shift(d, 0, k + 1), dcn = shift(d, 1, k + 1);
+      unsigned mk = 1u << fa;
+      if (dbn) mk |= 1u << fb;
+      if (dcn) mk |= 1u << fc;
+      tab[(size_t(d) * S + p) * 2] = int(sg * st[a] + dbn * st[b] + dcn * st[c]);
+      tab[(size_t(d) * S + p) * 2 + 1] = int(mk);
+    }
+  }
+  return true;
+}
+
 long long Lattice::downwind(int d, int x, int y, int z, int* face) const {
   int p[3] = {x, y, z};
   const int a = axis[d], b = bax[d], c = cax[d], s = sign[d];

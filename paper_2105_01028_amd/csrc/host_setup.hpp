@@ -43,6 +43,19 @@ struct Lattice {
 };
 Lattice build_lattice(const std::vector<Vec3>& dirs, int nx, int ny, int nz);
 
+// Tables of phase advance with the moves in the collision kernel, from the
+// lattice and its shift tables dl[(d * 2 + q) * dstride + k] (the shift along
+// b (q = 0) or c (q = 1) into plane k, k = 1 .. maxext).  tab [(NP + 1) *
+// maxext][2]: per direction d < ndir and coordinate p along its dominant
+// axis, the flat offset of the move (shifts into the next plane, also past
+// the last one) and the mask of faces a voxel there may leave through (face
+// 2 axis + side: the dominant-axis face always, the b / c face where the shift
+// into the next plane is not zero); zero rows elsewhere.  dir [NP]:
+// 10 axis | 3 << (2 axis + 8).  False, and the separate sweep is needed, when
+// a direction's b or c shifts are not all -1, 0 or +1 of one sign.
+bool build_move_tables(const Lattice& lat, const std::vector<int8_t>& dl, int dstride, int NP,
+                       std::vector<int>& tab, std::vector<int>& dir);
+
 // Time step (dt_ps > 0 wins; else dx * min(n) / c0) and per-voxel coefficients:
 // a = e^{-mu_t l}, b from the coefficient form, r = min(n)/n_v.
 struct Coefficients {

@@ -672,8 +672,98 @@ __device__ __forceinline__ void move_tile(const int2* sdesc, __amdgpu_buffer_rsr
   }
 }
 
-// P resident in LDS (FP32, or the bf16 hi/lo pair), then per step direction
-// descriptors (table row, coordinate shift, dominant-axis faces) after it.
+// This step's direction descriptors (table row, coordinate shift,
+// dominant-axis faces), for the whole workgroup; directions that stay point
+// at the table's zero row.
+template <int NP>
+__device__ __forceinline__ void move_descriptors(const CollideArgs& A, int2* sdesc, int m) {
+  for (int d = threadIdx.x; d < NP; d += blockDim.x) {
+    const bool mv = d < A.ndir && phase_move(A.dirs[d].nu64, m) != 0.0f;
+    sdesc[d] = make_int2((mv ? d : NP) * A.mvext * 8, A.mvdir[d]);
+  }
+}
+
+// What the scatter of step m needs, the same for the whole workgroup: the
+// field halves (input so, output dso) behind one buffer resource, the table,
+// and the byte offset of a move out through face f (2 axis + side) back
+// around the box.
+struct MoveStep {
+  __amdgpu_buffer_rsrc_t fld, tab;
+  unsigned so, dso;
+  int wrap4[6];
+};
+
+template <int NP>
+__device__ __forceinline__ MoveStep move_step(const CollideArgs& A, int m) {
+  MoveStep S;
+  const size_t half = size_t(NP) * size_t(A.Vp) * sizeof(float);
+  S.so = (m & 1) ? unsigned(half) : 0u;
+  S.dso = (m & 1) ? 0u : unsigned(half);
+  S.fld = raw_rsrc(A.pp, unsigned(2 * half));
+  S.tab = raw_rsrc(A.mvtab, unsigned(size_t(NP + 1) * size_t(A.mvext) * 2 * sizeof(int)));
+#pragma unroll
+  for (int f = 0; f < 6; ++f) {
+    const int ax = f >> 1;
+    const int ext = ax == 0 ? A.nx : (ax == 1 ? A.ny : A.nz);
+    const int stride = ax == 0 ? 1 : (ax == 1 ? A.nx : A.nx * A.ny);
+    S.wrap4[f] = (f & 1 ? 4 : -4) * ext * stride;
+  }
+  return S;
+}
+
+// The scatter of tile `tile`, whose accumulators collide_res_acc (or its
+// bf16 form) computed from the input half; adds the lane's escape per face
+// and light in the box.
+template <int NP>
+__device__ __forceinline__ void move_epilogue(const CollideArgs& A, const int2* sdesc,
+                                              const MoveStep& S, const floatx16 (&acc)[NP / 32],
+                                              int tile, double (&esc)[6], double& dom) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int hl = lane >> 5, cl = lane & 31;
+  const size_t rowbytes = size_t(A.Vp) * sizeof(float);
+  const long long col = (long long)tile * 256 + wave * 32 + cl;
+  const unsigned voff = unsigned(size_t(col) * sizeof(float) + size_t(4 * hl) * rowbytes);
+  const MoveLane L = move_lane(A, col);
+  // light leaving a detector's voxel is kept where the read-out finds it;
+  // elsewhere it is only tallied
+  const bool det = (A.mvdet[col >> 5] >> (col & 31)) & 1u;
+  const bool live = col < A.nvox;
+  const unsigned ssv = det ? S.so + voff : kDropOffset;
+  if (__any(__builtin_popcount(L.LF) > 1 || det || !live))
+    move_tile<NP / 32, true>(sdesc, S.tab, S.fld, acc, L, S.wrap4, ssv, S.dso + voff, live,
+                             unsigned(rowbytes), hl, esc, dom);
+  else
+    move_tile<NP / 32, false>(sdesc, S.tab, S.fld, acc, L, S.wrap4, ssv, S.dso + voff, live,
+                              unsigned(rowbytes), hl, esc, dom);
+}
+
+// Workgroup sums of the nine tallies (512 threads): absorbed and total to
+// part[q * stride + i] (q = 0, 1), escape per face and light in the box to
+// spart[q * stride + i] (q = 0..5 faces, 6 in the box).
+__device__ __forceinline__ void move_sums(const CollideArgs& A, double absorbed, double total,
+                                          const double (&esc)[6], double dom, long long i,
+                                          long long stride) {
+  __shared__ double red9[9][8];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const double v9[9] = {absorbed, total, esc[0], esc[1], esc[2], esc[3], esc[4], esc[5], dom};
+  __syncthreads();   // red9 may still be read by the previous call
+#pragma unroll
+  for (int q = 0; q < 9; ++q) {
+    const double t = wave_sum(v9[q]);
+    if (lane == 0) red9[q][wave] = t;
+  }
+  __syncthreads();
+  if (threadIdx.x < 9) {
+    double t = 0.0;
+    for (int w = 0; w < 8; ++w) t += red9[threadIdx.x][w];
+    const int q = threadIdx.x;
+    double* o = q < 2 ? A.part + q * stride + i : A.spart + (q < 8 ? q - 2 : 6) * stride + i;
+    *o = t;
+  }
+}
+
+// P resident in LDS (FP32, or the bf16 hi/lo pair), then this step's
+// direction descriptors.
 template <int NP, bool BF16>
 __global__ __launch_bounds__(512, 1) void collide_move_kernel(CollideArgs A, int ntiles) {
   extern __shared__ float Pm[];
@@ -687,31 +777,11 @@ __global__ __launch_bounds__(512, 1) void collide_move_kernel(CollideArgs A, int
   else
     load_p_lds<NP>(A.Prow, Pm);
   const int m = *A.step_ctr;
-  for (int d = threadIdx.x; d < NP; d += 512) {
-    const bool mv = d < A.ndir && phase_move(A.dirs[d].nu64, m) != 0.0f;
-    sdesc[d] = make_int2((mv ? d : NP) * A.mvext * 8, A.mvdir[d]);
-  }
+  move_descriptors<NP>(A, sdesc, m);
   __syncthreads();
-  const size_t half = size_t(NP) * size_t(A.Vp) * sizeof(float);
-  const unsigned so = (m & 1) ? unsigned(half) : 0u;
-  const unsigned dso = (m & 1) ? 0u : unsigned(half);
-  const __amdgpu_buffer_rsrc_t fld = raw_rsrc(A.pp, unsigned(2 * half));
-  const __amdgpu_buffer_rsrc_t tab =
-      raw_rsrc(A.mvtab, unsigned(size_t(NP + 1) * size_t(A.mvext) * 2 * sizeof(int)));
+  const MoveStep S = move_step<NP>(A, m);
   CollideArgs B = A;
-  B.X = reinterpret_cast<const float*>(reinterpret_cast<const char*>(A.pp) + so);
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int hl = lane >> 5, cl = lane & 31;
-  const size_t rowbytes = size_t(A.Vp) * sizeof(float);
-  // byte offset of a move out through face f (2 axis + side) back around the box
-  int wrap4[6];
-#pragma unroll
-  for (int f = 0; f < 6; ++f) {
-    const int ax = f >> 1;
-    const int ext = ax == 0 ? A.nx : (ax == 1 ? A.ny : A.nz);
-    const int stride = ax == 0 ? 1 : (ax == 1 ? A.nx : A.nx * A.ny);
-    wrap4[f] = (f & 1 ? 4 : -4) * ext * stride;
-  }
+  B.X = reinterpret_cast<const float*>(reinterpret_cast<const char*>(A.pp) + S.so);
   double absorbed = 0.0, total = 0.0, dom = 0.0;
   double esc[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
   // a contiguous range of s per workgroup, tile = s * A.mvscramble mod ntiles
@@ -729,38 +799,9 @@ __global__ __launch_bounds__(512, 1) void collide_move_kernel(CollideArgs A, int
       collide_bf16_res_acc<NP>(B, Sh, Sl, tile, acc, absorbed, total);
     else
       collide_res_acc<NP>(B, Pm, tile, acc, absorbed, total);
-    const long long col = (long long)tile * 256 + wave * 32 + cl;
-    const unsigned voff = unsigned(size_t(col) * sizeof(float) + size_t(4 * hl) * rowbytes);
-    const MoveLane L = move_lane(A, col);
-    // light leaving a detector's voxel is kept where the read-out finds it;
-    // elsewhere it is only tallied
-    const bool det = (A.mvdet[col >> 5] >> (col & 31)) & 1u;
-    const bool live = col < A.nvox;
-    const unsigned ssv = det ? so + voff : kDropOffset;
-    if (__any(__builtin_popcount(L.LF) > 1 || det || !live))
-      move_tile<NP / 32, true>(sdesc, tab, fld, acc, L, wrap4, ssv, dso + voff, live,
-                               unsigned(rowbytes), hl, esc, dom);
-    else
-      move_tile<NP / 32, false>(sdesc, tab, fld, acc, L, wrap4, ssv, dso + voff, live,
-                                unsigned(rowbytes), hl, esc, dom);
+    move_epilogue<NP>(A, sdesc, S, acc, tile, esc, dom);
   }
-  // workgroup sums: absorbed, total -> part; escape per face, in the box -> spart
-  __shared__ double red9[9][8];
-  const double v9[9] = {absorbed, total, esc[0], esc[1], esc[2], esc[3], esc[4], esc[5], dom};
-#pragma unroll
-  for (int i = 0; i < 9; ++i) {
-    const double t = wave_sum(v9[i]);
-    if (lane == 0) red9[i][wave] = t;
-  }
-  __syncthreads();
-  if (threadIdx.x < 9) {
-    double t = 0.0;
-    for (int w = 0; w < 8; ++w) t += red9[threadIdx.x][w];
-    const int i = threadIdx.x;
-    double* o = i < 2 ? A.part + (long long)i * gridDim.x + blockIdx.x
-                      : A.spart + (long long)(i < 8 ? i - 2 : 6) * gridDim.x + blockIdx.x;
-    *o = t;
-  }
+  move_sums(A, absorbed, total, esc, dom, blockIdx.x, gridDim.x);
 }
 
 // More directions than fit in LDS (NP > 192): the layout of the resident kernel
@@ -2215,11 +2256,15 @@ __global__ void srv_inject_kernel(const ReqDev* R) {
   inject_body(A);
 }
 
+// A request with the phase moves in the collision (col.pp set) takes the
+// fused path per tile (this step's descriptors for its directions in LDS after
+// P); the others store the collided field for the sweep items.
 template <int NP>
 __global__ __launch_bounds__(512, 1) void srv_collide_kernel(const ReqDev* R, const int2* items,
                                                              const int* counts,
                                                              const float* Prow) {
   extern __shared__ float Ps[];
+  int2* sdesc = reinterpret_cast<int2*>(Ps + NP * (NP + 4));
   load_p_lds<NP>(Prow, Ps);
   __syncthreads();
   const int n = counts[0];
@@ -2230,8 +2275,24 @@ __global__ __launch_bounds__(512, 1) void srv_collide_kernel(const ReqDev* R, co
     if (!req_running(r)) continue;
     const CollideArgs A = r.col;
     double ab = 0.0, tot = 0.0;
-    collide_res_tile<NP>(A, Ps, tile, ab, tot);
-    block_sums512(ab, tot, A.part + tile, A.part + r.ntiles + tile);
+    if (A.pp) {
+      const int m = *A.step_ctr;
+      __syncthreads();   // the previous item's scatter has read the descriptors
+      move_descriptors<NP>(A, sdesc, m);
+      __syncthreads();
+      const MoveStep S = move_step<NP>(A, m);
+      CollideArgs B = A;
+      B.X = reinterpret_cast<const float*>(reinterpret_cast<const char*>(A.pp) + S.so);
+      double dom = 0.0;
+      double esc[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+      floatx16 acc[NP / 32];
+      collide_res_acc<NP>(B, Ps, tile, acc, ab, tot);
+      move_epilogue<NP>(A, sdesc, S, acc, tile, esc, dom);
+      move_sums(A, ab, tot, esc, dom, tile, r.ntiles);
+    } else {
+      collide_res_tile<NP>(A, Ps, tile, ab, tot);
+      block_sums512(ab, tot, A.part + tile, A.part + r.ntiles + tile);
+    }
   }
 }
 
@@ -2747,7 +2808,7 @@ hipError_t launch_reduce(const ReduceArgs& a, hipStream_t s) {
 namespace {
 template <int NP>
 hipError_t prepare_srv() {
-  const size_t lds = size_t(NP) * (NP + 4) * sizeof(float);
+  const size_t lds = size_t(NP) * (NP + 4) * sizeof(float) + size_t(NP) * sizeof(int2);
   return hipFuncSetAttribute(reinterpret_cast<const void*>(&srv_collide_kernel<NP>),
                              hipFuncAttributeMaxDynamicSharedMemorySize, int(lds));
 }
@@ -2755,7 +2816,7 @@ hipError_t prepare_srv() {
 template <int NP>
 hipError_t launch_srv_collide(const ReqDev* reqs, const int* citems, const int* counts,
                               const float* Prow, hipStream_t s) {
-  const size_t lds = size_t(NP) * (NP + 4) * sizeof(float);
+  const size_t lds = size_t(NP) * (NP + 4) * sizeof(float) + size_t(NP) * sizeof(int2);
   hipLaunchKernelGGL(srv_collide_kernel<NP>, dim3(unsigned(resident_blocks())), dim3(512), lds, s,
                      reqs, reinterpret_cast<const int2*>(citems), counts, Prow);
   return hipGetLastError();

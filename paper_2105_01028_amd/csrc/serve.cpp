@@ -52,6 +52,11 @@ struct Request {
   int nbins = 0;
   size_t bytes = 0;
   int bpd = 0, ntiles = 0;
+  // phase moves in the collision kernel (build_move_tables); the separate
+  // sweep where they do not apply
+  bool mfused = false;
+  std::vector<int> mvtab, mvdir;
+  int mvext = 0;
   // device state
   int slot = -1;
   long long steps_done = 0;
@@ -65,10 +70,10 @@ struct Request {
 // Sizes of a request's device buffers, in allocation order.
 struct Layout {
   size_t X, Y, a, b, dirs, delta, src, q, dpairs, dfirst, dvox, budget, dsteps, ints, scratch,
-      cpart, spart;
+      cpart, spart, mvtab, mvdir, mvdet;
   size_t total() const {
     return X + Y + a + b + dirs + delta + src + q + dpairs + dfirst + dvox + budget + dsteps +
-           ints + scratch + cpart + spart;
+           ints + scratch + cpart + spart + mvtab + mvdir + mvdet;
   }
 };
 
@@ -76,6 +81,10 @@ Layout layout_of(const Request& r) {
   Layout L;
   const Field& f = r.f;
   L.X = L.Y = size_t(f.NP) * f.Vp * 4;
+  if (r.mfused) {   // both fields in one allocation
+    L.X *= 2;
+    L.Y = 0;
+  }
   L.a = L.b = size_t(f.Vp) * 4;
   L.dirs = size_t(f.ndir) * sizeof(DevDir);
   L.delta = r.delta.size();
@@ -89,7 +98,10 @@ Layout layout_of(const Request& r) {
   L.ints = 3 * 4;
   L.scratch = 8 * 8;
   L.cpart = 2 * size_t(r.ntiles) * 8;
-  L.spart = 7 * size_t(f.ndir) * r.bpd * 8;
+  L.spart = 7 * std::max(size_t(f.ndir) * r.bpd, size_t(r.ntiles)) * 8;
+  L.mvtab = r.mvtab.size() * 4;
+  L.mvdir = r.mvdir.size() * 4;
+  L.mvdet = r.mfused ? size_t(f.Vp / 32) * 4 : 0;
   return L;
 }
 
@@ -230,6 +242,9 @@ tr_status build_request(const tr_server* s, const tr_request* q, Request& r) {
   r.nbins = q->nbins;
   r.ntiles = int(f.Vp / 256);
   r.bpd = sweep_blocks_per_dir(f);
+  if (use_collide_move(f)) r.mfused = build_move_tables(lat, r.delta, r.dstride, f.NP, r.mvtab, r.mvdir);
+  if (!r.mfused) r.mvtab.clear(), r.mvdir.clear();
+  r.mvext = lat.maxext;
   r.bytes = layout_of(r).total();
   return TR_OK;
 }
@@ -247,8 +262,9 @@ void release(tr_server* s, Request* r) {
 // Allocate and fill a request's device buffers and describe them in r.rd.
 tr_status admit(tr_server* s, Request* r, int slot) {
   const Layout L = layout_of(*r);
-  const size_t sizes[] = {L.X, L.Y, L.a, L.b, L.dirs, L.delta, L.src, L.q, L.dpairs, L.dfirst,
-                          L.dvox, L.budget, L.dsteps, L.ints, L.scratch, L.cpart, L.spart};
+  const size_t sizes[] = {L.X,      L.Y,      L.a,    L.b,     L.dirs,  L.delta, L.src,
+                          L.q,      L.dpairs, L.dfirst, L.dvox, L.budget, L.dsteps, L.ints,
+                          L.scratch, L.cpart, L.spart,  L.mvtab, L.mvdir,  L.mvdet};
   std::vector<void*> p;
   for (size_t sz : sizes) {
     void* ptr = nullptr;
@@ -260,7 +276,7 @@ tr_status admit(tr_server* s, Request* r, int slot) {
   }
   r->dev = p;
   float* X = static_cast<float*>(p[0]);
-  float* Y = static_cast<float*>(p[1]);
+  float* Y = r->mfused ? X + size_t(r->f.NP) * r->f.Vp : static_cast<float*>(p[1]);
   float* a = static_cast<float*>(p[2]);
   float* b = static_cast<float*>(p[3]);
   DevDir* dd = static_cast<DevDir*>(p[4]);
@@ -276,6 +292,9 @@ tr_status admit(tr_server* s, Request* r, int slot) {
   double* scratch = static_cast<double*>(p[14]);
   double* cpart = static_cast<double*>(p[15]);
   double* spart = static_cast<double*>(p[16]);
+  int* mvtab = static_cast<int*>(p[17]);
+  int* mvdir = static_cast<int*>(p[18]);
+  unsigned* mvdet = static_cast<unsigned*>(p[19]);
   const Field& f = r->f;
   std::vector<float> av(f.Vp, 0.0f), bv(f.Vp, 0.0f);
   for (int v = 0; v < f.V; ++v) {
@@ -283,7 +302,14 @@ tr_status admit(tr_server* s, Request* r, int slot) {
     bv[v] = float(r->co.b[v]);
   }
   hipError_t e = hipMemsetAsync(X, 0, L.X, s->stream);
-  if (e == hipSuccess) e = hipMemsetAsync(Y, 0, L.Y, s->stream);
+  if (e == hipSuccess && !r->mfused) e = hipMemsetAsync(Y, 0, L.Y, s->stream);
+  if (e == hipSuccess && r->mfused) {
+    std::vector<unsigned> bits(size_t(f.Vp / 32), 0u);
+    for (int v : r->det_vox) bits[size_t(v) >> 5] |= 1u << (v & 31);
+    e = hipMemcpy(mvtab, r->mvtab.data(), L.mvtab, hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(mvdir, r->mvdir.data(), L.mvdir, hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(mvdet, bits.data(), L.mvdet, hipMemcpyHostToDevice);
+  }
   if (e == hipSuccess) e = hipMemsetAsync(budget, 0, L.budget, s->stream);
   if (e == hipSuccess) e = hipMemsetAsync(dsteps, 0, L.dsteps, s->stream);
   if (e == hipSuccess) e = hipMemsetAsync(ints, 0, L.ints, s->stream);
@@ -310,6 +336,28 @@ tr_status admit(tr_server* s, Request* r, int slot) {
                     nullptr, nullptr, nullptr, f.ndir, ints, spart};
   R.red = ReduceArgs{cpart, r->ntiles, spart, snwg, Y, f.Vp, dpairs, dfirst, dvox, r->ndet, dd,
                      nullptr, 0, ints, budget, dsteps, r->nsteps, ints + 1, scratch, ints + 2};
+  if (r->mfused) {
+    // the field alternates between X and Y by step parity; the collision
+    // moves, and its per-tile partials hold the transport tallies too
+    R.inj.X2 = Y;
+    R.col.step_ctr = ints;
+    R.col.pp = X;
+    R.col.mvtab = mvtab;
+    R.col.mvdir = mvdir;
+    R.col.dirs = dd;
+    R.col.ndir = f.ndir;
+    R.col.nx = f.nx;
+    R.col.ny = f.ny;
+    R.col.nz = f.nz;
+    R.col.nvox = f.V;
+    R.col.mvext = r->mvext;
+    R.col.mvdet = mvdet;
+    R.col.spart = spart;
+    R.red.snwg = r->ntiles;
+    R.red.mvfused = 1;
+    R.red.pp0 = X;
+    R.red.pp1 = Y;
+  }
   R.nsteps = r->nsteps;
   R.ntiles = r->ntiles;
   R.bpd = r->bpd;
@@ -356,6 +404,7 @@ tr_status rebuild_lists(tr_server* s) {
       citems.push_back(slot);
       citems.push_back(t);
     }
+    if (r->mfused) continue;   // the collision moves the field
     for (int d = 0; d < r->f.ndir; ++d)
       for (int b = 0; b < r->bpd; ++b) {
         sitems.push_back(slot);
