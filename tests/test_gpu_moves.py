@@ -81,6 +81,28 @@ def test_moves_in_collision_equal_separate_sweep(nside, precision, shape, steps)
     assert np.allclose(ba[:, 2:], bb[:, 2:], rtol=1e-6, atol=1e-12 * scale)
 
 
+@pytest.mark.parametrize("nside,shape", [(2, (13, 10, 9)), (4, (16, 12, 10))])
+def test_moves_in_collision_detectors_on_edges_and_corners(nside, shape):
+    """Detectors on box edges and corners: their voxels lie on two or three
+    faces, where the light that leaves is kept for the read-out and the face
+    of each exit follows the sweep's precedence."""
+    nx, ny, nz = shape
+    dets = ([W.FACE_TOP, W.FACE_TOP, W.FACE_TOP, W.FACE_XMAX, W.FACE_XMAX],
+            [0, nx - 1, nx // 2, 0, ny - 1], [0, ny - 1, 0, nz - 1, nz // 2])
+    p = W.small_problem(nside=nside, nx=nx, ny=ny, nz=nz, mua=0.05, mus=2.0, g=0.8, steps=30,
+                        seed=3, advance="phase", det_cone_deg=60.0, dets=dets)
+    rng = np.random.default_rng(nx)
+    N0 = rng.uniform(0, 1, (12 * nside * nside, p.nvox)).astype(np.float32)
+    a = _run(p, 30, N0)
+    b = _run(p.copy(transport="sweep"), 30, N0)
+    assert a["fused"] == 1 and b["fused"] == 0
+    assert np.array_equal(a["state"], b["state"])
+    assert np.array_equal(a["det"], b["det"])
+    assert np.abs(a["det"]).max() > 0
+    ba, bb = a["budget"], b["budget"]
+    assert np.allclose(ba[:, 2:], bb[:, 2:], rtol=1e-6, atol=1e-12 * ba[:, 2].max())
+
+
 def test_moves_in_collision_graph_replay_equals_single_steps():
     """The field alternates between two buffers by step parity read on the
     device: graph replays of 16 steps and single launches give the same bits."""
