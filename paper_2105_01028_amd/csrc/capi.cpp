@@ -64,7 +64,7 @@ struct tr_medium {
   int* mvtab = nullptr;
   int* mvdir = nullptr;
   int mvext = 0;
-  int mvscramble = 1;
+  int mvscramble = 1, mvunscramble = 1;
   unsigned* mvdet = nullptr;   // bit per voxel column: a detector's voxel
   float *M = nullptr, *T = nullptr, *zero = nullptr;
   int *children = nullptr, *parent = nullptr;
@@ -256,11 +256,11 @@ struct KernelTimer {
 hipError_t queue_step(tr_medium* m) {
   const Field& f = m->f;
   hipError_t e;
-  if (m->npairs > 0) {
+  InjectArgs ia{m->X,   f.Vp,        m->src_pairs, m->npairs, m->qdev,
+                m->cap, m->step_ctr, m->budget,    m->ddirs,  m->ring != nullptr,
+                m->tlfused || m->mfused ? m->Y : nullptr};
+  if (m->npairs > 0 && !m->mfused) {   // the collision with the moves injects itself
     KernelTimer t(m, TR_K_INJECT);
-    InjectArgs ia{m->X,   f.Vp,        m->src_pairs, m->npairs, m->qdev,
-                  m->cap, m->step_ctr, m->budget,    m->ddirs,  m->ring != nullptr,
-                  m->tlfused || m->mfused ? m->Y : nullptr};
     if ((e = launch_inject(ia, m->stream)) != hipSuccess) return e;
   }
   if (m->twolevel) {
@@ -338,7 +338,8 @@ hipError_t queue_step(tr_medium* m) {
     ca.mvscramble = m->mvscramble;
     ca.mvdet = m->mvdet;
     ca.spart = m->spart;
-    if ((e = launch_collide_move(ca, f, m->desc.precision, m->stream)) != hipSuccess) return e;
+    ca.mvunscramble = m->mvunscramble;
+    if ((e = launch_collide_move(ca, ia, f, m->desc.precision, m->stream)) != hipSuccess) return e;
   } else {
     KernelTimer t(m, TR_K_COLLIDE);
     CollideArgs ca{m->X,   m->Y, m->P,  m->Prow, m->Phi, m->Plo, m->a,   m->b,
@@ -663,6 +664,16 @@ tr_status tr_create_medium(const tr_grid_desc* desc, const float* mua, const flo
           break;
         }
       }
+      // and its inverse modulo ntiles (extended Euclid)
+      long long r0 = ntiles, r1 = m->mvscramble % ntiles, t0 = 0, t1 = 1;
+      while (r1 != 0) {
+        const long long qq = r0 / r1, r2 = r0 - qq * r1, t2 = t0 - qq * t1;
+        r0 = r1;
+        r1 = r2;
+        t0 = t1;
+        t1 = t2;
+      }
+      m->mvunscramble = int(((t0 % ntiles) + ntiles) % ntiles);
       m->mvtab = m->alloc<int>(tab.size());
       m->mvdir = m->alloc<int>(dir.size());
       m->mvdet = m->alloc<unsigned>(size_t(f.Vp / 32));

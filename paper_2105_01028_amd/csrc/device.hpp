@@ -90,6 +90,7 @@ struct CollideArgs {
   const DevDir* dirs;
   int ndir, nx, ny, nz, nvox, mvext;
   int mvscramble;          // tile order multiplier, prime to the number of 256-voxel tiles
+  int mvunscramble;        // its inverse modulo the number of tiles
   const unsigned* mvdet;   // bit per voxel column: a detector's voxel (light that leaves
                            // there is kept for the read-out; elsewhere it is only tallied)
   double* spart;
@@ -277,10 +278,12 @@ hipError_t launch_collide_implicit(const CollideArgs& a, const Field& f, hipStre
 // Phase stepping with the moves in the collision's epilogue (the A.pp fields
 // set); needs use_collide_move(f).  Writes the collision partials to A.part
 // ([2][nwg]) and the transport partials to A.spart ([7][nwg]), nwg =
-// collide_nwg(f, bf16split).
+// collide_nwg(f, bf16split).  With j.npairs > 0 it also does the step's
+// injection (as launch_inject with j.X2 set), in place of launch_inject.
 bool use_collide_move(const Field& f);
 hipError_t prepare_collide_move(const Field& f, int bf16split);
-hipError_t launch_collide_move(const CollideArgs& a, const Field& f, int bf16split, hipStream_t s);
+hipError_t launch_collide_move(const CollideArgs& a, const InjectArgs& j, const Field& f,
+                               int bf16split, hipStream_t s);
 hipError_t prepare_collide_implicit(const Field& f);
 hipError_t prepare_collide(const Field& f, int bf16split);   // once per process and shape
 // fast_split_ok: nx is a multiple of 4 and every direction's b shifts are unit

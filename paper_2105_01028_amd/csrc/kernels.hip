@@ -763,9 +763,13 @@ __device__ __forceinline__ void move_sums(const CollideArgs& A, double absorbed,
 }
 
 // P resident in LDS (FP32, or the bf16 hi/lo pair), then this step's
-// direction descriptors.
+// direction descriptors.  With J.npairs > 0 the kernel also does the step's
+// injection (inject_body's arithmetic): each source pair is added by the
+// workgroup whose tiles hold its voxel, the only one that reads that column,
+// before its first tile.
 template <int NP, bool BF16>
-__global__ __launch_bounds__(512, 1) void collide_move_kernel(CollideArgs A, int ntiles) {
+__global__ __launch_bounds__(512, 1) void collide_move_kernel(CollideArgs A, InjectArgs J,
+                                                              int ntiles) {
   extern __shared__ float Pm[];
   constexpr size_t kPB = BF16 ? 2 * size_t(NP) * (NP + 8) * sizeof(uint16_t)
                               : size_t(NP) * (NP + 4) * sizeof(float);
@@ -778,17 +782,29 @@ __global__ __launch_bounds__(512, 1) void collide_move_kernel(CollideArgs A, int
     load_p_lds<NP>(A.Prow, Pm);
   const int m = *A.step_ctr;
   move_descriptors<NP>(A, sdesc, m);
-  __syncthreads();
   const MoveStep S = move_step<NP>(A, m);
-  CollideArgs B = A;
-  B.X = reinterpret_cast<const float*>(reinterpret_cast<const char*>(A.pp) + S.so);
-  double absorbed = 0.0, total = 0.0, dom = 0.0;
-  double esc[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
   // a contiguous range of s per workgroup, tile = s * A.mvscramble mod ntiles
   // (a bijection: the multiplier is prime to ntiles), so that the tiles holding
   // edges of the box, which take the per-value face precedence, are spread
   // over the workgroups instead of recurring on the same ones
   const int per = (ntiles + int(gridDim.x) - 1) / int(gridDim.x);
+  if (J.npairs > 0) {
+    const double qm = m < J.cap ? J.q[m] : 0.0;
+    const float share = float(qm / double(J.npairs));
+    float* Xin = reinterpret_cast<float*>(reinterpret_cast<char*>(A.pp) + S.so);
+    for (int i = threadIdx.x; i < J.npairs; i += blockDim.x) {
+      const int d = J.pairs[2 * i], v = J.pairs[2 * i + 1];
+      const int s = int((long long)(v >> 8) * A.mvunscramble % ntiles);
+      if (s / per == int(blockIdx.x)) Xin[size_t(d) * A.Vp + v] += share;
+    }
+    if (blockIdx.x == 0 && threadIdx.x == 0 && m < J.cap)
+      J.budget[size_t(m) * 9 + 0] = double(share) * J.npairs;
+  }
+  __syncthreads();   // descriptors, and the injected values, before the tiles
+  CollideArgs B = A;
+  B.X = reinterpret_cast<const float*>(reinterpret_cast<const char*>(A.pp) + S.so);
+  double absorbed = 0.0, total = 0.0, dom = 0.0;
+  double esc[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
 #pragma unroll 1
   for (int i = 0; i < per; ++i) {
     const int s = int(blockIdx.x) * per + i;
@@ -2620,15 +2636,16 @@ hipError_t prepare_move_np(int bf16split) {
                              hipFuncAttributeMaxDynamicSharedMemorySize, int(move_lds<NP>(bf16split)));
 }
 template <int NP>
-hipError_t launch_move_np(const CollideArgs& a, const Field& f, int bf16split, hipStream_t s) {
+hipError_t launch_move_np(const CollideArgs& a, const InjectArgs& j, const Field& f,
+                          int bf16split, hipStream_t s) {
   const int ntiles = int(f.Vp / 256);
   const int nb = ntiles < resident_blocks() ? ntiles : resident_blocks();
   if (bf16split)
     hipLaunchKernelGGL((collide_move_kernel<NP, true>), dim3(unsigned(nb)), dim3(512),
-                       move_lds<NP>(bf16split), s, a, ntiles);
+                       move_lds<NP>(bf16split), s, a, j, ntiles);
   else
     hipLaunchKernelGGL((collide_move_kernel<NP, false>), dim3(unsigned(nb)), dim3(512),
-                       move_lds<NP>(bf16split), s, a, ntiles);
+                       move_lds<NP>(bf16split), s, a, j, ntiles);
   return hipGetLastError();
 }
 }  // namespace
@@ -2651,15 +2668,16 @@ hipError_t prepare_collide_move(const Field& f, int bf16split) {
   }
 }
 
-hipError_t launch_collide_move(const CollideArgs& a, const Field& f, int bf16split, hipStream_t s) {
+hipError_t launch_collide_move(const CollideArgs& a, const InjectArgs& j, const Field& f,
+                               int bf16split, hipStream_t s) {
   if (!use_collide_move(f)) return hipErrorInvalidValue;
   switch (f.NP) {
-    case 32: return launch_move_np<32>(a, f, bf16split, s);
-    case 64: return launch_move_np<64>(a, f, bf16split, s);
-    case 96: return launch_move_np<96>(a, f, bf16split, s);
-    case 128: return launch_move_np<128>(a, f, bf16split, s);
-    case 160: return launch_move_np<160>(a, f, bf16split, s);
-    default: return launch_move_np<192>(a, f, bf16split, s);
+    case 32: return launch_move_np<32>(a, j, f, bf16split, s);
+    case 64: return launch_move_np<64>(a, j, f, bf16split, s);
+    case 96: return launch_move_np<96>(a, j, f, bf16split, s);
+    case 128: return launch_move_np<128>(a, j, f, bf16split, s);
+    case 160: return launch_move_np<160>(a, j, f, bf16split, s);
+    default: return launch_move_np<192>(a, j, f, bf16split, s);
   }
 }
 
