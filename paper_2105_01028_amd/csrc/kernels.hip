@@ -2406,42 +2406,73 @@ __global__ __launch_bounds__(512, 1) void adj_collide_kernel(AdjArgs A, int ntil
     for (int q = 0; q < NQ; ++q)
 #pragma unroll
       for (int r = 0; r < 16; ++r) acc[q][r] = 0.0f;
-#pragma unroll 1
-    for (int c = 0; c < NQ; ++c) {
-      float bm[16];
+    // the rows of chunk c + 1 are loaded while chunk c feeds the MFMAs (the
+    // last chunk reloads itself: in bounds, unused); the lane's rows of the
+    // forward field x are loaded once, in the accumulator layout, so that
+    // dL/da (mu x) is summed as the mu rows arrive and dL/db (z x) in the
+    // epilogue without reading x again
+    float bcur[16], bnext[16];
+    const char* __restrict__ xb0 = reinterpret_cast<const char*>(A.xs);
+    floatx16 xr[NQ];
+    double ga = 0.0;
+#pragma unroll
+    for (int s = 0; s < 16; ++s)
+      bcur[s] = *reinterpret_cast<const float*>(
+          mb0 + size_t(8 * (s >> 2) + (s & 3)) * rowbytes + voff);
+#pragma unroll
+    for (int q = 0; q < NQ; ++q)
 #pragma unroll
       for (int s = 0; s < 16; ++s)
-        bm[s] = *reinterpret_cast<const float*>(
-            mb0 + size_t(32 * c + 8 * (s >> 2) + (s & 3)) * rowbytes + voff);
+        xr[q][s] = *reinterpret_cast<const float*>(
+            xb0 + size_t(32 * q + 8 * (s >> 2) + (s & 3)) * rowbytes + voff);
+#pragma unroll 1
+    for (int c = 0; c < NQ; ++c) {
+      const int cn = c + 1 < NQ ? c + 1 : c;
+#pragma unroll
+      for (int s = 0; s < 16; ++s)
+        bnext[s] = *reinterpret_cast<const float*>(
+            mb0 + size_t(32 * cn + 8 * (s >> 2) + (s & 3)) * rowbytes + voff);
+      {
+        float fa = 0.0f;
+#pragma unroll
+        for (int q = 0; q < NQ; ++q)
+          if (q == c) {
+#pragma unroll
+            for (int s = 0; s < 16; ++s) fa = fmaf(bcur[s], xr[q][s], fa);
+          }
+        ga += double(fa);
+      }
 #pragma unroll
       for (int s4 = 0; s4 < 16; s4 += 4) {
         const int kk = 32 * c + 8 * (s4 >> 2);
 #pragma unroll
         for (int q = 0; q < NQ; ++q) {
           const float4 a4 = *reinterpret_cast<const float4*>(Pl + q * 32 * LDK + kk);
-          acc[q] = __builtin_amdgcn_mfma_f32_32x32x2f32(a4.x, bm[s4 + 0], acc[q], 0, 0, 0);
-          acc[q] = __builtin_amdgcn_mfma_f32_32x32x2f32(a4.y, bm[s4 + 1], acc[q], 0, 0, 0);
-          acc[q] = __builtin_amdgcn_mfma_f32_32x32x2f32(a4.z, bm[s4 + 2], acc[q], 0, 0, 0);
-          acc[q] = __builtin_amdgcn_mfma_f32_32x32x2f32(a4.w, bm[s4 + 3], acc[q], 0, 0, 0);
+          acc[q] = __builtin_amdgcn_mfma_f32_32x32x2f32(a4.x, bcur[s4 + 0], acc[q], 0, 0, 0);
+          acc[q] = __builtin_amdgcn_mfma_f32_32x32x2f32(a4.y, bcur[s4 + 1], acc[q], 0, 0, 0);
+          acc[q] = __builtin_amdgcn_mfma_f32_32x32x2f32(a4.z, bcur[s4 + 2], acc[q], 0, 0, 0);
+          acc[q] = __builtin_amdgcn_mfma_f32_32x32x2f32(a4.w, bcur[s4 + 3], acc[q], 0, 0, 0);
         }
       }
+#pragma unroll
+      for (int s = 0; s < 16; ++s) bcur[s] = bnext[s];
     }
     const float av = A.a[col], bv = A.b[col];
-    const char* __restrict__ xb0 = reinterpret_cast<const char*>(A.xs);
     char* __restrict__ lb0 = reinterpret_cast<char*>(A.lam_out);
-    double ga = 0.0, gb = 0.0;
+    double gb = 0.0;
 #pragma unroll
-    for (int q = 0; q < NQ; ++q)
+    for (int q = 0; q < NQ; ++q) {
+      float fb = 0.0f;
 #pragma unroll
       for (int r = 0; r < 16; ++r) {
         const size_t off = size_t(q * 32 + 8 * (r >> 2) + (r & 3)) * rowbytes + voff;
         const float mu = *reinterpret_cast<const float*>(mb0 + off);
-        const float x = *reinterpret_cast<const float*>(xb0 + off);
         const float z = acc[q][r];
         *reinterpret_cast<float*>(lb0 + off) = av * mu + bv * z;
-        ga += double(mu) * double(x);
-        gb += double(z) * double(x);
+        fb = fmaf(z, xr[q][r], fb);
       }
+      gb += double(fb);
+    }
     ga += __shfl_xor(ga, 32, 64);
     gb += __shfl_xor(gb, 32, 64);
     if (hl == 0 && col < A.V) {
