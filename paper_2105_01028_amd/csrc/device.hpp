@@ -77,10 +77,10 @@ struct CollideArgs {
   // phase moves in the collision's epilogue (launch_collide_move; null otherwise):
   // the field alternates between the two halves of pp ([2][NP][Vp]), step m
   // reads half m & 1 and writes the other.  mvtab[d][p] (NP + 1 rows of mvext
-  // int pairs, row NP all zero for directions that stay) holds, for a voxel at
-  // coordinate p along d's dominant axis, the flat offset of its move (shifts
-  // into the next plane, also past the last one) and a mask of the faces it
-  // may leave through (face 2 axis + side, side 1 the high face);
+  // ints, row NP all zero for directions that stay) holds, for a voxel at
+  // coordinate p along d's dominant axis, 64 times the flat offset of its move
+  // (shifts into the next plane, also past the last one) plus a mask of the
+  // faces it may leave through (face 2 axis + side, side 1 the high face);
   // mvdir[d] = 10 axis | 3 << (2 axis + 8) (the coordinate's shift in
   // a packed x | y << 10 | z << 20, and both faces of the dominant axis).
   // spart: [7][nwg] escape per face and light in the box.

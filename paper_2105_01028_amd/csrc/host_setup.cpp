@@ -147,7 +147,7 @@ bool build_move_tables(const Lattice& lat, const std::vector<int8_t>& dl, int ds
   const int* ext = lat.ext;
   const long long st[3] = {1, ext[0], (long long)ext[0] * ext[1]};
   const int S = lat.maxext;
-  tab.assign(size_t(NP + 1) * S * 2, 0);
+  tab.assign(size_t(NP + 1) * S, 0);
   dir.assign(size_t(NP), 0);
   auto shift = [&](int d, int q, int k) { return int(dl[(size_t(d) * 2 + q) * dstride + k]); };
   for (int d = 0; d < lat.ndir; ++d) {
@@ -171,8 +171,9 @@ bool build_move_tables(const Lattice& lat, const std::vector<int8_t>& dl, int ds
       unsigned mk = 1u << fa;
       if (dbn) mk |= 1u << fb;
       if (dcn) mk |= 1u << fc;
-      tab[(size_t(d) * S + p) * 2] = int(sg * st[a] + dbn * st[b] + dcn * st[c]);
-      tab[(size_t(d) * S + p) * 2 + 1] = int(mk);
+      // |offset| <= 1 + 1023 + 1023^2 < 2^25: offset and mask share one int
+      const long long off = sg * st[a] + dbn * st[b] + dcn * st[c];
+      tab[size_t(d) * S + p] = int(off * 64 + mk);
     }
   }
   return true;

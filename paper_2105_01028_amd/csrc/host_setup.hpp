@@ -46,9 +46,9 @@ Lattice build_lattice(const std::vector<Vec3>& dirs, int nx, int ny, int nz);
 // Tables of phase advance with the moves in the collision kernel, from the
 // lattice and its shift tables dl[(d * 2 + q) * dstride + k] (the shift along
 // b (q = 0) or c (q = 1) into plane k, k = 1 .. maxext).  tab [(NP + 1) *
-// maxext][2]: per direction d < ndir and coordinate p along its dominant
-// axis, the flat offset of the move (shifts into the next plane, also past
-// the last one) and the mask of faces a voxel there may leave through (face
+// maxext]: per direction d < ndir and coordinate p along its dominant axis,
+// 64 times the flat offset of the move (shifts into the next plane, also past
+// the last one) plus the mask of faces a voxel there may leave through (face
 // 2 axis + side: the dominant-axis face always, the b / c face where the shift
 // into the next plane is not zero); zero rows elsewhere.  dir [NP]:
 // 10 axis | 3 << (2 axis + 8).  False, and the separate sweep is needed, when

@@ -609,27 +609,22 @@ __device__ __forceinline__ void move_tile(const int2* sdesc, __amdgpu_buffer_rsr
   for (int q = 0; q < NQ; ++q) {
     float fdom = 0.0f, fesc = 0.0f;
     float fe6[6] = {0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f};
+    {
+      // the block's 16 table entries (64 offset + face mask) in flight at once
+      int w[16];
 #pragma unroll
-    for (int r0 = 0; r0 < 16; r0 += 8) {
-      int w[8][2];
-#pragma unroll
-      for (int j = 0; j < 8; ++j) {
-        const int r = r0 + j;
+      for (int r = 0; r < 16; ++r) {
         const int2 dsc = sdesc[q * 32 + 8 * (r >> 2) + (r & 3) + 4 * hl];
         const unsigned p = __builtin_amdgcn_ubfe(L.P, unsigned(dsc.y) & 31u, 10u);
-        const auto t =
-            __builtin_amdgcn_raw_buffer_load_b64(tab, int(unsigned(dsc.x) + (p << 3)), 0, 0);
-        w[j][0] = int(t[0]);
-        w[j][1] = int(t[1]);
+        w[r] = __builtin_amdgcn_raw_buffer_load_b32(tab, int(unsigned(dsc.x) + (p << 2)), 0, 0);
       }
 #pragma unroll
-      for (int j = 0; j < 8; ++j) {
-        const int r = r0 + j;
+      for (int r = 0; r < 16; ++r) {
         const float val = acc[q][r];
-        const unsigned hits = unsigned(w[j][1]) & L.LF;
+        const unsigned hits = unsigned(w[r]) & L.LF;
         const bool ex = hits != 0u;
         const unsigned ro = unsigned(32 * q + 8 * (r >> 2) + (r & 3)) * rowbytes;
-        const unsigned dst = ro + dsv + 4u * unsigned(w[j][0]);
+        const unsigned dst = ro + dsv + 4u * unsigned(w[r] >> 6);
         unsigned off;
         if (SLOW) {
           int wr = 0;
@@ -679,7 +674,7 @@ template <int NP>
 __device__ __forceinline__ void move_descriptors(const CollideArgs& A, int2* sdesc, int m) {
   for (int d = threadIdx.x; d < NP; d += blockDim.x) {
     const bool mv = d < A.ndir && phase_move(A.dirs[d].nu64, m) != 0.0f;
-    sdesc[d] = make_int2((mv ? d : NP) * A.mvext * 8, A.mvdir[d]);
+    sdesc[d] = make_int2((mv ? d : NP) * A.mvext * 4, A.mvdir[d]);
   }
 }
 
@@ -700,7 +695,7 @@ __device__ __forceinline__ MoveStep move_step(const CollideArgs& A, int m) {
   S.so = (m & 1) ? unsigned(half) : 0u;
   S.dso = (m & 1) ? 0u : unsigned(half);
   S.fld = raw_rsrc(A.pp, unsigned(2 * half));
-  S.tab = raw_rsrc(A.mvtab, unsigned(size_t(NP + 1) * size_t(A.mvext) * 2 * sizeof(int)));
+  S.tab = raw_rsrc(A.mvtab, unsigned(size_t(NP + 1) * size_t(A.mvext) * sizeof(int)));
 #pragma unroll
   for (int f = 0; f < 6; ++f) {
     const int ax = f >> 1;
