@@ -56,13 +56,12 @@ __device__ inline int pick(int axis, int x, int y, int z) {
   return axis == 0 ? x : (axis == 1 ? y : z);
 }
 
-// bf16 round-to-nearest-even of a finite float, as raw bits.
-__device__ inline unsigned short bf16_bits(float x) {
-  unsigned int u = __float_as_uint(x);
-  u += 0x7FFFu + ((u >> 16) & 1u);
-  return (unsigned short)(u >> 16);
+// x as hi + lo, hi = bf16(x) and lo = bf16(x - hi), each rounded to nearest
+// even (the conversion is one gfx950 instruction); hi + lo holds 16 of x's 24
+// significand bits.
+__device__ inline __bf16 bf16_rest(float x, __bf16 hi) {
+  return static_cast<__bf16>(x - static_cast<float>(hi));
 }
-__device__ inline float bf16_to_float(unsigned short h) { return __uint_as_float(unsigned(h) << 16); }
 
 }  // namespace
 
@@ -486,9 +485,8 @@ __device__ __forceinline__ void collide_bf16_res_acc(const CollideArgs& A, const
 #pragma unroll
       for (int j = 0; j < 8; ++j) {
         const float x = bcur[8 * t + j] * bv;
-        const unsigned short hi = bf16_bits(x);
-        xh[j] = __builtin_bit_cast(__bf16, hi);
-        xl[j] = __builtin_bit_cast(__bf16, bf16_bits(x - bf16_to_float(hi)));
+        xh[j] = static_cast<__bf16>(x);
+        xl[j] = bf16_rest(x, xh[j]);
       }
       const int kk = 32 * c + 16 * t;
 #pragma unroll
@@ -1026,9 +1024,8 @@ __global__ __launch_bounds__(512, 1) void collide_bf16_stream_kernel(CollideArgs
 #pragma unroll
       for (int j = 0; j < 8; ++j) {
         const float x = bcur[8 * t + j] * bv;
-        const unsigned short hi = bf16_bits(x);
-        xh[j] = __builtin_bit_cast(__bf16, hi);
-        xl[j] = __builtin_bit_cast(__bf16, bf16_bits(x - bf16_to_float(hi)));
+        xh[j] = static_cast<__bf16>(x);
+        xl[j] = bf16_rest(x, xh[j]);
       }
 #pragma unroll
       for (int q = 0; q < NQ; ++q) {
@@ -1211,10 +1208,8 @@ __global__ __launch_bounds__(kThreads, 2) void collide_bf16split_kernel(CollideA
 #pragma unroll
       for (int j = 0; j < 8; ++j) {
         const float x = xcol[size_t(k0 + 16 * s + 8 * hl + j) * A.Vp];
-        const unsigned short h = bf16_bits(x);
-        const unsigned short l = bf16_bits(x - bf16_to_float(h));
-        xh[j] = __builtin_bit_cast(__bf16, h);
-        xl[j] = __builtin_bit_cast(__bf16, l);
+        xh[j] = static_cast<__bf16>(x);
+        xl[j] = bf16_rest(x, xh[j]);
       }
 #pragma unroll
       for (int q = 0; q < NQ; ++q) {
