@@ -2157,6 +2157,25 @@ __global__ void gather_kernel(GatherArgs A) {
 // faces 0..5); workgroup 0 also sums the light leaving through each detector
 // patch.  The last workgroup to finish writes the budget of step m, checks it
 // and advances the step counter.  Deterministic: same inputs, same bits.
+// Direction d's share of a detector record at voxel v in step m.
+__device__ __forceinline__ double det_term(const ReduceArgs& A, int d, int v, int m) {
+  const DevDir D = A.dirs[d];
+  if (A.ring) return double(D.rinvD * retarded_rows(A.ring, A.H, A.slot, A.Vp, D, d, m)[v]);
+  if (A.tlT) {
+    const float* x = (m & 1) ? A.pp1 : A.pp0;
+    const TwoLevelRow Y{x + size_t(d) * A.Vp, A.tlT + size_t(A.tlparent[d]) * A.Vp, A.tla,
+                        A.tlshare};
+    return double(phase_move(D.nu64, m) * Y[v]);
+  }
+  // with the moves in the collision, the light that left is in the input
+  // field of this step, at the voxel it left from
+  const float* Y = A.mvfused ? ((m & 1) ? A.pp1 : A.pp0) : A.Y;
+  const float f = A.split ? D.nu * A.r[v] : phase_move(D.nu64, m);
+  return double(f * Y[size_t(d) * A.Vp + v]);
+}
+
+constexpr int kDetTerms = 2048;
+
 __device__ __forceinline__ void reduce_part(const ReduceArgs& A, int q, int nq) {
   __shared__ double red[kThreads];
   __shared__ bool last;
@@ -2192,27 +2211,21 @@ __device__ __forceinline__ void reduce_part(const ReduceArgs& A, int q, int nq) 
   }
   if (tid == 0) A.scratch[q] = red[0];
   if (q == 0) {
+    // detector k's record is the sum, in pair order, of its pairs' terms; up
+    // to kDetTerms pairs the terms are formed one pair per thread first
+    __shared__ double term[kDetTerms];
+    const int npairs = A.ndet > 0 ? A.det_first[A.ndet] : 0;
+    const bool staged = npairs <= kDetTerms;
+    if (staged) {
+      for (int p = tid; p < npairs; p += kThreads)
+        term[p] = det_term(A, A.det_pairs[2 * p + 1], A.det_vox[A.det_pairs[2 * p]], m);
+      __syncthreads();
+    }
     for (int k = tid; k < A.ndet; k += kThreads) {
       double sd = 0;
       const int v = A.det_vox[k];
-      for (int p = A.det_first[k]; p < A.det_first[k + 1]; ++p) {
-        const int d = A.det_pairs[2 * p + 1];
-        const DevDir D = A.dirs[d];
-        if (A.ring) {
-          sd += double(D.rinvD * retarded_rows(A.ring, A.H, A.slot, A.Vp, D, d, m)[v]);
-        } else if (A.tlT) {
-          const float* x = (m & 1) ? A.pp1 : A.pp0;
-          const TwoLevelRow Y{x + size_t(d) * A.Vp, A.tlT + size_t(A.tlparent[d]) * A.Vp, A.tla,
-                              A.tlshare};
-          sd += double(phase_move(D.nu64, m) * Y[v]);
-        } else {
-          // with the moves in the collision, the light that left is in the
-          // input field of this step, at the voxel it left from
-          const float* Y = A.mvfused ? ((m & 1) ? A.pp1 : A.pp0) : A.Y;
-          const float f = A.split ? D.nu * A.r[v] : phase_move(D.nu64, m);
-          sd += double(f * Y[size_t(d) * A.Vp + v]);
-        }
-      }
+      for (int p = A.det_first[k]; p < A.det_first[k + 1]; ++p)
+        sd += staged ? term[p] : det_term(A, A.det_pairs[2 * p + 1], v, m);
       if (ok) A.det_steps[size_t(k) * A.cap + m] = sd;
     }
   }
