@@ -168,39 +168,64 @@ __device__ __forceinline__ void load_p_lds(const float* __restrict__ Prow, float
 // lane (h, c) of wavefront w holds column 256 tile + 32 w + c and, in acc[q][s],
 // row 32q + 8(s/4) + 4h + s%4.  Adds this thread's share of the tile's budget
 // sums to absorbed and total.
+// The lane's X rows of a chunk: row block c, step s, lane half h holds row
+// 32c + 8(s/4) + 4h + s%4 (the 4h part in the lane's offset).
+struct TileHead {
+  float x[16];   // chunk 0 of the lane's column
+  float av, bv;  // the column's collision coefficients
+};
+
+__device__ __forceinline__ unsigned tile_lane_offset(const CollideArgs& A, int tile) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const long long col = (long long)tile * 256 + wave * 32 + (lane & 31);
+  return unsigned(size_t(col) * sizeof(float) + size_t(4 * (lane >> 5)) * size_t(A.Vp) * sizeof(float));
+}
+
+__device__ __forceinline__ float tile_x(const CollideArgs& A, unsigned voff, int c, int s) {
+  const char* rb = reinterpret_cast<const char*>(A.X) +
+                   size_t(32 * c + 8 * (s >> 2) + (s & 3)) * size_t(A.Vp) * sizeof(float);
+  return *reinterpret_cast<const float*>(rb + voff);
+}
+
+__device__ __forceinline__ void load_tile_head(const CollideArgs& A, int tile, TileHead& H) {
+  const unsigned voff = tile_lane_offset(A, tile);
+  const long long col = (long long)tile * 256 + (threadIdx.x >> 6) * 32 + (threadIdx.x & 31);
+#pragma unroll
+  for (int s = 0; s < 16; ++s) H.x[s] = tile_x(A, voff, 0, s);
+  H.av = A.a[col];
+  H.bv = A.b[col];
+}
+
+// H holds the tile's head on entry; with next >= 0 it holds tile next's head
+// on return, loaded during the last chunk's MFMAs (else it is spent).
 template <int NP>
 __device__ __forceinline__ void collide_res_acc(const CollideArgs& A, const float* Ps, int tile,
                                                 floatx16 (&acc)[NP / 32], double& absorbed,
-                                                double& total) {
+                                                double& total, TileHead& H, int next) {
   constexpr int NQ = NP / 32;
   constexpr int LDK = NP + 4;
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int lane = threadIdx.x & 63;
   const int hl = lane >> 5, cl = lane & 31;
-  const size_t rowbytes = size_t(A.Vp) * sizeof(float);
   const float* __restrict__ Pl = Ps + cl * LDK + 4 * hl;
-  const long long col = (long long)tile * 256 + wave * 32 + cl;
-  // per-lane byte offset inside a group of rows: column plus the lane half's 4-row shift
-  const unsigned voff = unsigned(size_t(col) * sizeof(float) + size_t(4 * hl) * rowbytes);
-  const char* __restrict__ xb0 = reinterpret_cast<const char*>(A.X);
-  const float av = A.a[col], bv = A.b[col];
+  const unsigned voff = tile_lane_offset(A, tile);
+  const unsigned voffn = tile_lane_offset(A, next >= 0 ? next : tile);
+  const float av = H.av, bv = H.bv;
 #pragma unroll
   for (int q = 0; q < NQ; ++q)
 #pragma unroll
     for (int r = 0; r < 16; ++r) acc[q][r] = 0.0f;
-  // row of step s in chunk c for lane half h: 32c + 8(s/4) + 4h + s%4; the 4h part is in voff
-  auto ld = [&](int c, int s) {
-    const char* rb = xb0 + size_t(32 * c + 8 * (s >> 2) + (s & 3)) * rowbytes;
-    return *reinterpret_cast<const float*>(rb + voff);
-  };
   float bcur[16], bnext[16];
 #pragma unroll
-  for (int s = 0; s < 16; ++s) bcur[s] = ld(0, s);
+  for (int s = 0; s < 16; ++s) bcur[s] = H.x[s];
   double colsum64 = 0.0;
 #pragma unroll 1
   for (int c = 0; c < NQ; ++c) {
-    const int cn = c + 1 < NQ ? c + 1 : c;   // last chunk reloads itself (in bounds, unused)
+    // the last chunk loads the next tile's head (or its own first chunk again)
+    const bool last = c + 1 == NQ;
+    const unsigned vo = last ? voffn : voff;
+    const int cn = last ? 0 : c + 1;
 #pragma unroll
-    for (int s = 0; s < 16; ++s) bnext[s] = ld(cn, s);
+    for (int s = 0; s < 16; ++s) bnext[s] = tile_x(A, vo, cn, s);
     float colsum = 0.0f;
 #pragma unroll
     for (int s = 0; s < 16; ++s) colsum += bcur[s];
@@ -232,6 +257,22 @@ __device__ __forceinline__ void collide_res_acc(const CollideArgs& A, const floa
   }
   absorbed += (1.0 - double(av) - double(bv)) * colsum64;
   total += colsum64;
+  if (next >= 0) {
+    const long long coln = (long long)next * 256 + (threadIdx.x >> 6) * 32 + cl;
+#pragma unroll
+    for (int s = 0; s < 16; ++s) H.x[s] = bcur[s];
+    H.av = A.a[coln];
+    H.bv = A.b[coln];
+  }
+}
+
+template <int NP>
+__device__ __forceinline__ void collide_res_acc(const CollideArgs& A, const float* Ps, int tile,
+                                                floatx16 (&acc)[NP / 32], double& absorbed,
+                                                double& total) {
+  TileHead H;
+  load_tile_head(A, tile, H);
+  collide_res_acc<NP>(A, Ps, tile, acc, absorbed, total, H, -1);
 }
 
 // Stores a tile's accumulators (the layout of collide_res_acc) to Y.
@@ -436,39 +477,36 @@ __device__ __forceinline__ void load_p_bf16_lds(const uint16_t* __restrict__ Phi
   }
 }
 
+// The bf16-split form of collide_res_acc (same layouts; H as there).
 template <int NP>
 __device__ __forceinline__ void collide_bf16_res_acc(const CollideArgs& A, const uint16_t* Sh,
                                                      const uint16_t* Sl, int tile,
                                                      floatx16 (&acc)[NP / 32], double& absorbed,
-                                                     double& total) {
+                                                     double& total, TileHead& H, int next) {
   constexpr int NQ = NP / 32;
   constexpr int LDK = NP + 8;
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int lane = threadIdx.x & 63;
   const int hl = lane >> 5, cl = lane & 31;
-  const size_t rowbytes = size_t(A.Vp) * sizeof(float);
-  const long long col = (long long)tile * 256 + wave * 32 + cl;
-  const unsigned voff = unsigned(size_t(col) * sizeof(float) + size_t(4 * hl) * rowbytes);
-  const char* __restrict__ xb0 = reinterpret_cast<const char*>(A.X);
+  const unsigned voff = tile_lane_offset(A, tile);
+  const unsigned voffn = tile_lane_offset(A, next >= 0 ? next : tile);
   const uint16_t* __restrict__ Ph = Sh + cl * LDK + 8 * hl;
   const uint16_t* __restrict__ Pl = Sl + cl * LDK + 8 * hl;
-  const float av = A.a[col], bv = A.b[col];
+  const float av = H.av, bv = H.bv;
 #pragma unroll
   for (int q = 0; q < NQ; ++q)
 #pragma unroll
     for (int r = 0; r < 16; ++r) acc[q][r] = 0.0f;
-  auto ld = [&](int c, int s) {
-    const char* rb = xb0 + size_t(32 * c + 8 * (s >> 2) + (s & 3)) * rowbytes;
-    return *reinterpret_cast<const float*>(rb + voff);
-  };
   float bcur[16], bnext[16];
 #pragma unroll
-  for (int s = 0; s < 16; ++s) bcur[s] = ld(0, s);
+  for (int s = 0; s < 16; ++s) bcur[s] = H.x[s];
   double colsum64 = 0.0;
 #pragma unroll 1
   for (int c = 0; c < NQ; ++c) {
-    const int cn = c + 1 < NQ ? c + 1 : c;
+    const bool last = c + 1 == NQ;
+    const unsigned vo = last ? voffn : voff;
+    const int cn = last ? 0 : c + 1;
 #pragma unroll
-    for (int s = 0; s < 16; ++s) bnext[s] = ld(cn, s);
+    for (int s = 0; s < 16; ++s) bnext[s] = tile_x(A, vo, cn, s);
     float colsum = 0.0f;
 #pragma unroll
     for (int s = 0; s < 16; ++s) colsum += bcur[s];
@@ -504,6 +542,23 @@ __device__ __forceinline__ void collide_bf16_res_acc(const CollideArgs& A, const
   }
   absorbed += (1.0 - double(av) - double(bv)) * colsum64;
   total += colsum64;
+  if (next >= 0) {
+    const long long coln = (long long)next * 256 + (threadIdx.x >> 6) * 32 + cl;
+#pragma unroll
+    for (int s = 0; s < 16; ++s) H.x[s] = bcur[s];
+    H.av = A.a[coln];
+    H.bv = A.b[coln];
+  }
+}
+
+template <int NP>
+__device__ __forceinline__ void collide_bf16_res_acc(const CollideArgs& A, const uint16_t* Sh,
+                                                     const uint16_t* Sl, int tile,
+                                                     floatx16 (&acc)[NP / 32], double& absorbed,
+                                                     double& total) {
+  TileHead H;
+  load_tile_head(A, tile, H);
+  collide_bf16_res_acc<NP>(A, Sh, Sl, tile, acc, absorbed, total, H, -1);
 }
 
 template <int NP>
@@ -798,17 +853,23 @@ __global__ __launch_bounds__(512, 1) void collide_move_kernel(CollideArgs A, Inj
   B.X = reinterpret_cast<const float*>(reinterpret_cast<const char*>(A.pp) + S.so);
   double absorbed = 0.0, total = 0.0, dom = 0.0;
   double esc[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
-#pragma unroll 1
-  for (int i = 0; i < per; ++i) {
+  auto tile_of = [&](int i) {
     const int s = int(blockIdx.x) * per + i;
-    if (s >= ntiles) break;
-    const int tile = int((long long)s * A.mvscramble % ntiles);
+    return s < ntiles ? int((long long)s * A.mvscramble % ntiles) : -1;
+  };
+  TileHead H;
+  int tile = tile_of(0);
+  if (tile >= 0) load_tile_head(B, tile, H);
+#pragma unroll 1
+  for (int i = 0; i < per && tile >= 0; ++i) {
+    const int next = i + 1 < per ? tile_of(i + 1) : -1;
     floatx16 acc[NP / 32];
     if (BF16)
-      collide_bf16_res_acc<NP>(B, Sh, Sl, tile, acc, absorbed, total);
+      collide_bf16_res_acc<NP>(B, Sh, Sl, tile, acc, absorbed, total, H, next);
     else
-      collide_res_acc<NP>(B, Pm, tile, acc, absorbed, total);
+      collide_res_acc<NP>(B, Pm, tile, acc, absorbed, total, H, next);
     move_epilogue<NP>(A, sdesc, S, acc, tile, esc, dom);
+    tile = next;
   }
   move_sums(A, absorbed, total, esc, dom, blockIdx.x, gridDim.x);
 }
