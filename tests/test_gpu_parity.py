@@ -156,6 +156,32 @@ def test_ragged_noisy_medium(advance, coef, nside):
     assert budget_closure(got["budget"]) < closure_bound(got["budget"])
 
 
+@pytest.mark.parametrize("ndet,nside", [(8, 4), (64, 8)])
+def test_detector_records_with_many_pairs(ndet, nside):
+    """Up to 2048 (detector, direction) pairs the read-out forms one pair's term
+    per thread, beyond that each detector forms its own.  8 detectors of 192
+    directions stay below (at most the 96 upward directions each); 64 top-face
+    detectors (the most a medium takes) of 768 directions with a wide cone go
+    above: from a top-face voxel every direction whose dominant axis is +z
+    leaves through the top face."""
+    from oracle import angles
+    dirs = angles.healpix_ring(nside)
+    zdom = int(np.sum(dirs[:, 2] > np.maximum(np.abs(dirs[:, 0]), np.abs(dirs[:, 1]))))
+    up = int(np.sum(dirs[:, 2] > 0))
+    assert ndet * up <= 2048 if ndet == 8 else ndet * zdom > 2048
+    nx, ny, nz = 16, 12, 8
+    cells = np.random.default_rng(ndet).choice(nx * ny, ndet, replace=False)
+    dets = ([W.FACE_TOP] * ndet, [int(c % nx) for c in cells], [int(c // nx) for c in cells])
+    p = W.small_problem(nside=nside, nx=nx, ny=ny, nz=nz, mua=0.05, mus=2.0, g=0.8, steps=30,
+                        seed=11, advance="phase", det_cone_deg=89.0, dets=dets)
+    ref = solve.forward(p)
+    got = run_gpu(p)
+    assert got["steps"].shape == ref.det.shape == (ndet, 30)
+    assert rel_l2_above(got["steps"].ravel(), ref.det.ravel()) < 1e-4
+    for k in range(ndet):
+        assert rel_l2_above(got["steps"][k], ref.det[k]) < 1e-4, k
+
+
 def test_refraction_air_cylinder():
     """Split mode with an air cylinder: Fresnel interception and gather."""
     p = W.config3(nx=24).copy(nside=2, steps=80, nbins=400)
