@@ -79,3 +79,51 @@ def test_absorption_derivative_without_scattering():
     want = np.sum(seed * res.det * (-ell * (m + 1))[None, :])
     assert res.det.sum() > 0.5
     assert abs(gmua.sum() - want) < 1e-10 * abs(want)
+
+
+@pytest.mark.parametrize("coef", ["paper", "abs_exact"])
+def test_coefficient_derivatives_match_finite_differences(coef):
+    """The chain-rule factors da/dmu and db/dmu of both coefficient forms
+    against central differences of the coefficients themselves (which the
+    impulse pins tie to Eq. 9-10 and to the abs_exact factorisation), over
+    thin, moderate and thick voxels, including a voxel without absorption."""
+    from oracle import medium
+    mua = np.array([0.0, 1e-3, 0.01, 0.05, 0.3, 2.0, 0.02])
+    mus = np.array([0.5, 10.0, 8.0, 1.5, 0.0, 3.0, 1e-4])
+    n = np.array([1.4, 1.0, 1.5, 1.33, 1.4, 1.6, 1.0])
+    dt = 4.67
+    an = medium.coefficient_derivatives(mua, mus, n, dt, coef)
+    for k, (which, i_a, i_b) in enumerate((("mua", 0, 2), ("mus", 1, 3))):
+        h = 1e-5 * np.maximum(mua if which == "mua" else mus, 1e-2)
+        def coeffs(delta):
+            if which == "mua":
+                a, b, _, _ = medium.collision_coefficients(mua + delta, mus, n, dt, coef)
+            else:
+                a, b, _, _ = medium.collision_coefficients(mua, mus + delta, n, dt, coef)
+            return a, b
+        ap, bp = coeffs(h)
+        am, bm = coeffs(-h)
+        fd_a = (ap - am) / (2 * h)
+        fd_b = (bp - bm) / (2 * h)
+        ok = (mua if which == "mua" else mus) > 0      # central difference stays in mu >= 0
+        # truncation ~ h^2, rounding ~ 1e-16 / h: both far below the tolerance
+        np.testing.assert_allclose(an[i_a][ok], fd_a[ok], rtol=1e-6, atol=1e-9)
+        np.testing.assert_allclose(an[i_b][ok], fd_b[ok], rtol=1e-6, atol=1e-9)
+
+
+def test_gradient_matches_finite_differences_abs_exact():
+    """The whole adjoint with the abs_exact coefficients (db/dmu of that form)
+    against central differences of the loss."""
+    p = _problem("phase").copy(coef="abs_exact")
+    ref = p.copy(mua=(p.mua * 1.3).astype(np.float32))
+    target = solve.forward(ref).binned(p.bin_ps, p.nbins)
+    gmua, gmus, L = adjoint.gradient(p, target)
+    assert L > 0
+    rng = np.random.default_rng(56)
+    vox = rng.choice(p.nvox, 6, replace=False)
+    for which, g in (("mua", gmua), ("mus", gmus)):
+        fd = adjoint.finite_difference(p, target, vox, 1e-4, which)
+        ad = g.ravel()[vox]
+        scale = np.abs(ad).max()
+        assert scale > 0
+        assert np.abs(fd - ad).max() < 1e-6 * scale + 1e-8 * np.abs(g).max(), (which, fd, ad)

@@ -131,6 +131,24 @@ def test_discrete_anisotropy_regression():
     assert 0.95 < ge < 0.99
 
 
+def test_mean_cosine_hand_worked_and_limits():
+    """mean_cosine against a hand-worked 2-direction case (60 degrees apart,
+    columns = incoming directions: column 0 scatters 0.7 forward and 0.3 at
+    60 degrees, column 1 0.2 and 0.8: (0.7 + 0.15 + 0.1 + 0.8) / 2 = 0.875),
+    the identity matrix (no deflection: 1), the isotropic g = 0 matrix on
+    HEALPix directions (sum of the directions is zero: 0), and convergence to
+    the continuum g as the grid refines (within 1 % at nside 16, g = 0.5)."""
+    d2 = np.array([[0.0, 0.0, 1.0], [math.sqrt(3) / 2, 0.0, 0.5]])
+    P2 = np.array([[0.7, 0.2], [0.3, 0.8]])
+    assert abs(angles.mean_cosine(P2, d2) - 0.875) < 1e-15
+    d = angles.healpix_ring(4)
+    assert abs(angles.mean_cosine(np.eye(len(d)), d) - 1.0) < 1e-14
+    assert abs(angles.mean_cosine(angles.phase_matrix(d, 0.0), d)) < 1e-14
+    d16 = angles.healpix_ring(16)
+    g16 = angles.mean_cosine(angles.phase_matrix(d16, 0.5), d16)
+    assert abs(g16 - 0.5) < 0.005, g16
+
+
 def _eq9_by_quadrature(tau):
     """f0 and f1 straight from Eqs. (7)-(8): the source varies linearly in tau'
     between S0 at the upwind point and S1 at the current one, weighted by

@@ -34,6 +34,61 @@ def test_beer_lambert_impulse():
     assert np.allclose(r1.escaped, r0.escaped * fac[:, None], rtol=1e-13, atol=0)
 
 
+@pytest.mark.parametrize("advance", ["phase", "split"])
+def test_abs_exact_impulse_with_scattering(advance):
+    """coef="abs_exact" with scattering on: a = e^{-mu_a l} e^{-mu_s l} and
+    b = e^{-mu_a l} (1 - e^{-mu_s l}) are the mu_a = 0 coefficients times
+    e^{-mu_a l}, so with a uniform mu_a every collision scales the whole field by
+    e^{-mu_a l} whatever mu_s does, and for an impulse
+    det(mu_a)[m] = det(0)[m] e^{-mu_a l (m+1)} exactly, as without scattering.
+    The paper's form b = omega (1 - a) does not factor this way (checked below),
+    so a wrong b, a dropped factor or a sign error in either exponent fails."""
+    shape = (9, 8, 10)
+    n = 1.4
+    base = W.small_problem(nside=2, nx=10, ny=8, nz=9, mua=0.0, mus=2.0, g=0.8, n=n,
+                           steps=24, total_photons=0.0, det_cone_deg=0.0, seed=17,
+                           coef="abs_exact", advance=advance,
+                           dets=([4, 4, 1, 3, 5], [3, 6, 4, 2, 5], [4, 5, 6, 7, 3]))
+    base = base.copy(mua=np.zeros(shape, np.float32))
+    if advance == "split":
+        # a second index in a slab: split mode with per-voxel move fractions
+        nn = base.n.copy()
+        nn[5:] = 1.6
+        base = base.copy(n=nn)
+    rng = np.random.default_rng(9)
+    N0 = np.zeros((48, base.nvox))
+    N0[:, rng.integers(0, base.nvox, 8)] = rng.uniform(0.5, 1.0, (48, 8))
+    r0 = solve.forward(base, S=solve.build(base), state0=N0)
+    mua = float(np.float32(0.04))
+    p = base.copy(mua=np.full(shape, mua, np.float32))
+    S1 = solve.build(p)
+    r1 = solve.forward(p, S=S1, state0=N0)
+    # per-voxel path per step (split mode: two indices)
+    ell = S1.ell.reshape(-1)
+    assert r0.det.sum() > 1e-3 and r0.in_domain[-1] > 1e-3
+    if advance == "phase":
+        fac = np.exp(-mua * ell[0] * (np.arange(24) + 1))
+        assert np.allclose(r1.det, r0.det * fac[None, :], rtol=1e-12, atol=0)
+        assert np.allclose(r1.escaped, r0.escaped * fac[:, None], rtol=1e-12, atol=0)
+        assert np.allclose(r1.in_domain, r0.in_domain * fac, rtol=1e-12, atol=0)
+    else:
+        # with two path lengths the factor depends on where the light collided;
+        # it lies between the two uniform-path factors, and equals the slower
+        # medium's factor where only that medium was ever visited
+        lo = np.exp(-mua * ell.max() * (np.arange(24) + 1))
+        hi = np.exp(-mua * ell.min() * (np.arange(24) + 1))
+        ok = r0.in_domain > 0
+        q = r1.in_domain[ok] / r0.in_domain[ok]
+        assert np.all(q <= hi[ok] * (1 + 1e-12)) and np.all(q >= lo[ok] * (1 - 1e-12))
+    # the paper's coefficient form has no such factorisation
+    pp = p.copy(coef="paper")
+    rp = solve.forward(pp, S=solve.build(pp), state0=N0)
+    rp0 = solve.forward(base.copy(coef="paper"), S=solve.build(base.copy(coef="paper")),
+                        state0=N0)
+    if advance == "phase":
+        assert not np.allclose(rp.in_domain, rp0.in_domain * fac, rtol=1e-6, atol=0)
+
+
 @pytest.mark.parametrize("advance,coef,mua", [("phase", "paper", 0.0), ("phase", "paper", 0.05),
                                               ("split", "paper", 0.02),
                                               ("phase", "abs_exact", 0.05)])
