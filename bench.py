@@ -1,11 +1,15 @@
 """Benchmark of the TRINITY time step on one MI355X.
 
 A step is one pass of the whole hot path (inject, scattering contraction,
-transport, tallies) over the phantom-scale workload: a 64^3 voxel grid
-with +-5% voxel noise, 192 HEALPix directions (the Sec. 3.1 phantom shape on
-synthetic data).  The metric is voxel x direction x step updates per second,
-with the state resident in HBM.  Kernel durations come from HIP events
-recorded around every kernel on the medium's stream inside the timed region.
+transport with Fresnel interception and gather, tallies) over the
+heterogeneous refraction workload: a 128^3 voxel grid at 1 mm with an air
+cylinder (n = 1.0) inside n = 1.4 tissue and three absorbing spheres,
+768 HEALPix directions (nside 8), split advance (the air-hole study of
+Sec. 3.3 on synthetic data).  The headline is the FP32 solve; the BF16-split
+contraction of the same workload is reported beside it.  The metric is
+voxel x direction x step updates per second with the state resident in HBM.
+Kernel durations come from HIP events recorded around every kernel on the
+medium's stream inside the timed region.
 
 Prints one JSON line.  Usage: python bench.py [--gpus 1] [--steps K] [--warmup W]
 """
@@ -22,6 +26,10 @@ METRIC = ("voxel·direction·step updates/s (FP32 vs BF16-split); "
           "p50/p99 solve latency")
 PEAK_HBM_GBS = 8000.0
 PEAK_TFLOPS = {"fp32": 157.3, "bf16split": 2500.0}   # dense MFMA peaks
+# bf16 MFMA products per term of the BF16-split contraction (P_hi x_hi, P_hi x_lo,
+# P_lo x_hi, P_lo x_lo) and the dtype label they give
+BF16_PRODUCTS = 4
+BF16_DTYPE = f"bf16x{BF16_PRODUCTS}-f32acc"
 
 
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "hbm_traffic_collide_sweep.txt")
@@ -76,7 +84,7 @@ def kernel_rooflines(prof, prob, precision, workload="phantom64"):
     also moves every value to its downwind voxel, within the same 8 N V bytes.
 
     collide, FP32: 2 N^2 V FLOP on the FP32 MFMA peak.  collide, BF16-split:
-    the four hi/lo products execute 8 N^2 V bf16 FLOP; at few directions the
+    the hi/lo products execute 2 BF16_PRODUCTS N^2 V bf16 FLOP; at few directions the
     kernel is bound by its 8 N V bytes (read X, write Y) instead, and the
     binding roofline (the larger fraction) is reported, with the effective
     FP32-equivalent rate 2 N^2 V / t beside it.  sweep: 8 N V bytes (read the
@@ -92,7 +100,7 @@ def kernel_rooflines(prof, prob, precision, workload="phantom64"):
                               "unit": "TFLOP/s", "frac": flop / t / 1e12 / 157.3,
                               "avg_ms": ms / n, "work_per_launch": flop}
         else:
-            flop = 8.0 * N * N * V
+            flop = 2.0 * BF16_PRODUCTS * N * N * V
             byt = 8.0 * N * V
             f_mfma = flop / t / 1e12 / PEAK_TFLOPS["bf16split"]
             f_hbm = byt / t / 1e9 / PEAK_HBM_GBS
@@ -126,27 +134,40 @@ def step_roofline(prob, precision, ms_per_step):
     if precision == "fp32":
         t_mfma = 2.0 * N * N * V / (PEAK_TFLOPS["fp32"] * 1e12)
     else:
-        t_mfma = 8.0 * N * N * V / (PEAK_TFLOPS["bf16split"] * 1e12)
+        t_mfma = 2.0 * BF16_PRODUCTS * N * N * V / (PEAK_TFLOPS["bf16split"] * 1e12)
     t_hbm = 8.0 * N * V / (PEAK_HBM_GBS * 1e9)
     t_min = max(t_mfma, t_hbm)
     return {"bound": "mfma" if t_mfma >= t_hbm else "hbm", "min_ms": t_min * 1e3,
             "ms_per_step": ms_per_step, "frac": t_min * 1e3 / ms_per_step}
 
 
-def oracle_error(prob, det_steps):
-    """Relative L2 error of per-step detector records against the stored FP64
-    oracle run of the same phantom (bins above 1e-6 of the peak)."""
+def stored_oracle(name):
+    """Records of a stored FP64 oracle run (tests/golden/make_golden.py), or None."""
     import numpy as np
-    path = os.path.join(ROOT, "tests", "golden", "phantom64_oracle.npz")
-    if not os.path.exists(path):
+    path = os.path.join(ROOT, "tests", "golden", name + "_oracle.npz")
+    return np.load(path) if os.path.exists(path) else None
+
+
+def rel_l2_above(got, ref, floor=1e-6):
+    """Relative L2 over the bins whose reference exceeds floor * (its peak)."""
+    import numpy as np
+    mask = ref > floor * ref.max()
+    if not mask.any():
         return None
-    ref = np.load(path)["det"]
-    k = min(ref.shape[1], det_steps.shape[1])
-    if k < ref.shape[1]:
-        return None
-    got, ref = det_steps[:, :k].ravel(), ref[:, :k].ravel()
-    mask = ref > 1e-6 * ref.max()
     return float(np.linalg.norm(got[mask] - ref[mask]) / np.linalg.norm(ref[mask]))
+
+
+def oracle_error(name, det_steps):
+    """Relative L2 error of per-step detector records against the first k steps
+    of the stored FP64 oracle run of the same workload (k = the steps run; bins
+    above 1e-6 of the compared records' peak).  None without stored records or
+    signal."""
+    z = stored_oracle(name)
+    if z is None:
+        return None
+    ref = z["det"]
+    k = min(ref.shape[1], det_steps.shape[1])
+    return rel_l2_above(det_steps[:, :k].ravel(), ref[:, :k].ravel())
 
 
 def timed_run(prob, steps, warmup, stream):
@@ -203,12 +224,13 @@ def latency(prob, solves, stream):
     return float(np.percentile(times, 50)), float(np.percentile(times, 99))
 
 
-def serving(stream, count=16):
-    """Batched server on the first `count` requests of the seeded serving
-    stream (Poisson arrivals at 200/s, grids 32^3 .. 96^3, 192 directions,
-    500-1500 steps): p50/p99 latency with queueing, once at the offered rate
-    (far above capacity) and once with arrivals stretched to 0.8 x the
-    measured capacity."""
+def serving(stream, count=200, count_low=50):
+    """Batched server on the seeded serving stream (Poisson arrivals at 200/s,
+    grids 32^3 .. 96^3, 192 directions, 500-1500 steps): p50/p99 latency with
+    queueing over the first `count` arrivals at the offered rate (far above
+    capacity: 200 arrivals are one second of traffic), and over the first
+    `count_low` arrivals stretched to 0.8 x the capacity measured in the first
+    run."""
     import numpy as np
 
     from paper_2105_01028_amd import serve
@@ -217,15 +239,17 @@ def serving(stream, count=16):
     import torch
     reqs = W.serving_stream(count, seed=4)
     work = [r.problem.nvox * 192 * r.problem.steps for r in reqs]
-    out = {"requests": count, "updates": float(sum(work))}
+    count_low = min(count, count_low)
+    out = {"requests": count, "updates": float(sum(work)), "requests_at_0.8_capacity": count_low}
     with torch.cuda.stream(stream):
         srv = T.Server(nside=4, g=0.85, budget_bytes=32 << 30, max_slots=16)
         sat = serve.run_stream(srv, reqs, chunk_steps=64)
         cap = sum(work) / sat["wall_s"]
         print(f"serving: {count} requests at the offered rate in {sat['wall_s']:.1f} s",
               file=sys.stderr, flush=True)
-        ts = 200.0 * (sum(work) / count) / (0.8 * cap)
-        low = serve.run_stream(srv, reqs, chunk_steps=64, time_scale=ts)
+        low_reqs = reqs[:count_low]
+        ts = 200.0 * (sum(work[:count_low]) / count_low) / (0.8 * cap)
+        low = serve.run_stream(srv, low_reqs, chunk_steps=64, time_scale=ts)
         srv.close()
     for key, r in (("offered_200_per_s", sat), ("offered_0.8_capacity", low)):
         lat = r["latency_s"] * 1e3
@@ -510,90 +534,239 @@ def paper_fiducial(stream, steps=20):
             "paper_run_s_over_this": 20 * 3600.0 / run_s}
 
 
-def cpu_baseline(prob, budget_s=15.0):
-    """The FP64 oracle on the host cores, on the first steps of the same workload."""
+def c3_subbox(prob, x0=62, x1=66, y0=0, y1=128, z0=0, z1=128):
+    """A sub-box of the 128^3 refraction medium: by default a slab four voxels
+    thick across the cylinder's axis (x), so it holds the whole y-z cross
+    section (the air cylinder's wall, tissue, the spheres the slab cuts) with
+    about the full medium's density of interceptions (1.00 against 1.16 per
+    voxel).  Source and detectors on the sub-box's own top face."""
+    import numpy as np
+    sl = (slice(z0, z1), slice(y0, y1), slice(x0, x1))
+    nx, ny, nz = x1 - x0, y1 - y0, z1 - z0
+    return prob.copy(nx=nx, ny=ny, nz=nz, mua=np.ascontiguousarray(prob.mua[sl]),
+                     mus=np.ascontiguousarray(prob.mus[sl]), n=np.ascontiguousarray(prob.n[sl]),
+                     src_ix=nx // 2 - 1, src_iy=ny // 2 - 1, det_face=[4, 4],
+                     det_i=[nx // 2 + 4, nx // 2 + 8], det_j=[ny // 2, ny // 2])
+
+
+def cpu_baseline(prob, budget_s=15.0, single_budget_s=12.0):
+    """The FP64 oracle on the host cores, on a bounded sample of the workload:
+    the first steps of a sub-box of the same medium (c3_subbox), set-up
+    excluded, scaled to updates/s (so the full-size figure is extrapolated
+    from the sample).  Timed once with the BLAS pool at its default size and
+    once single-threaded."""
     from oracle import solve
+    from threadpoolctl import threadpool_info, threadpool_limits
+    q = c3_subbox(prob)
     t_setup = time.perf_counter()
-    S = solve.build(prob)
-    t0 = time.perf_counter()
-    res = None
-    steps = 0
-    while time.perf_counter() - t0 < budget_s or steps < 2:
-        res = solve.forward(prob, steps=1, S=S, state0=None if res is None else res.state,
-                            start_step=steps)
-        steps += 1
-    el = time.perf_counter() - t0
+    S = solve.build(q, steps=64)
+    setup_s = time.perf_counter() - t_setup
+
+    def run(budget):
+        t0 = time.perf_counter()
+        res, steps = None, 0
+        while time.perf_counter() - t0 < budget or steps < 2:
+            res = solve.forward(q, steps=1, S=S, state0=None if res is None else res.state,
+                                start_step=steps)
+            steps += 1
+        return steps, time.perf_counter() - t0
+
+    pools = threadpool_info()
+    threads = max([i.get("num_threads", 1) for i in pools] + [1])
+    steps, el = run(budget_s)
+    with threadpool_limits(limits=1):
+        steps1, el1 = run(single_budget_s)
     try:
-        from threadpoolctl import threadpool_info
-        cores = max([i.get("num_threads", 1) for i in threadpool_info()] + [1])
+        affinity = len(os.sched_getaffinity(0))
     except Exception:
-        cores = os.cpu_count()
-    return {"value": prob.nvox * prob.ndir * steps / el, "unit": "updates/s", "cores": cores,
-            "kind": "oracle",
-            "sample": f"first {steps} steps of the same 64^3 x 192 workload, FP64 NumPy "
-                      f"(set-up {t0 - t_setup:.1f} s excluded)"}
+        affinity = os.cpu_count()
+    upd = q.nvox * q.ndir
+    return {"value": upd * steps / el, "unit": "updates/s", "cores": threads, "kind": "oracle",
+            "sample": f"first {steps} steps of a {q.nx}x{q.ny}x{q.nz} slab of the 128^3 "
+                      f"refraction medium across the air cylinder ({len(S.icpt)} interceptions), "
+                      f"768 directions, FP64 NumPy with {threads} BLAS threads; set-up "
+                      f"{setup_s:.1f} s excluded; the full-size rate is extrapolated from it",
+            "nproc": os.cpu_count(), "cpus_available": affinity,
+            "single_thread": {"value": upd * steps1 / el1, "unit": "updates/s", "cores": 1,
+                              "steps": steps1}}
+
+
+def c3_accuracy(stream, steps=300):
+    """Detector records of the 128^3 x 768 refraction solve in BF16-split
+    against the plain FP32 solve over the first `steps` steps (relative L2 on
+    bins above 1e-6 of the FP32 peak), and both budget closures."""
+    import numpy as np
+    import torch
+
+    from paper_2105_01028_amd import trinity as T
+    from paper_2105_01028_amd import workloads as W
+    out = {"steps": steps}
+    recs = {}
+    for prec in ("fp32", "bf16split"):
+        with torch.cuda.stream(stream):
+            m = T.Medium.from_problem(W.config3().copy(precision=prec))
+            m.solve(steps)
+            recs[prec] = m.read_detector_steps()
+            b = m.read_budget()
+            m.close()
+        inj = b[:, 0].sum()
+        out[prec + "_budget_closure"] = float(
+            abs(inj - b[:, 1].sum() - b[:, 3:].sum() - b[-1, 2]) / inj)
+    out["bf16split_vs_fp32_rel_l2"] = rel_l2_above(recs["bf16split"].ravel(),
+                                                   recs["fp32"].ravel())
+    out["fp32_detector_peak"] = float(recs["fp32"].max())
+    return out
+
+
+def refraction32_vs_oracle(stream):
+    """The same path (768 directions, split advance, air cylinder with Fresnel
+    interfaces, spheres) on the medium scaled to 32^3, where the FP64 oracle's
+    stored 200-step run exists: detector rel L2 and the largest relative error
+    of any voxel's energy density, FP32 and BF16-split."""
+    import numpy as np
+    import torch
+
+    from paper_2105_01028_amd import trinity as T
+    from paper_2105_01028_amd import workloads as W
+    z = stored_oracle("refraction32")
+    if z is None:
+        return None
+    steps = int(z["steps"])
+    out = {"workload": "32^3 scaled refraction medium, 768 directions, split advance",
+           "steps": steps}
+    for prec in ("fp32", "bf16split"):
+        with torch.cuda.stream(stream):
+            m = T.Medium.from_problem(W.config3(nx=32).copy(precision=prec))
+            m.solve(steps)
+            det = m.read_detector_steps()
+            E = m.read_energy().astype(np.float64)
+            m.close()
+        Eref = z["energy"]
+        big = Eref > 1e-6 * Eref.max()
+        out[prec] = {"rel_l2_vs_fp64_oracle": rel_l2_above(det.ravel(), z["det"].ravel()),
+                     "energy_max_rel_error": float(np.max(np.abs(E[big] - Eref[big]) / Eref[big]))}
+    return out
+
+
+def phantom64_accuracy(stream):
+    """The 64^3 x 192 phantom for its full 1000 steps in FP32 and BF16-split
+    (moves in the collision kernel) against the stored FP64 oracle records."""
+    import torch
+
+    from paper_2105_01028_amd import trinity as T
+    from paper_2105_01028_amd import workloads as W
+    out = {}
+    for prec in ("fp32", "bf16split"):
+        p = W.config2().copy(precision=prec)
+        with torch.cuda.stream(stream):
+            m = T.Medium.from_problem(p)
+            m.solve(p.steps)
+            det = m.read_detector_steps()
+            m.close()
+        out[prec] = oracle_error("phantom64", det)
+    return out
+
+
+def phantom64(stream, K, Wm):
+    """The 64^3 x 192 phantom (uniform n, phase advance: the moves in the
+    collision kernel), FP32 and BF16-split, and both with the separate sweep
+    kernel."""
+    from paper_2105_01028_amd import workloads as W
+    prob = W.config2()
+    updates = prob.nvox * prob.ndir * K
+    out = {"workload": "phantom 64^3, 1 mm voxels, +-5% noise, 192 directions (nside 4), "
+                       "phase advance"}
+    for prec in ("fp32", "bf16split"):
+        e, g, p, c, d, fused = timed_run(prob.copy(precision=prec), K, Wm, stream)
+        out[prec] = {"value": updates / g, "ms_per_step": g / K * 1e3,
+                     "step_roofline": step_roofline(prob, prec, g / K * 1e3),
+                     "kernels_ms": {k: v[0] / v[1] for k, v in p.items() if v[1]},
+                     "instrumented_value": updates / e,
+                     "kernel_rooflines": kernel_rooflines(
+                         p, prob, prec, "phantom64" if fused else "phantom64-sweep"),
+                     "budget_closure": c,
+                     "rel_l2_vs_fp64_oracle_first_steps": oracle_error("phantom64", d)}
+        e3, g3, p3, _, _, _ = timed_run(prob.copy(precision=prec, transport="sweep"), K, Wm,
+                                        stream)
+        out["separate_sweep_" + prec] = {
+            "value": updates / g3, "ms_per_step": g3 / K * 1e3,
+            "step_roofline": step_roofline(prob, prec, g3 / K * 1e3),
+            "kernels_ms": {k: v[0] / v[1] for k, v in p3.items() if v[1]}}
+    return out
+
+
+C3_WORKLOAD = ("heterogeneous 128^3 at 1 mm: n = 1.4 tissue (mu_a 0.01, mu_s 10 /mm, g 0.9) "
+               "with a 6 mm air cylinder (n = 1.0, Fresnel interfaces) and 3 absorbing spheres, "
+               "768 directions (nside 8), split advance, dt = 3.336 ps")
 
 
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=1000)
-    ap.add_argument("--warmup", type=int, default=50)
+    ap.add_argument("--steps", type=int, default=100)
+    ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--precision", default="fp32", choices=["fp32", "bf16split"])
     ap.add_argument("--transport", default="auto", choices=["auto", "sweep"],
-                    help="auto: phase moves in the collision kernel; sweep: separate sweep kernel")
+                    help="phantom64 workload only -- auto: phase moves in the collision kernel; "
+                         "sweep: separate sweep kernel")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true")
-    ap.add_argument("--workload", default="phantom64",
-                    choices=["phantom64", "refraction128", "twolevel64", "retarded64",
-                             "fiducial101", "serving"],
-                    help="refraction128, twolevel64, retarded64: only time that medium "
-                         "(profiling runs)")
-    ap.add_argument("--serving-requests", type=int, default=16,
-                    help="requests of the serving stream (workload 'serving' or the extra)")
+    ap.add_argument("--workload", default="refraction128",
+                    choices=["refraction128", "refraction128-steps", "phantom64", "twolevel64",
+                             "retarded64", "fiducial101", "serving"],
+                    help="refraction128: the headline line; the others only time that "
+                         "medium (profiling runs)")
+    ap.add_argument("--serving-requests", type=int, default=200,
+                    help="arrivals of the serving stream (workload 'serving' or the extra)")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="BYTES",
                     help="only run a plain device copy of BYTES (counter calibration)")
     args = ap.parse_args()
-    if args.copy_probe:
-        copy_probe(args.copy_probe)
-        return
-    if args.workload == "serving":
-        import torch
-        print(json.dumps(serving(torch.cuda.Stream(), args.serving_requests)), flush=True)
-        return
-    if args.workload == "fiducial101":
-        import torch
-        print(json.dumps(paper_fiducial(torch.cuda.Stream(), args.steps)), flush=True)
-        return
-    if args.workload == "retarded64":
-        import torch
-        print(json.dumps(retarded(torch.cuda.Stream(), args.steps)), flush=True)
-        return
-    if args.workload == "twolevel64":
-        import torch
-        print(json.dumps(two_level(torch.cuda.Stream(), args.steps)), flush=True)
-        return
-    if args.workload == "refraction128":
-        import torch
-        print(json.dumps(refraction128(torch.cuda.Stream(), args.steps, (args.precision,))),
-              flush=True)
-        return
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only; --gpus {args.gpus} is not supported "
               "(the multi-GPU z-slab decomposition is a design, not part of this build)",
               file=sys.stderr)
         sys.exit(2)
-
+    if args.copy_probe:
+        copy_probe(args.copy_probe)
+        return
     import torch
+    if args.workload == "serving":
+        print(json.dumps(serving(torch.cuda.Stream(), args.serving_requests)), flush=True)
+        return
+    if args.workload == "refraction128-steps":
+        print(json.dumps(refraction128(torch.cuda.Stream(), args.steps, (args.precision,))),
+              flush=True)
+        return
+    if args.workload == "fiducial101":
+        print(json.dumps(paper_fiducial(torch.cuda.Stream(), args.steps)), flush=True)
+        return
+    if args.workload == "retarded64":
+        print(json.dumps(retarded(torch.cuda.Stream(), args.steps)), flush=True)
+        return
+    if args.workload == "twolevel64":
+        print(json.dumps(two_level(torch.cuda.Stream(), args.steps)), flush=True)
+        return
+    if args.workload == "phantom64":
+        from paper_2105_01028_amd import workloads as W
+        prob = W.config2().copy(precision=args.precision, transport=args.transport)
+        e, g, p, c, d, fused = timed_run(prob, args.steps, args.warmup, torch.cuda.Stream())
+        print(json.dumps({"workload": "phantom64", "precision": args.precision,
+                          "ms_per_step": g / args.steps * 1e3,
+                          "kernels_ms": {k: v[0] / v[1] for k, v in p.items() if v[1]},
+                          "kernel_rooflines": kernel_rooflines(
+                              p, prob, args.precision,
+                              "phantom64" if fused else "phantom64-sweep")}), flush=True)
+        return
 
     from paper_2105_01028_amd import workloads as W
     assert torch.cuda.is_available(), "bench.py needs the GPU"
     stream = torch.cuda.Stream()
-    prob = W.config2().copy(precision=args.precision, transport=args.transport)
     K, Wm = args.steps, args.warmup
-    el, el_graph, prof, closure, det_steps, fused = timed_run(prob, K, Wm, stream)
+    base = W.config3()
+    prob = base.copy(precision=args.precision)
+    el, el_graph, prof, closure, det_steps, _ = timed_run(prob, K, Wm, stream)
     updates = prob.nvox * prob.ndir * K
-    roof = kernel_rooflines(prof, prob, args.precision, "phantom64" if fused else "phantom64-sweep")
+    roof = kernel_rooflines(prof, prob, args.precision, "refraction128")
     dom = max(("collide", "sweep"), key=lambda k: prof[k][0])
     rl = dict(roof[dom])
     rl["kernel"] = dom
@@ -603,12 +776,10 @@ def main():
         "metric": METRIC, "value": updates / el_graph, "unit": "updates/s", "n_gpus": 1,
         "steps": K, "warmup": Wm, "ms_per_step": el_graph / K * 1e3, "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None,
-        "dtype": "f32" if args.precision == "fp32" else "bf16x3-f32acc",
+        "dtype": "f32" if args.precision == "fp32" else BF16_DTYPE,
         "data": "synthetic",
-        "config": {"workload": "phantom 64^3, 1 mm voxels, +-5% noise, 192 directions "
-                               "(nside 4), phase advance", "grid": [64, 64, 64], "ndir": 192,
-                   "precision": args.precision,
-                   "transport": "moves in the collision kernel" if fused else "sweep kernel"},
+        "config": {"workload": C3_WORKLOAD, "grid": [128, 128, 128], "ndir": 768,
+                   "precision": args.precision, "steps_per_solve": base.steps},
         "roofline": rl,
         "kernels": {k: {"avg_ms": v[0] / v[1] if v[1] else 0.0, "launches": v[1]}
                     for k, v in prof.items()},
@@ -619,37 +790,37 @@ def main():
                   "HIP events on the medium's stream (instrumented below)",
         "instrumented": {"value": updates / el, "ms_per_step": el / K * 1e3},
         "budget_closure": closure,
-        "rel_l2_vs_fp64_oracle": oracle_error(prob, det_steps),
     }
+    other = "bf16split" if args.precision == "fp32" else "fp32"
+    e2, g2, p2, c2, d2, _ = timed_run(base.copy(precision=other), K, Wm, stream)
+    out[other] = {"value": updates / g2, "ms_per_step": g2 / K * 1e3,
+                  "dtype": "f32" if other == "fp32" else BF16_DTYPE,
+                  "step_roofline": step_roofline(prob, other, g2 / K * 1e3),
+                  "kernels_ms": {k: v[0] / v[1] for k, v in p2.items() if v[1]},
+                  "instrumented_value": updates / e2,
+                  "kernel_rooflines": kernel_rooflines(p2, prob, other, "refraction128"),
+                  "budget_closure": c2}
+    print("headline and its other precision done", file=sys.stderr, flush=True)
+    acc = {"full_size_bf16split_vs_fp32": c3_accuracy(stream),
+           "scaled_32cube_vs_fp64_oracle": refraction32_vs_oracle(stream)}
+    out["accuracy"] = acc
+    print("accuracy done", file=sys.stderr, flush=True)
     if not args.no_extras:
-        other = "bf16split" if args.precision == "fp32" else "fp32"
-        e2, g2, p2, c2, d2, _ = timed_run(prob.copy(precision=other), K, Wm, stream)
-        out[other] = {"value": updates / g2, "ms_per_step": g2 / K * 1e3,
-                      "step_roofline": step_roofline(prob, other, g2 / K * 1e3),
-                      "kernels_ms": {k: v[0] / v[1] for k, v in p2.items() if v[1]},
-                      "instrumented_value": updates / e2, "kernel_rooflines":
-                      kernel_rooflines(p2, prob, other), "budget_closure": c2,
-                      "rel_l2_vs_fp64_oracle": oracle_error(prob, d2)}
-        # the same steps with the separate sweep kernel (TR_TRANSPORT_SWEEP)
-        for pr in (args.precision, other):
-            e3, g3, p3, _, _, _ = timed_run(prob.copy(precision=pr, transport="sweep"), K, Wm,
-                                            stream)
-            out["separate_sweep_" + pr] = {
-                "value": updates / g3, "ms_per_step": g3 / K * 1e3,
-                "step_roofline": step_roofline(prob, pr, g3 / K * 1e3),
-                "kernels_ms": {k: v[0] / v[1] for k, v in p3.items() if v[1]}}
+        out["phantom64"] = phantom64(stream, K, Wm)
+        out["phantom64"]["full_1000_steps_rel_l2_vs_fp64_oracle"] = phantom64_accuracy(stream)
         p50, p99 = latency(W.config1(), 30, stream)
         out["latency_uniform16"] = {"p50_ms": p50, "p99_ms": p99, "solves": 30,
                                     "workload": "16^3, 48 directions, 200 steps"}
+        print("phantom and latency done", file=sys.stderr, flush=True)
         out["serving"] = serving(stream, args.serving_requests)
         out["adjoint"] = adjoint_timing(stream)
-        out["refraction128"] = refraction128(stream)
         out["implicit_source"] = implicit_source(stream)
         out["two_level_3072_192"] = two_level(stream)
         out["retarded_courant02"] = retarded(stream)
         out["paper_fiducial_101"] = paper_fiducial(stream)
+        print("extras done", file=sys.stderr, flush=True)
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(prob)
+        out["cpu_baseline"] = cpu_baseline(base)
     print(json.dumps(out), flush=True)
 
 

@@ -4,6 +4,7 @@ Calls only the FP64 oracle (oracle/) on the seeded workloads; nothing here
 comes from the HIP path.  Usage:
     python tests/golden/make_golden.py phantom64      # ~20 min on 8 cores
     python tests/golden/make_golden.py retarded64     # ~30 min on 8 cores
+    python tests/golden/make_golden.py refraction32   # ~4 min on 8 cores
 """
 import os
 import sys
@@ -55,5 +56,56 @@ def retarded64():
                         dt=r.setup.dt, steps=RETARDED_STEPS, history=r.setup.H)
 
 
+REFRACTION_STEPS = 200
+
+
+def refraction_sample_voxels(p):
+    """Voxels whose every direction the refraction parity test compares: the
+    3x3x3 blocks around an air-cylinder interface voxel next to tissue, a
+    sphere voxel and the source (clipped to the box), plus 24 voxels drawn with
+    seed 32.  Depends on the medium only."""
+    nz, ny, nx = p.shape
+    n = np.asarray(p.n)
+    centres = []
+    iz, iy, ix = np.nonzero(n < n.max())
+    k = int(np.argmin((ix - nx // 2) ** 2 + iy * 0 + (iz - iz.min()) ** 2))
+    centres.append((ix[k], iy[k], iz.min() - 1))          # tissue just above the cylinder
+    mua = np.asarray(p.mua)
+    sz, sy, sx = np.nonzero(mua > 1.5 * np.median(mua))
+    centres.append((sx[len(sx) // 2], sy[len(sy) // 2], sz[len(sz) // 2]))
+    centres.append((p.src_ix, p.src_iy, 0))
+    vox = set()
+    for cx, cy, cz in centres:
+        for dz in (-1, 0, 1):
+            for dy in (-1, 0, 1):
+                for dx in (-1, 0, 1):
+                    x, y, z = cx + dx, cy + dy, cz + dz
+                    if 0 <= x < nx and 0 <= y < ny and 0 <= z < nz:
+                        vox.add(int((z * ny + y) * nx + x))
+    rng = np.random.default_rng(32)
+    vox.update(int(v) for v in rng.choice(p.nvox, 24, replace=False))
+    return np.array(sorted(vox), dtype=np.int64)
+
+
+def refraction32():
+    """The heterogeneous refraction medium scaled to 32^3 (air cylinder with
+    Fresnel interfaces, three absorbing spheres, 768 directions, split
+    advance): per-step detector records, per-step budget, the final energy
+    density of every voxel and every direction of the sampled voxels after
+    200 steps."""
+    p = W.config3(nx=32)
+    t0 = time.time()
+    S = solve.build(p, steps=REFRACTION_STEPS)
+    r = solve.forward(p, steps=REFRACTION_STEPS, S=S)
+    print(f"{REFRACTION_STEPS} steps {time.time() - t0:.0f} s", flush=True)
+    budget = np.concatenate([np.stack([r.injected, r.absorbed, r.in_domain], axis=1),
+                             r.escaped], axis=1)
+    vox = refraction_sample_voxels(p)
+    np.savez_compressed(os.path.join(HERE, "refraction32_oracle.npz"), det=r.det, budget=budget,
+                        energy=r.state.sum(axis=0), vox=vox, cols=r.state[:, vox],
+                        dt=S.dt, steps=REFRACTION_STEPS, ninterceptions=len(S.icpt))
+
+
 if __name__ == "__main__":
-    {"phantom64": phantom64, "retarded64": retarded64}[sys.argv[1]]()
+    {"phantom64": phantom64, "retarded64": retarded64,
+     "refraction32": refraction32}[sys.argv[1]]()
