@@ -191,6 +191,24 @@ tr_status tr_step(tr_medium* m, int nsteps);
  * steps for NaN/Inf (TR_ENUMERIC). */
 tr_status tr_solve(tr_medium* m, int nsteps);
 
+/* tr_step for callers that cannot allocate device memory: code under HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc.  The
+ * same steps with the same kernels, queued kernel by kernel, with no device
+ * or host allocation of any kind: the per-step records are not grown and no
+ * graph is instantiated.  The kernels' per-workgroup partial sums and the
+ * tally kernel's per-step sums and counter live in a workspace of 4 MiB per
+ * GPU (a file-scope device array the library holds until the process ends)
+ * instead of the medium's own buffers.  Every call on one GPU shares that
+ * workspace and the call clears only the counter, so calls that overlap on
+ * one GPU race: serialise them (one stream, or wait between them).  Needs
+ * steps_done + nsteps <= the record capacity (1024 steps from tr_create_medium
+ * and tr_set_detectors; tr_step and tr_solve grow it).  Asynchronous on the
+ * medium's stream, like tr_step; tr_synchronize reports the budget check.
+ * TR_EINVAL: nsteps < 0, steps beyond the record capacity, or a medium whose
+ * step needs more workspace than 4 MiB (2 x collision workgroups + 7 x the
+ * larger of the sweep and collision workgroup counts + 9 doubles). */
+tr_status tr_step_noalloc(tr_medium* m, int nsteps);
+
 /* Wait for the medium's queued work; report a device error if one occurred. */
 tr_status tr_synchronize(tr_medium* m);
 

@@ -87,6 +87,7 @@ struct tr_medium {
   int* rdone = nullptr;
   double *cpart = nullptr, *spart = nullptr;
   int cnwg = 0, snwg = 0, sweep_bpd = 0;
+  double* scratch = nullptr;   // this device's allocation-free workspace (tr_step_noalloc)
 
   // capacity-dependent (reallocated when more steps are needed)
   int cap = 0;
@@ -253,7 +254,39 @@ struct KernelTimer {
   }
 };
 
-hipError_t queue_step(tr_medium* m) {
+// Where a step's kernels keep their per-workgroup partial sums and the tally
+// kernel its per-step sums and finished-workgroup counter: the medium's own
+// buffers (tr_step), or the device's file-scope workspace (tr_step_noalloc).
+struct Workspace {
+  double* cpart;
+  double* spart;
+  double* cpart2;
+  double* rscratch;
+  int* rdone;
+};
+
+Workspace medium_workspace(tr_medium* m) {
+  return Workspace{m->cpart, m->spart, m->cpart2, m->rscratch, m->rdone};
+}
+
+// The same pieces laid out in the device workspace; false if they do not fit.
+// The counter takes the last double slot (it must start at zero).
+bool scratch_workspace(tr_medium* m, Workspace* w, long long* used) {
+  const long long nc = 2LL * m->cnwg, ns = 7LL * std::max(m->snwg, m->cnwg),
+                  nc2 = m->twolevel ? 2LL * m->cnwg2 : 0LL;
+  const long long need = nc + ns + nc2 + 8 + 1;
+  *used = need;
+  if (!m->scratch || need > kScratchDoubles) return false;
+  double* p = m->scratch;
+  w->cpart = p;
+  w->spart = p + nc;
+  w->cpart2 = m->twolevel ? p + nc + ns : nullptr;
+  w->rscratch = p + nc + ns + nc2;
+  w->rdone = reinterpret_cast<int*>(p + nc + ns + nc2 + 8);
+  return true;
+}
+
+hipError_t queue_step(tr_medium* m, const Workspace& w) {
   const Field& f = m->f;
   hipError_t e;
   InjectArgs ia{m->X,   f.Vp,        m->src_pairs, m->npairs, m->qdev,
@@ -266,7 +299,7 @@ hipError_t queue_step(tr_medium* m) {
   if (m->twolevel) {
     TwoLevelArgs ta{m->X,     m->Y,          m->M,                   m->T,  m->a,
                     m->b,     m->children,   m->parent,              f.ndir, m->nc,
-                    m->nkids, 1.0f / float(m->nkids), f.Vp,          f.V,   m->cpart,
+                    m->nkids, 1.0f / float(m->nkids), f.Vp,          f.V,   w.cpart,
                     m->tlfused ? m->Y : nullptr, m->step_ctr};
     Field fc = f;
     fc.ndir = m->nc;
@@ -274,7 +307,7 @@ hipError_t queue_step(tr_medium* m) {
     // coarse source T = b (P_c M); with the retarded history the factor is
     // omega, and each fine direction's (1 - a) comes in apply_hop
     CollideArgs cc{m->M, m->T, m->P, m->Prow, nullptr, nullptr, m->zero,
-                   m->ring ? m->omega : m->b, f.Vp, m->NPc, m->cpart2};
+                   m->ring ? m->omega : m->b, f.Vp, m->NPc, w.cpart2};
     {
       KernelTimer t(m, TR_K_COARSE_SUM);
       if ((e = launch_coarse_sum(ta, m->stream)) != hipSuccess) return e;
@@ -304,7 +337,7 @@ hipError_t queue_step(tr_medium* m) {
     ca.Prow = m->Prow;
     ca.Vp = f.Vp;
     ca.NP = f.NP;
-    ca.part = m->cpart;
+    ca.part = w.cpart;
     ca.ring = m->ring;
     ca.H = m->H;
     ca.step_ctr = m->step_ctr;
@@ -323,7 +356,7 @@ hipError_t queue_step(tr_medium* m) {
     ca.b = m->b;
     ca.Vp = f.Vp;
     ca.NP = f.NP;
-    ca.part = m->cpart;
+    ca.part = w.cpart;
     ca.step_ctr = m->step_ctr;
     ca.pp = m->X;
     ca.mvtab = m->mvtab;
@@ -337,13 +370,13 @@ hipError_t queue_step(tr_medium* m) {
     ca.mvext = m->mvext;
     ca.mvscramble = m->mvscramble;
     ca.mvdet = m->mvdet;
-    ca.spart = m->spart;
+    ca.spart = w.spart;
     ca.mvunscramble = m->mvunscramble;
     if ((e = launch_collide_move(ca, ia, f, m->desc.precision, m->stream)) != hipSuccess) return e;
   } else {
     KernelTimer t(m, TR_K_COLLIDE);
     CollideArgs ca{m->X,   m->Y, m->P,  m->Prow, m->Phi, m->Plo, m->a,   m->b,
-                   f.Vp,   f.NP, m->cpart, m->V, m->lam, m->w0,  m->w1, m->cimp};
+                   f.Vp,   f.NP, w.cpart, m->V, m->lam, m->w0,  m->w1, m->cimp};
     e = m->V ? launch_collide_implicit(ca, f, m->stream)
              : launch_collide(ca, f, m->desc.precision, 0, m->stream);
     if (e != hipSuccess) return e;
@@ -352,7 +385,7 @@ hipError_t queue_step(tr_medium* m) {
   if (!m->mfused) {
     KernelTimer t(m, TR_K_SWEEP);
     SweepArgs sa{m->Y, m->X, f.Vp, f.V, f.nx, f.ny, f.nz, m->ddirs, m->delta, m->dstride,
-                 m->r, m->iface, m->nvox, m->islot, m->icptF, f.ndir, m->step_ctr, m->spart,
+                 m->r, m->iface, m->nvox, m->islot, m->icptF, f.ndir, m->step_ctr, w.spart,
                  m->mat, m->rtab, m->rowbits, m->bgcls, m->ring, m->H, (long long)f.NP * f.Vp};
     if (m->tlfused) {
       sa.tlT = m->T;
@@ -376,9 +409,9 @@ hipError_t queue_step(tr_medium* m) {
     if ((e = launch_gather(ga, m->stream)) != hipSuccess) return e;
   }
   KernelTimer t(m, TR_K_REDUCE);
-  ReduceArgs ra{m->cpart, m->cnwg, m->spart, m->snwg, m->Y, f.Vp, m->det_pairs, m->det_first,
+  ReduceArgs ra{w.cpart, m->cnwg, w.spart, m->snwg, m->Y, f.Vp, m->det_pairs, m->det_first,
                 m->det_vox_dev, m->ndet, m->ddirs, m->r, split ? 1 : 0, m->step_ctr, m->budget,
-                m->det_steps, m->cap, m->flag, m->rscratch, m->rdone,
+                m->det_steps, m->cap, m->flag, w.rscratch, w.rdone,
                 m->ring, m->H, (long long)f.NP * f.Vp};
   if (m->tlfused) {
     ra.tlT = m->T;
@@ -619,7 +652,14 @@ tr_status tr_create_medium(const tr_grid_desc* desc, const float* mua, const flo
   }
   m->fast_split = f.nx % 4 == 0;
   for (const DevDir& D : dd) m->fast_split = m->fast_split && D.unitb;
-  hipError_t e = prepare_collide(f, desc->precision);
+  // this device's allocation-free workspace (tr_step_noalloc), looked up once
+  // per device with the device current
+  hipError_t e = scratch_address(&m->scratch);
+  if (e != hipSuccess) {
+    delete m;
+    return fail(TR_EDEVICE, std::string("workspace address: ") + hipGetErrorString(e));
+  }
+  e = prepare_collide(f, desc->precision);
   if (e == hipSuccess) e = hipMemset(m->X, 0, NV * 4);
   if (e == hipSuccess) e = hipMemset(m->Y, 0, NV * 4);
   if (e == hipSuccess) e = hipMemcpy(m->P, PT.data(), PT.size() * 4, hipMemcpyHostToDevice);
@@ -1069,6 +1109,7 @@ tr_status tr_step(tr_medium* m, int nsteps) {
   if (m->ndet == 0) return fail(TR_ESTATE, "detectors not set");
   st = ensure_capacity(m, m->steps_done + nsteps);
   if (st != TR_OK) return st;
+  const Workspace ws = medium_workspace(m);
   int left = nsteps;
   hipError_t e = hipSuccess;
   // Replay a captured graph of kGraphSteps steps where possible (the kernels
@@ -1078,7 +1119,7 @@ tr_status tr_step(tr_medium* m, int nsteps) {
     if (!m->graph) {
       hipGraph_t g;
       e = hipStreamBeginCapture(m->stream, hipStreamCaptureModeThreadLocal);
-      for (int s = 0; s < kGraphSteps && e == hipSuccess; ++s) e = queue_step(m);
+      for (int s = 0; s < kGraphSteps && e == hipSuccess; ++s) e = queue_step(m, ws);
       hipError_t e2 = hipStreamEndCapture(m->stream, &g);
       if (e == hipSuccess) e = e2;
       if (e == hipSuccess) {
@@ -1094,7 +1135,35 @@ tr_status tr_step(tr_medium* m, int nsteps) {
     }
   }
   for (; left > 0; --left) {
-    e = queue_step(m);
+    e = queue_step(m, ws);
+    if (e != hipSuccess) return device_fail(m, e, "kernel launch");
+  }
+  m->steps_done += nsteps;
+  return TR_OK;
+}
+
+tr_status tr_step_noalloc(tr_medium* m, int nsteps) {
+  tr_status st = check_medium(m);
+  if (st != TR_OK) return st;
+  if (nsteps < 0) return fail(TR_EINVAL, "nsteps < 0");
+  if (m->ndet == 0) return fail(TR_ESTATE, "detectors not set");
+  if (m->steps_done + nsteps > m->cap)
+    return fail(TR_EINVAL, "tr_step_noalloc: " + std::to_string(m->steps_done + nsteps) +
+                               " steps exceed the record capacity of " + std::to_string(m->cap) +
+                               " (tr_step grows it)");
+  Workspace ws;
+  long long used = 0;
+  if (!scratch_workspace(m, &ws, &used))
+    return fail(TR_EINVAL, "tr_step_noalloc: the step needs " + std::to_string(used) +
+                               " doubles of workspace, more than the " +
+                               std::to_string(kScratchDoubles) + " the library holds per device");
+  if (nsteps == 0) return TR_OK;
+  // the tally kernel's counter must start at zero; the workspace keeps
+  // whatever the previous call on this device left
+  hipError_t e = launch_zero_fill(ws.rscratch, 9, m->stream);
+  if (e != hipSuccess) return device_fail(m, e, "kernel launch");
+  for (int left = nsteps; left > 0; --left) {
+    e = queue_step(m, ws);
     if (e != hipSuccess) return device_fail(m, e, "kernel launch");
   }
   m->steps_done += nsteps;

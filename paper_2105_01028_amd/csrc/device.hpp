@@ -306,4 +306,13 @@ hipError_t launch_adjoint_step(const AdjArgs& a, int m, hipStream_t s);
 hipError_t prepare_adjoint(int NP);
 hipError_t launch_energy(const float* X, long long Vp, int ndir, int V, float* E, hipStream_t s);
 
+// The allocation-free step's workspace: a file-scope device array of
+// kScratchDoubles doubles (4 MiB) per GPU.  scratch_address gives its address
+// on the current device (looked up once per device, with that device
+// current); launch_zero_fill clears n doubles with a kernel (no memset node,
+// so the call can sit under graph capture).
+constexpr long long kScratchDoubles = 1LL << 19;
+hipError_t scratch_address(double** out);
+hipError_t launch_zero_fill(double* p, long long n, hipStream_t s);
+
 }  // namespace trinity

@@ -3,6 +3,8 @@
 // redistribution and the per-step tallies.
 #include <hip/hip_runtime.h>
 
+#include <mutex>
+
 #include "device.hpp"
 
 namespace trinity {
@@ -3024,6 +3026,54 @@ hipError_t launch_adjoint_step(const AdjArgs& a, int m, hipStream_t s) {
 hipError_t launch_energy(const float* X, long long Vp, int ndir, int V, float* E, hipStream_t s) {
   hipLaunchKernelGGL(energy_kernel, dim3(unsigned((V + 255) / 256)), dim3(256), 0, s, X, Vp, ndir,
                      V, E);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Workspace of the allocation-free step: the per-workgroup FP64 partial sums
+// of the collision and transport kernels, the tally kernel's per-step sums and
+// its finished-workgroup counter, in one file-scope device array.  Each GPU
+// the library runs on holds its own copy for the life of the process; host
+// code reaches it only through the address hipGetSymbolAddress returns on that
+// device (the array's name is a host-side stand-in, not a device address).
+static __device__ __align__(256) double scratch[kScratchDoubles];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+double* g_scratch_ptr[kMaxDevices] = {};
+}  // namespace
+
+hipError_t scratch_address(double** out) {
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    if (!p) return hipErrorInvalidSymbol;
+    g_scratch_ptr[dev] = static_cast<double*>(p);
+  }
+  *out = g_scratch_ptr[dev];
+  return hipSuccess;
+}
+
+namespace {
+__global__ void zero_fill_kernel(double* p, long long n) {
+  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n;
+       i += (long long)gridDim.x * blockDim.x)
+    p[i] = 0.0;
+}
+}  // namespace
+
+hipError_t launch_zero_fill(double* p, long long n, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  const long long blocks = (n + kThreads - 1) / kThreads;
+  hipLaunchKernelGGL(zero_fill_kernel, dim3(unsigned(blocks < 1024 ? blocks : 1024)),
+                     dim3(kThreads), 0, s, p, n);
   return hipGetLastError();
 }
 

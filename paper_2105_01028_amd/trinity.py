@@ -90,6 +90,7 @@ _SIGS = {
     "tr_set_source": [_P, _I, _I, _I, _D, _D, _D, _D],
     "tr_set_detectors": [_P, _I, _PI, _PI, _PI, _D, _D, _I],
     "tr_step": [_P, _I],
+    "tr_step_noalloc": [_P, _I],
     "tr_solve": [_P, _I],
     "tr_synchronize": [_P],
     "tr_reset": [_P],
@@ -268,6 +269,9 @@ class Medium:
 
     def solve(self, nsteps: int):
         _check(lib().tr_solve(self._h, int(nsteps)))
+
+    def step_noalloc(self, nsteps: int):
+        _check(lib().tr_step_noalloc(self._h, int(nsteps)))
 
     def synchronize(self):
         _check(lib().tr_synchronize(self._h))
