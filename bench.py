@@ -26,10 +26,18 @@ METRIC = ("voxel·direction·step updates/s (FP32 vs BF16-split); "
           "p50/p99 solve latency")
 PEAK_HBM_GBS = 8000.0
 PEAK_TFLOPS = {"fp32": 157.3, "bf16split": 2500.0}   # dense MFMA peaks
-# bf16 MFMA products per term of the BF16-split contraction (P_hi x_hi, P_hi x_lo,
-# P_lo x_hi, P_lo x_lo) and the dtype label they give
-BF16_PRODUCTS = 4
-BF16_DTYPE = f"bf16x{BF16_PRODUCTS}-f32acc"
+
+
+def bf16_products(ndir):
+    """bf16 MFMA products per term of the BF16-split contraction: P_hi x_hi,
+    P_hi x_lo, P_lo x_hi, and P_lo x_lo where P is resident in LDS (up to 192
+    directions); the kernels that stream P leave the last one out (its column
+    totals go to the diagonal)."""
+    return 4 if ndir <= 192 else 3
+
+
+def bf16_dtype(ndir):
+    return f"bf16x{bf16_products(ndir)}-f32acc"
 
 
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "hbm_traffic_collide_sweep.txt")
@@ -84,7 +92,7 @@ def kernel_rooflines(prof, prob, precision, workload="phantom64"):
     also moves every value to its downwind voxel, within the same 8 N V bytes.
 
     collide, FP32: 2 N^2 V FLOP on the FP32 MFMA peak.  collide, BF16-split:
-    the hi/lo products execute 2 BF16_PRODUCTS N^2 V bf16 FLOP; at few directions the
+    the hi/lo products execute 2 bf16_products(N) N^2 V bf16 FLOP; at few directions the
     kernel is bound by its 8 N V bytes (read X, write Y) instead, and the
     binding roofline (the larger fraction) is reported, with the effective
     FP32-equivalent rate 2 N^2 V / t beside it.  sweep: 8 N V bytes (read the
@@ -100,7 +108,7 @@ def kernel_rooflines(prof, prob, precision, workload="phantom64"):
                               "unit": "TFLOP/s", "frac": flop / t / 1e12 / 157.3,
                               "avg_ms": ms / n, "work_per_launch": flop}
         else:
-            flop = 2.0 * BF16_PRODUCTS * N * N * V
+            flop = 2.0 * bf16_products(N) * N * N * V
             byt = 8.0 * N * V
             f_mfma = flop / t / 1e12 / PEAK_TFLOPS["bf16split"]
             f_hbm = byt / t / 1e9 / PEAK_HBM_GBS
@@ -134,7 +142,7 @@ def step_roofline(prob, precision, ms_per_step):
     if precision == "fp32":
         t_mfma = 2.0 * N * N * V / (PEAK_TFLOPS["fp32"] * 1e12)
     else:
-        t_mfma = 2.0 * BF16_PRODUCTS * N * N * V / (PEAK_TFLOPS["bf16split"] * 1e12)
+        t_mfma = 2.0 * bf16_products(N) * N * N * V / (PEAK_TFLOPS["bf16split"] * 1e12)
     t_hbm = 8.0 * N * V / (PEAK_HBM_GBS * 1e9)
     t_min = max(t_mfma, t_hbm)
     return {"bound": "mfma" if t_mfma >= t_hbm else "hbm", "min_ms": t_min * 1e3,
@@ -776,7 +784,7 @@ def main():
         "metric": METRIC, "value": updates / el_graph, "unit": "updates/s", "n_gpus": 1,
         "steps": K, "warmup": Wm, "ms_per_step": el_graph / K * 1e3, "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None,
-        "dtype": "f32" if args.precision == "fp32" else BF16_DTYPE,
+        "dtype": "f32" if args.precision == "fp32" else bf16_dtype(prob.ndir),
         "data": "synthetic",
         "config": {"workload": C3_WORKLOAD, "grid": [128, 128, 128], "ndir": 768,
                    "precision": args.precision, "steps_per_solve": base.steps},
@@ -794,7 +802,7 @@ def main():
     other = "bf16split" if args.precision == "fp32" else "fp32"
     e2, g2, p2, c2, d2, _ = timed_run(base.copy(precision=other), K, Wm, stream)
     out[other] = {"value": updates / g2, "ms_per_step": g2 / K * 1e3,
-                  "dtype": "f32" if other == "fp32" else BF16_DTYPE,
+                  "dtype": "f32" if other == "fp32" else bf16_dtype(prob.ndir),
                   "step_roofline": step_roofline(prob, other, g2 / K * 1e3),
                   "kernels_ms": {k: v[0] / v[1] for k, v in p2.items() if v[1]},
                   "instrumented_value": updates / e2,

@@ -61,7 +61,9 @@ enum { TR_SOURCE_EXPLICIT = 0, TR_SOURCE_IMPLICIT = 1 };
 enum { TR_TRANSPORT_AUTO = 0, TR_TRANSPORT_SWEEP = 1 };
 
 typedef struct {
-  int nx, ny, nz;     /* voxels per axis, each >= 1 and <= 4096 */
+  int nx, ny, nz;     /* voxels per axis, each >= 1 and <= 4096, and at most 107374080
+                         voxels in all (the collision kernels address the field with
+                         32-bit offsets spanning five rows) */
   double dx_mm;       /* voxel edge */
   int nside;          /* HEALPix resolution: N = 12 nside^2 directions, RING order, 1..16 */
   double g;           /* Henyey-Greenstein anisotropy, Eq. (11); -1 < g < 1 */

@@ -41,6 +41,7 @@ struct tr_medium {
   float *X = nullptr, *Y = nullptr, *P = nullptr, *Prow = nullptr, *a = nullptr, *b = nullptr,
         *r = nullptr;
   uint16_t *Phi = nullptr, *Plo = nullptr;
+  float* plocol = nullptr;   // bf16-split: column sums of P_lo (the streamed kernels' fold)
   DevDir* ddirs = nullptr;
   int8_t* delta = nullptr;
   int dstride = 0;
@@ -377,6 +378,7 @@ hipError_t queue_step(tr_medium* m, const Workspace& w) {
     KernelTimer t(m, TR_K_COLLIDE);
     CollideArgs ca{m->X,   m->Y, m->P,  m->Prow, m->Phi, m->Plo, m->a,   m->b,
                    f.Vp,   f.NP, w.cpart, m->V, m->lam, m->w0,  m->w1, m->cimp};
+    ca.plocol = m->plocol;
     e = m->V ? launch_collide_implicit(ca, f, m->stream)
              : launch_collide(ca, f, m->desc.precision, 0, m->stream);
     if (e != hipSuccess) return e;
@@ -609,10 +611,11 @@ tr_status tr_create_medium(const tr_grid_desc* desc, const float* mua, const flo
   if (desc->precision == 1) {
     m->Phi = m->alloc<uint16_t>(size_t(f.NP) * f.NP);
     m->Plo = m->alloc<uint16_t>(size_t(f.NP) * f.NP);
+    m->plocol = m->alloc<float>(f.NP);
   }
   if (!m->X || !m->Y || !m->P || !m->Prow || !m->a || !m->b || !m->r || !m->ddirs || !m->delta ||
       !m->step_ctr || !m->flag || !m->cpart || !m->spart || !m->rscratch || !m->rdone ||
-      (desc->precision == 1 && (!m->Phi || !m->Plo))) {
+      (desc->precision == 1 && (!m->Phi || !m->Plo || !m->plocol))) {
     delete m;
     return fail(TR_ENOMEM, "device allocation failed");
   }
@@ -679,8 +682,18 @@ tr_status tr_create_medium(const tr_grid_desc* desc, const float* mua, const flo
       lo[i] = f32_to_bf16_bits(P32[i] - bf16_bits_to_f32(hi[i]));
     }
     if (desc->hg_norm == TR_HG_SINKHORN) conserve_columns_bf16(hi, lo, f.ndir, f.NP);
+    // column totals of P_lo (exact in FP64: sums of bf16 values), for the
+    // kernels that leave out the P_lo x_lo product and add its column total
+    // to the diagonal
+    std::vector<float> lc(f.NP, 0.0f);
+    for (int k = 0; k < f.NP; ++k) {
+      double t = 0.0;
+      for (int i = 0; i < f.NP; ++i) t += double(bf16_bits_to_f32(lo[size_t(i) * f.NP + k]));
+      lc[k] = float(t);
+    }
     e = hipMemcpy(m->Phi, hi.data(), hi.size() * 2, hipMemcpyHostToDevice);
     if (e == hipSuccess) e = hipMemcpy(m->Plo, lo.data(), lo.size() * 2, hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(m->plocol, lc.data(), lc.size() * 4, hipMemcpyHostToDevice);
   }
   if (e != hipSuccess) {
     delete m;

@@ -32,7 +32,10 @@ inline bool valid_desc(const tr_grid_desc* d, std::string& err) {
   if (!d) return err = "null descriptor", false;
   if (d->nx < 1 || d->ny < 1 || d->nz < 1 || d->nx > 4096 || d->ny > 4096 || d->nz > 4096)
     return err = "grid sizes must be in 1..4096", false;
-  if ((long long)d->nx * d->ny * d->nz > (1LL << 30)) return err = "grid too large", false;
+  // the collision kernels address five rows of the field with 32-bit byte
+  // offsets: fewer than 2^31 / 20 voxels after padding to 256
+  if (round_up((long long)d->nx * d->ny * d->nz, 256) * 20 >= (1LL << 31))
+    return err = "grid too large: at most 107374080 voxels", false;
   if (!(d->dx_mm > 0) || !std::isfinite(d->dx_mm)) return err = "dx_mm must be > 0", false;
   if (d->nside < 1 || d->nside > 16) return err = "nside must be in 1..16", false;
   if (!(d->g > -1.0 && d->g < 1.0)) return err = "g must be in (-1, 1)", false;

@@ -94,6 +94,9 @@ struct CollideArgs {
   const unsigned* mvdet;   // bit per voxel column: a detector's voxel (light that leaves
                            // there is kept for the read-out; elsewhere it is only tallied)
   double* spart;
+  // bf16-split with more than 192 directions (streamed P): [NP] column sums
+  // sum_i P_lo[i][k], the column totals of the P_lo x_lo term the kernel drops
+  const float* plocol;
 };
 
 struct SweepArgs {

@@ -87,64 +87,11 @@ __global__ void inject_kernel(InjectArgs A) { inject_body(A); }
 // ---------------------------------------------------------------------------
 // Collision (Eq. 10 with the explicit source of Eq. 2/12):
 //   Y[:, v] = a_v X[:, v] + b_v (P X)[:, v]
-// A GEMM with M = K = NP (directions) and N = voxels, on v_mfma_f32_32x32x2f32.
-// Workgroup tile: MT rows (directions) x 128 columns (voxels), four wavefronts
-// of 32 columns each, every wavefront holding all MT rows in accumulators.
-// P is staged through LDS in chunks of KC directions as [k][row], read from
-// its transpose PT (A.P holds P^T, row k = column k of P, contiguous in row);
-// X goes straight from HBM into the B operand.
-// The epilogue applies a, b per voxel and sums the FP64 budget partials:
-// absorbed = sum_v (1 - a_v - b_v) sum_d X[d][v], total = sum X.
-template <int MT>
-__global__ __launch_bounds__(kThreads, 2) void collide_f32_kernel(CollideArgs A) {
-  constexpr int KC = 32;
-  constexpr int NQ = MT / 32;
-  __shared__ float Ps[KC * MT];
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int hl = lane >> 5, cl = lane & 31;
-  const long long col = (long long)blockIdx.x * 128 + wave * 32 + cl;
-  const int row0 = blockIdx.y * MT;
-  floatx16 acc[NQ];
-#pragma unroll
-  for (int q = 0; q < NQ; ++q)
-#pragma unroll
-    for (int r = 0; r < 16; ++r) acc[q][r] = 0.0f;
-
-  const float* xcol = A.X + col;
-  for (int k0 = 0; k0 < A.NP; k0 += KC) {
-    __syncthreads();
-    for (int e = tid * 4; e < KC * MT; e += kThreads * 4) {
-      const int k = e / MT, rr = e - k * MT;
-      const float4 v = *reinterpret_cast<const float4*>(A.P + size_t(k0 + k) * A.NP + row0 + rr);
-      *reinterpret_cast<float4*>(Ps + k * MT + rr) = v;
-    }
-    __syncthreads();
-#pragma unroll 4
-    for (int s = 0; s < KC / 2; ++s) {
-      const float bv = xcol[size_t(k0 + 2 * s + hl) * A.Vp];
-      const float* prow = Ps + (2 * s + hl) * MT + cl;
-#pragma unroll
-      for (int q = 0; q < NQ; ++q)
-        acc[q] = __builtin_amdgcn_mfma_f32_32x32x2f32(prow[q * 32], bv, acc[q], 0, 0, 0);
-    }
-  }
-
-  const float av = A.a[col], bv = A.b[col];
-  double colsum = 0.0;
-#pragma unroll
-  for (int q = 0; q < NQ; ++q)
-#pragma unroll
-    for (int r = 0; r < 16; ++r) {
-      const int row = row0 + q * 32 + 8 * (r >> 2) + 4 * hl + (r & 3);
-      const size_t idx = size_t(row) * A.Vp + col;
-      const float x = A.X[idx];
-      A.Y[idx] = av * x + bv * acc[q][r];
-      colsum += double(x);
-    }
-  const double vals[2] = {(1.0 - double(av) - double(bv)) * colsum, colsum};
-  const long long nwg = (long long)gridDim.x * gridDim.y;
-  block_sums<2>(vals, A.part + (long long)blockIdx.y * gridDim.x + blockIdx.x, nwg);
-}
+// a GEMM with M = K = NP (directions) and N = voxels on MFMA; the epilogue's
+// FP64 budget partials are absorbed = sum_v (1 - a_v - b_v) sum_d X[d][v] and
+// total = sum X.  Lanes address X and Y with 32-bit byte offsets spanning up to
+// five rows, so a medium holds fewer than 2^31 / 20 padded voxels (checked at
+// creation).
 
 // Collision with P resident in LDS (NP <= 192, 147 KB): a persistent kernel,
 // one 512-thread workgroup per CU, each wavefront owning 32 voxel columns of a
@@ -876,6 +823,19 @@ __global__ __launch_bounds__(512, 1) void collide_move_kernel(CollideArgs A, Inj
   move_sums(A, absorbed, total, esc, dom, blockIdx.x, gridDim.x);
 }
 
+// Column tile and row block of workgroup L of a streamed collision (a 1-D
+// grid of ntiles x nrb workgroups).  The nrb row blocks of a column tile read
+// the same 256 columns of X.  Workgroups are dispatched to the eight XCDs in
+// turn (L mod 8), so the row blocks of a tile get ids L, L + 8, L + 16, ...:
+// the same XCD, one after another, and the later ones find X in its L2.
+__device__ __forceinline__ void stream_tile(int L, int ntiles, int nrb, int* tile, int* rb) {
+  const int G = 8 * nrb;
+  const int g = L / G, r = L - g * G;
+  const int in_group = ntiles - 8 * g < 8 ? ntiles - 8 * g : 8;
+  *tile = 8 * g + r % in_group;
+  *rb = r / in_group;
+}
+
 // More directions than fit in LDS (NP > 192): the layout of the resident kernel
 // (512 threads, 256 voxel columns, lane half h holding the X rows
 // 32c + 8(s/4) + 4h + s%4 of row block c, which are the rows of its accumulator
@@ -886,7 +846,7 @@ __global__ __launch_bounds__(512, 1) void collide_move_kernel(CollideArgs A, Inj
 // a_v X is added as the X rows of the workgroup's own row tile arrive, so the
 // epilogue only stores; the budget partials cover the tile's rows.
 template <int MT>
-__global__ __launch_bounds__(512, 1) void collide_f32_stream_kernel(CollideArgs A) {
+__global__ __launch_bounds__(512, 1) void collide_f32_stream_kernel(CollideArgs A, int ntiles) {
   constexpr int NQ = MT / 32;
   constexpr int KC = 32, LDK = KC + 4;
   constexpr int NPR = (MT * KC / 4 + 511) / 512;   // float4 of P per thread per chunk
@@ -898,9 +858,11 @@ __global__ __launch_bounds__(512, 1) void collide_f32_stream_kernel(CollideArgs 
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int hl = lane >> 5, cl = lane & 31;
   const int NC = A.NP / KC;
-  const int row0 = blockIdx.y * MT;
+  int tile, rb;
+  stream_tile(int(blockIdx.x), ntiles, A.NP / MT, &tile, &rb);
+  const int row0 = rb * MT;
   const size_t rowbytes = size_t(A.Vp) * sizeof(float);
-  const long long col = (long long)blockIdx.x * 256 + wave * 32 + cl;
+  const long long col = (long long)tile * 256 + wave * 32 + cl;
   const unsigned voff = unsigned(size_t(col) * sizeof(float) + size_t(4 * hl) * rowbytes);
   const char* __restrict__ xb0 = reinterpret_cast<const char*>(A.X);
   const float av = A.a[col], bv = A.b[col];
@@ -988,10 +950,8 @@ __global__ __launch_bounds__(512, 1) void collide_f32_stream_kernel(CollideArgs 
     for (int r = 0; r < 16; ++r)
       *reinterpret_cast<float*>(yb0 + size_t(row0 + q * 32 + 8 * (r >> 2) + (r & 3)) * rowbytes +
                                 voff) = acc[q][r];
-  const long long nwg = (long long)gridDim.x * gridDim.y;
-  const long long wg = (long long)blockIdx.y * gridDim.x + blockIdx.x;
-  block_sums512((1.0 - double(av) - double(bv)) * colsum64, colsum64, A.part + wg,
-                A.part + nwg + wg);
+  block_sums512((1.0 - double(av) - double(bv)) * colsum64, colsum64, A.part + blockIdx.x,
+                A.part + gridDim.x + blockIdx.x);
 #undef TRINITY_STAGE_P
 #undef TRINITY_PUT_P
 }
@@ -1001,8 +961,14 @@ __global__ __launch_bounds__(512, 1) void collide_f32_stream_kernel(CollideArgs 
 // slot order of collide_bf16_res_kernel (slot 16t + 8h + j holds column
 // 4h + 8(2t + j/4) + j%4 of the chunk), so each lane's 8 k of a K step are one
 // 16-byte read and its X rows are its accumulator rows.
+//   Three bf16 products per term: P_hi x_hi + P_hi x_lo + P_lo x_hi, with
+// x = b X split into x_hi + x_lo.  The fourth, P_lo x_lo (2^-16 of the term),
+// is left out, and so that scattering still conserves the light of every
+// incoming direction k, its column total x_lo[k] sum_i P_lo[i][k] is added to
+// row k itself (A.plocol[k] = sum_i P_lo[i][k]), as the lane's own rows of X
+// arrive together with a_v X.
 template <int MT>
-__global__ __launch_bounds__(512, 1) void collide_bf16_stream_kernel(CollideArgs A) {
+__global__ __launch_bounds__(512, 1) void collide_bf16_stream_kernel(CollideArgs A, int ntiles) {
   constexpr int NQ = MT / 32;
   constexpr int KC = 32, LDK = KC + 8;             // bf16 per LDS row
   constexpr int NG = MT * (KC / 4);                // 8-byte groups per matrix per chunk
@@ -1011,28 +977,46 @@ __global__ __launch_bounds__(512, 1) void collide_bf16_stream_kernel(CollideArgs
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int hl = lane >> 5, cl = lane & 31;
   const int NC = A.NP / KC;
-  const int row0 = blockIdx.y * MT;
-  const size_t rowbytes = size_t(A.Vp) * sizeof(float);
-  const long long col = (long long)blockIdx.x * 256 + wave * 32 + cl;
-  const unsigned voff = unsigned(size_t(col) * sizeof(float) + size_t(4 * hl) * rowbytes);
+  int tile, rb;
+  stream_tile(int(blockIdx.x), ntiles, A.NP / MT, &tile, &rb);
+  const int row0 = rb * MT;
+  const unsigned rowbytes = unsigned(A.Vp) * 4u;   // < 2^31 / 5 (grid limit)
+  const long long col = (long long)tile * 256 + wave * 32 + cl;
+  // X through buffer loads: a resource per group of 8 rows (its base in
+  // scalar registers), the lane's column and row half in one VGPR offset, the
+  // row within the group in the scalar offset
+  const unsigned voff = unsigned(col) * 4u + 4u * unsigned(hl) * rowbytes;
   const char* __restrict__ xb0 = reinterpret_cast<const char*>(A.X);
   const float av = A.a[col], bv = A.b[col];
-  auto ld = [&](int c, int s) {
-    const char* rb = xb0 + size_t(32 * c + 8 * (s >> 2) + (s & 3)) * rowbytes;
-    return *reinterpret_cast<const float*>(rb + voff);
+  auto ldc = [&](int c, float (&b)[16]) {
+#pragma unroll
+    for (int g = 0; g < 4; ++g) {
+      const __amdgpu_buffer_rsrc_t rs =
+          raw_rsrc(xb0 + size_t(32 * c + 8 * g) * rowbytes, 8u * rowbytes);
+#pragma unroll
+      for (int j = 0; j < 4; ++j)
+        b[4 * g + j] =
+            __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(rs, int(voff), int(j * rowbytes), 0));
+    }
   };
+  // P_hi / P_lo staging: slot i of a thread is 8-byte group tid + 512 i of the
+  // chunk, i.e. row tid / 8 + 64 i; the chunk and the slot go in the scalar
+  // offset
+  const __amdgpu_buffer_rsrc_t rph = raw_rsrc(A.Phi, unsigned(A.NP) * unsigned(A.NP) * 2u);
+  const __amdgpu_buffer_rsrc_t rpl = raw_rsrc(A.Plo, unsigned(A.NP) * unsigned(A.NP) * 2u);
+  const int sr = tid >> 3, skap = (tid & 7) * 4;
+  const unsigned poff = 2u * unsigned((row0 + sr) * A.NP + 4 * ((skap >> 3) & 1) +
+                                      8 * (2 * ((skap >> 4) & 1) + ((skap >> 2) & 1)));
   uint2 rh[NPR], rl[NPR];
   auto stage = [&](int c) {
 #pragma unroll
     for (int i = 0; i < NPR; ++i) {
-      const int e = tid + i * 512;
-      if (e < NG) {
-        const int r = e / (KC / 4), kap = (e - r * (KC / 4)) * 4;
-        const int t = (kap >> 4) & 1, h = (kap >> 3) & 1, g2 = (kap >> 2) & 1;
-        const size_t g = size_t(row0 + r) * A.NP + 32 * c + 4 * h + 8 * (2 * t + g2);
-        rh[i] = *reinterpret_cast<const uint2*>(A.Phi + g);
-        rl[i] = *reinterpret_cast<const uint2*>(A.Plo + g);
-      }
+      if (i + 1 == NPR && sr + 64 * i >= MT) break;   // a partial last slot
+      const int so = 64 * c + i * 128 * A.NP;
+      const auto h2 = __builtin_amdgcn_raw_buffer_load_b64(rph, int(poff), so, 0);
+      const auto l2 = __builtin_amdgcn_raw_buffer_load_b64(rpl, int(poff), so, 0);
+      rh[i] = make_uint2(h2[0], h2[1]);
+      rl[i] = make_uint2(l2[0], l2[1]);
     }
   };
   auto put = [&](int buf) {
@@ -1040,12 +1024,10 @@ __global__ __launch_bounds__(512, 1) void collide_bf16_stream_kernel(CollideArgs
     uint16_t* Sl = Sh + MT * LDK;
 #pragma unroll
     for (int i = 0; i < NPR; ++i) {
-      const int e = tid + i * 512;
-      if (e < NG) {
-        const int r = e / (KC / 4), kap = (e - r * (KC / 4)) * 4;
-        *reinterpret_cast<uint2*>(Sh + r * LDK + kap) = rh[i];
-        *reinterpret_cast<uint2*>(Sl + r * LDK + kap) = rl[i];
-      }
+      if (i + 1 == NPR && sr + 64 * i >= MT) break;
+      const int r = sr + 64 * i;
+      *reinterpret_cast<uint2*>(Sh + r * LDK + skap) = rh[i];
+      *reinterpret_cast<uint2*>(Sl + r * LDK + skap) = rl[i];
     }
   };
   floatx16 acc[NQ];
@@ -1053,69 +1035,84 @@ __global__ __launch_bounds__(512, 1) void collide_bf16_stream_kernel(CollideArgs
   for (int q = 0; q < NQ; ++q)
 #pragma unroll
     for (int r = 0; r < 16; ++r) acc[q][r] = 0.0f;
-  float bcur[16], bnext[16];
+  float b0[16], b1[16];
   stage(0);
-#pragma unroll
-  for (int s = 0; s < 16; ++s) bcur[s] = ld(0, s);
+  ldc(0, b0);
   put(0);
   __syncthreads();
   double colsum64 = 0.0;
 #pragma unroll 1
   for (int c = 0; c < NC; ++c) {
-    const int cn = c + 1 < NC ? c + 1 : c;   // the last chunk reloads itself (in bounds, unused)
+    const int cn = c + 1 < NC ? c + 1 : c;   // the last chunk restages itself (in bounds, unused)
     stage(cn);
+    if (c + 1 < NC) ldc(c + 1, b1);
+    // this chunk's B operands: x = b X split into bf16 hi + lo
+    bf16x8 xh[2], xl[2];
 #pragma unroll
-    for (int s = 0; s < 16; ++s) bnext[s] = ld(cn, s);
-    const int qc = c - row0 / 32;
+    for (int t = 0; t < 2; ++t)
+#pragma unroll
+      for (int j = 0; j < 8; ++j) {
+        const float x = b0[8 * t + j] * bv;
+        xh[t][j] = static_cast<__bf16>(x);
+        xl[t][j] = bf16_rest(x, xh[t][j]);
+      }
+    const int qc = c - row0 / 32;           // accumulator block of this chunk's rows, if in the tile
     if (qc >= 0 && qc < NQ) {
       float cs = 0.0f;
 #pragma unroll
-      for (int s = 0; s < 16; ++s) cs += bcur[s];
+      for (int s = 0; s < 16; ++s) cs += b0[s];
       colsum64 += double(cs);
+      float pc[16];
+#pragma unroll
+      for (int g = 0; g < 4; ++g) {
+        const float4 p4 = *reinterpret_cast<const float4*>(A.plocol + 32 * c + 8 * g + 4 * hl);
+        pc[4 * g + 0] = p4.x;
+        pc[4 * g + 1] = p4.y;
+        pc[4 * g + 2] = p4.z;
+        pc[4 * g + 3] = p4.w;
+      }
 #pragma unroll
       for (int q = 0; q < NQ; ++q)
         if (q == qc) {
 #pragma unroll
-          for (int s = 0; s < 16; ++s) acc[q][s] = fmaf(av, bcur[s], acc[q][s]);
+          for (int s = 0; s < 16; ++s) {
+            acc[q][s] = fmaf(av, b0[s], acc[q][s]);
+            acc[q][s] = fmaf(pc[s], static_cast<float>(xl[s >> 3][s & 7]), acc[q][s]);
+          }
         }
     }
     const uint16_t* __restrict__ Ph = Sbuf + (c & 1) * 2 * MT * LDK + cl * LDK + 8 * hl;
     const uint16_t* __restrict__ Pl = Ph + MT * LDK;
 #pragma unroll
     for (int t = 0; t < 2; ++t) {
-      bf16x8 xh, xl;
-#pragma unroll
-      for (int j = 0; j < 8; ++j) {
-        const float x = bcur[8 * t + j] * bv;
-        xh[j] = static_cast<__bf16>(x);
-        xl[j] = bf16_rest(x, xh[j]);
-      }
 #pragma unroll
       for (int q = 0; q < NQ; ++q) {
         const bf16x8 ph = *reinterpret_cast<const bf16x8*>(Ph + q * 32 * LDK + 16 * t);
         const bf16x8 pl = *reinterpret_cast<const bf16x8*>(Pl + q * 32 * LDK + 16 * t);
-        acc[q] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ph, xh, acc[q], 0, 0, 0);
-        acc[q] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ph, xl, acc[q], 0, 0, 0);
-        acc[q] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(pl, xh, acc[q], 0, 0, 0);
-        acc[q] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(pl, xl, acc[q], 0, 0, 0);
+        acc[q] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ph, xh[t], acc[q], 0, 0, 0);
+        acc[q] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ph, xl[t], acc[q], 0, 0, 0);
+        acc[q] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(pl, xh[t], acc[q], 0, 0, 0);
       }
     }
     if (c + 1 < NC) put((c + 1) & 1);
     __syncthreads();
 #pragma unroll
-    for (int s = 0; s < 16; ++s) bcur[s] = bnext[s];
+    for (int s = 0; s < 16; ++s) b0[s] = b1[s];
   }
   char* __restrict__ yb0 = reinterpret_cast<char*>(A.Y);
 #pragma unroll
   for (int q = 0; q < NQ; ++q)
 #pragma unroll
-    for (int r = 0; r < 16; ++r)
-      *reinterpret_cast<float*>(yb0 + size_t(row0 + q * 32 + 8 * (r >> 2) + (r & 3)) * rowbytes +
-                                voff) = acc[q][r];
-  const long long nwg = (long long)gridDim.x * gridDim.y;
-  const long long wg = (long long)blockIdx.y * gridDim.x + blockIdx.x;
-  block_sums512((1.0 - double(av) - double(bv)) * colsum64, colsum64, A.part + wg,
-                A.part + nwg + wg);
+    for (int g = 0; g < 4; ++g) {
+      const __amdgpu_buffer_rsrc_t rs =
+          raw_rsrc(yb0 + size_t(row0 + 32 * q + 8 * g) * rowbytes, 8u * rowbytes);
+#pragma unroll
+      for (int j = 0; j < 4; ++j)
+        __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(acc[q][4 * g + j]), rs, int(voff),
+                                              int(j * rowbytes), 0);
+    }
+  block_sums512((1.0 - double(av) - double(bv)) * colsum64, colsum64, A.part + blockIdx.x,
+                A.part + gridDim.x + blockIdx.x);
 }
 
 // Implicit source (the converged Steps 3-6 of Sec. 2.4): every voxel's column
@@ -1226,82 +1223,6 @@ __global__ __launch_bounds__(512, 1) void collide_implicit_kernel(CollideArgs A,
   for (int tile = blockIdx.x; tile < ntiles; tile += gridDim.x)
     collide_implicit_tile<NP>(A, Vsh, lamS, tile, absorbed, total);
   block_sums512(absorbed, total, A.part + blockIdx.x, A.part + gridDim.x + blockIdx.x);
-}
-
-// Same contraction with P and X each split into bf16 high and low parts,
-// X = X_hi + X_lo, P = P_hi + P_lo, and P X = (P_hi + P_lo)(X_hi + X_lo) as four
-// v_mfma_f32_32x32x16_bf16 products with fp32 accumulation.  The products of
-// bf16 values are exact in fp32, so the only errors are the two splits (2^-16
-// of each value) and the fp32 sums.  All four terms are kept: without
-// P_lo X_lo, whose column sums are not zero, the contraction would no longer
-// conserve the light of each incoming direction.  P_hi / P_lo are staged
-// through LDS as [row][k] so each lane reads its 8 consecutive k in one 16-byte
-// load.
-template <int MT>
-__global__ __launch_bounds__(kThreads, 2) void collide_bf16split_kernel(CollideArgs A) {
-  constexpr int KC = 32;
-  constexpr int NQ = MT / 32;
-  constexpr int LDK = KC + 8;   // row pitch in bf16, padded against bank conflicts
-  __shared__ unsigned short Sh[MT * LDK];
-  __shared__ unsigned short Sl[MT * LDK];
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int hl = lane >> 5, cl = lane & 31;
-  const long long col = (long long)blockIdx.x * 128 + wave * 32 + cl;
-  const int row0 = blockIdx.y * MT;
-  floatx16 acc[NQ];
-#pragma unroll
-  for (int q = 0; q < NQ; ++q)
-#pragma unroll
-    for (int r = 0; r < 16; ++r) acc[q][r] = 0.0f;
-
-  const float* xcol = A.X + col;
-  for (int k0 = 0; k0 < A.NP; k0 += KC) {
-    __syncthreads();
-    // stage rows row0..row0+MT-1, columns k0..k0+KC-1 of P_hi and P_lo (8 bf16 per load)
-    for (int e = tid; e < MT * (KC / 8); e += kThreads) {
-      const int rr = e / (KC / 8), kk = (e - rr * (KC / 8)) * 8;
-      const size_t g = size_t(row0 + rr) * A.NP + k0 + kk;
-      *reinterpret_cast<uint4*>(Sh + rr * LDK + kk) = *reinterpret_cast<const uint4*>(A.Phi + g);
-      *reinterpret_cast<uint4*>(Sl + rr * LDK + kk) = *reinterpret_cast<const uint4*>(A.Plo + g);
-    }
-    __syncthreads();
-#pragma unroll
-    for (int s = 0; s < KC / 16; ++s) {
-      bf16x8 xh, xl;
-#pragma unroll
-      for (int j = 0; j < 8; ++j) {
-        const float x = xcol[size_t(k0 + 16 * s + 8 * hl + j) * A.Vp];
-        xh[j] = static_cast<__bf16>(x);
-        xl[j] = bf16_rest(x, xh[j]);
-      }
-#pragma unroll
-      for (int q = 0; q < NQ; ++q) {
-        const int off = (q * 32 + cl) * LDK + 16 * s + 8 * hl;
-        const bf16x8 ph = *reinterpret_cast<const bf16x8*>(Sh + off);
-        const bf16x8 pl = *reinterpret_cast<const bf16x8*>(Sl + off);
-        acc[q] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ph, xh, acc[q], 0, 0, 0);
-        acc[q] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ph, xl, acc[q], 0, 0, 0);
-        acc[q] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(pl, xh, acc[q], 0, 0, 0);
-        acc[q] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(pl, xl, acc[q], 0, 0, 0);
-      }
-    }
-  }
-
-  const float av = A.a[col], bv = A.b[col];
-  double colsum = 0.0;
-#pragma unroll
-  for (int q = 0; q < NQ; ++q)
-#pragma unroll
-    for (int r = 0; r < 16; ++r) {
-      const int row = row0 + q * 32 + 8 * (r >> 2) + 4 * hl + (r & 3);
-      const size_t idx = size_t(row) * A.Vp + col;
-      const float x = A.X[idx];
-      A.Y[idx] = av * x + bv * acc[q][r];
-      colsum += double(x);
-    }
-  const double vals[2] = {(1.0 - double(av) - double(bv)) * colsum, colsum};
-  const long long nwg = (long long)gridDim.x * gridDim.y;
-  block_sums<2>(vals, A.part + (long long)blockIdx.y * gridDim.x + blockIdx.x, nwg);
 }
 
 // ---------------------------------------------------------------------------
@@ -2574,11 +2495,6 @@ int collide_mt(int NP) {
 template <template <int> class K>
 struct Dummy;
 
-// The streamed kernel keeps 32-bit per-lane byte offsets of up to 5 rows.
-bool use_stream(const Field& f, int) {
-  return f.Vp * 4 * 5 < (1LL << 31);
-}
-
 template <int MT>
 size_t stream_lds(int bf16split) {
   return bf16split ? 2 * 2 * size_t(MT) * (32 + 8) * sizeof(uint16_t)
@@ -2587,21 +2503,14 @@ size_t stream_lds(int bf16split) {
 
 template <int MT>
 hipError_t launch_collide_mt(const CollideArgs& a, const Field& f, int bf16split, hipStream_t s) {
-  if (use_stream(f, bf16split)) {
-    dim3 grid(unsigned(f.Vp / 256), unsigned(f.NP / MT));
-    if (bf16split)
-      hipLaunchKernelGGL(collide_bf16_stream_kernel<MT>, grid, dim3(512), stream_lds<MT>(1), s,
-                         a);
-    else
-      hipLaunchKernelGGL(collide_f32_stream_kernel<MT>, grid, dim3(512), stream_lds<MT>(0), s,
-                         a);
-    return hipGetLastError();
-  }
-  dim3 grid(unsigned(f.Vp / 128), unsigned(f.NP / MT));
+  const int ntiles = int(f.Vp / 256);
+  dim3 grid(unsigned(ntiles * (f.NP / MT)));
   if (bf16split)
-    hipLaunchKernelGGL(collide_bf16split_kernel<MT>, grid, dim3(kThreads), 0, s, a);
+    hipLaunchKernelGGL(collide_bf16_stream_kernel<MT>, grid, dim3(512), stream_lds<MT>(1), s, a,
+                       ntiles);
   else
-    hipLaunchKernelGGL(collide_f32_kernel<MT>, grid, dim3(kThreads), 0, s, a);
+    hipLaunchKernelGGL(collide_f32_stream_kernel<MT>, grid, dim3(512), stream_lds<MT>(0), s, a,
+                       ntiles);
   return hipGetLastError();
 }
 
@@ -2654,16 +2563,14 @@ hipError_t launch_res(const CollideArgs& a, const Field& f, int bf16split, hipSt
   return hipGetLastError();
 }
 
-// The resident kernels keep 32-bit per-lane byte offsets of up to 5 rows.
 bool use_resident(const Field& f, int) {
-  return f.NP <= 192 && f.Vp * 4 * 5 < (1LL << 31);
+  return f.NP <= 192;
 }
 
 }  // namespace
 
 hipError_t prepare_collide(const Field& f, int bf16split) {
   if (!use_resident(f, bf16split)) {
-    if (!use_stream(f, bf16split)) return hipSuccess;
     switch (collide_mt(f.NP)) {
       case 256: return prepare_stream_mt<256>(bf16split);
       case 224: return prepare_stream_mt<224>(bf16split);
@@ -2690,8 +2597,7 @@ int collide_nwg(const Field& f, int bf16split) {
     const int ntiles = int(f.Vp / 256);
     return ntiles < resident_blocks() ? ntiles : resident_blocks();
   }
-  if (use_stream(f, bf16split)) return int(f.Vp / 256) * (f.NP / collide_mt(f.NP));
-  return int(f.Vp / 128) * (f.NP / collide_mt(f.NP));
+  return int(f.Vp / 256) * (f.NP / collide_mt(f.NP));
 }
 
 hipError_t launch_collide(const CollideArgs& a, const Field& f, int bf16split, int, hipStream_t s) {

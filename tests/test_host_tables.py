@@ -121,6 +121,21 @@ def test_invalid_descriptor_is_rejected():
     assert "nside" in str(e.value)
 
 
+def test_grid_voxel_limit():
+    """The collision kernels address five rows of the field with 32-bit byte
+    offsets: 107374080 voxels (after padding to 256) is the largest grid."""
+    p = W.small_problem(nside=1)
+    d = T.grid_desc(p)
+    d.nx, d.ny, d.nz = 4096, 4096, 6          # 100663296 voxels
+    assert T.bytes_required(d) > 0
+    d.nx, d.ny, d.nz = 4096, 4096, 7          # 117440512 voxels
+    assert T.bytes_required(d) == 0
+    d.nx, d.ny, d.nz = 2560, 2560, 16         # 104857600 voxels
+    assert T.bytes_required(d) > 0
+    d.nx, d.ny, d.nz = 2560, 2560, 17         # 111411200 voxels
+    assert T.bytes_required(d) == 0
+
+
 @pytest.mark.parametrize("nf,nc", [(2, 1), (4, 1), (8, 2), (16, 4), (16, 16)])
 def test_host_parents_match_oracle(nf, nc):
     from oracle import angles
