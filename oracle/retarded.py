@@ -34,11 +34,32 @@ Readings (each one is what the paper leaves open):
     zero where v has no upwind voxel (vacuum inflow) and C^j = 0 for j < 0.
     The history holds n_max + 1 collided fields (n_max = max_d n_d): nine at
     a fifth of the crossing time, where D_d reaches 5 sqrt(3).
-  * Uniform refractive index only (one D_d per direction, no Fresnel
-    interception).
+  * A varying refractive index: the hop from u takes D[d, u] = dr_d n_u /
+    (c0 dt) steps, the index of the hop's start voxel (the nearest-voxel
+    reading of the coefficients), so lag and fraction are per direction and
+    voxel.  The light crossing a plane per step is content / D[d, u] (a flux),
+    and a move between voxels of the same index copies content.
+  * Interfaces (Sec. 3.3, Eq. 13-14): a hop that would carry light from u
+    into a voxel w of another index is intercepted, as in solve: of the flux
+    F = r / D[d, u] that reaches the interface (r the retarded collided
+    content), R F returns into u along the mirror direction d_r and (1 - R) F
+    enters w along Snell's direction d_t.  Each becomes content at the flux
+    it carries times the hop duration of its new direction and voxel:
+    R r D[d_r, u] / D[d, u] and (1 - R) r D[d_t, w] / D[d, u].  Photons are
+    then conserved across the interface.
+  * Source weighting (prob.retarded_source):
+      "target" (default): C = a N + b (P N), b = omega (1 - a), the formal
+        solution of Eq. 10 along the target direction's hop with the
+        explicit source; the target's own 1 - e^{-dtau} weights the source,
+        which the paper prints.  With unequal hops it conserves light only
+        to O(dtau) per scattering.
+      "flux": C = a N + D (omega P ((1 - a) / D N)) per voxel: the light each
+        direction loses to scattering per step, (1 - a_j) omega N_j / D_j,
+        is what the others gain per step, so scattering conserves photons
+        exactly.  It agrees with "target" to first order in dtau.
   * With the source on a coarser angular grid, P is the effective fine-grid
     matrix of angles.two_level_matrix, and the hop coefficients are those of
-    each fine direction.
+    each fine direction (uniform index only).
 
 Test infrastructure only (see the package docstring)."""
 from dataclasses import dataclass
@@ -46,7 +67,7 @@ from typing import List
 
 import numpy as np
 
-from . import angles, lattice, medium, setup
+from . import angles, lattice, medium, optics, setup
 
 
 @dataclass
@@ -56,11 +77,12 @@ class RetardedSetup:
     lat: lattice.RayLattice
     dt: float
     hop: np.ndarray          # dr_d [nd], mm
-    D: np.ndarray            # hop duration in steps [nd]
-    nlag: np.ndarray         # floor(D) [nd]
-    phi: np.ndarray          # D - floor(D) [nd]
+    D: np.ndarray            # hop duration in steps [nd, nv] (hop from the voxel)
+    nlag: np.ndarray         # floor(D) [nd, nv]
+    phi: np.ndarray          # D - floor(D) [nd, nv]
     a: np.ndarray            # [nd, nv] hop attenuation
     b: np.ndarray            # [nd, nv] hop source weight
+    omega: np.ndarray        # [nv] albedo
     H: int                   # collided fields kept
     downwind: List[np.ndarray]
     exit_face: List[np.ndarray]
@@ -71,6 +93,8 @@ class RetardedSetup:
     det_vox: List[int]
     det_face: List[int]
     det_acc: List[List[int]]
+    icpt: list               # interceptions (d, v, w, R, d_r, d_t, w_r, w_t): content weights
+    source: str = "target"   # "target" | "flux"
 
 
 def hop_lengths(lat: lattice.RayLattice, dx):
@@ -105,26 +129,34 @@ def build(prob, dirs=None, P=None) -> RetardedSetup:
     grid of prob.nside and its Sinkhorn HG matrix; tests may pass others."""
     shape = (prob.nz, prob.ny, prob.nx)
     n = np.asarray(prob.n, dtype=np.float64)
-    if not np.all(n == n.flat[0]):
-        raise ValueError("retarded stepping needs a uniform refractive index")
+    uniform = bool(np.all(n == n.flat[0]))
     if dirs is None:
         dirs = angles.healpix_ring(prob.nside)
     ns = getattr(prob, "nside_scatter", 0)
+    if ns and ns != prob.nside and not uniform:
+        raise ValueError("the two-level source needs a uniform refractive index here")
     if P is None and ns and ns != prob.nside:
         # the source on a coarser angular grid (Sec. 2.1): the effective
         # fine-grid matrix, as in solve.build
         P = angles.two_level_matrix(prob.nside, ns, prob.g, prob.hg_norm)
     if P is None:
         P = angles.phase_matrix(dirs, prob.g, prob.hg_norm)
+    source = getattr(prob, "retarded_source", "target")
+    if source not in ("target", "flux"):
+        raise ValueError(source)
     lat = lattice.RayLattice(dirs, shape)
     dt = medium.time_step(prob.dx_mm, n, prob.dt_ps)
     hop = hop_lengths(lat, prob.dx_mm)
-    D = hop * float(n.flat[0]) / (medium.C0_MM_PER_PS * dt)
+    D = hop[:, None] * n.ravel()[None, :] / (medium.C0_MM_PER_PS * dt)
     if np.min(D) < 1.0 - 1e-12:
         raise ValueError("time step longer than a hop (Courant number above one)")
     nlag = np.floor(D + 1e-12).astype(np.int64)
     phi = np.maximum(D - nlag, 0.0)
     a, b = hop_coefficients(prob.mua, prob.mus, hop)
+    mut = np.asarray(prob.mua, dtype=np.float64).ravel() + np.asarray(prob.mus,
+                                                                      dtype=np.float64).ravel()
+    omega = np.where(mut > 0.0, np.asarray(prob.mus, dtype=np.float64).ravel() /
+                     np.where(mut > 0.0, mut, 1.0), 0.0)
     nv = prob.nvox
     dw, ef, uw = [], [], []
     for d in range(len(dirs)):
@@ -132,9 +164,16 @@ def build(prob, dirs=None, P=None) -> RetardedSetup:
         dw.append(w)
         ef.append(f)
         uw.append(upwind_map(w, nv))
+    icpt = []
+    if not uniform:
+        for (d, v, w, R, dr, dtt) in optics.interceptions(lat, n):
+            wr = R * D[dr, v] / D[d, v]
+            wt = (1.0 - R) * D[dtt, w] / D[d, v] if dtt >= 0 else 0.0
+            icpt.append((d, v, w, R, dr, dtt, wr, wt))
     return RetardedSetup(
         dirs=np.asarray(dirs, dtype=np.float64), P=np.asarray(P, dtype=np.float64), lat=lat,
-        dt=dt, hop=hop, D=D, nlag=nlag, phi=phi, a=a, b=b, H=int(nlag.max()) + 1,
+        dt=dt, hop=hop, D=D, nlag=nlag, phi=phi, a=a, b=b, omega=omega,
+        H=int(nlag.max()) + 1,
         downwind=dw, exit_face=ef, upwind=uw,
         src_vox=setup.source_voxels(shape, prob.src_ix, prob.src_iy, prob.src_w),
         src_dirs=setup.source_directions(dirs, prob.src_cone_deg),
@@ -142,63 +181,85 @@ def build(prob, dirs=None, P=None) -> RetardedSetup:
         det_vox=[setup.detector_voxel(shape, f, i, j)
                  for f, i, j in zip(prob.det_face, prob.det_i, prob.det_j)],
         det_face=list(prob.det_face),
-        det_acc=[setup.detector_acceptance(dirs, f, prob.det_cone_deg) for f in prob.det_face])
+        det_acc=[setup.detector_acceptance(dirs, f, prob.det_cone_deg) for f in prob.det_face],
+        icpt=icpt, source=source)
 
 
 def inject(S: RetardedSetup, N, m):
     """The pulse's q_m photons of step m, spread evenly over the source pairs;
-    a pair of direction d gets content D_d times its share.  Returns q_m."""
+    a pair (d, v) gets content D[d, v] times its share.  Returns q_m."""
     q = setup.pulse_weight(m, S.dt, *S.pulse)
     share = q / (len(S.src_vox) * len(S.src_dirs))
     for d in S.src_dirs:
         for v in S.src_vox:
-            N[d, v] += S.D[d] * share
+            N[d, v] += S.D[d, v] * share
     return q
 
 
 def collide(S: RetardedSetup, N):
-    """C = a N + b (P N) with the hop coefficients; absorbed per step is
-    sum (1 - a - b) N / D_d."""
-    C = S.a * N + S.b * (S.P @ N)
-    absorbed = float(np.sum((1.0 - S.a - S.b) * N / S.D[:, None]))
+    """The collision of one hop, by the set-up's source weighting (see the
+    module docstring); absorbed per step is sum (1 - omega)(1 - a) N / D."""
+    if S.source == "flux":
+        C = S.a * N + S.D * (S.omega[None, :] * (S.P @ ((1.0 - S.a) / S.D * N)))
+    else:
+        C = S.a * N + S.b * (S.P @ N)
+    absorbed = float(np.sum((1.0 - S.omega[None, :]) * (1.0 - S.a) * N / S.D))
     return C, absorbed
 
 
 def retarded_value(S: RetardedSetup, hist, d, m):
-    """Row d of the collided field at the retarded time m + 1 - D_d:
-    (1 - phi) C^{m+1-n} + phi C^{m-n}, from hist[j] = C^j (missing = zero)."""
-    n, phi = int(S.nlag[d]), float(S.phi[d])
+    """Row d of the collided field at the retarded time m + 1 - D[d, v] of each
+    voxel: (1 - phi) C^{m+1-n} + phi C^{m-n}, from hist[j] = C^j (missing =
+    zero)."""
     nv = S.a.shape[1]
-    late = hist.get(m + 1 - n)
-    early = hist.get(m - n)
     r = np.zeros(nv)
-    if late is not None:
-        r += (1.0 - phi) * late[d]
-    if early is not None and phi > 0.0:
-        r += phi * early[d]
+    for n in np.unique(S.nlag[d]):
+        sel = S.nlag[d] == n
+        phi = S.phi[d, sel]
+        late = hist.get(m + 1 - int(n))
+        early = hist.get(m - int(n))
+        if late is not None:
+            r[sel] += (1.0 - phi) * late[d, sel]
+        if early is not None:
+            r[sel] += phi * early[d, sel]
     return r
 
 
 def transport(S: RetardedSetup, hist, m, ndet):
     """N^{m+1} from the history of collided fields; escape per face and the
-    detector records of step m (content / D_d of what crosses the boundary)."""
+    detector records of step m (flux: content / D of what crosses the
+    boundary); hops across an index jump are intercepted (module docstring)."""
     nd, nv = S.a.shape
     out = np.zeros((nd, nv))
     escape = np.zeros(6)
     det = np.zeros(ndet)
+    held = {}
+    cut = {}
+    for (d, v, w, R, dr, dtt, wr, wt) in S.icpt:
+        cut.setdefault(d, []).append(w)
     for d in range(nd):
         r = retarded_value(S, hist, d, m)
         u = S.upwind[d]
         has = u >= 0
+        if d in cut:
+            has = has.copy()
+            has[cut[d]] = False
         out[d, has] = r[u[has]]
+        held[d] = r
         leaving = np.nonzero(S.downwind[d] < 0)[0]
         faces = S.exit_face[d][leaving]
+        flux = r[leaving] / S.D[d, leaving]
         for fc in range(6):
-            escape[fc] += r[leaving[faces == fc]].sum() / S.D[d]
+            escape[fc] += flux[faces == fc].sum()
         for k in range(ndet):
             v = S.det_vox[k]
             if d in S.det_acc[k] and S.downwind[d][v] < 0 and S.exit_face[d][v] == S.det_face[k]:
-                det[k] += r[v] / S.D[d]
+                det[k] += r[v] / S.D[d, v]
+    for (d, v, w, R, dr, dtt, wr, wt) in S.icpt:
+        F = held[d][v]
+        out[dr, v] += wr * F
+        if dtt >= 0:
+            out[dtt, w] += wt * F
     return out, escape, det
 
 

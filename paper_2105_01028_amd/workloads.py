@@ -48,6 +48,9 @@ class Problem:
                                 # HEALPix grid (nside / nside_scatter a power of two)
     transport: str = "auto"     # "auto": phase moves in the collision kernel where it
                                 # applies | "sweep": always the separate sweep kernel
+    retarded_source: str = "target"   # retarded advance: "target" (the target direction's
+                                      # 1 - e^-dtau weights the source) | "flux" (the
+                                      # scattered flux of each direction, conservative)
     src_ix: int = 0
     src_iy: int = 0
     src_w: int = 2           # 1 = one top-face voxel, 2 = the 2x2 block at (ix..ix+1, iy..iy+1)
