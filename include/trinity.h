@@ -59,6 +59,7 @@ enum { TR_ADVANCE_AUTO = 0, TR_ADVANCE_PHASE = 1, TR_ADVANCE_SPLIT = 2, TR_ADVAN
 enum { TR_PREC_FP32 = 0, TR_PREC_BF16SPLIT = 1 };
 enum { TR_SOURCE_EXPLICIT = 0, TR_SOURCE_IMPLICIT = 1 };
 enum { TR_TRANSPORT_AUTO = 0, TR_TRANSPORT_SWEEP = 1 };
+enum { TR_RSRC_TARGET = 0, TR_RSRC_FLUX = 1 };
 
 typedef struct {
   int nx, ny, nz;     /* voxels per axis, each >= 1 and <= 4096, and at most 107374080
@@ -87,11 +88,18 @@ typedef struct {
                          between the two nearest steps).  A voxel's photons cross a plane at
                          1/D_d of them per step: the source puts D_d times its per-step
                          photons into its voxels, and escape, detector and absorption
-                         tallies count 1/D_d of the content per step.  Needs uniform n, FP32,
-                         the explicit source, TR_COEF_PAPER, and at most 192 directions
-                         unless nside_scatter puts the source on a coarser grid (then
-                         a = e^{-mu_t dr_d} per fine direction and b (P N) comes from the
-                         coarse bins); tr_set_state, the adjoint and the server refuse it */
+                         tallies count 1/D_d of the content per step.  A varying n makes
+                         the hop from voxel u last D_d n_u / min(n) steps, and a hop into a
+                         voxel of another index is intercepted (Eq. 13-14, Sec. 3.3): of
+                         the flux that reaches the interface, R returns along the mirror
+                         direction and 1 - R enters along Snell's direction, each turned
+                         into content with its new hop's duration (at most 127 distinct
+                         values of n).  Needs FP32, the explicit source, TR_COEF_PAPER, and
+                         at most 192 directions unless nside_scatter puts the source on a
+                         coarser grid (then a = e^{-mu_t dr_d} per fine direction and
+                         b (P N) comes from the coarse bins; uniform n only); see also
+                         retarded_source; tr_set_state, the adjoint and the server refuse
+                         it */
   int precision;      /* TR_PREC_FP32 or TR_PREC_BF16SPLIT (P and N split into bf16 hi+lo,
                          the four bf16 MFMA products, fp32 accumulation; each value
                          off by at most 2^-16 of itself) */
@@ -116,6 +124,15 @@ typedef struct {
                          each collided value straight to its downwind voxel: one kernel
                          per step instead of a collision and a sweep, same field values.
                          TR_TRANSPORT_SWEEP (1): always the separate sweep kernel. */
+  int retarded_source;  /* TR_ADVANCE_RETARDED only.  TR_RSRC_TARGET (0): the source of
+                         direction i weighted by its own hop's 1 - e^{-dtau_i} (the formal
+                         solution of Eq. 10 along the target's hop, as the paper prints it;
+                         with hops of unequal length scattering conserves light only to
+                         O(dtau)).  TR_RSRC_FLUX (1): C_i = a_i N_i + D_i omega
+                         sum_j P_ij (1 - a_j) N_j / D_j -- what each direction scatters per
+                         step is what the others gain, so light is conserved exactly; it
+                         agrees with TR_RSRC_TARGET to first order in dtau.  Needs one
+                         angular grid. */
 } tr_grid_desc;
 
 typedef struct {

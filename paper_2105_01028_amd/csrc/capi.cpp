@@ -53,6 +53,12 @@ struct tr_medium {
   // omega, per-row 1/|Omega_a| and 1/D
   float *ring = nullptr, *mutdx = nullptr, *omega = nullptr, *hinvc = nullptr, *hinvD = nullptr;
   int H = 0;
+  // retarded advance with a varying index: hop tables per direction and index
+  // class [NP][128] (whole steps, fraction, D, 1/D), D_d per row for the flux
+  // source, and per interception the content the gather makes of it
+  bool rhet = false;
+  int* rlagc = nullptr;
+  float *rphic = nullptr, *rDc = nullptr, *rinvDc = nullptr, *hD = nullptr, *icptW = nullptr;
   // two-level angular grid: coarse field of nc directions (NPc rows)
   bool twolevel = false;
   bool tlfused = false;     // two-level phase stepping: the sweep forms the collided value, the
@@ -293,6 +299,10 @@ hipError_t queue_step(tr_medium* m, const Workspace& w) {
   InjectArgs ia{m->X,   f.Vp,        m->src_pairs, m->npairs, m->qdev,
                 m->cap, m->step_ctr, m->budget,    m->ddirs,  m->ring != nullptr,
                 m->tlfused || m->mfused ? m->Y : nullptr};
+  if (m->rhet) {
+    ia.mat = m->mat;
+    ia.rDc = m->rDc;
+  }
   if (m->npairs > 0 && !m->mfused) {   // the collision with the moves injects itself
     KernelTimer t(m, TR_K_INJECT);
     if ((e = launch_inject(ia, m->stream)) != hipSuccess) return e;
@@ -346,6 +356,9 @@ hipError_t queue_step(tr_medium* m, const Workspace& w) {
     ca.omega = m->omega;
     ca.hinvc = m->hinvc;
     ca.hinvD = m->hinvD;
+    ca.rvox = m->rhet ? m->r : nullptr;
+    ca.hD = m->hD;
+    ca.flux = m->desc.retarded_source;
     if ((e = launch_collide_hop(ca, f, m->stream)) != hipSuccess) return e;
   } else if (m->mfused) {
     KernelTimer t(m, TR_K_COLLIDE);
@@ -398,6 +411,12 @@ hipError_t queue_step(tr_medium* m, const Workspace& w) {
       sa.pp1 = m->Y;
       sa.dorder = m->children;   // the children of each coarse bin together
       e = launch_sweep_twolevel(sa, f, m->sweep_bpd, m->stream);
+    } else if (m->ring && m->rhet) {
+      sa.rlagc = m->rlagc;
+      sa.rphic = m->rphic;
+      sa.rinvDc = m->rinvDc;
+      sa.icptW = m->icptW;
+      e = launch_sweep_retarded_het(sa, f, m->sweep_bpd, m->stream);
     } else if (m->ring) {
       e = launch_sweep_retarded(sa, f, m->sweep_bpd, m->stream);
     } else {
@@ -422,6 +441,12 @@ hipError_t queue_step(tr_medium* m, const Workspace& w) {
     ra.tlshare = 1.0f / float(m->nkids);
     ra.pp0 = m->X;
     ra.pp1 = m->Y;
+  }
+  if (m->rhet) {
+    ra.mat = m->mat;
+    ra.rlagc = m->rlagc;
+    ra.rphic = m->rphic;
+    ra.rinvDc = m->rinvDc;
   }
   if (m->mfused) {
     ra.snwg = m->cnwg;   // the transport partials come from the collision's workgroups
@@ -555,10 +580,13 @@ tr_status tr_create_medium(const tr_grid_desc* desc, const float* mua, const flo
     delete m;
     return fail(TR_EINVAL, "phase advance needs a uniform refractive index");
   }
-  if (mode == TR_ADVANCE_RETARDED && !m->co.uniform_n) {
+  if (mode == TR_ADVANCE_RETARDED && !m->co.uniform_n &&
+      desc->nside_scatter != 0 && desc->nside_scatter != desc->nside) {
     delete m;
-    return fail(TR_EINVAL, "the retarded advance needs a uniform refractive index");
+    return fail(TR_EINVAL, "the retarded advance on a two-level angular grid needs a uniform "
+                           "refractive index");
   }
+  m->rhet = mode == TR_ADVANCE_RETARDED && !m->co.uniform_n;
   m->mode = mode;
   double maxspeed = 0, maxr = 0;
   for (double s : m->lat.speed) maxspeed = std::max(maxspeed, s);
@@ -582,7 +610,7 @@ tr_status tr_create_medium(const tr_grid_desc* desc, const float* mua, const flo
     delete m;
     return fail(TR_EINVAL, "phase matrix scaling did not converge");
   }
-  if (mode == TR_ADVANCE_SPLIT && !m->co.uniform_n) {
+  if ((mode == TR_ADVANCE_SPLIT || mode == TR_ADVANCE_RETARDED) && !m->co.uniform_n) {
     m->icpt = interceptions(m->lat, m->dirs, pn);
     m->fresnel = !m->icpt.empty();
   }
@@ -756,8 +784,23 @@ tr_status tr_create_medium(const tr_grid_desc* desc, const float* mua, const flo
     m->niface = ni;
     // targets: (d_refl, v) gets R F, (d_refr, w) gets (1 - R) F
     std::map<std::pair<int, long long>, std::vector<std::pair<int, float>>> tg;
+    // retarded advance: F is the content that reached the interface, a flux of
+    // F / D[d][v]; each share becomes content at the hop duration of its new
+    // direction and voxel, D[d][v] = D_d n_v / n_ref
+    auto hop = [&](int d, long long v) { return (1.0 / dd[d].nu64) / m->co.r[v]; };
+    std::vector<float> wsum;
+    if (m->rhet) wsum.assign(size_t(ni) * f.ndir, 0.0f);
     for (const Interception& ic : m->icpt) {
       const int slot = islot[ic.v] * f.ndir + ic.d;
+      if (m->rhet) {
+        const double Dd = hop(ic.d, ic.v);
+        const float wr = float(ic.R * hop(ic.d_refl, ic.v) / Dd);
+        const float wt = ic.d_refr >= 0 ? float((1.0 - ic.R) * hop(ic.d_refr, ic.w) / Dd) : 0.0f;
+        tg[{ic.d_refl, ic.v}].push_back({slot, wr});
+        if (ic.d_refr >= 0) tg[{ic.d_refr, ic.w}].push_back({slot, wt});
+        wsum[slot] = float(double(wr) + double(wt));
+        continue;
+      }
       // reflected share R F; refracted share F - R F, encoded as weight -R
       tg[{ic.d_refl, ic.v}].push_back({slot, float(ic.R)});
       if (ic.d_refr >= 0) tg[{ic.d_refr, ic.w}].push_back({slot, -float(ic.R)});
@@ -801,6 +844,11 @@ tr_status tr_create_medium(const tr_grid_desc* desc, const float* mua, const flo
     if (e == hipSuccess) e = hipMemcpy(m->gptr, ptr.data(), ptr.size() * 4, hipMemcpyHostToDevice);
     if (e == hipSuccess) e = hipMemcpy(m->gsrc, src.data(), src.size() * 4, hipMemcpyHostToDevice);
     if (e == hipSuccess) e = hipMemcpy(m->gw, w.data(), w.size() * 4, hipMemcpyHostToDevice);
+    if (e == hipSuccess && m->rhet) {
+      m->icptW = m->alloc<float>(wsum.size());
+      e = m->icptW ? hipMemcpy(m->icptW, wsum.data(), wsum.size() * 4, hipMemcpyHostToDevice)
+                   : hipErrorOutOfMemory;
+    }
     if (e != hipSuccess) {
       delete m;
       return fail(TR_EDEVICE, std::string("upload: ") + hipGetErrorString(e));
@@ -857,11 +905,52 @@ tr_status tr_create_medium(const tr_grid_desc* desc, const float* mua, const flo
   // ---- retarded advance: history ring of collided fields and hop tables
   if (m->mode == TR_ADVANCE_RETARDED) {
     int maxlag = 0;
-    std::vector<float> ic(f.NP, 0.0f), iD(f.NP, 0.0f);
+    std::vector<float> ic(f.NP, 0.0f), iD(f.NP, 0.0f), hDv(f.NP, 0.0f);
     for (int d = 0; d < f.ndir; ++d) {
       maxlag = std::max(maxlag, dd[d].rlag);
       ic[d] = float(1.0 / m->lat.speed[d]);
       iD[d] = dd[d].rinvD;
+      hDv[d] = dd[d].rD;
+    }
+    // a varying index: per direction and index class, the hop's whole steps,
+    // fraction, D and 1/D, D = D_d n / n_ref (the class's path ratio r =
+    // n_ref / n, rtab)
+    std::vector<int> lc;
+    std::vector<float> pc, Dc, iDc;
+    if (m->rhet) {
+      // the index classes of the split-mode class bytes: distinct n in
+      // increasing order (at most 127, checked there)
+      std::map<float, int> cls;
+      for (int v = 0; v < f.V && cls.size() <= 127; ++v) cls.emplace(pn[v], 0);
+      if (cls.size() > 127) {
+        delete m;
+        return fail(TR_EINVAL, "the retarded advance takes at most 127 distinct refractive "
+                               "indices");
+      }
+      int nc = 0;
+      for (auto& kv : cls) kv.second = nc++;
+      std::vector<double> rcls(128, 0.0);
+      std::vector<char> seen(128, 0);
+      for (int v = 0; v < f.V; ++v) {
+        const int c = cls[pn[v]];
+        rcls[c] = m->co.r[v];
+        seen[c] = 1;
+      }
+      lc.assign(size_t(f.NP) * 128, 0);
+      pc.assign(size_t(f.NP) * 128, 0.0f);
+      Dc.assign(size_t(f.NP) * 128, 0.0f);
+      iDc.assign(size_t(f.NP) * 128, 0.0f);
+      for (int d = 0; d < f.ndir; ++d)
+        for (int c = 0; c < 128; ++c) {
+          if (!seen[c]) continue;
+          const double D = (1.0 / dd[d].nu64) / rcls[c];
+          const int lag = int(std::floor(D + 1e-12));
+          lc[size_t(d) * 128 + c] = lag;
+          pc[size_t(d) * 128 + c] = float(std::max(D - lag, 0.0));
+          Dc[size_t(d) * 128 + c] = float(D);
+          iDc[size_t(d) * 128 + c] = float(1.0 / D);
+          maxlag = std::max(maxlag, lag);
+        }
     }
     m->H = maxlag + 1;
     std::vector<float> mx(f.Vp, 0.0f), om(f.Vp, 0.0f);
@@ -877,7 +966,15 @@ tr_status tr_create_medium(const tr_grid_desc* desc, const float* mua, const flo
     m->omega = m->alloc<float>(f.Vp);
     m->hinvc = m->alloc<float>(f.NP);
     m->hinvD = m->alloc<float>(f.NP);
-    if (!m->ring || !m->mutdx || !m->omega || !m->hinvc || !m->hinvD) {
+    m->hD = m->alloc<float>(f.NP);
+    if (m->rhet) {
+      m->rlagc = m->alloc<int>(lc.size());
+      m->rphic = m->alloc<float>(pc.size());
+      m->rDc = m->alloc<float>(Dc.size());
+      m->rinvDc = m->alloc<float>(iDc.size());
+    }
+    if (!m->ring || !m->mutdx || !m->omega || !m->hinvc || !m->hinvD || !m->hD ||
+        (m->rhet && (!m->rlagc || !m->rphic || !m->rDc || !m->rinvDc))) {
       delete m;
       return fail(TR_ENOMEM, "device allocation failed (history of the retarded advance)");
     }
@@ -886,6 +983,14 @@ tr_status tr_create_medium(const tr_grid_desc* desc, const float* mua, const flo
     if (e == hipSuccess) e = hipMemcpy(m->omega, om.data(), om.size() * 4, hipMemcpyHostToDevice);
     if (e == hipSuccess) e = hipMemcpy(m->hinvc, ic.data(), ic.size() * 4, hipMemcpyHostToDevice);
     if (e == hipSuccess) e = hipMemcpy(m->hinvD, iD.data(), iD.size() * 4, hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(m->hD, hDv.data(), hDv.size() * 4, hipMemcpyHostToDevice);
+    if (e == hipSuccess && m->rhet) {
+      e = hipMemcpy(m->rlagc, lc.data(), lc.size() * 4, hipMemcpyHostToDevice);
+      if (e == hipSuccess) e = hipMemcpy(m->rphic, pc.data(), pc.size() * 4, hipMemcpyHostToDevice);
+      if (e == hipSuccess) e = hipMemcpy(m->rDc, Dc.data(), Dc.size() * 4, hipMemcpyHostToDevice);
+      if (e == hipSuccess)
+        e = hipMemcpy(m->rinvDc, iDc.data(), iDc.size() * 4, hipMemcpyHostToDevice);
+    }
     // (on a two-level grid the hop collision is apply_hop's, from the coarse source)
     if (e == hipSuccess && !m->twolevel) e = prepare_collide_hop(f);
     if (e != hipSuccess) {
@@ -936,9 +1041,13 @@ tr_status tr_create_medium(const tr_grid_desc* desc, const float* mua, const flo
   }
   // ---- split mode: one byte per voxel naming its index class (at most 127
   // distinct values of n) and whether it starts an interception
-  if (m->mode == TR_ADVANCE_SPLIT) {
+  if (m->mode == TR_ADVANCE_SPLIT || m->rhet) {
     std::map<float, int> cls;
     for (int v = 0; v < f.V && cls.size() <= 127; ++v) cls.emplace(pn[v], 0);
+    if (m->rhet && cls.size() > 127) {
+      delete m;
+      return fail(TR_EINVAL, "the retarded advance takes at most 127 distinct refractive indices");
+    }
     if (cls.size() <= 127) {
       std::vector<float> rt(128, 0.0f);
       std::vector<uint8_t> mb(f.Vp, 0);

@@ -52,6 +52,12 @@ inline bool valid_desc(const tr_grid_desc* d, std::string& err) {
   if (d->precision != 0 && d->precision != 1) return err = "bad precision", false;
   if (d->source != 0 && d->source != 1) return err = "bad source", false;
   if (d->transport != 0 && d->transport != 1) return err = "bad transport", false;
+  if (d->retarded_source != 0 && d->retarded_source != 1)
+    return err = "bad retarded_source", false;
+  if (d->retarded_source == 1 &&
+      (d->advance != 3 || (d->nside_scatter != 0 && d->nside_scatter != d->nside)))
+    return err = "the flux-weighted source needs the retarded advance on one angular grid",
+           false;
   if (d->nside_scatter != 0 && d->nside_scatter != d->nside) {
     const int ns = d->nside_scatter;
     if (ns < 1 || ns > d->nside || d->nside % ns != 0 || ((d->nside / ns) & (d->nside / ns - 1)))

@@ -42,6 +42,10 @@ struct InjectArgs {
   int retarded;
   float* X2;               // two-level phase stepping: the field alternates between X (even
                            // steps) and X2 (odd steps); null otherwise
+  // retarded stepping with a varying index (null otherwise): a pair (d, v) gets
+  // rDc[d * 128 + class] times its share, class = mat[v] & 0x7f
+  const uint8_t* mat;
+  const float* rDc;
 };
 
 struct CollideArgs {
@@ -97,6 +101,13 @@ struct CollideArgs {
   // bf16-split with more than 192 directions (streamed P): [NP] column sums
   // sum_i P_lo[i][k], the column totals of the P_lo x_lo term the kernel drops
   const float* plocol;
+  // retarded stepping: rvox = n_ref / n per voxel (null: uniform index), so a
+  // hop from voxel v lasts D[d][v] = D_d / rvox[v] steps; with flux = 1 the
+  // source is weighted by the scattered flux of each direction and hD holds D_d
+  // per row (zero on padding rows)
+  const float* rvox;
+  const float* hD;
+  int flux;
 };
 
 struct SweepArgs {
@@ -135,6 +146,14 @@ struct SweepArgs {
   float* pp0;
   float* pp1;
   const int* dorder;
+  // retarded stepping with a varying index (launch_sweep_retarded_het): per
+  // direction and index class ([NP][128]) the hop's whole steps, fraction and
+  // 1/D; icptW[slot * ndir + d] = the content the intercepted light becomes
+  // per unit of what reached the interface (reflected + refracted weights)
+  const int* rlagc;
+  const float* rphic;
+  const float* rinvDc;
+  const float* icptW;
 };
 
 constexpr int kMaxRowBits = 65536;   // rows covered by the uniform-row bitmap (8 KB)
@@ -186,6 +205,12 @@ struct ReduceArgs {
   // phase moves in the collision (launch_collide_move): detectors read the
   // exiting light that the collision left in the field of this step's parity
   int mvfused;
+  // retarded stepping with a varying index: class bytes and the per-class hop
+  // tables of SweepArgs (detectors blend and scale by the voxel's class)
+  const uint8_t* mat;
+  const int* rlagc;
+  const float* rphic;
+  const float* rinvDc;
 };
 
 // One request of the batched server: its argument blocks as the single-medium
@@ -274,6 +299,11 @@ hipError_t prepare_collide_hop(const Field& f);
 hipError_t launch_collide_hop(const CollideArgs& a, const Field& f, hipStream_t s);
 hipError_t launch_sweep_retarded(const SweepArgs& a, const Field& f, int blocks_per_dir,
                                  hipStream_t s);
+// The same with a varying refractive index: per-voxel hop durations through
+// index classes (a.mat, a.rlagc, a.rphic, a.rinvDc), hops across an index jump
+// held in a.icptF for the gather (launch_gather with the content weights).
+hipError_t launch_sweep_retarded_het(const SweepArgs& a, const Field& f, int blocks_per_dir,
+                                     hipStream_t s);
 // Two-level phase stepping: the sweep with the collided value formed as it reads.
 hipError_t launch_sweep_twolevel(const SweepArgs& a, const Field& f, int blocks_per_dir,
                                  hipStream_t s);

@@ -77,7 +77,10 @@ __device__ __forceinline__ void inject_body(const InjectArgs& A) {
   float* X = A.X2 && (m & 1) ? A.X2 : A.X;
   for (int i = threadIdx.x; i < A.npairs; i += blockDim.x) {
     const int d = A.pairs[2 * i], v = A.pairs[2 * i + 1];
-    X[size_t(d) * A.Vp + v] += A.retarded ? share * A.dirs[d].rD : share;
+    float content = share;
+    if (A.retarded)
+      content = share * (A.rDc ? A.rDc[d * 128 + (A.mat[v] & 0x7f)] : A.dirs[d].rD);
+    X[size_t(d) * A.Vp + v] += content;
   }
   if (threadIdx.x == 0 && m < A.cap) A.budget[size_t(m) * 9 + 0] = double(share) * A.npairs;
 }
@@ -292,11 +295,19 @@ __global__ __launch_bounds__(512, 1) void collide_f32_res_kernel(CollideArgs A, 
 // mu_t dx < 2^-20 come with omega = 0 from the host and take C = X (a = 1).
 // C goes to the history slot of the current step.  Absorbed per step, with the
 // light of a hop spread over its D_i steps: e (1 - omega) X[i][v] / D_i.
-template <int NP>
+// With a varying index the hop from v lasts D_i / rvox[v] steps (the absorbed
+// tally takes the factor rvox[v]).
+// FLUX: the source weighted by the light each direction scatters per step,
+//   C_i = a_i X_i + D_i omega sum_j P_ij e_j X_j / D_j,
+// so scattering conserves photons; the B operand is omega e_j X_j / D_j, the
+// lane's own rows add a_i X_i / D_i, and the epilogue multiplies by D_i (the
+// voxel factor rvox cancels in D_i / D_j).  A voxel that does not scatter
+// keeps C = a X.
+template <int NP, bool FLUX>
 __device__ __forceinline__ void collide_hop_tile(const CollideArgs& A, const float* Ps,
                                                  const float* sinvc, const float* sinvD,
-                                                 float* __restrict__ Cout, int tile,
-                                                 double& absorbed, double& total) {
+                                                 const float* sD, float* __restrict__ Cout,
+                                                 int tile, double& absorbed, double& total) {
   constexpr int NQ = NP / 32;
   constexpr int LDK = NP + 4;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -338,17 +349,22 @@ __device__ __forceinline__ void collide_hop_tile(const CollideArgs& A, const flo
       const int ro = 32 * c + 8 * (s >> 2) + (s & 3);   // row minus 4h
       const float a = __builtin_amdgcn_exp2f(-ml2 * ic[ro]);
       const float e = 1.0f - a;
-      const float w = e > 0.0f ? a * __builtin_amdgcn_rcpf(e) : 1.0f;
+      // FLUX without scattering (air, pure absorbers): C = a X exactly
+      const float w = FLUX ? (om > 0.0f ? a * iD[ro] : a)
+                           : (e > 0.0f ? a * __builtin_amdgcn_rcpf(e) : 1.0f);
       csum += bcur[s];
       clost = fmaf(e * bcur[s], iD[ro], clost);
 #pragma unroll
       for (int q = 0; q < NQ; ++q)
         if (q == c) acc[q][s] = fmaf(w, bcur[s], acc[q][s]);
+      if (FLUX) bcur[s] *= om * (e * iD[ro]);
     }
     colsum += double(csum);
     lost += double(clost);
+    if (!FLUX) {
 #pragma unroll
-    for (int s = 0; s < 16; ++s) bcur[s] *= om;
+      for (int s = 0; s < 16; ++s) bcur[s] *= om;
+    }
 #pragma unroll
     for (int s4 = 0; s4 < 16; s4 += 4) {
       const int kk = 32 * c + 8 * (s4 >> 2);
@@ -371,24 +387,32 @@ __device__ __forceinline__ void collide_hop_tile(const CollideArgs& A, const flo
 #pragma unroll
     for (int r = 0; r < 16; ++r) {
       const int ro = q * 32 + 8 * (r >> 2) + (r & 3);
-      const float e = 1.0f - __builtin_amdgcn_exp2f(-ml2 * ic[ro]);
-      *reinterpret_cast<float*>(cq + size_t(8 * (r >> 2) + (r & 3)) * rowbytes) =
-          (e > 0.0f ? e : 1.0f) * acc[q][r];
+      float f;
+      if (FLUX) {
+        f = om > 0.0f ? sD[ro + 4 * hl] : 1.0f;
+      } else {
+        const float e = 1.0f - __builtin_amdgcn_exp2f(-ml2 * ic[ro]);
+        f = e > 0.0f ? e : 1.0f;
+      }
+      *reinterpret_cast<float*>(cq + size_t(8 * (r >> 2) + (r & 3)) * rowbytes) = f * acc[q][r];
     }
   }
-  absorbed += (1.0 - double(om)) * lost;
+  const double rv = A.rvox ? double(A.rvox[col]) : 1.0;
+  absorbed += (1.0 - double(om)) * lost * rv;
   total += colsum;
 }
 
-template <int NP>
+template <int NP, bool FLUX>
 __global__ __launch_bounds__(512, 1) void collide_hop_kernel(CollideArgs A, int ntiles) {
   extern __shared__ float Ps[];
   float* sinvc = Ps + NP * (NP + 4);
   float* sinvD = sinvc + NP;
+  float* sD = sinvD + NP;
   load_p_lds<NP>(A.Prow, Ps);
   for (int i = threadIdx.x; i < NP; i += 512) {
     sinvc[i] = A.hinvc[i];
     sinvD[i] = A.hinvD[i];
+    if (FLUX) sD[i] = A.hD[i];
   }
   __syncthreads();
   const int m = *A.step_ctr;
@@ -396,7 +420,7 @@ __global__ __launch_bounds__(512, 1) void collide_hop_kernel(CollideArgs A, int 
   double absorbed = 0.0, total = 0.0;
 #pragma unroll 1
   for (int tile = blockIdx.x; tile < ntiles; tile += gridDim.x)
-    collide_hop_tile<NP>(A, Ps, sinvc, sinvD, Cout, tile, absorbed, total);
+    collide_hop_tile<NP, FLUX>(A, Ps, sinvc, sinvD, sD, Cout, tile, absorbed, total);
   block_sums512(absorbed, total, A.part + blockIdx.x, A.part + gridDim.x + blockIdx.x);
 }
 
@@ -1307,6 +1331,18 @@ __device__ __forceinline__ TwoFields retarded_rows(const float* ring, int H, lon
   return t;
 }
 
+// Row d of the collided field at voxel v at the retarded time m + 1 - (lag + phi)
+// for a hop of lag whole steps and fraction phi (the voxel's own class).
+__device__ __forceinline__ float retarded_value(const float* ring, int H, long long slot,
+                                                long long Vp, int d, int m, int lag, float phi,
+                                                long long v) {
+  const int sl = ((m + 1 - lag) % H + H) % H;
+  const float late = ring[sl * slot + size_t(d) * Vp + v];
+  if (!(phi > 0.0f)) return late;
+  const int se = ((m - lag) % H + H) % H;
+  return fmaf(phi, ring[se * slot + size_t(d) * Vp + v], (1.0f - phi) * late);
+}
+
 constexpr int kMaxExt = 4096;   // largest grid extent (the C-ABI rejects larger)
 #ifndef TRINITY_SWEEP_ROWS
 #define TRINITY_SWEEP_ROWS 4
@@ -2069,6 +2105,94 @@ void sweep_fast_kernel(SweepArgs A) {
 // its upwind voxel's collided value at step m + 1 - D_d, blended from two
 // history slots.  Light leaving the box crosses the face at its content over
 // D_d per step.
+// Retarded stepping with a varying refractive index.  The hop from voxel u
+// along d lasts D[d][u] = lag + phi steps by u's index class, so each voxel v
+// takes the blend of its upwind voxel u at u's own retarded time.  A hop into
+// a voxel of another index is intercepted: the light that reached the
+// interface goes to A.icptF and the gather returns it as reflected and
+// refracted content (Eq. 13-14).  Escape and interception tallies count the
+// flux blend / D[d][v]; light in the box counts the content written, plus the
+// content the gather will make of the intercepted light (A.icptW).  Voxels of
+// a block in flat order, one per thread per pass.
+__global__ __launch_bounds__(kThreads) void sweep_retarded_het_kernel(SweepArgs A) {
+  __shared__ int8_t sdelta[2][kMaxExt + 2];
+  __shared__ int slag[128];
+  __shared__ float sphi[128], sinvD[128];
+  const int d = blockIdx.y, blk = blockIdx.x, nblk = gridDim.x;
+  const DevDir D = A.dirs[d];
+  const int m = *A.step_ctr;
+  const int nx = A.nx, ny = A.ny, nz = A.nz;
+  const int ea = D.axis == 0 ? nx : (D.axis == 1 ? ny : nz);
+  const int eb = D.bax == 0 ? nx : (D.bax == 1 ? ny : nz);
+  const int ec = D.cax == 0 ? nx : (D.cax == 1 ? ny : nz);
+  for (int i = threadIdx.x; i <= ea; i += kThreads) {
+    sdelta[0][i] = A.delta[(size_t(d) * 2 + 0) * A.dstride + i];
+    sdelta[1][i] = A.delta[(size_t(d) * 2 + 1) * A.dstride + i];
+  }
+  for (int i = threadIdx.x; i < 128; i += kThreads) {
+    slag[i] = A.rlagc[d * 128 + i];
+    sphi[i] = A.rphic[d * 128 + i];
+    sinvD[i] = A.rinvDc[d * 128 + i];
+  }
+  __syncthreads();
+  const long long sa = D.axis == 0 ? 1 : (D.axis == 1 ? nx : (long long)nx * ny);
+  const long long sb = D.bax == 0 ? 1 : (D.bax == 1 ? nx : (long long)nx * ny);
+  const long long sc = D.cax == 0 ? 1 : (D.cax == 1 ? nx : (long long)nx * ny);
+  const float* __restrict__ ring = A.ring;
+  float* __restrict__ Xd = A.X + size_t(d) * A.Vp;
+  const long long V = A.V;
+  const long long vb = V * blk / nblk, ve = V * (blk + 1) / nblk;
+  SweepAcc acc;
+  for (long long v = vb + threadIdx.x; v < ve; v += kThreads) {
+    const int x = int(v % nx), y = int((v / nx) % ny), z = int(v / ((long long)nx * ny));
+    const int pa = D.axis == 0 ? x : (D.axis == 1 ? y : z);
+    const int pb = D.bax == 0 ? x : (D.bax == 1 ? y : z);
+    const int pc = D.cax == 0 ? x : (D.cax == 1 ? y : z);
+    const int k = D.sign > 0 ? pa : ea - 1 - pa;
+    const int dbk = sdelta[0][k], dck = sdelta[1][k];
+    const int dbn = sdelta[0][k + 1], dcn = sdelta[1][k + 1];
+    const uint8_t cv = A.mat[v];
+    // inflow from the upwind voxel, unless that hop is intercepted
+    float out = 0.0f;
+    const int ub = pb - dbk, uc = pc - dck;
+    if (k > 0 && (unsigned)ub < (unsigned)eb && (unsigned)uc < (unsigned)ec) {
+      const long long u = v - D.sign * sa - dbk * sb - dck * sc;
+      const uint8_t cu = A.mat[u];
+      if (!((cu & 0x80) && A.nvox[u] != A.nvox[v])) {
+        const int c = cu & 0x7f;
+        out = retarded_value(ring, A.H, A.slot, A.Vp, d, m, slag[c], sphi[c], u);
+      }
+    }
+    Xd[v] = out;
+    acc.dom += double(out);
+    // what leaves this voxel: through a face, or into a voxel of another index
+    int e = 0;   // 0 none, 1 a, 2 b0, 3 b1, 4 c0, 5 c1
+    if (k + 1 >= ea) e = 1;
+    else if ((unsigned)(pb + dbn) >= (unsigned)eb) e = dbn > 0 ? 3 : 2;
+    else if ((unsigned)(pc + dcn) >= (unsigned)ec) e = dcn > 0 ? 5 : 4;
+    const bool icpt = e == 0 && (cv & 0x80) &&
+                      A.nvox[v + D.sign * sa + dbn * sb + dcn * sc] != A.nvox[v];
+    if (e != 0 || icpt) {
+      const int c = cv & 0x7f;
+      const float r = retarded_value(ring, A.H, A.slot, A.Vp, d, m, slag[c], sphi[c], v);
+      const double fl = double(r * sinvD[c]);
+      switch (e) {
+        case 1: acc.esc_a += fl; break;
+        case 2: acc.esc_b0 += fl; break;
+        case 3: acc.esc_b1 += fl; break;
+        case 4: acc.esc_c0 += fl; break;
+        case 5: acc.esc_c1 += fl; break;
+        default: {
+          const size_t sl = size_t(A.islot[v]) * A.ndir + d;
+          A.icptF[sl] = r;
+          acc.dom += double(r * A.icptW[sl]);
+        }
+      }
+    }
+  }
+  store_sweep_partials(A, D, d, blk, nblk, acc, 1.0);
+}
+
 __global__ __launch_bounds__(kThreads) void sweep_retarded_kernel(SweepArgs A) {
   __shared__ int8_t sdelta[2][kMaxExt + 2];
   const int d = blockIdx.y, blk = blockIdx.x, nblk = gridDim.x;
@@ -2144,6 +2268,12 @@ __global__ void gather_kernel(GatherArgs A) {
 // Direction d's share of a detector record at voxel v in step m.
 __device__ __forceinline__ double det_term(const ReduceArgs& A, int d, int v, int m) {
   const DevDir D = A.dirs[d];
+  if (A.ring && A.rlagc) {
+    // varying index: the voxel's class fixes its hop's steps, fraction and 1/D
+    const int k = d * 128 + (A.mat[v] & 0x7f);
+    return double(A.rinvDc[k] * retarded_value(A.ring, A.H, A.slot, A.Vp, d, m, A.rlagc[k],
+                                               A.rphic[k], v));
+  }
   if (A.ring) return double(D.rinvD * retarded_rows(A.ring, A.H, A.slot, A.Vp, D, d, m)[v]);
   if (A.tlT) {
     const float* x = (m & 1) ? A.pp1 : A.pp0;
@@ -2707,19 +2837,27 @@ hipError_t launch_implicit_np(const CollideArgs& a, const Field& f, hipStream_t 
 namespace {
 template <int NP>
 size_t hop_lds() {
-  return (size_t(NP) * (NP + 4) + 2 * NP) * sizeof(float);
+  return (size_t(NP) * (NP + 4) + 3 * NP) * sizeof(float);
 }
 template <int NP>
 hipError_t prepare_hop_np() {
-  return hipFuncSetAttribute(reinterpret_cast<const void*>(&collide_hop_kernel<NP>),
+  hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&collide_hop_kernel<NP, false>),
+                                     hipFuncAttributeMaxDynamicSharedMemorySize,
+                                     int(hop_lds<NP>()));
+  if (e != hipSuccess) return e;
+  return hipFuncSetAttribute(reinterpret_cast<const void*>(&collide_hop_kernel<NP, true>),
                              hipFuncAttributeMaxDynamicSharedMemorySize, int(hop_lds<NP>()));
 }
 template <int NP>
 hipError_t launch_hop_np(const CollideArgs& a, const Field& f, hipStream_t s) {
   const int ntiles = int(f.Vp / 256);
   const int nb = ntiles < resident_blocks() ? ntiles : resident_blocks();
-  hipLaunchKernelGGL(collide_hop_kernel<NP>, dim3(unsigned(nb)), dim3(512), hop_lds<NP>(), s, a,
-                     ntiles);
+  if (a.flux)
+    hipLaunchKernelGGL((collide_hop_kernel<NP, true>), dim3(unsigned(nb)), dim3(512),
+                       hop_lds<NP>(), s, a, ntiles);
+  else
+    hipLaunchKernelGGL((collide_hop_kernel<NP, false>), dim3(unsigned(nb)), dim3(512),
+                       hop_lds<NP>(), s, a, ntiles);
   return hipGetLastError();
 }
 }  // namespace
@@ -2750,6 +2888,12 @@ hipError_t launch_collide_hop(const CollideArgs& a, const Field& f, hipStream_t 
 
 hipError_t launch_sweep_twolevel(const SweepArgs& a, const Field& f, int bpd, hipStream_t s) {
   hipLaunchKernelGGL(sweep_twolevel_kernel, dim3(unsigned(bpd), unsigned(f.ndir)),
+                     dim3(kThreads), 0, s, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_sweep_retarded_het(const SweepArgs& a, const Field& f, int bpd, hipStream_t s) {
+  hipLaunchKernelGGL(sweep_retarded_het_kernel, dim3(unsigned(bpd), unsigned(f.ndir)),
                      dim3(kThreads), 0, s, a);
   return hipGetLastError();
 }

@@ -24,6 +24,7 @@ ADVANCE = {"auto": 0, "phase": 1, "split": 2, "retarded": 3}
 PRECISION = {"fp32": 0, "bf16split": 1}
 SOURCE = {"explicit": 0, "implicit": 1}
 TRANSPORT = {"auto": 0, "sweep": 1}
+RSOURCE = {"target": 0, "flux": 1}
 MODE_NAMES = {1: "phase", 2: "split"}
 BUDGET_FIELDS = ("injected", "absorbed", "in_domain", "esc0", "esc1", "esc2", "esc3", "esc4",
                  "esc5")
@@ -40,7 +41,8 @@ class GridDesc(ctypes.Structure):
                 ("dx_mm", ctypes.c_double), ("nside", ctypes.c_int), ("g", ctypes.c_double),
                 ("dt_ps", ctypes.c_double), ("hg_norm", ctypes.c_int), ("coef", ctypes.c_int),
                 ("advance", ctypes.c_int), ("precision", ctypes.c_int), ("source", ctypes.c_int),
-                ("nside_scatter", ctypes.c_int), ("transport", ctypes.c_int)]
+                ("nside_scatter", ctypes.c_int), ("transport", ctypes.c_int),
+                ("retarded_source", ctypes.c_int)]
 
 
 class Info(ctypes.Structure):
@@ -168,7 +170,8 @@ def grid_desc(prob) -> GridDesc:
                     float(prob.dt_ps), HG[prob.hg_norm], COEF[prob.coef], ADVANCE[prob.advance],
                     PRECISION[prob.precision], SOURCE[getattr(prob, "source", "explicit")],
                     int(getattr(prob, "nside_scatter", 0)),
-                    TRANSPORT[getattr(prob, "transport", "auto")])
+                    TRANSPORT[getattr(prob, "transport", "auto")],
+                    RSOURCE[getattr(prob, "retarded_source", "target")])
 
 
 def current_stream() -> int:
