@@ -501,6 +501,64 @@ def retarded(stream, steps=200):
                 (inj - b[:, 1].sum() - b[:, 3:].sum() - b[-1, 2]) / max(inj, 1e-300)}
 
 
+def retarded_varying_index(stream, steps=50):
+    """Stepping below Courant one with a varying refractive index (per-voxel
+    hop durations, Fresnel interception at the air cylinder's wall), both
+    source weightings: ms per step on the 64^3 refraction medium (air
+    cylinder and spheres, 192 directions, a fifth of the crossing time in
+    air), and the photon budget imbalance after a small medium has emptied
+    (9 x 10 x 9, tissue around an air cylinder, 700 steps): the flux-weighted
+    source conserves light, the target-direction form of Eq. 10 does not."""
+    import numpy as np
+    import torch
+
+    from paper_2105_01028_amd import trinity as T
+    from paper_2105_01028_amd import workloads as W
+    C0 = 0.299792458
+    out = {"workload": "64^3 refraction medium (air cylinder r = 3 mm, 3 spheres), "
+                       "192 directions, dt = a fifth of the crossing time in air",
+           "steps": steps}
+    big = W.config3(nx=64).copy(nside=4, advance="retarded", dt_ps=0.2 / C0)
+    z, y = np.meshgrid(np.arange(9) + 0.5, np.arange(10) + 0.5, indexing="ij")
+    small = W.small_problem(nside=2, nx=9, ny=10, nz=9, mua=0.03, mus=2.0, g=0.8, n=1.4,
+                            steps=700, seed=7, det_cone_deg=0.0, t0_ps=3.0, fwhm_ps=2.0)
+    cyl = np.broadcast_to(((y - 5.0) ** 2 + (z - 4.95) ** 2 <= 2.7 ** 2)[:, :, None],
+                          small.n.shape)
+    n, mua, mus = small.n.copy(), small.mua.copy(), small.mus.copy()
+    n[cyl], mua[cyl], mus[cyl] = 1.0, 0.0, 0.0
+    small = small.copy(n=n, mua=mua, mus=mus, advance="retarded", dt_ps=0.2 / C0)
+    for src in ("target", "flux"):
+        q = big.copy(retarded_source=src)
+        with torch.cuda.stream(stream):
+            m = T.Medium.from_problem(q)
+            info = m.info()
+            m.solve(5)
+            m.reset()
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            m.step(steps)
+            m.synchronize()
+            t1 = time.perf_counter()
+            m.reset()
+            m.profile_begin(10)
+            m.step(10)
+            prof = m.profile_end()
+            m.close()
+            s = T.Medium.from_problem(small.copy(retarded_source=src))
+            s.solve(small.steps)
+            b = s.read_budget()
+            s.close()
+        inj = b[:, 0].sum()
+        out[src] = {"ms_per_step": (t1 - t0) / steps * 1e3,
+                    "updates_per_s": q.nvox * q.ndir * steps / (t1 - t0),
+                    "history": info.history, "interceptions": info.ninterceptions,
+                    "kernels_ms": {k: v[0] / v[1] for k, v in prof.items() if v[1]},
+                    "budget_imbalance_small_medium_emptied":
+                        float((inj - b[:, 1].sum() - b[:, 3:].sum() - b[-1, 2]) / inj),
+                    "left_in_box": float(b[-1, 2] / inj)}
+    return out
+
+
 def paper_fiducial(stream, steps=20):
     """The paper's fiducial phantom configuration end to end on one GPU:
     101^3 voxels, 3072 transport / 192 source directions, 0.4 ps steps with the
@@ -825,6 +883,7 @@ def main():
         out["implicit_source"] = implicit_source(stream)
         out["two_level_3072_192"] = two_level(stream)
         out["retarded_courant02"] = retarded(stream)
+        out["retarded_varying_index"] = retarded_varying_index(stream)
         out["paper_fiducial_101"] = paper_fiducial(stream)
         print("extras done", file=sys.stderr, flush=True)
     if not args.no_cpu_baseline:

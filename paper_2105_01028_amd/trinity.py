@@ -13,7 +13,9 @@ from typing import Optional, Sequence
 import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "libtrinity.so")
+# TRINITY_LIB names another build of the same library (the host-sanitizer test
+# loads an AddressSanitizer build this way); by default the in-tree one
+LIB_PATH = os.environ.get("TRINITY_LIB") or os.path.join(_HERE, "libtrinity.so")
 
 TR_OK, TR_EINVAL, TR_ENOMEM, TR_EDEVICE, TR_ENUMERIC, TR_ESTATE = 0, -1, -2, -3, -4, -5
 STATUS_NAMES = {0: "TR_OK", -1: "TR_EINVAL", -2: "TR_ENOMEM", -3: "TR_EDEVICE",

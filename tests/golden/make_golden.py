@@ -5,6 +5,7 @@ comes from the HIP path.  Usage:
     python tests/golden/make_golden.py phantom64      # ~20 min on 8 cores
     python tests/golden/make_golden.py retarded64     # ~30 min on 8 cores
     python tests/golden/make_golden.py refraction32   # ~4 min on 8 cores
+    python tests/golden/make_golden.py adjoint64_fd   # ~1.5 h on 8 cores (21 solves)
 """
 import os
 import sys
@@ -106,6 +107,66 @@ def refraction32():
                         dt=S.dt, steps=REFRACTION_STEPS, ninterceptions=len(S.icpt))
 
 
+ADJ_RELH = 1e-4
+ADJ_NVOX = 20
+ADJ_SINGLE = 4
+
+
+def _adj_loss(args):
+    """Loss of one FP64 oracle solve of the adjoint medium with mu_a or mu_s
+    of the given voxels scaled by (1 + eps) (a worker of adjoint64_fd)."""
+    which, vox, eps, target = args
+    from threadpoolctl import threadpool_limits
+    with threadpool_limits(limits=2):
+        p = W.config5()
+        arr = getattr(p, which).astype(np.float64)
+        arr.flat[vox] *= 1.0 + eps
+        r = solve.forward(p.copy(**{which: arr}))
+        y = r.binned(p.bin_ps, p.nbins)
+    return float(np.sum((y - target) ** 2))
+
+
+def adjoint64_fd():
+    """Central differences of the FP64 oracle's loss on the 64^3 x 192 x 500-step
+    adjoint medium (L = sum over detectors and bins of (y - y_target)^2, the
+    target from the medium with each sphere's mu_a x 1.2), step h = 1e-4 of
+    each coefficient: along a +-1 pattern over 20 voxels drawn with seed 55
+    (for mu_a and for mu_s), and for the first 4 of them one by one."""
+    from multiprocessing import Pool
+    p = W.config5()
+    t0 = time.time()
+    target = solve.forward(W.config5(perturbed=True)).binned(p.bin_ps, p.nbins)
+    print(f"target {time.time() - t0:.0f} s", flush=True)
+    rng = np.random.default_rng(55)
+    vox = rng.choice(p.nvox, ADJ_NVOX, replace=False)
+    sgn = np.random.default_rng(56).choice([-1.0, 1.0], ADJ_NVOX)
+    h = ADJ_RELH
+    jobs = []
+    for which in ("mua", "mus"):
+        for s in (1.0, -1.0):
+            jobs.append((which, vox, s * h * sgn, target))
+        for v in vox[:ADJ_SINGLE]:
+            for s in (1.0, -1.0):
+                jobs.append((which, np.array([v]), np.array([s * h]), target))
+    with Pool(4) as pool:
+        L = []
+        for i, val in enumerate(pool.imap(_adj_loss, jobs)):
+            L.append(val)
+            print(f"solve {i + 1}/{len(jobs)} {time.time() - t0:.0f} s", flush=True)
+    out = {}
+    k = 0
+    for which in ("mua", "mus"):
+        out["dir_" + which] = (L[k] - L[k + 1]) / (2.0 * h)   # d L / d eps along sgn
+        k += 2
+        single = []
+        for _ in range(ADJ_SINGLE):
+            single.append((L[k] - L[k + 1]) / (2.0 * h))     # d L / d eps at one voxel
+            k += 2
+        out["single_" + which] = np.array(single)
+    np.savez_compressed(os.path.join(HERE, "adjoint64_fd_oracle.npz"), vox=vox, sgn=sgn,
+                        rel_h=h, target=target, **out)
+
+
 if __name__ == "__main__":
-    {"phantom64": phantom64, "retarded64": retarded64,
-     "refraction32": refraction32}[sys.argv[1]]()
+    {"phantom64": phantom64, "retarded64": retarded64, "refraction32": refraction32,
+     "adjoint64_fd": adjoint64_fd}[sys.argv[1]]()
