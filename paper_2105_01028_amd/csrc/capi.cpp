@@ -410,6 +410,10 @@ hipError_t queue_step(tr_medium* m, const Workspace& w) {
       sa.pp0 = m->X;
       sa.pp1 = m->Y;
       sa.dorder = m->children;   // the children of each coarse bin together
+      if (m->sweep_bpd % 8 == 0) {
+        sa.tlbpd = m->sweep_bpd;
+        sa.tlnk = m->nkids;
+      }
       e = launch_sweep_twolevel(sa, f, m->sweep_bpd, m->stream);
     } else if (m->ring && m->rhet) {
       sa.rlagc = m->rlagc;
@@ -633,6 +637,9 @@ tr_status tr_create_medium(const tr_grid_desc* desc, const float* mua, const flo
   m->rdone = m->alloc<int>(1);
   m->cnwg = collide_nwg(f, desc->precision);
   m->sweep_bpd = sweep_blocks_per_dir(f);
+  // two-level phase stepping: row blocks in multiples of 8 for the XCD-ordered
+  // grid of the fused sweep (each XCD keeps its blocks for every direction)
+  if (m->tlfused && f.ny * f.nz >= 8) m->sweep_bpd = std::max(8, m->sweep_bpd / 8 * 8);
   m->snwg = m->sweep_bpd * f.ndir;
   m->cpart = m->alloc<double>(2 * size_t(m->cnwg));
   m->spart = m->alloc<double>(7 * size_t(std::max(m->snwg, m->cnwg)));

@@ -154,6 +154,12 @@ struct SweepArgs {
   const float* rphic;
   const float* rinvDc;
   const float* icptW;
+  // two-level phase stepping, XCD-ordered grid (tlbpd a multiple of 8): a 1-D
+  // grid of tlbpd x ndir workgroups; XCD x (workgroup ids x mod 8) takes row
+  // blocks x, x + 8, ... of every direction, and the tlnk children of a coarse
+  // bin one after another on the same block, so T[J]'s rows stay in its L2
+  int tlbpd;
+  int tlnk;
 };
 
 constexpr int kMaxRowBits = 65536;   // rows covered by the uniform-row bitmap (8 KB)

@@ -2220,8 +2220,23 @@ __global__ __launch_bounds__(kThreads) void sweep_retarded_kernel(SweepArgs A) {
 // together, so that a row of T is read from HBM about once.
 __global__ __launch_bounds__(kThreads) void sweep_twolevel_kernel(SweepArgs A) {
   __shared__ int8_t sdelta[2][kMaxExt + 2];
-  const int d = A.dorder[blockIdx.y];
-  const int blk = blockIdx.x, nblk = gridDim.x;
+  int d, blk, nblk;
+  if (A.tlbpd > 0) {
+    // XCD-ordered: id L runs on XCD L mod 8; on it, for each coarse bin, each
+    // of the XCD's row blocks takes the bin's children in turn
+    const int L = int(blockIdx.x), xcd = L & 7, j = L >> 3;
+    const int nbx = A.tlbpd >> 3;
+    const int per_bin = nbx * A.tlnk;
+    const int J = j / per_bin, rem = j - J * per_bin;
+    const int kb = rem / A.tlnk, c = rem - kb * A.tlnk;
+    d = A.dorder[J * A.tlnk + c];
+    blk = xcd + 8 * kb;
+    nblk = A.tlbpd;
+  } else {
+    d = A.dorder[blockIdx.y];
+    blk = blockIdx.x;
+    nblk = gridDim.x;
+  }
   const DevDir D = A.dirs[d];
   const int m = *A.step_ctr;
   SweepArgs B = A;
@@ -2887,8 +2902,12 @@ hipError_t launch_collide_hop(const CollideArgs& a, const Field& f, hipStream_t 
 }
 
 hipError_t launch_sweep_twolevel(const SweepArgs& a, const Field& f, int bpd, hipStream_t s) {
-  hipLaunchKernelGGL(sweep_twolevel_kernel, dim3(unsigned(bpd), unsigned(f.ndir)),
-                     dim3(kThreads), 0, s, a);
+  if (a.tlbpd > 0)
+    hipLaunchKernelGGL(sweep_twolevel_kernel, dim3(unsigned(bpd) * unsigned(f.ndir)),
+                       dim3(kThreads), 0, s, a);
+  else
+    hipLaunchKernelGGL(sweep_twolevel_kernel, dim3(unsigned(bpd), unsigned(f.ndir)),
+                       dim3(kThreads), 0, s, a);
   return hipGetLastError();
 }
 
