@@ -1495,20 +1495,21 @@ tr_status tr_backward(tr_medium* m, const double* dL_dbins, float* dmua, float* 
   for (int sgi = m->nckpt - 1; sgi >= 0 && e == hipSuccess; --sgi) {
     const int m0 = sgi * K;
     const int cnt = int(std::min<long long>(K, steps - m0));
-    // recompute the segment's pre-collision fields from its checkpoint
-    e = hipMemcpyAsync(m->X, m->ckpt + NV * sgi, NV * 4, hipMemcpyDeviceToDevice, m->stream);
+    // recompute the segment's pre-collision fields from its checkpoint, in
+    // place: step i injects into slot i, collides it, and sweeps into slot i + 1
+    e = hipMemcpyAsync(seg, m->ckpt + NV * sgi, NV * 4, hipMemcpyDeviceToDevice, m->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(m->stream);
     if (e == hipSuccess) e = hipMemcpy(m->step_ctr, &m0, 4, hipMemcpyHostToDevice);
     for (int i = 0; i < cnt && e == hipSuccess; ++i) {
+      float* xi = seg + NV * i;
+      float* xn = i + 1 < cnt ? seg + NV * (i + 1) : m->X;
       if (m->npairs > 0) {
-        InjectArgs ia{m->X, f.Vp, m->src_pairs, m->npairs, m->qdev, m->cap, m->step_ctr, m->budget};
+        InjectArgs ia{xi, f.Vp, m->src_pairs, m->npairs, m->qdev, m->cap, m->step_ctr, m->budget};
         e = launch_inject(ia, m->stream);
       }
-      if (e == hipSuccess)
-        e = hipMemcpyAsync(seg + NV * i, m->X, NV * 4, hipMemcpyDeviceToDevice, m->stream);
-      CollideArgs ca{m->X, m->Y, m->P, m->Prow, m->Phi, m->Plo, m->a, m->b, f.Vp, f.NP, m->cpart};
+      CollideArgs ca{xi, m->Y, m->P, m->Prow, m->Phi, m->Plo, m->a, m->b, f.Vp, f.NP, m->cpart};
       if (e == hipSuccess) e = launch_collide(ca, f, 0, 0, m->stream);
-      SweepArgs sa{m->Y, m->X, f.Vp, f.V, f.nx, f.ny, f.nz, m->ddirs, m->delta, m->dstride,
+      SweepArgs sa{m->Y, xn, f.Vp, f.V, f.nx, f.ny, f.nz, m->ddirs, m->delta, m->dstride,
                    m->r, m->iface, m->nvox, m->islot, m->icptF, f.ndir, m->step_ctr, m->spart};
       if (e == hipSuccess) e = launch_sweep(sa, f, split, 0, m->sweep_bpd, m->stream);
       ReduceArgs ra{m->cpart, m->cnwg, m->spart, m->snwg, m->Y, f.Vp, m->det_pairs, m->det_first,

@@ -2486,32 +2486,45 @@ __global__ __launch_bounds__(kThreads) void adj_sweep_kernel(AdjArgs A, int m) {
   const long long sc = D.cax == 0 ? 1 : (D.cax == 1 ? nx : sxy);
   const int8_t* db = A.delta + (size_t(d) * 2 + 0) * A.dstride;
   const int8_t* dc = A.delta + (size_t(d) * 2 + 1) * A.dstride;
-  for (int v = blockIdx.x * kThreads + threadIdx.x; v < A.V; v += gridDim.x * kThreads) {
+  // rows (y, z) of this block, x across the threads: one division per row
+  const int R = ny * nz;
+  const int rb = int((long long)R * blockIdx.x / gridDim.x);
+  const int re = int((long long)R * (blockIdx.x + 1) / gridDim.x);
+  const int tpr = nx < kThreads ? nx : kThreads;
+  const int rpi = kThreads / tpr;
+  const int rsub = threadIdx.x / tpr, xs = threadIdx.x - rsub * tpr;
+  if (rsub >= rpi) return;
+  for (int row = rb + rsub; row < re; row += rpi) {
+    const int z = row / ny, y = row - z * ny;
+    const long long v0 = (long long)row * nx;
     if (f == 0.0f) {
-      M[v] = L[v];
+      for (int x = xs; x < nx; x += tpr) M[v0 + x] = L[v0 + x];
       continue;
     }
-    const int x = v % nx, t = v / nx, y = t % ny, z = t / ny;
-    const int pa = pick(D.axis, x, y, z), pb = pick(D.bax, x, y, z), pc = pick(D.cax, x, y, z);
-    const int k = D.sign > 0 ? pa : ea - 1 - pa;
-    float out = 0.0f;
-    if (k + 1 < ea) {
-      const int dbn = db[k + 1], dcn = dc[k + 1];
-      if ((unsigned)(pb + dbn) < (unsigned)eb && (unsigned)(pc + dcn) < (unsigned)ec)
-        out = L[v + D.sign * sa + dbn * sb + dcn * sc];
+    for (int x = xs; x < nx; x += tpr) {
+      const int pa = pick(D.axis, x, y, z), pb = pick(D.bax, x, y, z), pc = pick(D.cax, x, y, z);
+      const int k = D.sign > 0 ? pa : ea - 1 - pa;
+      float out = 0.0f;
+      if (k + 1 < ea) {
+        const int dbn = db[k + 1], dcn = dc[k + 1];
+        if ((unsigned)(pb + dbn) < (unsigned)eb && (unsigned)(pc + dcn) < (unsigned)ec)
+          out = L[v0 + x + D.sign * sa + dbn * sb + dcn * sc];
+      }
+      M[v0 + x] = out;
     }
-    M[v] = out;
   }
 }
 
 // mu[d][v_k] += f_d(m) seed[k][m] for every (detector k, direction d) pair.
+// One pair per thread; two detectors on one voxel and face share (direction,
+// voxel) targets, hence the atomic add.
 __global__ void adj_detector_kernel(AdjArgs A, int m) {
-  if (threadIdx.x != 0) return;
-  for (int p = 0; p < A.ndet_pairs; ++p) {
+  for (int p = blockIdx.x * blockDim.x + threadIdx.x; p < A.ndet_pairs;
+       p += gridDim.x * blockDim.x) {
     const int k = A.det_pairs[2 * p], d = A.det_pairs[2 * p + 1];
     const float f = phase_move(A.dirs[d].nu64, m);
     const int v = A.det_vox[k];
-    A.mu[size_t(d) * A.Vp + v] += f * float(A.seed[size_t(k) * A.steps + m]);
+    atomicAdd(A.mu + size_t(d) * A.Vp + v, f * float(A.seed[size_t(k) * A.steps + m]));
   }
 }
 
@@ -3078,7 +3091,8 @@ hipError_t launch_adjoint_step(const AdjArgs& a, int m, hipStream_t s) {
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   if (a.ndet_pairs > 0) {
-    hipLaunchKernelGGL(adj_detector_kernel, dim3(1), dim3(64), 0, s, a, m);
+    hipLaunchKernelGGL(adj_detector_kernel, dim3(unsigned((a.ndet_pairs + 255) / 256)),
+                       dim3(256), 0, s, a, m);
     if ((e = hipGetLastError()) != hipSuccess) return e;
   }
   switch (a.NP) {
