@@ -779,7 +779,8 @@ def main():
     ap.add_argument("--no-extras", action="store_true")
     ap.add_argument("--workload", default="refraction128",
                     choices=["refraction128", "refraction128-steps", "phantom64", "twolevel64",
-                             "retarded64", "fiducial101", "serving", "adjoint64"],
+                             "retarded64", "fiducial101", "serving", "adjoint64",
+                             "implicit64"],
                     help="refraction128: the headline line; the others only time that "
                          "medium (profiling runs)")
     ap.add_argument("--serving-requests", type=int, default=200,
@@ -805,6 +806,9 @@ def main():
         return
     if args.workload == "adjoint64":
         print(json.dumps(adjoint_timing(torch.cuda.Stream())), flush=True)
+        return
+    if args.workload == "implicit64":
+        print(json.dumps(implicit_source(torch.cuda.Stream(), args.steps)), flush=True)
         return
     if args.workload == "fiducial101":
         print(json.dumps(paper_fiducial(torch.cuda.Stream(), args.steps)), flush=True)

@@ -164,10 +164,20 @@ tr_status tr_create_medium(const tr_grid_desc* desc, const float* mua, const flo
                            tr_medium** out);
 
 /* Device bytes tr_create_medium would allocate for this descriptor with
- * ndet detectors and room for max_steps steps (for admission by HBM budget).
+ * ndet detectors and room for max_steps steps (for admission by HBM budget),
+ * for a uniform refractive index: an upper bound, within a few per cent.
  * Returns 0 for an invalid descriptor, and for TR_ADVANCE_RETARDED, whose
- * history length depends on n. */
+ * history length depends on n (tr_bytes_required_n covers it). */
 size_t tr_bytes_required(const tr_grid_desc* desc, int ndet, int max_steps);
+
+/* The same for the given refractive index n (nx*ny*nz floats, host memory):
+ * adds what n decides -- the mode TR_ADVANCE_AUTO resolves to, the interface
+ * and gather tables of index jumps, the index classes, and with
+ * TR_ADVANCE_RETARDED the history of floor(max D) + 1 fields.  Runs the host
+ * set-up of the time step and the interceptions (FP64, no device work).
+ * Returns 0 for an invalid descriptor or n, or phase advance with a
+ * non-uniform n. */
+size_t tr_bytes_required_n(const tr_grid_desc* desc, const float* n, int ndet, int max_steps);
 
 /* Release every resource of the medium; waits for its queued work. NULL is OK. */
 tr_status tr_destroy_medium(tr_medium* m);
@@ -262,6 +272,34 @@ tr_status tr_get_state(tr_medium* m, float* out, int on_device);
 tr_status tr_set_state(tr_medium* m, const float* in, int on_device);
 
 tr_status tr_get_info(tr_medium* m, tr_info* out);
+
+/* ---- resuming a solve ----------------------------------------------------- */
+
+/* Save and restore everything a solve carries from step to step, so that a
+ * solve can stop and resume (in this process or another) with the same
+ * results as an uninterrupted one: the photon field N, with TR_ADVANCE_RETARDED
+ * also the history of collided fields, the step index, and the per-step
+ * detector records and budget rows of the steps done.  A saved state is a
+ * block of host memory laid out as a 64-byte header (magic "TRSTATE1", a
+ * 64-bit fingerprint of the medium, then steps, ndir, nvox, ndet, history and
+ * the total size as 64-bit integers), the field [ndir][nvox] float32, the
+ * history [history][ndir][nvox] float32, the budget rows [steps][9] FP64 and
+ * the detector records [ndet][steps] FP64, in the host's byte order.
+ *
+ * tr_state_bytes: the size of a saved state of the medium as it stands.
+ * tr_save_state: waits for the medium's queued work (reporting its errors as
+ *   tr_synchronize does) and writes the state to out (host memory,
+ *   n_out >= tr_state_bytes).  TR_EINVAL: null or short output.
+ * tr_load_state: restores a saved state into a medium built with the same
+ *   description, the same mu_a, mu_s and n, the same source and the same
+ *   detectors (the fingerprint checks all of them); the next step is the saved
+ *   step index.  Checkpoints of an earlier tr_solve_checkpointed are dropped.
+ *   Synchronises.  TR_EINVAL: not a saved state, truncated, of another shape,
+ *   or saved from a medium that differs in any of the above (nothing changed);
+ *   TR_ENOMEM: no room for the records. */
+tr_status tr_state_bytes(tr_medium* m, size_t* bytes);
+tr_status tr_save_state(tr_medium* m, void* out, size_t n_out);
+tr_status tr_load_state(tr_medium* m, const void* in, size_t n_in);
 
 /* ---- gradients (adjoint) ------------------------------------------------- */
 

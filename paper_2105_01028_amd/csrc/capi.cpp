@@ -112,6 +112,7 @@ struct tr_medium {
   // detectors
   int ndet = 0;
   std::vector<int> det_face, det_vox;
+  double det_cone = 0;
   double bin_ps = 1.0;
   int nbins = 0;
   int* det_pairs = nullptr;
@@ -503,18 +504,12 @@ tr_status check_medium(tr_medium* m) {
   return TR_OK;
 }
 
-}  // namespace
-
-extern "C" {
-
-const char* tr_last_error(void) { return last_error().c_str(); }
-
-size_t tr_bytes_required(const tr_grid_desc* desc, int ndet, int max_steps) {
-  std::string err;
-  if (!valid_desc(desc, err) || ndet < 0 || max_steps < 0) return 0;
-  if (desc->advance == TR_ADVANCE_RETARDED) return 0;   // the history length depends on n
+// Device bytes of a medium that do not depend on n: fields, tables, partials,
+// the records of max_steps steps.
+size_t base_bytes(const tr_grid_desc* desc, int ndet, int max_steps) {
   Field f = field_of(desc);
   size_t b = fixed_bytes(f, desc->precision, 0);
+  if (desc->precision == TR_PREC_BF16SPLIT) b += size_t(f.NP) * sizeof(float);   // P_lo sums
   if (desc->source == TR_SOURCE_IMPLICIT)   // V, its eigenvalues, w0, w1, c
     b += (size_t(f.NP) * f.NP + f.NP + 3 * size_t(f.Vp)) * sizeof(float);
   if (desc->nside_scatter != 0 && desc->nside_scatter != desc->nside) {
@@ -526,6 +521,133 @@ size_t tr_bytes_required(const tr_grid_desc* desc, int ndet, int max_steps) {
   long long cap = std::max(1024, max_steps);
   b += size_t(cap) * (9 + std::max(ndet, 1) + 1) * sizeof(double);
   b += size_t(f.ndir) * 8 * sizeof(int) + 4096;
+  return b;
+}
+
+// Header of a saved state (tr_save_state): the body follows it.
+struct SavedState {
+  char magic[8];
+  uint64_t fingerprint;
+  long long steps, ndir, nvox, ndet, history, total;
+};
+constexpr char kStateMagic[8] = {'T', 'R', 'S', 'T', 'A', 'T', 'E', '1'};
+
+// FNV-1a, 64 bit, over bytes (the fingerprint of a saved state's medium).
+struct Fnv1a {
+  uint64_t h = 14695981039346656037ull;
+  void bytes(const void* p, size_t n) {
+    const unsigned char* c = static_cast<const unsigned char*>(p);
+    for (size_t i = 0; i < n; ++i) h = (h ^ c[i]) * 1099511628211ull;
+  }
+  template <class T> void val(T v) { bytes(&v, sizeof v); }
+};
+
+// What a saved state is only valid for: the resolved description, the
+// medium arrays, the source and the detectors.
+uint64_t state_fingerprint(const tr_medium* m) {
+  Fnv1a h;
+  const tr_grid_desc& d = m->desc;
+  for (int v : {d.nx, d.ny, d.nz, d.nside, d.hg_norm, d.coef, m->mode, d.precision, d.source,
+                d.nside_scatter, d.transport, d.retarded_source})
+    h.val(v);
+  for (double v : {d.dx_mm, d.g, m->dt}) h.val(v);
+  h.bytes(m->mua_host.data(), m->mua_host.size() * sizeof(float));
+  h.bytes(m->mus_host.data(), m->mus_host.size() * sizeof(float));
+  h.bytes(m->nhost.data(), m->nhost.size() * sizeof(float));
+  h.val(int(m->have_source));
+  for (int v : {m->src_ix, m->src_iy, m->src_w}) h.val(v);
+  for (double v : {m->src_cone, m->src_t0, m->src_fwhm, m->src_total}) h.val(v);
+  h.val(m->ndet);
+  h.bytes(m->det_face.data(), m->det_face.size() * sizeof(int));
+  h.bytes(m->det_vox.data(), m->det_vox.size() * sizeof(int));
+  for (double v : {m->det_cone, m->bin_ps}) h.val(v);
+  h.val(m->nbins);
+  return h.h;
+}
+
+size_t state_bytes(const tr_medium* m, long long steps) {
+  return sizeof(SavedState) + size_t(1 + m->H) * m->f.ndir * m->f.V * sizeof(float) +
+         size_t(steps) * (9 + m->ndet) * sizeof(double);
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* tr_last_error(void) { return last_error().c_str(); }
+
+size_t tr_bytes_required(const tr_grid_desc* desc, int ndet, int max_steps) {
+  std::string err;
+  if (!valid_desc(desc, err) || ndet < 0 || max_steps < 0) return 0;
+  if (desc->advance == TR_ADVANCE_RETARDED) return 0;   // the history length depends on n
+  return base_bytes(desc, ndet, max_steps);
+}
+
+size_t tr_bytes_required_n(const tr_grid_desc* desc, const float* n, int ndet, int max_steps) {
+  std::string err;
+  if (!valid_desc(desc, err) || !n || ndet < 0 || max_steps < 0) return 0;
+  const Field f = field_of(desc);
+  // the coefficients' set-up resolves the time step and the path ratios; the
+  // sizes do not depend on mu_a and mu_s
+  std::vector<float> zero(f.V, 0.0f);
+  Coefficients co;
+  if (!build_coefficients(int(f.V), zero.data(), zero.data(), n, desc->dx_mm, desc->dt_ps,
+                          desc->coef, co, err))
+    return 0;
+  int mode = desc->advance;
+  if (mode == TR_ADVANCE_AUTO) mode = co.uniform_n ? TR_ADVANCE_PHASE : TR_ADVANCE_SPLIT;
+  if (mode == TR_ADVANCE_PHASE && !co.uniform_n) return 0;
+  tr_grid_desc d = *desc;
+  d.advance = mode;
+  size_t b = base_bytes(&d, ndet, max_steps);
+  const std::vector<Vec3> dirs = healpix_ring(desc->nside);
+  const Lattice lat = build_lattice(dirs, f.nx, f.ny, f.nz);
+  const bool het = (mode == TR_ADVANCE_SPLIT || mode == TR_ADVANCE_RETARDED) && !co.uniform_n;
+  if (het) {
+    // interception lists and the gather's targets (one per distinct
+    // destination of a reflected or refracted share)
+    const std::vector<Interception> icpt = interceptions(lat, dirs, n);
+    if (!icpt.empty()) {
+      std::vector<char> iface(f.V, 0);
+      for (const Interception& ic : icpt) iface[ic.v] = 1;
+      size_t ni = 0;
+      for (char c : iface) ni += c;
+      std::map<std::pair<int, long long>, int> tg;
+      size_t nsrc = 0;
+      for (const Interception& ic : icpt) {
+        tg[{ic.d_refl, ic.v}] = 0;
+        ++nsrc;
+        if (ic.d_refr >= 0) {
+          tg[{ic.d_refr, ic.w}] = 0;
+          ++nsrc;
+        }
+      }
+      b += size_t(f.Vp) * (1 + 4 + 4);                          // iface, nvox, islot
+      b += ni * f.ndir * sizeof(float);                          // icptF
+      if (mode == TR_ADVANCE_RETARDED) b += ni * f.ndir * sizeof(float);   // icptW
+      b += (3 * tg.size() + 1 + 2 * nsrc) * 4;                   // targets, ptr, sources, weights
+    }
+  }
+  if (mode == TR_ADVANCE_SPLIT || (mode == TR_ADVANCE_RETARDED && het)) {
+    // index classes (at most 127 distinct n): class bytes, path ratios, row bitmap
+    std::map<float, int> cls;
+    for (long long v = 0; v < f.V && cls.size() <= 127; ++v) cls.emplace(n[v], 0);
+    if (cls.size() <= 127)
+      b += size_t(f.Vp) + 128 * 4 + (size_t(std::min(f.ny * f.nz, kMaxRowBits)) + 31) / 32 * 4;
+  }
+  if (mode == TR_ADVANCE_RETARDED) {
+    // history length: the longest hop in steps, D = dx / (|Omega_a| l_ref) / r_v
+    double rmin = 1.0;
+    for (double r : co.r) rmin = std::min(rmin, r);
+    int maxlag = 0;
+    for (int k = 0; k < f.ndir; ++k) {
+      const double D = 1.0 / (lat.speed[k] * (co.ell_ref / desc->dx_mm)) / rmin;
+      maxlag = std::max(maxlag, int(std::floor(D + 1e-12)));
+    }
+    b += size_t(maxlag + 1) * f.NP * f.Vp * sizeof(float);     // the ring
+    b += 2 * size_t(f.Vp) * sizeof(float) + 3 * size_t(f.NP) * sizeof(float);
+    if (het) b += 4 * size_t(f.NP) * 128 * 4;                   // class hop tables
+  }
   return b;
 }
 
@@ -1195,6 +1317,7 @@ tr_status tr_set_detectors(tr_medium* m, int ndet, const int* face, const int* i
   m->ndet = ndet;
   m->det_face = fv;
   m->det_vox = vv;
+  m->det_cone = cone_deg;
   m->bin_ps = bin_ps;
   m->nbins = nbins;
   st = upload_detector_pairs(m, acc);
@@ -1402,6 +1525,96 @@ tr_status tr_set_state(tr_medium* m, const float* in, int on_device) {
                                   m->stream);
   if (e == hipSuccess) e = hipStreamSynchronize(m->stream);
   if (e != hipSuccess) return device_fail(m, e, "state write");
+  return TR_OK;
+}
+
+tr_status tr_state_bytes(tr_medium* m, size_t* bytes) {
+  tr_status st = check_medium(m);
+  if (st != TR_OK) return st;
+  if (!bytes) return fail(TR_EINVAL, "null output");
+  *bytes = state_bytes(m, m->steps_done);
+  return TR_OK;
+}
+
+tr_status tr_save_state(tr_medium* m, void* out, size_t n_out) {
+  tr_status st = tr_synchronize(m);
+  if (st != TR_OK) return st;
+  if (!out) return fail(TR_EINVAL, "null output");
+  const Field& f = m->f;
+  const long long steps = m->steps_done;
+  const size_t need = state_bytes(m, steps);
+  if (n_out < need) return fail(TR_EINVAL, "output too small for the saved state");
+  SavedState h{};
+  std::memcpy(h.magic, kStateMagic, 8);
+  h.fingerprint = state_fingerprint(m);
+  h.steps = steps;
+  h.ndir = f.ndir;
+  h.nvox = f.V;
+  h.ndet = m->ndet;
+  h.history = m->H;
+  h.total = (long long)need;
+  char* p = static_cast<char*>(out);
+  std::memcpy(p, &h, sizeof h);
+  p += sizeof h;
+  const size_t field = size_t(f.ndir) * f.V * sizeof(float), slot = size_t(f.NP) * f.Vp;
+  hipError_t e = hipMemcpy2DAsync(p, f.V * 4, state_field(m), f.Vp * 4, f.V * 4, f.ndir,
+                                  hipMemcpyDeviceToHost, m->stream);
+  p += field;
+  for (int s = 0; s < m->H && e == hipSuccess; ++s, p += field)
+    e = hipMemcpy2DAsync(p, f.V * 4, m->ring + slot * s, f.Vp * 4, f.V * 4, f.ndir,
+                         hipMemcpyDeviceToHost, m->stream);
+  if (e == hipSuccess && steps > 0)
+    e = hipMemcpyAsync(p, m->budget, size_t(steps) * 9 * 8, hipMemcpyDeviceToHost, m->stream);
+  p += size_t(steps) * 9 * 8;
+  for (int k = 0; k < m->ndet && e == hipSuccess && steps > 0; ++k, p += size_t(steps) * 8)
+    e = hipMemcpyAsync(p, m->det_steps + size_t(k) * m->cap, size_t(steps) * 8,
+                       hipMemcpyDeviceToHost, m->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(m->stream);
+  if (e != hipSuccess) return device_fail(m, e, "state save");
+  return TR_OK;
+}
+
+tr_status tr_load_state(tr_medium* m, const void* in, size_t n_in) {
+  tr_status st = check_medium(m);
+  if (st != TR_OK) return st;
+  if (!in) return fail(TR_EINVAL, "null input");
+  const Field& f = m->f;
+  SavedState h;
+  if (n_in < sizeof h) return fail(TR_EINVAL, "input shorter than a saved state's header");
+  std::memcpy(&h, in, sizeof h);
+  if (std::memcmp(h.magic, kStateMagic, 8) != 0) return fail(TR_EINVAL, "not a saved state");
+  if (h.ndir != f.ndir || h.nvox != f.V || h.ndet != m->ndet || h.history != m->H ||
+      h.steps < 0 || h.steps > (1LL << 30))
+    return fail(TR_EINVAL, "saved state of another shape (directions, voxels, detectors or "
+                           "history)");
+  if (h.total != (long long)state_bytes(m, h.steps) || n_in < size_t(h.total))
+    return fail(TR_EINVAL, "saved state truncated or of another size");
+  if (h.fingerprint != state_fingerprint(m))
+    return fail(TR_EINVAL, "saved from a medium with another description, medium arrays, "
+                           "source or detectors");
+  if ((st = ensure_capacity(m, h.steps)) != TR_OK) return st;
+  if ((st = tr_reset(m)) != TR_OK) return st;
+  m->steps_done = h.steps;   // the state field follows the step's parity
+  m->nckpt = 0;              // checkpoints of an earlier solve no longer apply
+  const char* p = static_cast<const char*>(in) + sizeof h;
+  const size_t field = size_t(f.ndir) * f.V * sizeof(float), slot = size_t(f.NP) * f.Vp;
+  hipError_t e = hipMemcpy2DAsync(state_field(m), f.Vp * 4, p, f.V * 4, f.V * 4, f.ndir,
+                                  hipMemcpyHostToDevice, m->stream);
+  p += field;
+  for (int s = 0; s < m->H && e == hipSuccess; ++s, p += field)
+    e = hipMemcpy2DAsync(m->ring + slot * s, f.Vp * 4, p, f.V * 4, f.V * 4, f.ndir,
+                         hipMemcpyHostToDevice, m->stream);
+  if (e == hipSuccess && h.steps > 0)
+    e = hipMemcpyAsync(m->budget, p, size_t(h.steps) * 9 * 8, hipMemcpyHostToDevice, m->stream);
+  p += size_t(h.steps) * 9 * 8;
+  for (int k = 0; k < m->ndet && e == hipSuccess && h.steps > 0; ++k, p += size_t(h.steps) * 8)
+    e = hipMemcpyAsync(m->det_steps + size_t(k) * m->cap, p, size_t(h.steps) * 8,
+                       hipMemcpyHostToDevice, m->stream);
+  const int ctr = int(h.steps);
+  if (e == hipSuccess) e = hipMemcpyAsync(m->step_ctr, &ctr, sizeof ctr, hipMemcpyHostToDevice,
+                                          m->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(m->stream);
+  if (e != hipSuccess) return device_fail(m, e, "state load");
   return TR_OK;
 }
 

@@ -90,6 +90,10 @@ _PF = ctypes.POINTER(ctypes.c_float)
 _SIGS = {
     "tr_create_medium": [ctypes.POINTER(GridDesc), _P, _P, _P, _I, _P, ctypes.POINTER(_P)],
     "tr_bytes_required": [ctypes.POINTER(GridDesc), _I, _I],
+    "tr_bytes_required_n": [ctypes.POINTER(GridDesc), _PF, _I, _I],
+    "tr_state_bytes": [_P, ctypes.POINTER(ctypes.c_size_t)],
+    "tr_save_state": [_P, _P, ctypes.c_size_t],
+    "tr_load_state": [_P, _P, ctypes.c_size_t],
     "tr_destroy_medium": [_P],
     "tr_set_source": [_P, _I, _I, _I, _D, _D, _D, _D],
     "tr_set_detectors": [_P, _I, _PI, _PI, _PI, _D, _D, _I],
@@ -143,7 +147,8 @@ def lib():
         for name, args in _SIGS.items():
             fn = getattr(L, name)
             fn.argtypes = args
-            fn.restype = ctypes.c_size_t if name == "tr_bytes_required" else ctypes.c_int
+            fn.restype = (ctypes.c_size_t if name.startswith("tr_bytes_required")
+                          else ctypes.c_int)
         L.tr_last_error.argtypes = []
         L.tr_last_error.restype = ctypes.c_char_p
         _lib = L
@@ -361,6 +366,20 @@ class Medium:
             s = np.ascontiguousarray(state, dtype=np.float32)
             _check(lib().tr_set_state(self._h, s.ctypes.data, 0))
 
+    def save_state(self) -> np.ndarray:
+        """Everything a solve carries between steps (field, history, step index,
+        records) as a byte array for load_state."""
+        n = ctypes.c_size_t()
+        _check(lib().tr_state_bytes(self._h, ctypes.byref(n)))
+        buf = np.zeros(n.value, np.uint8)
+        _check(lib().tr_save_state(self._h, buf.ctypes.data, buf.size))
+        return buf
+
+    def load_state(self, buf):
+        b = np.ascontiguousarray(np.frombuffer(buf, np.uint8) if isinstance(buf, (bytes, bytearray))
+                                 else buf, dtype=np.uint8)
+        _check(lib().tr_load_state(self._h, b.ctypes.data, b.size))
+
 
 class Server:
     """Continuous-batching server of forward solves (tr_server_* of the C-ABI)."""
@@ -442,6 +461,14 @@ def create_medium(prob, stream=None) -> Medium:
 
 def bytes_required(desc: GridDesc, ndet=8, max_steps=1024) -> int:
     return int(lib().tr_bytes_required(ctypes.byref(desc), int(ndet), int(max_steps)))
+
+
+def bytes_required_n(desc: GridDesc, n, ndet=8, max_steps=1024) -> int:
+    nn = np.ascontiguousarray(n, np.float32).ravel()
+    if nn.size != desc.nx * desc.ny * desc.nz:
+        raise ValueError("n must hold nx*ny*nz values")
+    return int(lib().tr_bytes_required_n(ctypes.byref(desc), _fptr(nn), int(ndet),
+                                         int(max_steps)))
 
 
 # ---- host set-up tables (no device needed) ---------------------------------

@@ -1,0 +1,155 @@
+"""Resuming a solve (tr_state_bytes / tr_save_state / tr_load_state through
+the C-ABI): a solve stopped at any step, saved, and resumed -- in a fresh
+medium, or in the same one after it ran on -- gives the same per-step
+detector records, budget rows and field as the solve run straight through,
+bit for bit (the same kernels in the same order on the same values).  Covers
+every way the field is carried between steps: one buffer (sweep), two
+buffers by step parity (moves in the collision, two-level phase stepping),
+the interception slots of index jumps, and the history of the retarded
+advance.  Also the medium bytes estimate against what creation allocates."""
+import numpy as np
+import pytest
+
+from oracle import medium
+from paper_2105_01028_amd import trinity as T
+from paper_2105_01028_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+C0 = medium.C0_MM_PER_PS
+
+
+def _stream():
+    import torch
+    assert torch.cuda.is_available(), "these tests need the GPU"
+    return torch.cuda.Stream()
+
+
+def _air_slab(p):
+    n, mua, mus = p.n.copy(), p.mua.copy(), p.mus.copy()
+    n[3:5], mua[3:5], mus[3:5] = 1.0, 0.0, 0.0
+    return p.copy(n=n, mua=mua, mus=mus)
+
+
+def _cases():
+    base = dict(nside=2, nx=13, ny=10, nz=9, mua=0.03, mus=2.0, g=0.8, n=1.4, seed=4,
+                det_cone_deg=0.0, t0_ps=3.0, fwhm_ps=2.0)
+    ph = W.small_problem(**base)
+    yield "phase-moves-in-collision", ph
+    yield "phase-sweep", ph.copy(transport="sweep")
+    yield "split-fresnel", _air_slab(ph).copy(advance="split")
+    yield "split-fresnel-bf16", _air_slab(ph).copy(advance="split", precision="bf16split")
+    yield "implicit", ph.copy(source="implicit")
+    yield "two-level-phase", W.small_problem(**{**base, "nside": 4}).copy(nside_scatter=2)
+    yield "retarded", ph.copy(advance="retarded", dt_ps=0.2 * ph.dx_mm * 1.4 / C0)
+    yield "retarded-varying-n", _air_slab(ph).copy(advance="retarded", dt_ps=0.2 * ph.dx_mm / C0,
+                                                   retarded_source="flux")
+
+
+CASES = list(_cases())
+
+
+def _outputs(m):
+    return m.read_detector_steps(), m.read_budget(), m.get_state()
+
+
+def _same(a, b):
+    for x, y in zip(a, b):
+        assert x.shape == y.shape
+        assert np.array_equal(x, y)
+
+
+@pytest.mark.parametrize("name,prob", CASES, ids=[c[0] for c in CASES])
+def test_resume_matches_an_uninterrupted_solve(name, prob):
+    import torch
+    total, stop = 70, 37          # an odd step: the parity-buffered fields sit in Y
+    with torch.cuda.stream(_stream()):
+        ref = T.Medium.from_problem(prob)
+        ref.solve(total)
+        want = _outputs(ref)
+        ref.close()
+
+        m = T.Medium.from_problem(prob)
+        m.solve(stop)
+        saved = m.save_state()
+        part = _outputs(m)
+        m.solve(total - stop)
+        _same(_outputs(m), want)
+        # rewind the same medium and run the rest again
+        m.load_state(saved)
+        assert m.info().steps_done == stop
+        _same(_outputs(m), part)
+        m.solve(total - stop)
+        _same(_outputs(m), want)
+        m.close()
+
+        # a fresh medium of the same problem
+        m2 = T.Medium.from_problem(prob)
+        m2.load_state(bytes(saved))
+        m2.solve(total - stop)
+        _same(_outputs(m2), want)
+        m2.close()
+    print(f"[{name}] resumed at step {stop} of {total}: identical; state {saved.size} bytes",
+          flush=True)
+
+
+def test_load_rejects_other_media_and_damaged_states():
+    import torch
+    p = CASES[0][1]
+    with torch.cuda.stream(_stream()):
+        m = T.Medium.from_problem(p)
+        m.solve(9)
+        saved = m.save_state()
+        m.solve(4)
+        before = _outputs(m)
+        mua = p.mua.copy()
+        mua.flat[17] *= 1.001
+        others = [p.copy(mua=mua), p.copy(g=0.7), p.copy(t0_ps=4.0),
+                  p.copy(det_i=list(p.det_i[:-1]) + [p.det_i[-1] + 1])]
+        for q in others:
+            o = T.Medium.from_problem(q)
+            with pytest.raises(T.TrinityError) as e:
+                o.load_state(saved)
+            assert e.value.status == T.TR_EINVAL
+            o.close()
+        bad = saved.copy()
+        bad[0] ^= 1
+        for b in (saved[:-1], saved[:40], bad):
+            with pytest.raises(T.TrinityError) as e:
+                m.load_state(b)
+            assert e.value.status == T.TR_EINVAL
+        # nothing changed by the refused calls
+        assert m.info().steps_done == 13
+        _same(_outputs(m), before)
+        # a checkpointed solve's checkpoints do not survive a load
+        m.solve_checkpointed(12, 4)
+        m.load_state(saved)
+        with pytest.raises(T.TrinityError) as e:
+            m.backward(np.ones((p.ndet, p.nbins)))
+        assert e.value.status == T.TR_ESTATE
+        m.close()
+
+
+def _full_size():
+    c2 = W.config2()
+    yield "phantom64", c2
+    yield "phantom64-retarded", c2.copy(advance="retarded",
+                                        dt_ps=0.2 * c2.dx_mm * float(c2.n.flat[0]) / C0)
+    yield "refraction32-768", W.config3(nx=32)
+
+
+SIZES = CASES + list(_full_size())
+
+
+@pytest.mark.parametrize("name,prob", SIZES, ids=[c[0] for c in SIZES])
+def test_bytes_required_bounds_what_creation_allocates(name, prob):
+    """tr_bytes_required_n is at least the device memory a medium holds after
+    creation (records for 1024 steps) and within 3 % + 1 MiB of it."""
+    import torch
+    with torch.cuda.stream(_stream()):
+        m = T.Medium.from_problem(prob)
+        got = m.info().device_bytes
+        m.close()
+    est = T.bytes_required_n(T.grid_desc(prob), prob.n, ndet=prob.ndet, max_steps=1024)
+    print(f"[{name}] device bytes {got}, estimate {est} ({est / got - 1:+.3%})", flush=True)
+    assert got <= est <= 1.03 * got + (1 << 20)

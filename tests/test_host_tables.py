@@ -140,3 +140,55 @@ def test_grid_voxel_limit():
 def test_host_parents_match_oracle(nf, nc):
     from oracle import angles
     assert np.array_equal(T.host_parents(nf, nc), angles.parents(nf, nc))
+
+
+def test_bytes_required_with_index():
+    """tr_bytes_required_n adds what n decides.  A uniform n in phase advance
+    adds nothing; the retarded advance adds its history of H fields, H the
+    oracle's floor(max D) + 1 (so two time steps, or two uniform indices,
+    differ by exactly the difference of their H fields); an index jump adds
+    the interface tables; an invalid n, or
+    phase advance with a varying n, gives 0."""
+    from oracle import medium, retarded
+    p = W.small_problem(nside=2, nx=13, ny=10, nz=9)
+    d = T.grid_desc(p)
+    assert T.bytes_required_n(d, p.n) == T.bytes_required(d) > 0
+    C0 = medium.C0_MM_PER_PS
+    n0 = float(p.n.flat[0])
+    # one field: 48 directions padded to 64 rows (a multiple of 32) of the
+    # voxels padded to a multiple of 256, float32
+    row = 4 * 64 * (-(-p.nvox // 256) * 256)
+    sizes = {}
+    for courant in (1.0, 0.5, 0.2):
+        q = p.copy(advance="retarded", dt_ps=courant * p.dx_mm * n0 / C0)
+        H = retarded.build(q).H
+        b = T.bytes_required_n(T.grid_desc(q), q.n)
+        assert T.bytes_required(T.grid_desc(q)) == 0
+        sizes[courant] = (H, b)
+    (h1, b1), (h5, b5), (h2, b2) = sizes[1.0], sizes[0.5], sizes[0.2]
+    assert h1 < h5 < h2
+    assert b5 - b1 == (h5 - h1) * row and b2 - b5 == (h2 - h5) * row
+    # a slab of air at a fifth of the crossing time of the fastest light
+    n = p.n.copy()
+    n[3:5] = 1.0
+    q = p.copy(n=n, advance="retarded", dt_ps=0.2 * p.dx_mm / C0)
+    H = retarded.build(q).H
+    bq = T.bytes_required_n(T.grid_desc(q), n)
+    # the longest hop is in the tissue: the same history as all tissue, plus
+    # the interface and class tables; all air has the shortest history
+    qu = p.copy(advance="retarded", dt_ps=0.2 * p.dx_mm / C0)
+    qa = qu.copy(n=np.ones_like(p.n))
+    Ha = retarded.build(qa).H
+    assert retarded.build(qu).H == H > Ha
+    bu = T.bytes_required_n(T.grid_desc(qu), qu.n)
+    assert bq > bu
+    assert bu - T.bytes_required_n(T.grid_desc(qa), qa.n) == (H - Ha) * row
+    # split advance: the index jump adds interface tables
+    s = p.copy(n=n, advance="split")
+    assert T.bytes_required_n(T.grid_desc(s), n) > T.bytes_required(T.grid_desc(s))
+    assert T.bytes_required_n(T.grid_desc(p.copy(advance="phase")), n) == 0
+    bad = p.n.copy()
+    bad[0, 0, 0] = 0.5
+    assert T.bytes_required_n(d, bad) == 0
+    with pytest.raises(ValueError):
+        T.bytes_required_n(d, p.n[:-1])
