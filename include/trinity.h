@@ -443,6 +443,19 @@ tr_status tr_host_phase_matrix(int nside, double g, int hg_norm, double* out);
  * maxext = max(nx, ny, nz). */
 tr_status tr_host_lattice(int nside, int nx, int ny, int nz, int* axis, int* sign, int* offset);
 
+/* Move tables of phase advance with the moves in the collision kernel (the
+ * lattice's plane-to-plane moves, Sec. 2.1 and Fig. 1), NP = 12 nside^2
+ * rounded up to a multiple of 32, maxext = max(nx, ny, nz) <= 1023.
+ * tab[d*maxext + p] (NP + 1 rows): for a voxel at coordinate p along direction
+ * d's dominant axis, 64 times the flat offset of its move plus the mask of the
+ * faces (2 axis + side) the move may leave through; row NP and rows of padding
+ * directions are zero.  dir[d] = 10 axis | 3 << (2 axis + 8).  reverse = 1:
+ * the inverse moves of the adjoint (each voxel back to the voxel whose photons
+ * moved into it, on the box taken periodically along the dominant axis).
+ * TR_EINVAL: a direction whose transverse shifts are not -1, 0, +1 of one sign
+ * (such grids step with the separate sweep). */
+tr_status tr_host_move_tables(int nside, int nx, int ny, int nz, int reverse, int* tab, int* dir);
+
 /* Per-voxel collision coefficients a, b and relative path r (split-mode move
  * fraction factor), and the resolved time step. */
 tr_status tr_host_coefficients(const tr_grid_desc* desc, const float* mua, const float* mus,

@@ -570,6 +570,216 @@ size_t state_bytes(const tr_medium* m, long long steps) {
          size_t(steps) * (9 + m->ndet) * sizeof(double);
 }
 
+// The adjoint passes of tr_backward: dL/da and dL/db per voxel into hga, hgb
+// (seed[k * steps + s] = dL/d det[k][s]).  The medium's field, step counter
+// and records are left as they were.
+
+// With the separate transposed sweep (media stepped with the sweep kernel):
+// per segment, recompute its pre-collision fields from the checkpoint
+// (inject, collide, sweep, tallies), then step backwards: transposed sweep,
+// seeds, transposed collision.
+tr_status backward_sweep(tr_medium* m, const std::vector<double>& seed, std::vector<double>& hga,
+                         std::vector<double>& hgb) {
+  const Field& f = m->f;
+  const size_t NV = size_t(f.NP) * f.Vp;
+  const long long steps = m->steps_done;
+  const int K = m->ckpt_every;
+  hipError_t e = prepare_adjoint(f.NP);
+  if (e != hipSuccess) return device_fail(m, e, "adjoint set-up");
+  float* lam = m->alloc<float>(NV);
+  float* mu = m->alloc<float>(NV);
+  float* seg = m->alloc<float>(NV * size_t(K));
+  float* keep = m->alloc<float>(NV);
+  double* ga = m->alloc<double>(f.Vp);
+  double* gb = m->alloc<double>(f.Vp);
+  double* sd = m->alloc<double>(seed.size());
+  auto cleanup = [&]() {
+    for (void* p : {(void*)lam, (void*)mu, (void*)seg, (void*)keep, (void*)ga, (void*)gb, (void*)sd})
+      m->release(p);
+  };
+  if (!lam || !mu || !seg || !keep || !ga || !gb || !sd) {
+    cleanup();
+    return fail(TR_ENOMEM, "no device memory for the adjoint");
+  }
+  e = hipMemcpyAsync(keep, state_field(m), NV * 4, hipMemcpyDeviceToDevice, m->stream);
+  if (e == hipSuccess) e = hipMemsetAsync(lam, 0, NV * 4, m->stream);
+  if (e == hipSuccess) e = hipMemsetAsync(mu, 0, NV * 4, m->stream);
+  if (e == hipSuccess) e = hipMemsetAsync(seg, 0, NV * 4 * size_t(K), m->stream);
+  if (e == hipSuccess) e = hipMemsetAsync(ga, 0, f.Vp * 8, m->stream);
+  if (e == hipSuccess) e = hipMemsetAsync(gb, 0, f.Vp * 8, m->stream);
+  if (e == hipSuccess) e = hipMemcpy(sd, seed.data(), seed.size() * 8, hipMemcpyHostToDevice);
+  AdjArgs A{lam, mu, lam, nullptr, m->P, m->a, m->b, ga, gb, f.Vp, f.V, f.nx, f.ny, f.nz, f.ndir,
+            f.NP, m->ddirs, m->delta, m->dstride, nullptr, 0, m->det_vox_dev, sd, int(steps)};
+  // detector pairs of the medium (host copy rebuilt from the device lists)
+  std::vector<int> first(m->ndet + 1);
+  if (e == hipSuccess) e = hipMemcpy(first.data(), m->det_first, first.size() * 4, hipMemcpyDeviceToHost);
+  A.det_pairs = m->det_pairs;
+  A.ndet_pairs = first[m->ndet];
+  const bool split = false;
+  for (int sgi = m->nckpt - 1; sgi >= 0 && e == hipSuccess; --sgi) {
+    const int m0 = sgi * K;
+    const int cnt = int(std::min<long long>(K, steps - m0));
+    // recompute the segment's pre-collision fields from its checkpoint, in
+    // place: step i injects into slot i, collides it, and sweeps into slot i + 1
+    e = hipMemcpyAsync(seg, m->ckpt + NV * sgi, NV * 4, hipMemcpyDeviceToDevice, m->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(m->stream);
+    if (e == hipSuccess) e = hipMemcpy(m->step_ctr, &m0, 4, hipMemcpyHostToDevice);
+    for (int i = 0; i < cnt && e == hipSuccess; ++i) {
+      float* xi = seg + NV * i;
+      float* xn = i + 1 < cnt ? seg + NV * (i + 1) : m->X;
+      if (m->npairs > 0) {
+        InjectArgs ia{xi, f.Vp, m->src_pairs, m->npairs, m->qdev, m->cap, m->step_ctr, m->budget};
+        e = launch_inject(ia, m->stream);
+      }
+      CollideArgs ca{xi, m->Y, m->P, m->Prow, m->Phi, m->Plo, m->a, m->b, f.Vp, f.NP, m->cpart};
+      if (e == hipSuccess) e = launch_collide(ca, f, 0, 0, m->stream);
+      SweepArgs sa{m->Y, xn, f.Vp, f.V, f.nx, f.ny, f.nz, m->ddirs, m->delta, m->dstride,
+                   m->r, m->iface, m->nvox, m->islot, m->icptF, f.ndir, m->step_ctr, m->spart};
+      if (e == hipSuccess) e = launch_sweep(sa, f, split, 0, m->sweep_bpd, m->stream);
+      ReduceArgs ra{m->cpart, m->cnwg, m->spart, m->snwg, m->Y, f.Vp, m->det_pairs, m->det_first,
+                    m->det_vox_dev, m->ndet, m->ddirs, m->r, 0, m->step_ctr, m->budget,
+                    m->det_steps, m->cap, m->flag, m->rscratch, m->rdone};
+      if (e == hipSuccess) e = launch_reduce(ra, m->stream);
+    }
+    // adjoint steps backwards through the segment
+    for (int i = cnt - 1; i >= 0 && e == hipSuccess; --i) {
+      A.xs = seg + NV * i;
+      e = launch_adjoint_step(A, m0 + i, m->stream);
+    }
+  }
+  if (e == hipSuccess) e = hipMemcpyAsync(state_field(m), keep, NV * 4, hipMemcpyDeviceToDevice, m->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(m->stream);
+  if (e == hipSuccess) {
+    const int sd_steps = int(steps);
+    e = hipMemcpy(m->step_ctr, &sd_steps, 4, hipMemcpyHostToDevice);
+  }
+  if (e == hipSuccess) e = hipMemcpy(hga.data(), ga, f.V * 8, hipMemcpyDeviceToHost);
+  if (e == hipSuccess) e = hipMemcpy(hgb.data(), gb, f.V * 8, hipMemcpyDeviceToHost);
+  cleanup();
+  if (e != hipSuccess) return device_fail(m, e, "adjoint");
+  return TR_OK;
+}
+
+// With the moves in the collision kernels (media whose forward step does the
+// moves in the collision's epilogue): the recompute runs the forward step's
+// kernel on the segment's slots (slot i to slot i + 1, its injection added in
+// place in slot i, no detector keeps and no tallies), and each backward step is
+// one kernel, the transposed collision of step m with the transposed moves of
+// step m - 1 in its epilogue, plus the seeds of step m - 1.
+tr_status backward_fused(tr_medium* m, const std::vector<double>& seed, std::vector<double>& hga,
+                         std::vector<double>& hgb) {
+  const Field& f = m->f;
+  const size_t NV = size_t(f.NP) * f.Vp;
+  const long long steps = m->steps_done;
+  const int K = m->ckpt_every;
+  // the tables of the inverse moves
+  std::vector<int8_t> dl(size_t(f.ndir) * 2 * m->dstride, 0);
+  for (int d = 0; d < f.ndir; ++d)
+    for (int q = 0; q < 2; ++q)
+      for (int k = 1; k <= m->lat.maxext; ++k)
+        dl[(size_t(d) * 2 + q) * m->dstride + k] =
+            int8_t(m->lat.off(d, q, k) - m->lat.off(d, q, k - 1));
+  std::vector<int> rtab, rdir;
+  if (!build_move_tables(m->lat, dl, m->dstride, f.NP, rtab, rdir, true))
+    return fail(TR_EINVAL, "no reversed move tables for this lattice");
+  hipError_t e = prepare_adjoint_move(f.NP);
+  if (e != hipSuccess) return device_fail(m, e, "adjoint set-up");
+  float* mu2 = m->alloc<float>(2 * NV);                   // mu_m in half m & 1
+  float* seg = m->alloc<float>(NV * (size_t(K) + 1));      // recomputed fields, and one spare
+  double* ga = m->alloc<double>(f.Vp);
+  double* gb = m->alloc<double>(f.Vp);
+  double* sd = m->alloc<double>(std::max<size_t>(seed.size(), 1));
+  int* rt = m->alloc<int>(rtab.size());
+  unsigned* nodet = m->alloc<unsigned>(size_t(f.Vp / 32));
+  auto cleanup = [&]() {
+    for (void* p : {(void*)mu2, (void*)seg, (void*)ga, (void*)gb, (void*)sd, (void*)rt,
+                    (void*)nodet})
+      m->release(p);
+  };
+  if (!mu2 || !seg || !ga || !gb || !sd || !rt || !nodet) {
+    cleanup();
+    return fail(TR_ENOMEM, "no device memory for the adjoint");
+  }
+  e = hipMemsetAsync(mu2, 0, 2 * NV * 4, m->stream);
+  if (e == hipSuccess) e = hipMemsetAsync(seg, 0, NV * 4 * (size_t(K) + 1), m->stream);
+  if (e == hipSuccess) e = hipMemsetAsync(ga, 0, f.Vp * 8, m->stream);
+  if (e == hipSuccess) e = hipMemsetAsync(gb, 0, f.Vp * 8, m->stream);
+  if (e == hipSuccess) e = hipMemsetAsync(nodet, 0, size_t(f.Vp / 32) * 4, m->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(m->stream);
+  if (e == hipSuccess && !seed.empty())
+    e = hipMemcpy(sd, seed.data(), seed.size() * 8, hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemcpy(rt, rtab.data(), rtab.size() * 4, hipMemcpyHostToDevice);
+  std::vector<int> first(m->ndet + 1);
+  if (e == hipSuccess)
+    e = hipMemcpy(first.data(), m->det_first, first.size() * 4, hipMemcpyDeviceToHost);
+  AdjArgs A{nullptr, nullptr, nullptr, nullptr, m->P, m->a, m->b, ga, gb, f.Vp, f.V, f.nx,
+            f.ny, f.nz, f.ndir, f.NP, m->ddirs, m->delta, m->dstride, m->det_pairs, 0,
+            m->det_vox_dev, sd, int(steps)};
+  A.ndet_pairs = first[m->ndet];
+  // the forward step's kernel on the slots
+  CollideArgs fw{};
+  fw.Prow = m->Prow;
+  fw.a = m->a;
+  fw.b = m->b;
+  fw.Vp = f.Vp;
+  fw.NP = f.NP;
+  fw.part = m->cpart;
+  fw.step_ctr = m->step_ctr;
+  fw.mvtab = m->mvtab;
+  fw.mvdir = m->mvdir;
+  fw.dirs = m->ddirs;
+  fw.ndir = f.ndir;
+  fw.nx = f.nx;
+  fw.ny = f.ny;
+  fw.nz = f.nz;
+  fw.nvox = f.V;
+  fw.mvext = m->mvext;
+  fw.mvscramble = m->mvscramble;
+  fw.mvunscramble = m->mvunscramble;
+  fw.mvdet = nodet;
+  fw.spart = m->spart;
+  fw.mvfixed = 1;
+  InjectArgs ia{m->X, f.Vp, m->src_pairs, m->npairs, m->qdev, m->cap, m->step_ctr, m->budget,
+                m->ddirs, false, nullptr};
+  // the adjoint's moves: reversed tables over the pair of mu halves
+  CollideArgs bw = fw;
+  bw.pp = mu2;
+  bw.mvtab = rt;
+  bw.mvfixed = 0;
+  // mu_{steps-1}: the seeds of the last step
+  if (e == hipSuccess) {
+    AdjArgs a0 = A;
+    a0.mu = mu2 + size_t((steps - 1) & 1) * NV;
+    e = launch_adjoint_seeds(a0, int(steps - 1), m->stream);
+  }
+  for (int sgi = m->nckpt - 1; sgi >= 0 && e == hipSuccess; --sgi) {
+    const int m0 = sgi * K;
+    const int cnt = int(std::min<long long>(K, steps - m0));
+    e = hipMemcpyAsync(seg, m->ckpt + NV * sgi, NV * 4, hipMemcpyDeviceToDevice, m->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(m->stream);
+    if (e == hipSuccess) e = hipMemcpy(m->step_ctr, &m0, 4, hipMemcpyHostToDevice);
+    for (int i = 0; i < cnt && e == hipSuccess; ++i) {
+      fw.pp = seg + NV * i;
+      e = launch_collide_move(fw, ia, f, 0, m->stream);
+      if (e == hipSuccess) e = launch_advance_step(m->step_ctr, m->stream);
+    }
+    for (int i = cnt - 1; i >= 0 && e == hipSuccess; --i) {
+      A.xs = seg + NV * i;
+      e = launch_adjoint_move_step(A, bw, m0 + i, m->stream);
+    }
+  }
+  if (e == hipSuccess) e = hipStreamSynchronize(m->stream);
+  if (e == hipSuccess) {
+    const int sd_steps = int(steps);
+    e = hipMemcpy(m->step_ctr, &sd_steps, 4, hipMemcpyHostToDevice);
+  }
+  if (e == hipSuccess) e = hipMemcpy(hga.data(), ga, f.V * 8, hipMemcpyDeviceToHost);
+  if (e == hipSuccess) e = hipMemcpy(hgb.data(), gb, f.V * 8, hipMemcpyDeviceToHost);
+  cleanup();
+  if (e != hipSuccess) return device_fail(m, e, "adjoint");
+  return TR_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -1656,9 +1866,7 @@ tr_status tr_backward(tr_medium* m, const double* dL_dbins, float* dmua, float* 
       m->f.Vp * 4 * 5 >= (1LL << 31))
     return fail(TR_EINVAL, "the adjoint supports phase advance, fp32 and up to 192 directions");
   const Field& f = m->f;
-  const size_t NV = size_t(f.NP) * f.Vp;
   const long long steps = m->steps_done;
-  const int K = m->ckpt_every;
   // seeds dL/d det[k][s]: transpose of the rebinning
   std::vector<double> seed(size_t(m->ndet) * steps, 0.0);
   for (long long s = 0; s < steps; ++s) {
@@ -1673,80 +1881,9 @@ tr_status tr_backward(tr_medium* m, const double* dL_dbins, float* dmua, float* 
         seed[size_t(k) * steps + s] += dL_dbins[size_t(k) * m->nbins + j] * wgt;
     }
   }
-  hipError_t e = prepare_adjoint(f.NP);
-  if (e != hipSuccess) return device_fail(m, e, "adjoint set-up");
-  float* lam = m->alloc<float>(NV);
-  float* mu = m->alloc<float>(NV);
-  float* seg = m->alloc<float>(NV * size_t(K));
-  float* keep = m->alloc<float>(NV);
-  double* ga = m->alloc<double>(f.Vp);
-  double* gb = m->alloc<double>(f.Vp);
-  double* sd = m->alloc<double>(seed.size());
-  auto cleanup = [&]() {
-    for (void* p : {(void*)lam, (void*)mu, (void*)seg, (void*)keep, (void*)ga, (void*)gb, (void*)sd})
-      m->release(p);
-  };
-  if (!lam || !mu || !seg || !keep || !ga || !gb || !sd) {
-    cleanup();
-    return fail(TR_ENOMEM, "no device memory for the adjoint");
-  }
-  e = hipMemcpyAsync(keep, state_field(m), NV * 4, hipMemcpyDeviceToDevice, m->stream);
-  if (e == hipSuccess) e = hipMemsetAsync(lam, 0, NV * 4, m->stream);
-  if (e == hipSuccess) e = hipMemsetAsync(mu, 0, NV * 4, m->stream);
-  if (e == hipSuccess) e = hipMemsetAsync(seg, 0, NV * 4 * size_t(K), m->stream);
-  if (e == hipSuccess) e = hipMemsetAsync(ga, 0, f.Vp * 8, m->stream);
-  if (e == hipSuccess) e = hipMemsetAsync(gb, 0, f.Vp * 8, m->stream);
-  if (e == hipSuccess) e = hipMemcpy(sd, seed.data(), seed.size() * 8, hipMemcpyHostToDevice);
-  AdjArgs A{lam, mu, lam, nullptr, m->P, m->a, m->b, ga, gb, f.Vp, f.V, f.nx, f.ny, f.nz, f.ndir,
-            f.NP, m->ddirs, m->delta, m->dstride, nullptr, 0, m->det_vox_dev, sd, int(steps)};
-  // detector pairs of the medium (host copy rebuilt from the device lists)
-  std::vector<int> first(m->ndet + 1);
-  if (e == hipSuccess) e = hipMemcpy(first.data(), m->det_first, first.size() * 4, hipMemcpyDeviceToHost);
-  A.det_pairs = m->det_pairs;
-  A.ndet_pairs = first[m->ndet];
-  const bool split = false;
-  for (int sgi = m->nckpt - 1; sgi >= 0 && e == hipSuccess; --sgi) {
-    const int m0 = sgi * K;
-    const int cnt = int(std::min<long long>(K, steps - m0));
-    // recompute the segment's pre-collision fields from its checkpoint, in
-    // place: step i injects into slot i, collides it, and sweeps into slot i + 1
-    e = hipMemcpyAsync(seg, m->ckpt + NV * sgi, NV * 4, hipMemcpyDeviceToDevice, m->stream);
-    if (e == hipSuccess) e = hipStreamSynchronize(m->stream);
-    if (e == hipSuccess) e = hipMemcpy(m->step_ctr, &m0, 4, hipMemcpyHostToDevice);
-    for (int i = 0; i < cnt && e == hipSuccess; ++i) {
-      float* xi = seg + NV * i;
-      float* xn = i + 1 < cnt ? seg + NV * (i + 1) : m->X;
-      if (m->npairs > 0) {
-        InjectArgs ia{xi, f.Vp, m->src_pairs, m->npairs, m->qdev, m->cap, m->step_ctr, m->budget};
-        e = launch_inject(ia, m->stream);
-      }
-      CollideArgs ca{xi, m->Y, m->P, m->Prow, m->Phi, m->Plo, m->a, m->b, f.Vp, f.NP, m->cpart};
-      if (e == hipSuccess) e = launch_collide(ca, f, 0, 0, m->stream);
-      SweepArgs sa{m->Y, xn, f.Vp, f.V, f.nx, f.ny, f.nz, m->ddirs, m->delta, m->dstride,
-                   m->r, m->iface, m->nvox, m->islot, m->icptF, f.ndir, m->step_ctr, m->spart};
-      if (e == hipSuccess) e = launch_sweep(sa, f, split, 0, m->sweep_bpd, m->stream);
-      ReduceArgs ra{m->cpart, m->cnwg, m->spart, m->snwg, m->Y, f.Vp, m->det_pairs, m->det_first,
-                    m->det_vox_dev, m->ndet, m->ddirs, m->r, 0, m->step_ctr, m->budget,
-                    m->det_steps, m->cap, m->flag, m->rscratch, m->rdone};
-      if (e == hipSuccess) e = launch_reduce(ra, m->stream);
-    }
-    // adjoint steps backwards through the segment
-    for (int i = cnt - 1; i >= 0 && e == hipSuccess; --i) {
-      A.xs = seg + NV * i;
-      e = launch_adjoint_step(A, m0 + i, m->stream);
-    }
-  }
   std::vector<double> hga(f.V), hgb(f.V);
-  if (e == hipSuccess) e = hipMemcpyAsync(state_field(m), keep, NV * 4, hipMemcpyDeviceToDevice, m->stream);
-  if (e == hipSuccess) e = hipStreamSynchronize(m->stream);
-  if (e == hipSuccess) {
-    const int sd_steps = int(steps);
-    e = hipMemcpy(m->step_ctr, &sd_steps, 4, hipMemcpyHostToDevice);
-  }
-  if (e == hipSuccess) e = hipMemcpy(hga.data(), ga, f.V * 8, hipMemcpyDeviceToHost);
-  if (e == hipSuccess) e = hipMemcpy(hgb.data(), gb, f.V * 8, hipMemcpyDeviceToHost);
-  cleanup();
-  if (e != hipSuccess) return device_fail(m, e, "adjoint");
+  st = m->mfused ? backward_fused(m, seed, hga, hgb) : backward_sweep(m, seed, hga, hgb);
+  if (st != TR_OK) return st;
   // chain rule through a(mu_a, mu_s), b(mu_a, mu_s)
   for (int v = 0; v < f.V; ++v) {
     const double ma = m->mua_host[v], ms = m->mus_host[v], mt = ma + ms;
@@ -1869,6 +2006,27 @@ tr_status tr_host_lattice(int nside, int nx, int ny, int nz, int* axis, int* sig
   std::copy(L.axis.begin(), L.axis.end(), axis);
   std::copy(L.sign.begin(), L.sign.end(), sign);
   std::copy(L.offset.begin(), L.offset.end(), offset);
+  return TR_OK;
+}
+
+tr_status tr_host_move_tables(int nside, int nx, int ny, int nz, int reverse, int* tab, int* dir) {
+  if (nside < 1 || nside > 16 || nx < 1 || ny < 1 || nz < 1 || nx > 1023 || ny > 1023 ||
+      nz > 1023 || !tab || !dir)
+    return fail(TR_EINVAL, "bad arguments");
+  const std::vector<Vec3> dirs = healpix_ring(nside);
+  const Lattice L = build_lattice(dirs, nx, ny, nz);
+  const int ndir = int(dirs.size()), NP = int(round_up(ndir, 32));
+  const int dstride = L.maxext + 2;
+  std::vector<int8_t> dl(size_t(ndir) * 2 * dstride, 0);
+  for (int d = 0; d < ndir; ++d)
+    for (int q = 0; q < 2; ++q)
+      for (int k = 1; k <= L.maxext; ++k)
+        dl[(size_t(d) * 2 + q) * dstride + k] = int8_t(L.off(d, q, k) - L.off(d, q, k - 1));
+  std::vector<int> t, dr;
+  if (!build_move_tables(L, dl, dstride, NP, t, dr, reverse != 0))
+    return fail(TR_EINVAL, "a direction's transverse shifts are not -1, 0, +1 of one sign");
+  std::copy(t.begin(), t.end(), tab);
+  std::copy(dr.begin(), dr.end(), dir);
   return TR_OK;
 }
 

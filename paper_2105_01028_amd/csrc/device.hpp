@@ -108,6 +108,9 @@ struct CollideArgs {
   const float* rvox;
   const float* hD;
   int flux;
+  // phase moves in the collision: 1 = read half 0 and write half 1 of pp
+  // whatever the step's parity (the adjoint's recompute into its own slots)
+  int mvfixed;
 };
 
 struct SweepArgs {
@@ -343,6 +346,16 @@ hipError_t prepare_server(int NP);
 // gb += sum_d (P^T mu) xs.  Needs NP <= 192.
 hipError_t launch_adjoint_step(const AdjArgs& a, int m, hipStream_t s);
 hipError_t prepare_adjoint(int NP);
+// Adjoint step m with the moves in the collision's epilogue (mv: the move
+// arguments, pp the pair of mu halves, mvtab the reversed move tables, mvdet
+// all zero), then the seeds of step m - 1 into the half it wrote.
+hipError_t launch_adjoint_move_step(const AdjArgs& a, const CollideArgs& mv, int m,
+                                    hipStream_t s);
+hipError_t prepare_adjoint_move(int NP);
+// The seeds of step m into a.mu.
+hipError_t launch_adjoint_seeds(const AdjArgs& a, int m, hipStream_t s);
+// Advance the device step counter by one (no tallies).
+hipError_t launch_advance_step(int* ctr, hipStream_t s);
 hipError_t launch_energy(const float* X, long long Vp, int ndir, int V, float* E, hipStream_t s);
 
 // The allocation-free step's workspace: a file-scope device array of

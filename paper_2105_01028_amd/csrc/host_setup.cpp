@@ -143,7 +143,7 @@ Lattice build_lattice(const std::vector<Vec3>& dirs, int nx, int ny, int nz) {
 }
 
 bool build_move_tables(const Lattice& lat, const std::vector<int8_t>& dl, int dstride, int NP,
-                       std::vector<int>& tab, std::vector<int>& dir) {
+                       std::vector<int>& tab, std::vector<int>& dir, bool reverse) {
   const int* ext = lat.ext;
   const long long st[3] = {1, ext[0], (long long)ext[0] * ext[1]};
   const int S = lat.maxext;
@@ -162,17 +162,22 @@ bool build_move_tables(const Lattice& lat, const std::vector<int8_t>& dl, int ds
       if (s0) sb = s0;
       if (s1) sc = s1;
     }
-    const int fa = 2 * a + (sg > 0 ? 1 : 0), fb = 2 * b + (sb > 0 ? 1 : 0),
-              fc = 2 * c + (sc > 0 ? 1 : 0);
+    // reversed: the move back to the plane the ray came from, faces opposite
+    const int rs = reverse ? -1 : 1;
+    const int fa = 2 * a + (rs * sg > 0 ? 1 : 0), fb = 2 * b + (rs * sb > 0 ? 1 : 0),
+              fc = 2 * c + (rs * sc > 0 ? 1 : 0);
     dir[d] = 10 * a | (3 << (2 * a)) << 8;
     for (int p = 0; p < ext[a]; ++p) {
       const int k = sg > 0 ? p : ext[a] - 1 - p;
-      const int dbn = shift(d, 0, k + 1), dcn = shift(d, 1, k + 1);
+      // forward: the shift into plane k + 1; reversed: minus the shift into
+      // plane k (into plane 0 from past the last plane, the periodic box)
+      const int ks = reverse ? (k >= 1 ? k : ext[a]) : k + 1;
+      const int dbn = rs * shift(d, 0, ks), dcn = rs * shift(d, 1, ks);
       unsigned mk = 1u << fa;
       if (dbn) mk |= 1u << fb;
       if (dcn) mk |= 1u << fc;
       // |offset| <= 1 + 1023 + 1023^2 < 2^25: offset and mask share one int
-      const long long off = sg * st[a] + dbn * st[b] + dcn * st[c];
+      const long long off = rs * sg * st[a] + dbn * st[b] + dcn * st[c];
       tab[size_t(d) * S + p] = int(off * 64 + mk);
     }
   }

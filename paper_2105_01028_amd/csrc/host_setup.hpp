@@ -52,9 +52,14 @@ Lattice build_lattice(const std::vector<Vec3>& dirs, int nx, int ny, int nz);
 // 2 axis + side: the dominant-axis face always, the b / c face where the shift
 // into the next plane is not zero); zero rows elsewhere.  dir [NP]:
 // 10 axis | 3 << (2 axis + 8).  False, and the separate sweep is needed, when
-// a direction's b or c shifts are not all -1, 0 or +1 of one sign.
+// a direction's b or c shifts are not all -1, 0 or +1 of one sign.  reverse:
+// the tables of the inverse moves (the adjoint's), each voxel back to where
+// the forward ray came from, on the box taken periodically along the dominant
+// axis: minus the shift into the voxel's own plane (into plane 0: minus the
+// shift past the last plane), and the faces on the other side.
 bool build_move_tables(const Lattice& lat, const std::vector<int8_t>& dl, int dstride, int NP,
-                       std::vector<int>& tab, std::vector<int>& dir);
+                       std::vector<int>& tab, std::vector<int>& dir,
+                       bool reverse = false);
 
 // Time step (dt_ps > 0 wins; else dx * min(n) / c0) and per-voxel coefficients:
 // a = e^{-mu_t l}, b from the coefficient form, r = min(n)/n_v.

@@ -803,7 +803,7 @@ __global__ __launch_bounds__(512, 1) void collide_move_kernel(CollideArgs A, Inj
     load_p_lds<NP>(A.Prow, Pm);
   const int m = *A.step_ctr;
   move_descriptors<NP>(A, sdesc, m);
-  const MoveStep S = move_step<NP>(A, m);
+  const MoveStep S = move_step<NP>(A, A.mvfixed ? 0 : m);
   // a contiguous range of s per workgroup, tile = s * A.mvscramble mod ntiles
   // (a bijection: the multiplier is prime to ntiles), so that the tiles holding
   // edges of the box, which take the per-value face precedence, are spread
@@ -2627,6 +2627,130 @@ __global__ __launch_bounds__(512, 1) void adj_collide_kernel(AdjArgs A, int ntil
   }
 }
 
+// Adjoint step m with the moves in its epilogue.  mu_m (the seeds of step m
+// included) is half m & 1 of M.pp.  The transposed collision gives
+// lam_m = a mu_m + b P^T mu_m and the voxel's gradient sums (as
+// adj_collide_kernel), then lam_m goes through the transposed moves of step
+// m - 1 into the other half: mu_{m-1}[v] = lam_m[w], w the voxel v's photons
+// moved to at step m - 1, or 0 when they left the box.  That map is the
+// inverse of the forward moves on the box taken periodically, so it is written
+// as the forward scatter along reversed move tables (M.mvtab: for a voxel at
+// coordinate p of d's dominant axis, the offset back to the plane the forward
+// ray came from; a value that leaves writes a zero to the voxel whose forward
+// downwind lies outside).  At m = 0 there is no earlier step and nothing is
+// moved.  M.mvdet must be all zero (no detector keeps its value here).
+template <int NP>
+__global__ __launch_bounds__(512, 1) void adj_collide_move_kernel(AdjArgs A, CollideArgs M,
+                                                                  int ntiles, int m) {
+  constexpr int NQ = NP / 32;
+  constexpr int LDK = NP + 4;
+  extern __shared__ float Ps[];
+  int2* sdesc = reinterpret_cast<int2*>(Ps + size_t(NP) * LDK);
+  load_p_lds<NP>(A.PT, Ps);
+  move_descriptors<NP>(M, sdesc, m > 0 ? m - 1 : 0);
+  __syncthreads();
+  const MoveStep S = move_step<NP>(M, m);
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int hl = lane >> 5, cl = lane & 31;
+  const size_t rowbytes = size_t(A.Vp) * sizeof(float);
+  const float* __restrict__ Pl = Ps + cl * LDK + 4 * hl;
+  const char* __restrict__ mb0 = reinterpret_cast<const char*>(M.pp) + S.so;
+  const char* __restrict__ xb0 = reinterpret_cast<const char*>(A.xs);
+#pragma unroll 1
+  for (int tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+    const long long col = (long long)tile * 256 + wave * 32 + cl;
+    const unsigned voff = unsigned(size_t(col) * sizeof(float) + size_t(4 * hl) * rowbytes);
+    floatx16 acc[NQ];
+#pragma unroll
+    for (int q = 0; q < NQ; ++q)
+#pragma unroll
+      for (int r = 0; r < 16; ++r) acc[q][r] = 0.0f;
+    // z = P^T mu: the rows of chunk c + 1 are loaded while chunk c feeds the
+    // MFMAs (the last chunk reloads itself: in bounds, unused)
+    float bcur[16], bnext[16];
+#pragma unroll
+    for (int s = 0; s < 16; ++s)
+      bcur[s] = *reinterpret_cast<const float*>(
+          mb0 + size_t(8 * (s >> 2) + (s & 3)) * rowbytes + voff);
+#pragma unroll 1
+    for (int c = 0; c < NQ; ++c) {
+      const int cn = c + 1 < NQ ? c + 1 : c;
+#pragma unroll
+      for (int s = 0; s < 16; ++s)
+        bnext[s] = *reinterpret_cast<const float*>(
+            mb0 + size_t(32 * cn + 8 * (s >> 2) + (s & 3)) * rowbytes + voff);
+#pragma unroll
+      for (int s4 = 0; s4 < 16; s4 += 4) {
+        const int kk = 32 * c + 8 * (s4 >> 2);
+#pragma unroll
+        for (int q = 0; q < NQ; ++q) {
+          const float4 a4 = *reinterpret_cast<const float4*>(Pl + q * 32 * LDK + kk);
+          acc[q] = __builtin_amdgcn_mfma_f32_32x32x2f32(a4.x, bcur[s4 + 0], acc[q], 0, 0, 0);
+          acc[q] = __builtin_amdgcn_mfma_f32_32x32x2f32(a4.y, bcur[s4 + 1], acc[q], 0, 0, 0);
+          acc[q] = __builtin_amdgcn_mfma_f32_32x32x2f32(a4.z, bcur[s4 + 2], acc[q], 0, 0, 0);
+          acc[q] = __builtin_amdgcn_mfma_f32_32x32x2f32(a4.w, bcur[s4 + 3], acc[q], 0, 0, 0);
+        }
+      }
+#pragma unroll
+      for (int s = 0; s < 16; ++s) bcur[s] = bnext[s];
+    }
+    // the gradient sums mu x and z x, and lam = a mu + b z in place of z,
+    // block by block with the next block's mu and x rows in flight
+    const float av = A.a[col], bv = A.b[col];
+    double ga = 0.0, gb = 0.0;
+    float mc[16], xc[16], mn[16], xn[16];
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+      const size_t off = size_t(8 * (r >> 2) + (r & 3)) * rowbytes + voff;
+      mc[r] = *reinterpret_cast<const float*>(mb0 + off);
+      xc[r] = *reinterpret_cast<const float*>(xb0 + off);
+    }
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) {
+      if (q + 1 < NQ) {
+#pragma unroll
+        for (int r = 0; r < 16; ++r) {
+          const size_t off = size_t((q + 1) * 32 + 8 * (r >> 2) + (r & 3)) * rowbytes + voff;
+          mn[r] = *reinterpret_cast<const float*>(mb0 + off);
+          xn[r] = *reinterpret_cast<const float*>(xb0 + off);
+        }
+      }
+      float fa = 0.0f, fb = 0.0f;
+#pragma unroll
+      for (int r = 0; r < 16; ++r) {
+        const float z = acc[q][r];
+        fa = fmaf(mc[r], xc[r], fa);
+        fb = fmaf(z, xc[r], fb);
+        acc[q][r] = av * mc[r] + bv * z;
+      }
+      ga += double(fa);
+      gb += double(fb);
+      if (q + 1 < NQ) {
+#pragma unroll
+        for (int r = 0; r < 16; ++r) {
+          mc[r] = mn[r];
+          xc[r] = xn[r];
+        }
+      }
+    }
+    ga += __shfl_xor(ga, 32, 64);
+    gb += __shfl_xor(gb, 32, 64);
+    if (hl == 0 && col < A.V) {
+      A.ga[col] += ga;
+      A.gb[col] += gb;
+    }
+    if (m > 0) {
+      double esc[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0}, dom = 0.0;
+      move_epilogue<NP>(M, sdesc, S, acc, tile, esc, dom);
+    }
+  }
+}
+
+// The step counter, advanced without the tallies (the adjoint's recompute).
+__global__ void advance_step_kernel(int* ctr) {
+  if (threadIdx.x == 0) *ctr = *ctr + 1;
+}
+
 __global__ void energy_kernel(const float* X, long long Vp, int ndir, int V, float* E) {
   const int v = blockIdx.x * blockDim.x + threadIdx.x;
   if (v >= V) return;
@@ -3071,6 +3195,71 @@ hipError_t launch_adj_collide(const AdjArgs& a, hipStream_t s) {
   return hipGetLastError();
 }
 }  // namespace
+
+namespace {
+template <int NP>
+size_t adj_move_lds() {
+  return size_t(NP) * (NP + 4) * sizeof(float) + size_t(NP) * sizeof(int2);
+}
+template <int NP>
+hipError_t prepare_adj_move() {
+  return hipFuncSetAttribute(reinterpret_cast<const void*>(&adj_collide_move_kernel<NP>),
+                             hipFuncAttributeMaxDynamicSharedMemorySize, int(adj_move_lds<NP>()));
+}
+template <int NP>
+hipError_t launch_adj_move_np(const AdjArgs& a, const CollideArgs& mv, int m, hipStream_t s) {
+  const int ntiles = int(a.Vp / 256);
+  const int nb = ntiles < resident_blocks() ? ntiles : resident_blocks();
+  hipLaunchKernelGGL(adj_collide_move_kernel<NP>, dim3(unsigned(nb)), dim3(512),
+                     adj_move_lds<NP>(), s, a, mv, ntiles, m);
+  return hipGetLastError();
+}
+}  // namespace
+
+hipError_t prepare_adjoint_move(int NP) {
+  switch (NP) {
+    case 32: return prepare_adj_move<32>();
+    case 64: return prepare_adj_move<64>();
+    case 96: return prepare_adj_move<96>();
+    case 128: return prepare_adj_move<128>();
+    case 160: return prepare_adj_move<160>();
+    case 192: return prepare_adj_move<192>();
+    default: return hipErrorInvalidValue;
+  }
+}
+
+hipError_t launch_adjoint_move_step(const AdjArgs& a, const CollideArgs& mv, int m,
+                                    hipStream_t s) {
+  hipError_t e;
+  switch (a.NP) {
+    case 32: e = launch_adj_move_np<32>(a, mv, m, s); break;
+    case 64: e = launch_adj_move_np<64>(a, mv, m, s); break;
+    case 96: e = launch_adj_move_np<96>(a, mv, m, s); break;
+    case 128: e = launch_adj_move_np<128>(a, mv, m, s); break;
+    case 160: e = launch_adj_move_np<160>(a, mv, m, s); break;
+    case 192: e = launch_adj_move_np<192>(a, mv, m, s); break;
+    default: return hipErrorInvalidValue;
+  }
+  if (e != hipSuccess || m == 0 || a.ndet_pairs == 0) return e;
+  // the seeds of step m - 1 into mu_{m-1}
+  AdjArgs d = a;
+  d.mu = mv.pp + ((m - 1) & 1) * size_t(a.NP) * size_t(a.Vp);
+  hipLaunchKernelGGL(adj_detector_kernel, dim3(unsigned((a.ndet_pairs + 255) / 256)), dim3(256),
+                     0, s, d, m - 1);
+  return hipGetLastError();
+}
+
+hipError_t launch_adjoint_seeds(const AdjArgs& a, int m, hipStream_t s) {
+  if (a.ndet_pairs == 0) return hipSuccess;
+  hipLaunchKernelGGL(adj_detector_kernel, dim3(unsigned((a.ndet_pairs + 255) / 256)), dim3(256),
+                     0, s, a, m);
+  return hipGetLastError();
+}
+
+hipError_t launch_advance_step(int* ctr, hipStream_t s) {
+  hipLaunchKernelGGL(advance_step_kernel, dim3(1), dim3(64), 0, s, ctr);
+  return hipGetLastError();
+}
 
 hipError_t prepare_adjoint(int NP) {
   switch (NP) {

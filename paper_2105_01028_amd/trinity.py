@@ -125,6 +125,7 @@ _SIGS = {
     "tr_host_parents": [_I, _I, _PI],
     "tr_host_phase_matrix": [_I, _D, _I, _PD],
     "tr_host_lattice": [_I, _I, _I, _I, _PI, _PI, _PI],
+    "tr_host_move_tables": [_I, _I, _I, _I, _I, _PI, _PI],
     "tr_host_coefficients": [ctypes.POINTER(GridDesc), _PF, _PF, _PF, _PD, _PD, _PD, _PD],
     "tr_host_cone_set": [_I, _D, _D, _D, _D, _PI, _I, _PI],
     "tr_host_pulse": [_D, _D, _D, _D, _I, _I, _PD],
@@ -500,6 +501,17 @@ def host_lattice(nside, nx, ny, nz):
     off = np.zeros(n * 2 * (me + 1), np.int32)
     _check(lib().tr_host_lattice(nside, nx, ny, nz, _iptr(axis), _iptr(sign), _iptr(off)))
     return axis, sign, off.reshape(n, 2, me + 1)
+
+
+def host_move_tables(nside, nx, ny, nz, reverse=False):
+    n = 12 * nside * nside
+    NP = -(-n // 32) * 32
+    me = max(nx, ny, nz)
+    tab = np.zeros((NP + 1) * me, np.int32)
+    dr = np.zeros(NP, np.int32)
+    _check(lib().tr_host_move_tables(nside, nx, ny, nz, int(bool(reverse)), _iptr(tab),
+                                     _iptr(dr)))
+    return tab.reshape(NP + 1, me), dr
 
 
 def host_coefficients(prob):

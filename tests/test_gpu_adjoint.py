@@ -47,10 +47,16 @@ def rel_l2(a, b):
     return float(np.linalg.norm(a - b) / np.linalg.norm(b))
 
 
-@pytest.mark.parametrize("nside,ckpt,coef", [(2, 7, "paper"), (2, 40, "paper"),
-                                              (4, 13, "abs_exact")])
-def test_gradient_matches_oracle(nside, ckpt, coef):
-    p = _problem(nside).copy(coef=coef)
+@pytest.mark.parametrize("nside,ckpt,coef,transport", [
+    (2, 7, "paper", "auto"), (2, 40, "paper", "auto"), (4, 13, "abs_exact", "auto"),
+    # media stepped with the separate sweep: the adjoint's separate transposed sweep
+    (2, 7, "paper", "sweep"), (4, 13, "abs_exact", "sweep")])
+def test_gradient_matches_oracle(nside, ckpt, coef, transport):
+    """Media stepped with the moves in the collision (transport auto) take the
+    adjoint whose transposed collision does the transposed moves in its
+    epilogue; media stepped with the sweep take the separate transposed
+    sweep.  Both against the oracle's gradient."""
+    p = _problem(nside).copy(coef=coef, transport=transport)
     target = _target(p)
     gmua_ref, gmus_ref, _ = adjoint.gradient(p, target)
     gmua, gmus, _ = _gpu_grad(p, target, ckpt)
@@ -58,8 +64,9 @@ def test_gradient_matches_oracle(nside, ckpt, coef):
     assert rel_l2(gmus, gmus_ref) < 1e-4
 
 
-def test_backward_leaves_medium_unchanged():
-    p = _problem()
+@pytest.mark.parametrize("transport", ["auto", "sweep"])
+def test_backward_leaves_medium_unchanged(transport):
+    p = _problem().copy(transport=transport)
     _, _, (before, after, state, cont, state2, cont2) = _gpu_grad(p, _target(p), 9)
     assert np.array_equal(before, after)
     assert np.array_equal(state, state2)

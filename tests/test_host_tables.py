@@ -192,3 +192,60 @@ def test_bytes_required_with_index():
     assert T.bytes_required_n(d, bad) == 0
     with pytest.raises(ValueError):
         T.bytes_required_n(d, p.n[:-1])
+
+
+@pytest.mark.parametrize("nside,shape", [(2, (7, 5, 6)), (4, (9, 8, 5)), (4, (6, 11, 7)),
+                                         (1, (3, 4, 9))])
+def test_move_tables_against_oracle_lattice(nside, shape):
+    """The move tables of the fused collision and of its adjoint, checked
+    against the oracle's lattice (Sec. 2.1, Fig. 1): a forward entry moves each
+    voxel to its downwind voxel or flags its exit; a reversed entry moves each
+    voxel back to its upwind voxel (the one whose photons moved into it) or
+    flags that none is in the box.  The exits, sent around the box by the
+    wrap offsets of the faces they leave through, land one to one on the
+    voxels the other way has nothing for: forward exits on the voxels with no
+    upwind voxel, reversed exits on the voxels whose photons leave."""
+    from oracle import angles, lattice
+    nx, ny, nz = shape
+    tab, dr = T.host_move_tables(nside, nx, ny, nz)
+    rtab, rdr = T.host_move_tables(nside, nx, ny, nz, reverse=True)
+    assert np.array_equal(dr, rdr)
+    dirs = angles.healpix_ring(nside)
+    lat = lattice.RayLattice(dirs, (nz, ny, nx))
+    p = lat.coords()
+    v = np.arange(nx * ny * nz)
+    ext = (nx, ny, nz)
+    stride = (1, nx, nx * ny)
+    LF = np.zeros(v.size, np.int64)
+    for ax in range(3):
+        LF |= (p[ax] == 0).astype(np.int64) << (2 * ax)
+        LF |= (p[ax] == ext[ax] - 1).astype(np.int64) << (2 * ax + 1)
+    wrap = [(1 if f & 1 else -1) * ext[f >> 1] * stride[f >> 1] for f in range(6)]
+
+    def around(src, w, hits):
+        t = src + (w >> 6)
+        for f in range(6):
+            t = t - np.where((hits >> f) & 1, wrap[f], 0)
+        return t
+
+    for d in range(len(dirs)):
+        a = lat.axis[d]
+        assert dr[d] & 0xFF == 10 * a
+        dest, _ = lat.downwind(d)
+        inside = dest >= 0
+        up = np.full(v.size, -1)
+        up[dest[inside]] = v[inside]
+        has_up = up >= 0
+        w = tab[d, p[a]].astype(np.int64)
+        hits = w & 63 & LF
+        assert np.all(hits[inside] == 0) and np.all(hits[~inside] != 0)
+        assert np.array_equal(v[inside] + (w[inside] >> 6), dest[inside])
+        assert np.array_equal(np.sort(around(v[~inside], w[~inside], hits[~inside])),
+                              v[~has_up])
+        rw = rtab[d, p[a]].astype(np.int64)
+        rhits = rw & 63 & LF
+        assert np.all(rhits[has_up] == 0) and np.all(rhits[~has_up] != 0)
+        assert np.array_equal(v[has_up] + (rw[has_up] >> 6), up[has_up])
+        assert np.array_equal(np.sort(around(v[~has_up], rw[~has_up], rhits[~has_up])),
+                              v[~inside])
+    assert not tab[len(dirs):].any() and not rtab[len(dirs):].any()
