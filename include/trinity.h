@@ -131,8 +131,10 @@ typedef struct {
                          O(dtau)).  TR_RSRC_FLUX (1): C_i = a_i N_i + D_i omega
                          sum_j P_ij (1 - a_j) N_j / D_j -- what each direction scatters per
                          step is what the others gain, so light is conserved exactly; it
-                         agrees with TR_RSRC_TARGET to first order in dtau.  Needs one
-                         angular grid. */
+                         agrees with TR_RSRC_TARGET to first order in dtau.  With
+                         nside_scatter the coarse sums weight fine direction j by
+                         (1 - a_j) / D_j and fine direction i takes D_i times its share
+                         of the coarse source. */
 } tr_grid_desc;
 
 typedef struct {

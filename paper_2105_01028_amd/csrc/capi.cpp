@@ -313,6 +313,17 @@ hipError_t queue_step(tr_medium* m, const Workspace& w) {
                     m->b,     m->children,   m->parent,              f.ndir, m->nc,
                     m->nkids, 1.0f / float(m->nkids), f.Vp,          f.V,   w.cpart,
                     m->tlfused ? m->Y : nullptr, m->step_ctr};
+    if (m->ring) {
+      ta.ring = m->ring;
+      ta.H = m->H;
+      ta.slot = (long long)f.NP * f.Vp;
+      ta.mutdx = m->mutdx;
+      ta.omega = m->omega;
+      ta.hinvc = m->hinvc;
+      ta.hinvD = m->hinvD;
+      ta.hD = m->hD;
+      ta.flux = m->desc.retarded_source;
+    }
     Field fc = f;
     fc.ndir = m->nc;
     fc.NP = m->NPc;
@@ -330,13 +341,6 @@ hipError_t queue_step(tr_medium* m, const Workspace& w) {
     }
     if (m->ring) {
       KernelTimer t(m, TR_K_APPLY);
-      ta.ring = m->ring;
-      ta.H = m->H;
-      ta.slot = (long long)f.NP * f.Vp;
-      ta.mutdx = m->mutdx;
-      ta.omega = m->omega;
-      ta.hinvc = m->hinvc;
-      ta.hinvD = m->hinvD;
       if ((e = launch_apply_hop(ta, m->stream)) != hipSuccess) return e;
     } else if (!m->tlfused) {
       KernelTimer t(m, TR_K_APPLY);

@@ -54,10 +54,8 @@ inline bool valid_desc(const tr_grid_desc* d, std::string& err) {
   if (d->transport != 0 && d->transport != 1) return err = "bad transport", false;
   if (d->retarded_source != 0 && d->retarded_source != 1)
     return err = "bad retarded_source", false;
-  if (d->retarded_source == 1 &&
-      (d->advance != 3 || (d->nside_scatter != 0 && d->nside_scatter != d->nside)))
-    return err = "the flux-weighted source needs the retarded advance on one angular grid",
-           false;
+  if (d->retarded_source == 1 && d->advance != 3)
+    return err = "the flux-weighted source needs the retarded advance", false;
   if (d->nside_scatter != 0 && d->nside_scatter != d->nside) {
     const int ns = d->nside_scatter;
     if (ns < 1 || ns > d->nside || d->nside % ns != 0 || ((d->nside / ns) & (d->nside / ns - 1)))

@@ -286,6 +286,11 @@ struct TwoLevelArgs {
   const float* omega;
   const float* hinvc;
   const float* hinvD;
+  // retarded stepping with the flux-weighted source: the coarse sums weight
+  // fine row i by (1 - a_i) / D_i and the hop collision takes D_i (hD[i]) times
+  // the coarse source in place of 1 - a_i
+  int flux;
+  const float* hD;
 };
 long long coarse_sum_workgroups(const TwoLevelArgs& a);   // budget partial pairs written
 hipError_t launch_coarse_sum(const TwoLevelArgs& a, hipStream_t s);

@@ -51,13 +51,60 @@ __device__ __forceinline__ const_ints kids_of(const TwoLevelArgs& A, int J) {
   return (const_ints)(A.children + size_t(J) * A.nkids);
 }
 
+typedef const __attribute__((address_space(4))) float* const_floats;
+constexpr float kLog2e = 1.44269504088896341f;
+
+// The flux-weighted coarse sums of the retarded advance:
+//   M[J][v] = sum over children i of J of (1 - a_i(v)) X[i][v] / D_i,
+// a_i(v) = exp(-mu_t(v) dx / |Omega_a|_i), computed as apply_hop_kernel does.
+__device__ void coarse_sum_flux(const TwoLevelArgs& A, long long v0) {
+  const const_floats ic = (const_floats)A.hinvc;
+  const const_floats iD = (const_floats)A.hinvD;
+  const int ne = v0 + 4 <= A.V ? 4 : int(A.V - v0);
+  float ml2[4] = {0.f, 0.f, 0.f, 0.f};
+  for (int e = 0; e < ne; ++e) ml2[e] = A.mutdx[v0 + e] * kLog2e;
+  for (int J = blockIdx.y; J < A.nc; J += gridDim.y) {
+    const const_ints kids = kids_of(A, J);
+    float s[4] = {0.f, 0.f, 0.f, 0.f};
+    for (int k = 0; k < A.nkids; ++k) {
+      const int i = kids[k];
+      const size_t o = size_t(i) * A.Vp + v0;
+      const float c = ic[i], w = iD[i];
+      float x[4] = {0.f, 0.f, 0.f, 0.f};
+      if (ne == 4) {
+        const float4 x4 = ld4(A.X + o);
+        x[0] = x4.x;
+        x[1] = x4.y;
+        x[2] = x4.z;
+        x[3] = x4.w;
+      } else {
+        for (int e = 0; e < ne; ++e) x[e] = A.X[o + e];
+      }
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const float a = __builtin_amdgcn_exp2f(-ml2[e] * c);
+        s[e] = fmaf((1.0f - a) * x[e], w, s[e]);
+      }
+    }
+    if (ne == 4)
+      st4(A.M + size_t(J) * A.Vp + v0, make_float4(s[0], s[1], s[2], s[3]));
+    else
+      for (int e = 0; e < ne; ++e) A.M[size_t(J) * A.Vp + v0 + e] = s[e];
+  }
+}
+
 // Workgroup (quad block bx, coarse group by): coarse bins J = by, by + gy, ...
-// of the block's voxels; the budget partials cover the fine rows of those bins.
+// of the block's voxels; the budget partials cover the fine rows of those bins
+// (the retarded advance replaces them in apply_hop_kernel).
 __global__ __launch_bounds__(kTwoThreads) void coarse_sum_kernel(TwoLevelArgs A) {
   __shared__ double red[kTwoThreads / 64];
   // the field of this step's parity when it alternates between two buffers
   if (A.X2 && (*A.step_ctr & 1)) A.X = A.X2;
   const long long v0 = 4 * ((long long)blockIdx.x * kTwoThreads + threadIdx.x);
+  if (A.flux) {
+    if (v0 < A.V) coarse_sum_flux(A, v0);
+    return;
+  }
   double col[4] = {0.0, 0.0, 0.0, 0.0};
   double ab = 0.0;
   if (v0 + 4 <= A.V) {
@@ -156,18 +203,19 @@ __global__ __launch_bounds__(kTwoThreads) void apply_kernel(TwoLevelArgs A) {
 // form of Eq. 10 with the source from the coarse bins): fine direction i hops
 // dx/|Omega_a|_i, so
 //   C[i][v] = a X[i][v] + (1 - a) T[J(i)][v] / r^2,  a = exp(-mu_t(v) dx / |Omega_a|_i),
-// with T = omega (P_c M) from the coarse collide; C goes to the history slot
-// of the step.  The budget partials (absorbed (1 - a)(1 - omega) X / D_i per
+// with T = omega (P_c M) from the coarse collide; with the flux-weighted
+// source D_i T[J(i)][v] / r^2 in place of the second term (M then holds the
+// weighted sums of coarse_sum_flux).  C goes to the history slot of the step.  The budget partials (absorbed (1 - a)(1 - omega) X / D_i per
 // element, total X) replace those coarse_sum wrote, in the same layout.
 __global__ __launch_bounds__(kTwoThreads) void apply_hop_kernel(TwoLevelArgs A) {
   __shared__ double red[kTwoThreads / 64];
   const long long v0 = 4 * ((long long)blockIdx.x * kTwoThreads + threadIdx.x);
   const int m = *A.step_ctr;
   float* __restrict__ C = A.ring + size_t(m % A.H) * size_t(A.slot);
-  typedef const __attribute__((address_space(4))) float* const_floats;
   const const_floats ic = (const_floats)A.hinvc;
   const const_floats iD = (const_floats)A.hinvD;
-  constexpr float kLog2e = 1.44269504088896341f;
+  const const_floats hD = (const_floats)A.hD;
+  const bool flux = A.flux != 0;
   double lost[4] = {0.0, 0.0, 0.0, 0.0}, tot[4] = {0.0, 0.0, 0.0, 0.0};
   float om[4] = {0.f, 0.f, 0.f, 0.f};
   if (v0 < A.V) {
@@ -185,7 +233,7 @@ __global__ __launch_bounds__(kTwoThreads) void apply_hop_kernel(TwoLevelArgs A) 
       for (int k = 0; k < A.nkids; ++k) {
         const int i = kids[k];
         const size_t o = size_t(i) * A.Vp + v0;
-        const float c = ic[i], w = iD[i];
+        const float c = ic[i], w = iD[i], Di = flux ? hD[i] : 0.0f;
         float x[4] = {0.f, 0.f, 0.f, 0.f};
         if (ne == 4) {
           const float4 x4 = ld4(A.X + o);
@@ -201,7 +249,7 @@ __global__ __launch_bounds__(kTwoThreads) void apply_hop_kernel(TwoLevelArgs A) 
         for (int e = 0; e < 4; ++e) {
           const float a = __builtin_amdgcn_exp2f(-ml2[e] * c);
           const float oma = 1.0f - a;
-          y[e] = fmaf(a, x[e], oma * t[e]);
+          y[e] = fmaf(a, x[e], (flux ? Di : oma) * t[e]);
           lf[e] = fmaf(oma * x[e], w, lf[e]);
           tf[e] += x[e];
         }

@@ -5,7 +5,7 @@ comes from the HIP path.  Usage:
     python tests/golden/make_golden.py phantom64      # ~20 min on 8 cores
     python tests/golden/make_golden.py retarded64     # ~30 min on 8 cores
     python tests/golden/make_golden.py refraction32   # ~4 min on 8 cores
-    python tests/golden/make_golden.py adjoint64_fd   # ~1.5 h on 8 cores (21 solves)
+    python tests/golden/make_golden.py adjoint64_fd   # ~3 h on 8 cores (42 solves)
 """
 import os
 import sys
@@ -126,28 +126,54 @@ def _adj_loss(args):
     return float(np.sum((y - target) ** 2))
 
 
+def _adj_signals(perturbed):
+    """Binned detector signals of the FP64 oracle on the adjoint medium (the
+    target medium when perturbed)."""
+    from threadpoolctl import threadpool_limits
+    with threadpool_limits(limits=4):
+        p = W.config5(perturbed=perturbed)
+        return solve.forward(p).binned(p.bin_ps, p.nbins)
+
+
+def adjoint64_fd_voxels(p):
+    """The two voxel draws of adjoint64_fd (20 each, seed 55, signs seed 56):
+    'box', uniformly over the whole medium (most of them deep, where the loss
+    depends on them by 1e-27 against L of 1e-22, still far above the FP64
+    rounding of L); 'near', the shallow slab between the source (31-32,
+    31-32) and the nearer detectors on the line y = 32 (x = 37, 42, ...)."""
+    z, y, x = np.meshgrid(np.arange(p.nz), np.arange(p.ny), np.arange(p.nx), indexing="ij")
+    region = np.flatnonzero(((z < 6) & (np.abs(y - 32) <= 3) & (x >= 28) & (x < 56)).ravel())
+    sgn = np.random.default_rng(56).choice([-1.0, 1.0], ADJ_NVOX)
+    return {"box": (np.random.default_rng(55).choice(p.nvox, ADJ_NVOX, replace=False), sgn),
+            "near": (np.random.default_rng(55).choice(region, ADJ_NVOX, replace=False), sgn)}
+
+
 def adjoint64_fd():
     """Central differences of the FP64 oracle's loss on the 64^3 x 192 x 500-step
     adjoint medium (L = sum over detectors and bins of (y - y_target)^2, the
     target from the medium with each sphere's mu_a x 1.2), step h = 1e-4 of
-    each coefficient: along a +-1 pattern over 20 voxels drawn with seed 55
-    (for mu_a and for mu_s), and for the first 4 of them one by one."""
+    each coefficient, for both voxel draws of adjoint64_fd_voxels: along a +-1
+    pattern over the 20 voxels (for mu_a and for mu_s), and for the first 4 of
+    them one by one.  Also the oracle's own signals y0 and L0, so that a check
+    can seed its adjoint with the FP64 dL/dy = 2 (y0 - target): the target
+    differs from y0 by little more than an FP32 solve's rounding of y."""
     from multiprocessing import Pool
     p = W.config5()
     t0 = time.time()
-    target = solve.forward(W.config5(perturbed=True)).binned(p.bin_ps, p.nbins)
-    print(f"target {time.time() - t0:.0f} s", flush=True)
-    rng = np.random.default_rng(55)
-    vox = rng.choice(p.nvox, ADJ_NVOX, replace=False)
-    sgn = np.random.default_rng(56).choice([-1.0, 1.0], ADJ_NVOX)
+    with Pool(2) as pool:
+        target, y0 = pool.map(_adj_signals, [True, False])
+    print(f"target and base signals {time.time() - t0:.0f} s", flush=True)
     h = ADJ_RELH
+    draws = adjoint64_fd_voxels(p)
     jobs = []
-    for which in ("mua", "mus"):
-        for s in (1.0, -1.0):
-            jobs.append((which, vox, s * h * sgn, target))
-        for v in vox[:ADJ_SINGLE]:
+    for name in ("box", "near"):
+        vox, sgn = draws[name]
+        for which in ("mua", "mus"):
             for s in (1.0, -1.0):
-                jobs.append((which, np.array([v]), np.array([s * h]), target))
+                jobs.append((which, vox, s * h * sgn, target))
+            for v in vox[:ADJ_SINGLE]:
+                for s in (1.0, -1.0):
+                    jobs.append((which, np.array([v]), np.array([s * h]), target))
     with Pool(4) as pool:
         L = []
         for i, val in enumerate(pool.imap(_adj_loss, jobs)):
@@ -155,16 +181,18 @@ def adjoint64_fd():
             print(f"solve {i + 1}/{len(jobs)} {time.time() - t0:.0f} s", flush=True)
     out = {}
     k = 0
-    for which in ("mua", "mus"):
-        out["dir_" + which] = (L[k] - L[k + 1]) / (2.0 * h)   # d L / d eps along sgn
-        k += 2
-        single = []
-        for _ in range(ADJ_SINGLE):
-            single.append((L[k] - L[k + 1]) / (2.0 * h))     # d L / d eps at one voxel
+    for name in ("box", "near"):
+        out[f"vox_{name}"], out[f"sgn_{name}"] = draws[name]
+        for which in ("mua", "mus"):
+            out[f"dir_{name}_{which}"] = (L[k] - L[k + 1]) / (2.0 * h)   # dL/d eps along sgn
             k += 2
-        out["single_" + which] = np.array(single)
-    np.savez_compressed(os.path.join(HERE, "adjoint64_fd_oracle.npz"), vox=vox, sgn=sgn,
-                        rel_h=h, target=target, **out)
+            single = []
+            for _ in range(ADJ_SINGLE):
+                single.append((L[k] - L[k + 1]) / (2.0 * h))            # dL/d eps at one voxel
+                k += 2
+            out[f"single_{name}_{which}"] = np.array(single)
+    np.savez_compressed(os.path.join(HERE, "adjoint64_fd_oracle.npz"), rel_h=h, target=target,
+                        y0=y0, L0=float(np.sum((y0 - target) ** 2)), **out)
 
 
 if __name__ == "__main__":

@@ -84,13 +84,41 @@ def test_retarded_long_run_through_graph_replays():
     assert ref.in_domain[-1] < 0.5 * ref.in_domain.max()
 
 
+@pytest.mark.parametrize("source", ["target", "flux"])
 @pytest.mark.parametrize("nside,nsc,shape", [(4, 2, (12, 9, 7)), (4, 1, (9, 8, 6)),
                                               (8, 2, (10, 8, 6))])
-def test_retarded_two_level_matches_oracle(nside, nsc, shape):
+def test_retarded_two_level_matches_oracle(nside, nsc, shape, source):
     """The paper's combination: transport on a fine grid below the crossing
-    time, source from coarse bins (hop coefficients per fine direction)."""
-    p = _problem(nside, shape, 0.2, 8, 40).copy(nside_scatter=nsc)
+    time, source from coarse bins (hop coefficients per fine direction), with
+    both source weightings (flux: the coarse sums weighted per fine
+    direction)."""
+    p = _problem(nside, shape, 0.2, 8, 40).copy(nside_scatter=nsc, retarded_source=source)
     _compare(p, 40)
+
+
+@pytest.mark.parametrize("source", ["target", "flux"])
+def test_retarded_two_level_budget_per_source_form(source):
+    """The two-level grid until the box has emptied: the flux-weighted source
+    closes the photon budget to the FP32 rounding bound, the target form
+    shows its O(dtau) imbalance, the same on the GPU as in the oracle."""
+    p = _problem(4, (6, 6, 6), 0.2, 8, 450).copy(nside_scatter=2, retarded_source=source,
+                                                 mus=np.full((6, 6, 6), 1.5, np.float32))
+    ref = retarded.forward(p, p.steps)
+    got = run_gpu(p, p.steps)
+    b = got["budget"]
+    inj = b[:, 0].sum()
+    assert b[-1, 2] < 1e-7 * inj
+    imb_gpu = (inj - b[:, 1].sum() - b[:, 3:].sum() - b[-1, 2]) / inj
+    rinj = ref.injected.sum()
+    imb_ref = (rinj - ref.absorbed.sum() - ref.escaped.sum() - ref.in_domain[-1]) / rinj
+    print(f"[two-level {source}] budget imbalance GPU {imb_gpu:.3e}, oracle {imb_ref:.3e}",
+          flush=True)
+    if source == "flux":
+        assert abs(imb_ref) < 1e-11
+        assert abs(imb_gpu) < 2.0 ** -23 * b[:, 2].sum() / inj + 1e-9
+    else:
+        assert abs(imb_ref) > 1e-4
+        assert abs(imb_gpu - imb_ref) < 1e-4 * abs(imb_ref) + 2.0 ** -23 * b[:, 2].sum() / inj
 
 
 def test_retarded_rejected_where_unsupported():
@@ -102,7 +130,6 @@ def test_retarded_rejected_where_unsupported():
         for bad in (p.copy(precision="bf16split"), p.copy(source="implicit"),
                     p.copy(coef="abs_exact"), p.copy(nside=8),
                     p.copy(n=n2, nside=4, nside_scatter=2),
-                    p.copy(retarded_source="flux", nside=4, nside_scatter=2),
                     p.copy(retarded_source="flux", advance="split"),
                     p.copy(nside=16, nside_scatter=8)):
             with pytest.raises(T.TrinityError) as e:

@@ -373,3 +373,26 @@ def test_flux_and_target_sources_agree_to_first_order():
     St = retarded.build(p, dirs=dirs, P=P)
     N = np.random.default_rng(5).uniform(0.0, 1.0, S.a.shape)
     assert np.abs(retarded.collide(S, N)[0] - retarded.collide(St, N)[0]).max() < 1e-14
+
+
+def test_flux_source_conserves_light_on_the_two_level_grid():
+    """The flux-weighted source with the source on a coarser angular grid
+    (192 transport, 48 scattering directions, unequal hops): every photon
+    injected is absorbed or escapes, to rounding; the target-direction form
+    on the same medium does not close."""
+    mu_a, mu_s, n = W.uniform_medium(6, 6, 6, 0.02, 1.5, 1.4)
+    p = W.Problem(nx=6, ny=6, nz=6, dx_mm=1.0, nside=4, g=0.8, mua=mu_a, mus=mu_s, n=n,
+                  steps=1, dt_ps=0.2 * 1.4 / C0, src_ix=2, src_iy=2, src_w=2, t0_ps=6.0,
+                  fwhm_ps=4.0, det_face=[4], det_i=[4], det_j=[2], advance="retarded",
+                  nside_scatter=2, retarded_source="flux")
+    S = retarded.build(p)
+    assert np.unique(np.round(S.D[:, 0], 9)).size > 3
+    steps = 450
+    res = retarded.forward(p, steps, S)
+    inj = res.injected.sum()
+    assert res.in_domain[-1] < 1e-10 * inj
+    closure = (inj - res.absorbed.sum() - res.escaped.sum() - res.in_domain[-1]) / inj
+    assert abs(closure) < 1e-11, closure
+    rt = retarded.forward(p.copy(retarded_source="target"), steps)
+    clt = (rt.injected.sum() - rt.absorbed.sum() - rt.escaped.sum() - rt.in_domain[-1]) / inj
+    assert abs(clt) > 1e-4, clt
