@@ -169,6 +169,24 @@ def test_cancel():
         s1.close()
 
 
+def test_destroy_with_requests_in_flight():
+    """Destroying a server with requests running and queued waits for the
+    work already queued on its stream and frees everything; a new server
+    then serves as before."""
+    with _ctx():
+        s = T.Server(nside=2, g=0.7, max_slots=2)
+        ids = [s.submit(req(12, 300, 17 + k)) for k in range(4)]
+        running, queued = s.advance(8)
+        assert running == 2 and queued == 2
+        assert s.info(ids[0]).status == T.REQ_RUNNING
+        s.close()
+        s2 = T.Server(nside=2, g=0.7)
+        i = s2.submit(req(12, 30, 11))
+        drain(s2, [i])
+        assert s2.info(i).status == T.REQ_DONE
+        s2.close()
+
+
 def test_phantom_scale_stream_smoke():
     """A few requests of the serving workload (192 directions, 32^3 .. 48^3)
     with shortened step counts complete and conserve light."""
