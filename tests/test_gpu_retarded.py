@@ -86,7 +86,9 @@ def test_retarded_long_run_through_graph_replays():
 
 @pytest.mark.parametrize("source", ["target", "flux"])
 @pytest.mark.parametrize("nside,nsc,shape", [(4, 2, (12, 9, 7)), (4, 1, (9, 8, 6)),
-                                              (8, 2, (10, 8, 6))])
+                                              (8, 2, (10, 8, 6)),
+                                              # the fiducial run's 3072 / 192 directions
+                                              (16, 4, (9, 7, 5))])
 def test_retarded_two_level_matches_oracle(nside, nsc, shape, source):
     """The paper's combination: transport on a fine grid below the crossing
     time, source from coarse bins (hop coefficients per fine direction), with
