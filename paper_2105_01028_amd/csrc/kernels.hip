@@ -1491,12 +1491,16 @@ __device__ __forceinline__ void sweep_phase_flat(const SweepArgs& A, const Src& 
   const int sc = CX == 1 ? nx : nx * ny;
   float* __restrict__ Xd = A.X + size_t(d) * A.Vp;
   const int sign = D.sign;
-  const int ve = re * nx;
+  const int vb = rb * nx, ve = re * nx;
+  // passes start on a 128-byte line (32 voxels) at or before the block's first
+  // voxel, so a wave's 64 voxels are two whole lines; slots before vb belong
+  // to the block before and are skipped
+  const int gs = vb & ~31;
   const int drow = kThreads / nx, dxs = kThreads - drow * nx;
   // slot j of a pass takes flat index g0 + j kThreads: its (x, y, z)
   int xs[U], yys[U], zzs[U];
   {
-    const int g = rb * nx + threadIdx.x;
+    const int g = gs + threadIdx.x;
     const int row = g / nx;
     xs[0] = g - row * nx;
     zzs[0] = row / ny;
@@ -1511,14 +1515,14 @@ __device__ __forceinline__ void sweep_phase_flat(const SweepArgs& A, const Src& 
     }
   }
   const int drowU = U * kThreads / nx, dxU = U * kThreads - drowU * nx;
-  for (int g0 = rb * nx + threadIdx.x; g0 < ve; g0 += U * kThreads) {
+  for (int g0 = gs + threadIdx.x; g0 < ve; g0 += U * kThreads) {
     float out[U];
     int kk[U], dbn[U], dcn[U];
     bool live[U];
 #pragma unroll
     for (int j = 0; j < U; ++j) {
       const int v = g0 + j * kThreads;
-      live[j] = v < ve;
+      live[j] = v >= vb && v < ve;
       const int pa = AX == 1 ? yys[j] : zzs[j];
       const int pc = CX == 1 ? yys[j] : zzs[j];
       kk[j] = sign > 0 ? pa : ea - 1 - pa;
