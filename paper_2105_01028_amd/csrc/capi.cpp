@@ -181,7 +181,7 @@ tr_status device_fail(tr_medium* m, hipError_t e, const char* what) {
   if (!(p)) return fail(TR_ENOMEM, "device allocation failed")
 
 // Bytes of the allocations that do not depend on the step capacity.
-size_t fixed_bytes(const Field& f, int precision, size_t niface_guess) {
+size_t fixed_bytes(const Field& f, int precision, int retarded, size_t niface_guess) {
   size_t b = 0;
   b += 2 * size_t(f.NP) * f.Vp * sizeof(float);         // X, Y
   b += 2 * size_t(f.NP) * f.NP * sizeof(float);          // P and its transpose
@@ -189,7 +189,7 @@ size_t fixed_bytes(const Field& f, int precision, size_t niface_guess) {
   b += 3 * size_t(f.Vp) * sizeof(float);                 // a, b, r
   b += size_t(f.ndir) * sizeof(DevDir);
   b += size_t(f.ndir) * 2 * (std::max(f.nx, std::max(f.ny, f.nz)) + 2);
-  const int cn = collide_nwg(f, precision), sn = sweep_blocks_per_dir(f) * f.ndir;
+  const int cn = collide_nwg(f, precision), sn = sweep_blocks_per_dir(f, retarded) * f.ndir;
   b += (2 * size_t(cn) + 7 * size_t(std::max(sn, cn))) * sizeof(double);
   // move tables and detector bitmap of the phase moves in the collision
   const int S = std::max(f.nx, std::max(f.ny, f.nz));
@@ -512,7 +512,7 @@ tr_status check_medium(tr_medium* m) {
 // the records of max_steps steps.
 size_t base_bytes(const tr_grid_desc* desc, int ndet, int max_steps) {
   Field f = field_of(desc);
-  size_t b = fixed_bytes(f, desc->precision, 0);
+  size_t b = fixed_bytes(f, desc->precision, desc->advance == TR_ADVANCE_RETARDED, 0);
   if (desc->precision == TR_PREC_BF16SPLIT) b += size_t(f.NP) * sizeof(float);   // P_lo sums
   if (desc->source == TR_SOURCE_IMPLICIT)   // V, its eigenvalues, w0, w1, c
     b += (size_t(f.NP) * f.NP + f.NP + 3 * size_t(f.Vp)) * sizeof(float);
@@ -972,7 +972,7 @@ tr_status tr_create_medium(const tr_grid_desc* desc, const float* mua, const flo
   m->rscratch = m->alloc<double>(8);
   m->rdone = m->alloc<int>(1);
   m->cnwg = collide_nwg(f, desc->precision);
-  m->sweep_bpd = sweep_blocks_per_dir(f);
+  m->sweep_bpd = sweep_blocks_per_dir(f, mode == TR_ADVANCE_RETARDED);
   // two-level phase stepping: row blocks in multiples of 8 for the XCD-ordered
   // grid of the fused sweep (each XCD keeps its blocks for every direction)
   if (m->tlfused && f.ny * f.nz >= 8) m->sweep_bpd = std::max(8, m->sweep_bpd / 8 * 8);

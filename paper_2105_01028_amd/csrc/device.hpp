@@ -337,7 +337,7 @@ hipError_t prepare_collide(const Field& f, int bf16split);   // once per process
 // (then split mode with class bytes runs the fast kernel).
 hipError_t launch_sweep(const SweepArgs& a, const Field& f, int split, int fresnel, int bpd,
                         hipStream_t s, int fast_split_ok = 0);
-int sweep_blocks_per_dir(const Field& f);
+int sweep_blocks_per_dir(const Field& f, int retarded);
 hipError_t launch_gather(const GatherArgs& a, hipStream_t s);
 hipError_t launch_reduce(const ReduceArgs& a, hipStream_t s);
 // Batched server step over `nslots` request slots: work lists citems (slot,

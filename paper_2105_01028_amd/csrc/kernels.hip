@@ -995,8 +995,6 @@ template <int MT>
 __global__ __launch_bounds__(512, 1) void collide_bf16_stream_kernel(CollideArgs A, int ntiles) {
   constexpr int NQ = MT / 32;
   constexpr int KC = 32, LDK = KC + 8;             // bf16 per LDS row
-  constexpr int NG = MT * (KC / 4);                // 8-byte groups per matrix per chunk
-  constexpr int NPR = (NG + 511) / 512;
   extern __shared__ uint16_t Sbuf[];               // [2][hi, lo][MT][LDK]
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int hl = lane >> 5, cl = lane & 31;
@@ -1023,36 +1021,34 @@ __global__ __launch_bounds__(512, 1) void collide_bf16_stream_kernel(CollideArgs
             __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(rs, int(voff), int(j * rowbytes), 0));
     }
   };
-  // P_hi / P_lo staging: slot i of a thread is 8-byte group tid + 512 i of the
-  // chunk, i.e. row tid / 8 + 64 i; the chunk and the slot go in the scalar
-  // offset
+  // P_hi / P_lo staging: thread tid takes row tid / 2 of the chunk and its 16
+  // columns 16 (tid & 1) .. +15, read as two 16-byte loads (columns 0-7 and
+  // 8-15 of the group, the chunk in the scalar offset) and written as two
+  // 16-byte LDS stores in the operand order of the MFMA's k slots: slots 0-7
+  // take columns 0-3 and 8-11, slots 8-15 columns 4-7 and 12-15 (the X rows
+  // the lane halves hold)
   const __amdgpu_buffer_rsrc_t rph = raw_rsrc(A.Phi, unsigned(A.NP) * unsigned(A.NP) * 2u);
   const __amdgpu_buffer_rsrc_t rpl = raw_rsrc(A.Plo, unsigned(A.NP) * unsigned(A.NP) * 2u);
-  const int sr = tid >> 3, skap = (tid & 7) * 4;
-  const unsigned poff = 2u * unsigned((row0 + sr) * A.NP + 4 * ((skap >> 3) & 1) +
-                                      8 * (2 * ((skap >> 4) & 1) + ((skap >> 2) & 1)));
-  uint2 rh[NPR], rl[NPR];
+  const int sr = tid >> 1, sg = 16 * (tid & 1);
+  const bool sact = sr < MT;
+  const unsigned poff = 2u * unsigned((row0 + (sact ? sr : 0)) * A.NP + sg);
+  using u32x4 = unsigned __attribute__((ext_vector_type(4)));
+  u32x4 ha, hb, la, lb;
   auto stage = [&](int c) {
-#pragma unroll
-    for (int i = 0; i < NPR; ++i) {
-      if (i + 1 == NPR && sr + 64 * i >= MT) break;   // a partial last slot
-      const int so = 64 * c + i * 128 * A.NP;
-      const auto h2 = __builtin_amdgcn_raw_buffer_load_b64(rph, int(poff), so, 0);
-      const auto l2 = __builtin_amdgcn_raw_buffer_load_b64(rpl, int(poff), so, 0);
-      rh[i] = make_uint2(h2[0], h2[1]);
-      rl[i] = make_uint2(l2[0], l2[1]);
-    }
+    if (!sact) return;
+    ha = __builtin_amdgcn_raw_buffer_load_b128(rph, int(poff), 64 * c, 0);
+    hb = __builtin_amdgcn_raw_buffer_load_b128(rph, int(poff), 64 * c + 16, 0);
+    la = __builtin_amdgcn_raw_buffer_load_b128(rpl, int(poff), 64 * c, 0);
+    lb = __builtin_amdgcn_raw_buffer_load_b128(rpl, int(poff), 64 * c + 16, 0);
   };
   auto put = [&](int buf) {
-    uint16_t* Sh = Sbuf + buf * 2 * MT * LDK;
+    if (!sact) return;
+    uint16_t* Sh = Sbuf + buf * 2 * MT * LDK + sr * LDK + sg;
     uint16_t* Sl = Sh + MT * LDK;
-#pragma unroll
-    for (int i = 0; i < NPR; ++i) {
-      if (i + 1 == NPR && sr + 64 * i >= MT) break;
-      const int r = sr + 64 * i;
-      *reinterpret_cast<uint2*>(Sh + r * LDK + skap) = rh[i];
-      *reinterpret_cast<uint2*>(Sl + r * LDK + skap) = rl[i];
-    }
+    *reinterpret_cast<u32x4*>(Sh) = u32x4{ha[0], ha[1], hb[0], hb[1]};
+    *reinterpret_cast<u32x4*>(Sh + 8) = u32x4{ha[2], ha[3], hb[2], hb[3]};
+    *reinterpret_cast<u32x4*>(Sl) = u32x4{la[0], la[1], lb[0], lb[1]};
+    *reinterpret_cast<u32x4*>(Sl + 8) = u32x4{la[2], la[3], lb[2], lb[3]};
   };
   floatx16 acc[NQ];
 #pragma unroll
@@ -1065,21 +1061,25 @@ __global__ __launch_bounds__(512, 1) void collide_bf16_stream_kernel(CollideArgs
   put(0);
   __syncthreads();
   double colsum64 = 0.0;
+  // B operands of a chunk: x = b X split into bf16 hi + lo; the next chunk's
+  // are formed after the current chunk's MFMAs are issued, before the barrier
+  bf16x8 xh[2], xl[2];
+  auto split = [&](const float (&bx)[16]) {
+#pragma unroll
+    for (int t = 0; t < 2; ++t)
+#pragma unroll
+      for (int j = 0; j < 8; ++j) {
+        const float x = bx[8 * t + j] * bv;
+        xh[t][j] = static_cast<__bf16>(x);
+        xl[t][j] = bf16_rest(x, xh[t][j]);
+      }
+  };
+  split(b0);
 #pragma unroll 1
   for (int c = 0; c < NC; ++c) {
     const int cn = c + 1 < NC ? c + 1 : c;   // the last chunk restages itself (in bounds, unused)
     stage(cn);
     if (c + 1 < NC) ldc(c + 1, b1);
-    // this chunk's B operands: x = b X split into bf16 hi + lo
-    bf16x8 xh[2], xl[2];
-#pragma unroll
-    for (int t = 0; t < 2; ++t)
-#pragma unroll
-      for (int j = 0; j < 8; ++j) {
-        const float x = b0[8 * t + j] * bv;
-        xh[t][j] = static_cast<__bf16>(x);
-        xl[t][j] = bf16_rest(x, xh[t][j]);
-      }
     const int qc = c - row0 / 32;           // accumulator block of this chunk's rows, if in the tile
     if (qc >= 0 && qc < NQ) {
       float cs = 0.0f;
@@ -1107,6 +1107,9 @@ __global__ __launch_bounds__(512, 1) void collide_bf16_stream_kernel(CollideArgs
     }
     const uint16_t* __restrict__ Ph = Sbuf + (c & 1) * 2 * MT * LDK + cl * LDK + 8 * hl;
     const uint16_t* __restrict__ Pl = Ph + MT * LDK;
+    // the issuing wave's priority is raised while it feeds the MFMAs, so the
+    // other wave of the SIMD does its staging and splitting in the gaps
+    __builtin_amdgcn_s_setprio(1);
 #pragma unroll
     for (int t = 0; t < 2; ++t) {
 #pragma unroll
@@ -1118,6 +1121,8 @@ __global__ __launch_bounds__(512, 1) void collide_bf16_stream_kernel(CollideArgs
         acc[q] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(pl, xh[t], acc[q], 0, 0, 0);
       }
     }
+    __builtin_amdgcn_s_setprio(0);
+    if (c + 1 < NC) split(b1);
     if (c + 1 < NC) put((c + 1) & 1);
     __syncthreads();
 #pragma unroll
@@ -1539,7 +1544,8 @@ __device__ __forceinline__ void sweep_phase_flat(const SweepArgs& A, const Src& 
       if (!live[j]) continue;
       const int v = g0 + j * kThreads;
       const int pc = CX == 1 ? yys[j] : zzs[j];
-      Xd[v] = out[j];
+      // the field is not read again in this step: stream it past the caches
+      __builtin_nontemporal_store(out[j], Xd + v);
       acc.dom += double(out[j]);
       if (kk[j] + 1 >= ea) {
         acc.esc_a += double(Yd[v]);
@@ -3088,14 +3094,19 @@ hipError_t launch_collide_implicit(const CollideArgs& a, const Field& f, hipStre
   }
 }
 
-int sweep_blocks_per_dir(const Field& f) {
+int sweep_blocks_per_dir(const Field& f, int retarded) {
   // about 6144 voxels (24 per thread) or more per workgroup, at least one row,
   // and no more than about 32768 workgroups in all (each leaves 7 partial
   // sums): enough rounds of resident workgroups that the last, partly filled
-  // round costs little
+  // round costs little.  The retarded sweep, which reads two history slots
+  // per direction, takes up to 98304: with more, shorter workgroups per
+  // direction the resident ones cover fewer directions at once, which on
+  // 101^3 voxels x 3072 directions took the sweep from 11.9 to 9.6 ms (with
+  // its streaming stores)
   long long b = f.V / 6144;
   const long long rows = (long long)f.ny * f.nz;
-  const long long cap = 32768 / f.ndir > 1 ? 32768 / f.ndir : 1;
+  const long long most = retarded ? 98304 : 32768;
+  const long long cap = most / f.ndir > 1 ? most / f.ndir : 1;
   if (b > cap) b = cap;
   if (b > rows) b = rows;
   return int(b < 1 ? 1 : b);

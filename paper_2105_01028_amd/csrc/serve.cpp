@@ -241,7 +241,7 @@ tr_status build_request(const tr_server* s, const tr_request* q, Request& r) {
   r.bin_ps = q->bin_ps;
   r.nbins = q->nbins;
   r.ntiles = int(f.Vp / 256);
-  r.bpd = sweep_blocks_per_dir(f);
+  r.bpd = sweep_blocks_per_dir(f, 0);   // phase advance
   if (use_collide_move(f)) r.mfused = build_move_tables(lat, r.delta, r.dstride, f.NP, r.mvtab, r.mvdir);
   if (!r.mfused) r.mvtab.clear(), r.mvdir.clear();
   r.mvext = lat.maxext;
