@@ -5,8 +5,8 @@ detector records, budget rows and field as the solve run straight through,
 bit for bit (the same kernels in the same order on the same values).  Covers
 every way the field is carried between steps: one buffer (sweep), two
 buffers by step parity (moves in the collision, two-level phase stepping),
-the interception slots of index jumps, and the history of the retarded
-advance.  Also the medium bytes estimate against what creation allocates."""
+the interception slots of index jumps, the history of the retarded advance,
+and the two-level grid with the split and the retarded advance.  Also the medium bytes estimate against what creation allocates."""
 import numpy as np
 import pytest
 
@@ -40,7 +40,11 @@ def _cases():
     yield "split-fresnel", _air_slab(ph).copy(advance="split")
     yield "split-fresnel-bf16", _air_slab(ph).copy(advance="split", precision="bf16split")
     yield "implicit", ph.copy(source="implicit")
-    yield "two-level-phase", W.small_problem(**{**base, "nside": 4}).copy(nside_scatter=2)
+    tl = W.small_problem(**{**base, "nside": 4})
+    yield "two-level-phase", tl.copy(nside_scatter=2)
+    yield "two-level-split", tl.copy(nside_scatter=2, advance="split")
+    yield "two-level-retarded", tl.copy(nside_scatter=2, advance="retarded",
+                                        dt_ps=0.2 * tl.dx_mm * 1.4 / C0, retarded_source="flux")
     yield "retarded", ph.copy(advance="retarded", dt_ps=0.2 * ph.dx_mm * 1.4 / C0)
     yield "retarded-varying-n", _air_slab(ph).copy(advance="retarded", dt_ps=0.2 * ph.dx_mm / C0,
                                                    retarded_source="flux")
@@ -136,6 +140,7 @@ def _full_size():
     yield "phantom64-retarded", c2.copy(advance="retarded",
                                         dt_ps=0.2 * c2.dx_mm * float(c2.n.flat[0]) / C0)
     yield "refraction32-768", W.config3(nx=32)
+    yield "fiducial101", W.fiducial101()   # 3072 / 192 directions, retarded: 141 GB
 
 
 SIZES = CASES + list(_full_size())
