@@ -85,6 +85,36 @@ def copy_probe(nbytes):
                       "copies": 5}), flush=True)
 
 
+def copy_bandwidth(sizes=(1 << 30, 4 << 30, 12 << 30), reps=10):
+    """What plain device copies, reductions and fills reach on this GPU (torch's
+    own kernels, HIP events): the practical ceiling beside the 8 TB/s peak the
+    rooflines are priced against, per buffer size."""
+    import torch
+    out = {}
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+
+    def timed(fn):
+        for _ in range(3):
+            fn()
+        torch.cuda.synchronize()
+        e0.record()
+        for _ in range(reps):
+            fn()
+        e1.record()
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / reps
+
+    for nbytes in sizes:
+        a = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda")
+        b = torch.empty_like(a)
+        out[str(nbytes)] = {
+            "copy_TBps_read_plus_write": 2 * nbytes / timed(lambda: b.copy_(a)) / 1e9,
+            "sum_TBps_read": nbytes / timed(lambda: a.sum()) / 1e9,
+            "fill_TBps_write": nbytes / timed(lambda: b.fill_(1.0)) / 1e9}
+        del a, b
+    return out
+
+
 def kernel_rooflines(prof, prob, precision, workload="phantom64"):
     """Achieved rates of the collide and sweep kernels from their average
     launch durations and the algorithmic work per launch.  With the phase
@@ -868,6 +898,8 @@ def main():
                     help="arrivals of the serving stream (workload 'serving' or the extra)")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="BYTES",
                     help="only run a plain device copy of BYTES (counter calibration)")
+    ap.add_argument("--copy-bandwidth", action="store_true",
+                    help="only time plain device copies, sums and fills of 1, 4 and 12 GiB")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only; --gpus {args.gpus} is not supported "
@@ -876,6 +908,9 @@ def main():
         sys.exit(2)
     if args.copy_probe:
         copy_probe(args.copy_probe)
+        return
+    if args.copy_bandwidth:
+        print(json.dumps(copy_bandwidth()), flush=True)
         return
     import torch
     if args.workload == "serving":
