@@ -115,6 +115,18 @@ def copy_bandwidth(sizes=(1 << 30, 4 << 30, 12 << 30), reps=10):
     return out
 
 
+def mfma_ceiling():
+    """What the two MFMA shapes of the collision kernels deliver here
+    (tr_probe_mfma: back-to-back register-operand MFMAs, two wavefronts per
+    SIMD), beside the datasheet peaks the rooflines quote."""
+    from paper_2105_01028_amd import trinity as T
+    f32, f32_ms = T.probe_mfma(T.TR_PROBE_MFMA_F32, iters=20000)
+    b16, b16_ms = T.probe_mfma(T.TR_PROBE_MFMA_BF16, iters=40000)
+    return {"fp32_32x32x2_tflops": f32, "fp32_frac_of_peak": f32 / PEAK_TFLOPS["fp32"],
+            "bf16_32x32x16_tflops": b16, "bf16_frac_of_peak": b16 / PEAK_TFLOPS["bf16split"],
+            "probe_ms": {"fp32": f32_ms, "bf16": b16_ms}}
+
+
 def kernel_rooflines(prof, prob, precision, workload="phantom64"):
     """Achieved rates of the collide and sweep kernels from their average
     launch durations and the algorithmic work per launch.  With the phase
@@ -900,6 +912,8 @@ def main():
                     help="only run a plain device copy of BYTES (counter calibration)")
     ap.add_argument("--copy-bandwidth", action="store_true",
                     help="only time plain device copies, sums and fills of 1, 4 and 12 GiB")
+    ap.add_argument("--mfma-probe", action="store_true",
+                    help="only run the matrix-core rate probe (tr_probe_mfma)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only; --gpus {args.gpus} is not supported "
@@ -911,6 +925,9 @@ def main():
         return
     if args.copy_bandwidth:
         print(json.dumps(copy_bandwidth()), flush=True)
+        return
+    if args.mfma_probe:
+        print(json.dumps(mfma_ceiling()), flush=True)
         return
     import torch
     if args.workload == "serving":
@@ -996,6 +1013,14 @@ def main():
                   "instrumented_value": updates / e2,
                   "kernel_rooflines": kernel_rooflines(p2, prob, other, "refraction128"),
                   "budget_closure": c2}
+    ceil = mfma_ceiling()
+    ceil["collide_fp32_frac_of_probe"] = (
+        (out if args.precision == "fp32" else out[other])["kernel_rooflines"]["collide"]["achieved"]
+        / ceil["fp32_32x32x2_tflops"])
+    ceil["collide_bf16split_frac_of_probe"] = (
+        (out if args.precision == "bf16split" else out[other])["kernel_rooflines"]["collide"]
+        ["achieved"] / ceil["bf16_32x32x16_tflops"])
+    out["mfma_ceiling"] = ceil
     print("headline and its other precision done", file=sys.stderr, flush=True)
     acc = {"full_size_bf16split_vs_fp32": c3_accuracy(stream),
            "scaled_32cube_vs_fp64_oracle": refraction32_vs_oracle(stream)}

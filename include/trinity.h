@@ -479,6 +479,23 @@ tr_status tr_host_interceptions(const tr_grid_desc* desc, const float* n, int* d
                                 int* w, double* R, int* d_refl, int* d_refr, int cap,
                                 int* count);
 
+/* ---- Measurement --------------------------------------------------------
+ * Not part of the method: a probe of what the matrix cores deliver on the GPU
+ * at hand, the ceiling beside the datasheet peak for the collision kernels'
+ * rates. */
+enum { TR_PROBE_MFMA_F32 = 0, TR_PROBE_MFMA_BF16 = 1 };
+
+/* Runs `blocks` workgroups of 512 threads on the current device, each
+ * wavefront issuing iters x 8 independent MFMAs from registers (kind
+ * TR_PROBE_MFMA_F32: 32x32x2 FP32, the FP32 collision's instruction;
+ * TR_PROBE_MFMA_BF16: 32x32x16 bf16, the BF16-split one), once to warm up and
+ * once timed with HIP events on a stream of its own.  Writes the achieved
+ * TFLOP/s (2 M N K per MFMA) to *tflops and the timed launch's duration to
+ * *ms.  Allocates and frees a small device buffer (blocks x 2 KiB).
+ * TR_EINVAL: unknown kind, iters outside 1..2^24, blocks outside 1..2^20, or
+ * a null output; TR_EDEVICE: a HIP call failed. */
+tr_status tr_probe_mfma(int kind, int iters, int blocks, double* tflops, double* ms);
+
 #ifdef __cplusplus
 }
 #endif

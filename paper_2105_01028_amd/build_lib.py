@@ -12,7 +12,8 @@ CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libtrinity.so")
 BUILD = os.path.join(ROOT, "_build")
 
-SOURCES = ["kernels.hip", "capi.cpp", "serve.cpp", "host_setup.cpp", "twolevel.hip"]
+SOURCES = ["kernels.hip", "capi.cpp", "serve.cpp", "host_setup.cpp", "twolevel.hip",
+           "probe.hip"]
 ARCH = "gfx950"
 
 

@@ -131,6 +131,7 @@ _SIGS = {
     "tr_host_pulse": [_D, _D, _D, _D, _I, _I, _PD],
     "tr_host_interceptions": [ctypes.POINTER(GridDesc), _PF, _PI, _PI, _PI, _PD, _PI, _PI, _I,
                               _PI],
+    "tr_probe_mfma": [_I, _I, _I, _PD, _PD],
 }
 EXPORTED = tuple(_SIGS) + ("tr_last_error",)
 
@@ -556,3 +557,16 @@ def host_interceptions(prob):
     _check(lib().tr_host_interceptions(ctypes.byref(d), _fptr(n), _iptr(dd), _iptr(vv), _iptr(ww),
                                        _dptr(R), _iptr(rf), _iptr(rr), c, ctypes.byref(cnt)))
     return list(zip(dd.tolist(), vv.tolist(), ww.tolist(), R.tolist(), rf.tolist(), rr.tolist()))
+
+
+TR_PROBE_MFMA_F32, TR_PROBE_MFMA_BF16 = 0, 1
+
+
+def probe_mfma(kind, iters=20000, blocks=1024):
+    """tr_probe_mfma: (achieved TFLOP/s, ms) of back-to-back register-operand
+    MFMAs, kind TR_PROBE_MFMA_F32 (32x32x2 FP32) or TR_PROBE_MFMA_BF16
+    (32x32x16 bf16)."""
+    tf, ms = ctypes.c_double(), ctypes.c_double()
+    _check(lib().tr_probe_mfma(int(kind), int(iters), int(blocks), ctypes.byref(tf),
+                               ctypes.byref(ms)))
+    return tf.value, ms.value

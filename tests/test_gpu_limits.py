@@ -70,3 +70,12 @@ def test_largest_grids_single_step(shape):
     # the budget of the step: what was in the box is absorbed, escaped or still in it
     total = float(cols.astype(np.float64).sum())
     assert abs(b[0, 1] + b[0, 2] + b[0, 3:].sum() - total) <= 2e-6 * total
+
+
+def test_mfma_probe_reports_a_rate_within_the_peak():
+    """tr_probe_mfma runs both shapes and reports a positive rate no higher
+    than the datasheet dense peak (157.3 TFLOP/s FP32, 2500 bf16) plus 2 %."""
+    for kind, peak in ((T.TR_PROBE_MFMA_F32, 157.3), (T.TR_PROBE_MFMA_BF16, 2500.0)):
+        tf, ms = T.probe_mfma(kind, iters=2000, blocks=512)
+        print(f"probe kind {kind}: {tf:.1f} TFLOP/s in {ms:.3f} ms", flush=True)
+        assert ms > 0.0 and 0.0 < tf <= 1.02 * peak

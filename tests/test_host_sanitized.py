@@ -25,7 +25,8 @@ def _run(cmd, **kw):
 def _device_objects():
     """The HIP kernel objects of the regular build (built here if missing)."""
     from paper_2105_01028_amd import build_lib
-    objs = [os.path.join(build_lib.BUILD, s + ".o") for s in ("kernels.hip", "twolevel.hip")]
+    objs = [os.path.join(build_lib.BUILD, s + ".o") for s in build_lib.SOURCES
+            if s.endswith(".hip")]
     if not all(os.path.exists(o) for o in objs):
         build_lib.build(verbose=False)
     return objs
