@@ -1477,9 +1477,10 @@ __device__ __forceinline__ void sweep_rows(const SweepArgs& A, const DevDir& D, 
 }
 
 // Phase mode, a moving direction whose dominant axis is y or z, any nx: the
-// voxels of rows [rb, re) in flat order, kThreads apart, four per thread per
+// voxels of rows [rb, re) in flat order, kThreads apart, two per thread per
 // pass with all loads issued before the stores, so that every lane works
-// whatever the row length.  Same tallies, in the same order of precedence, as
+// whatever the row length (one, three, four or eight per pass were slower on
+// the 101^3 x 3072 retarded sweep).  Same tallies, in the same order of precedence, as
 // the row paths.
 template <int AX, class Src>
 __device__ __forceinline__ void sweep_phase_flat(const SweepArgs& A, const Src& Yd,
@@ -1488,7 +1489,7 @@ __device__ __forceinline__ void sweep_phase_flat(const SweepArgs& A, const Src& 
                                                  const int8_t* __restrict__ dc, SweepAcc& acc) {
   static_assert(AX == 1 || AX == 2, "rows run along x");
   constexpr int CX = AX == 2 ? 1 : 2;
-  constexpr int U = 4;
+  constexpr int U = 2;
   const int nx = A.nx, ny = A.ny, nz = A.nz;
   const int ea = AX == 1 ? ny : nz;
   const int ec = CX == 1 ? ny : nz;
