@@ -737,6 +737,26 @@ def c3_subbox(prob, x0=62, x1=66, y0=0, y1=128, z0=0, z1=128):
                      det_i=[nx // 2 + 4, nx // 2 + 8], det_j=[ny // 2, ny // 2])
 
 
+def slab_share(stream, steps=50, warmup=3, z0=56, nzs=16):
+    """The kernels at one GPU's share of a z-slab decomposition of the
+    128^3 x 768 refraction medium over eight GPUs: the 128 x 128 x 16 slab
+    z0 .. z0+15 (through the air cylinder), FP32 and BF16-split.  One GPU
+    only; the halo a slab would exchange per face and step is reported as
+    bytes, not timed."""
+    from paper_2105_01028_amd import workloads as W
+    sub = c3_subbox(W.config3(), 0, 128, 0, 128, z0, z0 + nzs)
+    out = {"workload": f"128 x 128 x {nzs} slab (z {z0}..{z0 + nzs - 1}) of the 128^3 "
+                       "refraction medium, 768 directions, split advance",
+           "halo_bytes_per_face_per_step": sub.ndir * sub.nx * sub.ny * 4}
+    for prec in ("fp32", "bf16split"):
+        e, g, prof, clos, det, _ = timed_run(sub.copy(precision=prec), steps, warmup, stream)
+        out[prec] = {"ms_per_step": g / steps * 1e3,
+                     "updates_per_s": sub.nvox * sub.ndir * steps / g,
+                     "kernels_ms": {k: v[0] / v[1] for k, v in prof.items() if v[1]},
+                     "budget_closure": clos}
+    return out
+
+
 def cpu_baseline(prob, budget_s=15.0, single_budget_s=12.0):
     """The FP64 oracle on the host cores, on a bounded sample of the workload:
     the first steps of a sub-box of the same medium (c3_subbox), set-up
@@ -900,7 +920,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true")
     ap.add_argument("--workload", default="refraction128",
-                    choices=["refraction128", "refraction128-steps", "phantom64", "twolevel64",
+                    choices=["refraction128", "refraction128-steps", "slab16", "phantom64",
+                             "twolevel64",
                              "retarded64", "fiducial101", "fiducial101-run", "serving",
                              "adjoint64", "implicit64"],
                     help="refraction128: the headline line; fiducial101-run: the paper's "
@@ -945,6 +966,9 @@ def main():
         return
     if args.workload == "fiducial101":
         print(json.dumps(paper_fiducial(torch.cuda.Stream(), args.steps)), flush=True)
+        return
+    if args.workload == "slab16":
+        print(json.dumps(slab_share(torch.cuda.Stream(), args.steps)), flush=True)
         return
     if args.workload == "fiducial101-run":
         # the whole run, both source forms (about three minutes each)
@@ -1040,6 +1064,7 @@ def main():
         out["retarded_courant02"] = retarded(stream)
         out["retarded_varying_index"] = retarded_varying_index(stream)
         out["paper_fiducial_101"] = paper_fiducial(stream)
+        out["slab_share_128x128x16"] = slab_share(stream)
         print("extras done", file=sys.stderr, flush=True)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(base)
