@@ -492,8 +492,9 @@ enum { TR_PROBE_MFMA_F32 = 0, TR_PROBE_MFMA_BF16 = 1 };
  * once timed with HIP events on a stream of its own.  Writes the achieved
  * TFLOP/s (2 M N K per MFMA) to *tflops and the timed launch's duration to
  * *ms.  Allocates and frees a small device buffer (blocks x 2 KiB).
- * TR_EINVAL: unknown kind, iters outside 1..2^24, blocks outside 1..2^20, or
- * a null output; TR_EDEVICE: a HIP call failed. */
+ * TR_EINVAL: unknown kind, iters outside 1..2^20, blocks outside 1..2^16
+ * (bounds that keep a launch to about two minutes at most), or a null output;
+ * TR_EDEVICE: a HIP call failed. */
 tr_status tr_probe_mfma(int kind, int iters, int blocks, double* tflops, double* ms);
 
 #ifdef __cplusplus

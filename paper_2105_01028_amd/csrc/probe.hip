@@ -60,8 +60,9 @@ extern "C" tr_status tr_probe_mfma(int kind, int iters, int blocks, double* tflo
                                    double* ms) {
   if (kind != TR_PROBE_MFMA_F32 && kind != TR_PROBE_MFMA_BF16)
     return fail(TR_EINVAL, "kind must be TR_PROBE_MFMA_F32 or TR_PROBE_MFMA_BF16");
-  if (iters < 1 || iters > (1 << 24) || blocks < 1 || blocks > (1 << 20))
-    return fail(TR_EINVAL, "iters must be in 1..2^24 and blocks in 1..2^20");
+  // bounds that keep a launch to about two minutes at most
+  if (iters < 1 || iters > (1 << 20) || blocks < 1 || blocks > (1 << 16))
+    return fail(TR_EINVAL, "iters must be in 1..2^20 and blocks in 1..2^16");
   if (!tflops || !ms) return fail(TR_EINVAL, "null output");
   float* out = nullptr;
   hipStream_t st = nullptr;

@@ -256,8 +256,8 @@ def test_mfma_probe_rejects_bad_arguments_before_touching_the_device():
     import ctypes
     tf, ms = ctypes.c_double(), ctypes.c_double()
     lib = T.lib()
-    for kind, iters, blocks in ((2, 10, 10), (-1, 10, 10), (0, 0, 10), (0, 1 << 25, 10),
-                                (1, 10, 0), (1, 10, (1 << 20) + 1)):
+    for kind, iters, blocks in ((2, 10, 10), (-1, 10, 10), (0, 0, 10), (0, (1 << 20) + 1, 10),
+                                (1, 10, 0), (1, 10, (1 << 16) + 1)):
         assert lib.tr_probe_mfma(kind, iters, blocks, ctypes.byref(tf),
                                  ctypes.byref(ms)) == T.TR_EINVAL
     assert lib.tr_probe_mfma(0, 10, 10, None, ctypes.byref(ms)) == T.TR_EINVAL
