@@ -1086,15 +1086,20 @@ __global__ __launch_bounds__(512, 1) void collide_bf16_stream_kernel(CollideArgs
 #pragma unroll
       for (int s = 0; s < 16; ++s) cs += b0[s];
       colsum64 += double(cs);
+      // the chunk's 32 column totals through scalar loads (the table is
+      // read-only): the wait for a vector load here would also wait for the
+      // next chunk's X loads issued before it; each lane half picks its rows
+      typedef const __attribute__((address_space(4))) float* const_f32p;
+      const const_f32p pq = (const_f32p)(A.plocol + 32 * c);
+      float pv[32];
+#pragma unroll
+      for (int k = 0; k < 32; ++k)
+        pv[k] = __uint_as_float(__builtin_amdgcn_readfirstlane(__float_as_uint(pq[k])));
       float pc[16];
 #pragma unroll
-      for (int g = 0; g < 4; ++g) {
-        const float4 p4 = *reinterpret_cast<const float4*>(A.plocol + 32 * c + 8 * g + 4 * hl);
-        pc[4 * g + 0] = p4.x;
-        pc[4 * g + 1] = p4.y;
-        pc[4 * g + 2] = p4.z;
-        pc[4 * g + 3] = p4.w;
-      }
+      for (int g = 0; g < 4; ++g)
+#pragma unroll
+        for (int i = 0; i < 4; ++i) pc[4 * g + i] = hl ? pv[8 * g + 4 + i] : pv[8 * g + i];
 #pragma unroll
       for (int q = 0; q < NQ; ++q)
         if (q == qc) {
